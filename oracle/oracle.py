@@ -1,0 +1,268 @@
+"""ctypes wrapper of the FP64 NEP oracle (``nep_oracle.c``).
+
+TEST INFRASTRUCTURE: only the tests, ``__graft_entry__.smoke()`` and the
+cpu_baseline leg of ``bench.py`` may import this module.  The HIP library
+never calls it and shares nothing with it.
+
+Arrays follow the conventions of ``paper_2205_10046_amd.synth``: positions
+(3, N) float64, types (N,) int32, box (9,) float64 with the cell vectors as
+rows, per-atom virials (9, N) row-major per atom (W_ab at row 3a + b).
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "nep_oracle.c")
+_LIB = os.environ.get("NEP_ORACLE_LIB",
+                      os.path.join(_HERE, "libnep_oracle.so"))
+
+GCC_CMD = ["gcc", "-O2", "-std=c99", "-ffp-contract=off", "-fno-fast-math",
+           "-fopenmp", "-fPIC", "-shared", _SRC, "-o", _LIB, "-lm"]
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle into oracle/libnep_oracle.so (plain gcc, FP64)."""
+    if force or not os.path.exists(_LIB) or (
+            os.path.getmtime(_LIB) < os.path.getmtime(_SRC)):
+        subprocess.run(GCC_CMD, check=True)
+    return _LIB
+
+
+class _HP(C.Structure):
+    _fields_ = [("n_types", C.c_int32), ("rc_radial", C.c_double),
+                ("rc_angular", C.c_double), ("n_max_radial", C.c_int32),
+                ("n_max_angular", C.c_int32), ("basis_radial", C.c_int32),
+                ("basis_angular", C.c_int32), ("l_max_3b", C.c_int32),
+                ("l_max_4b", C.c_int32), ("l_max_5b", C.c_int32),
+                ("n_neurons", C.c_int32), ("nn_per_type", C.c_int32)]
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB) or (
+                os.path.getmtime(_LIB) < os.path.getmtime(_SRC)):
+            build(force=True)
+        L = C.CDLL(_LIB)
+        P = C.POINTER
+        d, i32, i64 = C.c_double, C.c_int32, C.c_int64
+        pd, pi32, pi64 = P(d), P(i32), P(i64)
+        hp = P(_HP)
+        L.ora_num_descriptors.argtypes = [hp]
+        L.ora_num_descriptors.restype = C.c_int
+        L.ora_num_params.argtypes = [hp]
+        L.ora_num_params.restype = i64
+        L.ora_pairs.argtypes = [i64, pd, pd, pi32, d, i32, pi32, pi32, pi32,
+                                pi32]
+        L.ora_radial_basis.argtypes = [d, C.c_int, d, pd, pd]
+        L.ora_radial_basis.restype = None
+        L.ora_angular_poly.argtypes = [C.c_int, pd, pd, pd]
+        L.ora_angular_poly.restype = None
+        L.ora_coefficients.argtypes = [C.c_int, pd, pd, pd]
+        L.ora_coefficients.restype = None
+        L.ora_ann.argtypes = [hp, pd, C.c_int, pd, pd]
+        L.ora_ann.restype = d
+        L.ora_evaluate.argtypes = [hp, pd, i64, pd, pi32, pd, pi32, pd, pd,
+                                   pd, pd]
+        L.ora_descriptors.argtypes = [hp, pd, i64, pd, pi32, pd, pi32, pd]
+        L.ora_evaluate_atoms.argtypes = [hp, pd, i64, pd, pi32, pd, pi32,
+                                         i64, pi64, pd, pd, pd]
+        L.ora_md_nve.argtypes = [hp, pd, i64, pd, pd, pi32, pd, pd, pi32, d,
+                                 i64, i64, pd]
+        L.ora_set_threads.argtypes = [C.c_int]
+        L.ora_set_threads.restype = None
+        L.ora_get_threads.restype = C.c_int
+        _lib = L
+    return _lib
+
+
+def _hp(h):
+    return _HP(**{k: h[k] for k, _ in _HP._fields_})
+
+
+def _p(a, ct):
+    return a.ctypes.data_as(C.POINTER(ct))
+
+
+def _f64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def _i32(a):
+    return np.ascontiguousarray(a, dtype=np.int32)
+
+
+def _pbc(pbc):
+    return _i32(np.ones(3) if pbc is None else pbc)
+
+
+def set_threads(n: int) -> None:
+    lib().ora_set_threads(int(n))
+
+
+def get_threads() -> int:
+    return int(lib().ora_get_threads())
+
+
+def num_descriptors(h) -> int:
+    return int(lib().ora_num_descriptors(C.byref(_hp(h))))
+
+
+def num_params(h) -> int:
+    return int(lib().ora_num_params(C.byref(_hp(h))))
+
+
+def radial_basis(rc, K, r):
+    f = np.zeros(K)
+    df = np.zeros(K)
+    lib().ora_radial_basis(float(rc), int(K), float(r), _p(f, C.c_double),
+                           _p(df, C.c_double))
+    return f, df
+
+
+def angular_poly(lmax, d):
+    nb = (lmax + 1) ** 2 - 1
+    d = _f64(d)
+    b = np.zeros(nb)
+    g = np.zeros(3 * nb)
+    lib().ora_angular_poly(int(lmax), _p(d, C.c_double), _p(b, C.c_double),
+                           _p(g, C.c_double))
+    return b, g.reshape(nb, 3)
+
+
+def coefficients(lmax):
+    nb = (lmax + 1) ** 2 - 1
+    c3 = np.zeros(max(nb, 48))
+    c4 = np.zeros(5)
+    c5 = np.zeros(3)
+    lib().ora_coefficients(int(lmax), _p(c3, C.c_double), _p(c4, C.c_double),
+                           _p(c5, C.c_double))
+    return c3[:nb], c4, c5
+
+
+def pairs(pos, box, rc, pbc=None, cap=None):
+    """Neighbour rows at cutoff rc: list of (j array, shift (m,3) array)."""
+    pos = _f64(pos)
+    box = _f64(box)
+    n = pos.shape[1]
+    if cap is None:
+        cap = 512
+    while True:
+        cnt = np.zeros(n, np.int32)
+        nb = np.zeros(n * cap, np.int32)
+        sh = np.zeros(n * cap * 3, np.int32)
+        mx = C.c_int32(0)
+        err = lib().ora_pairs(n, _p(pos, C.c_double), _p(box, C.c_double),
+                              _p(_pbc(pbc), C.c_int32), float(rc), cap,
+                              _p(cnt, C.c_int32), _p(nb, C.c_int32),
+                              _p(sh, C.c_int32), C.byref(mx))
+        if err:
+            raise RuntimeError(f"ora_pairs failed ({err})")
+        if mx.value <= cap:
+            break
+        cap = mx.value
+    nb = nb.reshape(n, cap)
+    sh = sh.reshape(n, cap, 3)
+    return [(nb[i, :cnt[i]].copy(), sh[i, :cnt[i]].copy()) for i in range(n)]
+
+
+def ann(h, params, type_, q):
+    params = _f64(params)
+    q = _f64(q)
+    fp = np.zeros_like(q)
+    u = lib().ora_ann(C.byref(_hp(h)), _p(params, C.c_double), int(type_),
+                      _p(q, C.c_double), _p(fp, C.c_double))
+    return u, fp
+
+
+def evaluate(h, params, pos, types, box, pbc=None, want_q=False):
+    """Full evaluation: returns dict U (N,), F (3,N), W (9,N) [, q (N,Nd)]."""
+    params = _f64(params)
+    pos = _f64(pos)
+    types = _i32(types)
+    box = _f64(box)
+    n = pos.shape[1]
+    U = np.zeros(n)
+    F = np.zeros((3, n))
+    W = np.zeros((9, n))
+    q = np.zeros((n, num_descriptors(h))) if want_q else None
+    err = lib().ora_evaluate(C.byref(_hp(h)), _p(params, C.c_double), n,
+                             _p(pos, C.c_double), _p(types, C.c_int32),
+                             _p(box, C.c_double), _p(_pbc(pbc), C.c_int32),
+                             _p(U, C.c_double), _p(F, C.c_double),
+                             _p(W, C.c_double),
+                             _p(q, C.c_double) if want_q else None)
+    if err:
+        raise RuntimeError(f"ora_evaluate failed ({err})")
+    out = dict(U=U, F=F, W=W)
+    if want_q:
+        out["q"] = q
+    return out
+
+
+def descriptors(h, params, pos, types, box, pbc=None):
+    params = _f64(params)
+    pos = _f64(pos)
+    types = _i32(types)
+    box = _f64(box)
+    n = pos.shape[1]
+    q = np.zeros((n, num_descriptors(h)))
+    err = lib().ora_descriptors(C.byref(_hp(h)), _p(params, C.c_double), n,
+                                _p(pos, C.c_double), _p(types, C.c_int32),
+                                _p(box, C.c_double), _p(_pbc(pbc), C.c_int32),
+                                _p(q, C.c_double))
+    if err:
+        raise RuntimeError(f"ora_descriptors failed ({err})")
+    return q
+
+
+def evaluate_atoms(h, params, pos, types, box, idx, pbc=None):
+    """U (k,), F (k,3), W (k,9) of the atoms idx only (large structures)."""
+    params = _f64(params)
+    pos = _f64(pos)
+    types = _i32(types)
+    box = _f64(box)
+    idx = np.ascontiguousarray(idx, dtype=np.int64)
+    k = idx.shape[0]
+    U = np.zeros(k)
+    F = np.zeros((k, 3))
+    W = np.zeros((k, 9))
+    err = lib().ora_evaluate_atoms(C.byref(_hp(h)), _p(params, C.c_double),
+                                   pos.shape[1], _p(pos, C.c_double),
+                                   _p(types, C.c_int32), _p(box, C.c_double),
+                                   _p(_pbc(pbc), C.c_int32), k,
+                                   _p(idx, C.c_int64), _p(U, C.c_double),
+                                   _p(F, C.c_double), _p(W, C.c_double))
+    if err:
+        raise RuntimeError(f"ora_evaluate_atoms failed ({err})")
+    return dict(U=U, F=F, W=W)
+
+
+def md_nve(h, params, pos, vel, types, mass_per_type, box, dt, n_steps,
+           thermo_every, pbc=None):
+    """Run NVE; returns (pos, vel, thermo rows (n_rows, 13))."""
+    params = _f64(params)
+    pos = _f64(pos).copy()
+    vel = _f64(vel).copy()
+    types = _i32(types)
+    m = _f64(mass_per_type)
+    box = _f64(box)
+    rows = n_steps // thermo_every if thermo_every > 0 else 0
+    th = np.zeros((max(rows, 1), 13))
+    err = lib().ora_md_nve(C.byref(_hp(h)), _p(params, C.c_double),
+                           pos.shape[1], _p(pos, C.c_double),
+                           _p(vel, C.c_double), _p(types, C.c_int32),
+                           _p(m, C.c_double), _p(box, C.c_double),
+                           _p(_pbc(pbc), C.c_int32), float(dt), int(n_steps),
+                           int(thermo_every), _p(th, C.c_double))
+    if err:
+        raise RuntimeError(f"ora_md_nve failed ({err})")
+    return pos, vel, th[:rows]
