@@ -1,0 +1,200 @@
+"""NEP MD throughput on one MI355X: the 131,072-atom 4-species FCC alloy.
+
+python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-bf16] [--no-cpu]
+
+A step is one velocity-Verlet NVE step of the whole hot path (cell sort and
+neighbour rows, descriptors, network on MFMA, partial forces, Newton-3 force
+and virial gather, float64 integration, thermo reduction every 10 steps).
+Positions, velocities and species are resident in device memory before the
+timed region; the timed region is one nep_md_run_dev call of K steps,
+bracketed by device synchronisations.  Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+WORKLOAD = "fcc131k"
+THERMO_EVERY = 10
+# MI355X: FP32 vector peak without packed-FP32 instructions (all device code is
+# built with packed FP32 disabled): 256 CU x 64 lanes x 2 flop x 2.4 GHz
+PEAK_FP32_VALU = 256 * 64 * 2 * 2.4e9 / 1e12
+PEAK_FP32_MFMA = 157.3
+PEAK_BF16_MFMA = 2500.0
+PEAK_HBM = 8000.0  # GB/s
+
+
+def algorithmic_flops(h, p_r, p_a):
+    """Useful float work per atom of each pass (flop; a multiply-add counts 2).
+
+    p_r, p_a: mean neighbours within r_c^R and r_c^A.  Per bond: the float64
+    minimum image and displacement (20), length and direction (8), cutoff
+    function and derivative (10); Chebyshev recurrences, basis values and
+    derivatives (5-12 per basis function); the radial-function contractions
+    (2 n K per value); the angular polynomials and their gradients (2 and 4
+    per polynomial) and the n_A x NB contractions with the sums or with
+    dU/dS.  The network is 2 GEMMs of 2 N_des N_neu each.
+    """
+    nR, KR = h["n_max_radial"] + 1, h["basis_radial"] + 1
+    nA, KA = h["n_max_angular"] + 1, h["basis_angular"] + 1
+    T, L, nd, nn = h["n_types"], h["l_max_3b"], None, h["n_neurons"]
+    NB = (L + 1) ** 2 - 1
+    nd = nR + nA * (L + (h["l_max_4b"] >= 2) + (h["l_max_5b"] >= 1))
+    geom = 20 + 8 + 10
+    desc = (p_r * (geom + 5 * KR) + 2 * nR * T * KR
+            + p_a * (geom + 5 * KA + 2 * nA * KA + 2 * NB + 2 * nA * NB)
+            + nA * (3 * NB + 40))
+    mlp = 4 * nd * nn + 6 * nn
+    force = (2 * T * KR * nR + p_r * (geom + 12 * KR + 6)
+             + p_a * (geom + 12 * KA + 4 * nA * KA + 4 * NB + NB * (4 * nA + 6) + 30)
+             + nA * NB * 8)
+    gather = (p_r + p_a) * (20 + 6 + 18)
+    return dict(descriptor=desc, mlp=mlp, partial_forces=force, gather=gather)
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1000)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--no-bf16", action="store_true")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    return ap.parse_args()
+
+
+def run_md(handle, pos_d, vel_d, types_d, masses, box, steps, warmup, torch):
+    th = torch.zeros((max(steps // THERMO_EVERY, 1), 13), dtype=torch.float64,
+                     device=pos_d.device)
+    if warmup:
+        handle.md_run_dev(pos_d, vel_d, types_d, masses, box, 1.0, warmup, 0, th)
+    torch.cuda.synchronize()
+    handle.set_timing(True)
+    t0 = time.perf_counter()
+    handle.md_run_dev(pos_d, vel_d, types_d, masses, box, 1.0, steps, THERMO_EVERY, th)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    stages = handle.timing()
+    handle.set_timing(False)
+    return dt, stages, th.cpu().numpy()
+
+
+def cpu_baseline(h, params, seconds):
+    """The oracle, as it is, on a bounded sample of the same workload: an
+    FCC 6x6x6 sub-cell (864 atoms) of the same alloy and model, NVE steps."""
+    from oracle import oracle as ora
+    from paper_2205_10046_amd import synth
+    pos, types, box = synth.lattice("fcc", 6, 4.05, 0.0, 4)
+    m = np.array(synth.MASSES[WORKLOAD])
+    vel = synth.maxwell_velocities(m[types], 300.0)
+    n = pos.shape[1]
+    t0 = time.perf_counter()
+    ora.md_nve(h, params, pos, vel, types, m, box, 1.0, 1, 0)
+    t1 = time.perf_counter() - t0           # one step + the initial evaluation
+    steps = max(2, min(200, int(seconds / max(t1 / 2, 1e-3))))
+    t0 = time.perf_counter()
+    ora.md_nve(h, params, pos, vel, types, m, box, 1.0, steps, 0)
+    dt = time.perf_counter() - t0
+    # steps + 1 evaluations were done; count steps only
+    return dict(value=n * steps / dt, unit="atom-step/s", cores=ora.get_threads(),
+                kind="oracle",
+                sample=(f"FP64 C oracle, {steps} NVE steps of an 864-atom 6x6x6 FCC "
+                        f"sub-cell of the same 4-species alloy and model "
+                        f"({dt:.1f} s); O(N^2) image pair search as written"))
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
+              "(no multi-GPU path is built).", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    from oracle import oracle as ora
+    from paper_2205_10046_amd import nep, synth
+
+    dev = torch.device("cuda:0")
+    h = synth.WORKLOADS[WORKLOAD]
+    params = synth.random_params(nep.nep_num_params(h))
+    pos, types, box = synth.fcc131k()
+    masses = np.array(synth.MASSES[WORKLOAD])
+    vel = synth.maxwell_velocities(masses[types], 300.0)
+    n = pos.shape[1]
+    p_r, p_a = 54.0, 42.0   # perfect FCC shells within 6 A and 5 A
+
+    results = {}
+    for prec in ([nep.NEP_MLP_FP32] + ([] if args.no_bf16 else [nep.NEP_MLP_BF16])):
+        handle = nep.Handle(h, params, mlp_precision=prec)
+        pos_d = torch.tensor(pos, device=dev)
+        vel_d = torch.tensor(vel, device=dev)
+        types_d = torch.tensor(types, device=dev)
+        dt, stages, th = run_md(handle, pos_d, vel_d, types_d, masses, box, args.steps,
+                                args.warmup, torch)
+        results[prec] = (dt, stages, th)
+        handle.close()
+        del pos_d, vel_d, types_d
+        torch.cuda.empty_cache()
+
+    dt, stages, th = results[nep.NEP_MLP_FP32]
+    value = n * args.steps / dt
+    fl = algorithmic_flops(h, p_r, p_a)
+    avg = {k: v[0] / v[1] for k, v in stages.items()}
+    dom = max(("descriptor", "partial_forces"), key=lambda k: avg.get(k, 0.0))
+    achieved = fl[dom] * n / (avg[dom] * 1e-3) / 1e12
+    mlp_t = fl["mlp"] * n / (avg["mlp"] * 1e-3) / 1e12
+    e = th[:, 1] + th[:, 2]
+    out = {
+        "metric": "NEP MD atom-step/s, 131k atoms, FP32 vs BF16-MLP; served p50/p99 latency",
+        "value": value,
+        "unit": "atom-step/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": dt / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "fcc131k: 131,072-atom 4-species random FCC alloy "
+                               "(32^3 cells, a=4.05 A), NEP r_c 6/5 A, n_max 8/6, "
+                               "N_bas 8/6, l_max 4 + 4-body, 50 neurons per species, "
+                               "NVE dt=1 fs from 300 K, thermo every 10 steps",
+                   "atoms": n, "mlp": "fp32"},
+        "roofline": {"bound": "alu", "kernel": dom, "achieved": achieved,
+                     "peak": PEAK_FP32_VALU, "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_VALU,
+                     "traffic": None,
+                     "flop_per_atom": fl[dom], "avg_launch_ms": avg[dom]},
+        "mlp_roofline": {"bound": "mfma", "achieved": mlp_t, "peak": PEAK_FP32_MFMA,
+                         "unit": "TFLOP/s", "frac": mlp_t / PEAK_FP32_MFMA,
+                         "avg_launch_ms": avg["mlp"]},
+        "stages_ms_per_step": {k: v[0] / args.steps for k, v in stages.items()},
+        "nve_drift_eV_per_atom": float(np.abs(e - e[0]).max() / n) if len(e) else None,
+    }
+    if nep.NEP_MLP_BF16 in results:
+        dtb, stb, _ = results[nep.NEP_MLP_BF16]
+        avgb = {k: v[0] / v[1] for k, v in stb.items()}
+        mlpb = fl["mlp"] * n / (avgb["mlp"] * 1e-3) / 1e12
+        out["bf16"] = {"value": n * args.steps / dtb, "ms_per_step": dtb / args.steps * 1e3,
+                       "mlp_roofline": {"bound": "mfma", "achieved": mlpb,
+                                        "peak": PEAK_BF16_MFMA, "unit": "TFLOP/s",
+                                        "frac": mlpb / PEAK_BF16_MFMA,
+                                        "avg_launch_ms": avgb["mlp"]}}
+    out["paper_context"] = {"A100_NEP3_MgAlCu": 1.5e7, "V100_NEP_carbon_4.2A": 3.6e6,
+                            "unit": "atom-step/s", "note": "other hardware and models"}
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(h, params, args.cpu_seconds)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

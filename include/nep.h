@@ -1,0 +1,172 @@
+/*
+ * nep.h -- C ABI of the MI355X (gfx950) NEP3 library.
+ *
+ * The library evaluates the neuroevolution potential NEP3 of Fan et al.
+ * (GPUMD, Sec. II): per-atom site energies U_i (eq. Ui), forces
+ * F_i = sum_j (dU_i/dr_ij - dU_j/dr_ji) (eqs. F_ij, F_i) and per-atom virials
+ * W_i = sum_j r_ij (x) dU_j/dr_ji (eq. virial), and drives velocity-Verlet NVE
+ * dynamics with them.  Every step of the computation runs in hand-written HIP
+ * kernels for gfx950; the host code only validates, allocates and launches.
+ *
+ * Conventions
+ *   units        Angstrom, eV, amu, fs; velocities in Angstrom/fs
+ *   positions    SoA float64 [3][N]: x[0..N), then y, then z
+ *   box          float64[9]: the cell vectors a, b, c as rows
+ *                (a_x a_y a_z b_x b_y b_z c_x c_y c_z), det > 0
+ *   pbc          int32[3], nonzero = periodic along a, b, c
+ *   types        int32[N] in [0, n_types)
+ *   forces       float64 [3][N]
+ *   virials      float64 [9][N]: row 3a+b holds W_ab of every atom
+ *   totals       float64[10]: E = sum U_i, then W_xx, W_xy, .. W_zz summed
+ *   Neighbours of i are all images (j, n) with |d|^2 < r_c^2 in float64,
+ *   d = (r_j - r_i) + ((n_a a + n_b b) + n_c c), except (i, 0).  Positions need
+ *   not be wrapped into the cell.
+ *
+ * Ownership and threading: every input and output buffer belongs to the
+ * caller.  A handle owns its device workspaces (neighbour lists, descriptor
+ * sums, partial forces), grown on demand by the host-synchronous calls.
+ * A handle is bound to one device and is not re-entrant: calls on one handle
+ * must not overlap.  Different handles are independent.
+ *
+ * Errors: every int-returning call returns NEP_OK (0) or a NEP_E_* code and
+ * never aborts; nep_last_error() gives a message.  On error the outputs are
+ * unspecified.
+ */
+#ifndef NEP_H
+#define NEP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define NEP_OK 0
+#define NEP_E_INVALID_ARG 1      /* bad hyper-parameter, size, type or pointer */
+#define NEP_E_BOX 2              /* det(box) <= 0, non-finite, or cell too thin */
+#define NEP_E_NONFINITE 3        /* NaN or Inf in positions or velocities */
+#define NEP_E_NEIGHBOR_OVERFLOW 4/* a neighbour row exceeded its capacity */
+#define NEP_E_OOM 5              /* device allocation failed */
+#define NEP_E_HIP 6              /* a HIP runtime call failed */
+#define NEP_E_UNSUPPORTED 7      /* no GPU, or a hyper-parameter beyond limits */
+#define NEP_E_BUDGET 8           /* serving: request larger than the budget */
+#define NEP_PENDING 9            /* serving: result not ready yet */
+
+#define NEP_MLP_FP32 0           /* network GEMMs in FP32 on MFMA */
+#define NEP_MLP_BF16 1           /* BF16 operands, FP32 accumulation, on MFMA */
+
+/* Hyper-parameters (names follow the paper's notation, Sec. II and III.A). */
+typedef struct nep_hparams {
+  int32_t n_types;        /* N_typ >= 1 */
+  double rc_radial;       /* r_c^R (Angstrom) */
+  double rc_angular;      /* r_c^A, 0 < r_c^A <= r_c^R */
+  int32_t n_max_radial;   /* n_max^R: radial functions n = 0..n_max^R (<= 15) */
+  int32_t n_max_angular;  /* n_max^A (<= 15) */
+  int32_t basis_radial;   /* N_bas^R: basis functions k = 0..N_bas^R (<= 15) */
+  int32_t basis_angular;  /* N_bas^A (<= 15) */
+  int32_t l_max_3b;       /* 1..6; 1..4 are printed in the paper, 5 and 6 use
+                             real solid harmonics with the addition theorem */
+  int32_t l_max_4b;       /* 0, or 2 (3 is the same): adds q_{n222} */
+  int32_t l_max_5b;       /* 0, or 1: adds q_{n1111} */
+  int32_t n_neurons;      /* N_neu, 1..128 */
+  int32_t nn_per_type;    /* 0: one network (eq. Ui); 1: one network per species */
+  int32_t mlp_precision;  /* NEP_MLP_FP32 or NEP_MLP_BF16 */
+  int32_t max_nb_radial;  /* neighbour-row capacity M_R (0 = from density) */
+  int32_t max_nb_angular; /* neighbour-row capacity M_A (0 = from density) */
+  double skin;            /* Verlet skin for nep_md_run (Angstrom, >= 0) */
+} nep_hparams;
+
+typedef struct nep_handle nep_handle;
+
+/* Descriptor length N_des (Sec. II.D), or -1 for invalid hyper-parameters. */
+int nep_num_descriptors(const nep_hparams *hp);
+
+/* Length of the parameter vector (Sec. II.E, N_par of NEP3; with
+ * nn_per_type = 1 the network block is repeated per species), or 0 if hp is
+ * invalid.  Layout, float64: for each network t (1 or n_types of them)
+ * w0[N_neu][N_des] row-major, b0[N_neu], w1[N_neu]; then b1; then
+ * c^R[t_i][t_j][n][k] (n <= n_max^R, k <= N_bas^R); then c^A[t_i][t_j][n][k]. */
+size_t nep_num_params(const nep_hparams *hp);
+
+/* Create a handle on the current HIP device from hyper-parameters and a
+ * parameter vector of n_params = nep_num_params(hp) doubles (host memory,
+ * copied).  Returns NEP_E_UNSUPPORTED when no GPU is present. */
+int nep_create(const nep_hparams *hp, const double *params, size_t n_params,
+               nep_handle **out);
+
+/* Replace the parameter vector (same hyper-parameters). */
+int nep_set_params(nep_handle *h, const double *params, size_t n_params);
+
+void nep_destroy(nep_handle *h);
+
+/* Message of the last error on this handle (or of the last nep_create on
+ * this thread when h is NULL).  Valid until the next call on the handle. */
+const char *nep_last_error(const nep_handle *h);
+
+/* Energy, forces and virial of one structure (eqs. Ui, F_ij, F_i, virial).
+ * Host pointers; energy (per-atom, [N]), force ([3][N]), virial ([9][N]) and
+ * totals ([10]) may each be NULL.  Synchronous. */
+int nep_compute(nep_handle *h, int64_t n_atoms, const double *pos,
+                const int32_t *types, const double box[9], const int32_t pbc[3],
+                double *energy, double *force, double *virial, double totals[10]);
+
+/* Same as nep_compute with device pointers (pos, types, energy, force, virial,
+ * totals all in device memory; outputs may be NULL) on the HIP stream
+ * `stream` (hipStream_t, NULL = default).  box and pbc are host arrays.
+ * Returns after the work is enqueued and the neighbour-capacity check has
+ * been read back. */
+int nep_compute_dev(nep_handle *h, int64_t n_atoms, const double *pos,
+                    const int32_t *types, const double box[9], const int32_t pbc[3],
+                    double *energy, double *force, double *virial, double *totals,
+                    void *stream);
+
+/* Neighbour rows at the radial (which = 0) or angular (which = 1) cutoff,
+ * as defined above, for diagnostics and parity.  Host pointers: count[N];
+ * nbr[N][cap] neighbour indices and shift[N][cap][3] integer images n, each
+ * row sorted by (j, n) lexicographically.  Rows longer than cap fail with
+ * NEP_E_NEIGHBOR_OVERFLOW. */
+int nep_neighbors(nep_handle *h, int64_t n_atoms, const double *pos,
+                  const double box[9], const int32_t pbc[3], int32_t which,
+                  int32_t cap, int32_t *count, int32_t *nbr, int32_t *shift);
+
+/* Descriptor vectors q[N][N_des] (host, float64) in the order: radial q_n,
+ * then q_{nl} (index n_R + (l-1) n_A + n), then q_{n222}, then q_{n1111}
+ * (eqs. qin, S_nk and the explicit angular forms of Sec. II.D). */
+int nep_descriptors(nep_handle *h, int64_t n_atoms, const double *pos,
+                    const int32_t *types, const double box[9], const int32_t pbc[3],
+                    double *q);
+
+/* Velocity-Verlet NVE for n_steps of dt_fs (the 'nve' ensemble of the paper,
+ * Sec. IV): v += dt/2 F/m; r += dt v; F(r); v += dt/2 F/m.  pos and vel
+ * (host, [3][N]) are updated in place.  mass_per_type: amu, [n_types].
+ * Every thermo_every steps (0 = never) a row of 13 doubles
+ * [step, E_pot, E_kin, T, W_xx .. W_zz] is written to thermo (host,
+ * [n_steps / thermo_every][13]); T uses 3N - 3 degrees of freedom.
+ * Neighbour rows are kept at r_c + skin and rebuilt when an atom has moved
+ * more than skin / 2 since the last build. */
+int nep_md_run(nep_handle *h, int64_t n_atoms, double *pos, double *vel,
+               const int32_t *types, const double *mass_per_type,
+               const double box[9], const int32_t pbc[3], double dt_fs,
+               int64_t n_steps, int64_t thermo_every, double *thermo);
+
+/* Same as nep_md_run with pos, vel, types and thermo in device memory on
+ * `stream`; mass_per_type, box and pbc are host arrays.  Synchronous. */
+int nep_md_run_dev(nep_handle *h, int64_t n_atoms, double *pos, double *vel,
+                   const int32_t *types, const double *mass_per_type,
+                   const double box[9], const int32_t pbc[3], double dt_fs,
+                   int64_t n_steps, int64_t thermo_every, double *thermo,
+                   void *stream);
+
+/* Per-stage timing of the last nep_compute / nep_md_run call, filled when
+ * timing was enabled with nep_set_timing(h, 1).  names[i] are static
+ * strings; ms[i] is the summed time of that stage, calls[i] its launch
+ * count.  Returns the number of stages written (<= max). */
+int nep_set_timing(nep_handle *h, int32_t enable);
+int nep_get_timing(const nep_handle *h, int32_t max, const char **names,
+                   double *ms, int64_t *calls);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* NEP_H */

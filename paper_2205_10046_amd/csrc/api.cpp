@@ -1,0 +1,1074 @@
+// api.cpp -- host implementation of the C ABI declared in include/nep.h.
+//
+// Validates arguments, converts the float64 parameter vector into the float32
+// / bf16 device tables, owns the device workspaces of a handle, and launches
+// the passes:
+//   order atoms (cell sort) -> neighbour rows + reverse index -> descriptors
+//   -> network (MFMA) -> partial forces -> Newton-3 gather -> outputs
+// with velocity-Verlet steps around them for the MD entry points.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <array>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "nep.h"
+#include "nep_kernels.h"
+
+using namespace nep;
+
+namespace {
+
+thread_local std::string g_thread_error;
+
+constexpr double kPi = 3.14159265358979323846;
+// 1 amu (Angstrom/fs)^2 in eV (CODATA 2018 amu and elementary charge)
+constexpr double kAmuA2fs2 = 1.66053906660e-27 * 1e10 / 1.602176634e-19;
+constexpr double kBoltzmann = 8.617333262e-5;  // eV/K
+
+struct Failure {
+  int code;
+  std::string msg;
+};
+
+#define HIPCHK(call)                                                                   \
+  do {                                                                                 \
+    hipError_t e_ = (call);                                                            \
+    if (e_ != hipSuccess)                                                              \
+      throw Failure{NEP_E_HIP, std::string(#call) + ": " + hipGetErrorString(e_)};     \
+  } while (0)
+
+int n_descriptors(const nep_hparams& h) {
+  return (h.n_max_radial + 1) +
+         (h.n_max_angular + 1) * (h.l_max_3b + (h.l_max_4b >= 2 ? 1 : 0) + (h.l_max_5b >= 1 ? 1 : 0));
+}
+
+size_t n_params(const nep_hparams& h) {
+  const size_t nd = n_descriptors(h);
+  const size_t nets = h.nn_per_type ? h.n_types : 1;
+  const size_t t2 = (size_t)h.n_types * h.n_types;
+  return nets * (nd + 2) * h.n_neurons + 1 + t2 * (h.n_max_radial + 1) * (h.basis_radial + 1) +
+         t2 * (h.n_max_angular + 1) * (h.basis_angular + 1);
+}
+
+bool check_hparams(const nep_hparams* hp, std::string& why) {
+  if (!hp) { why = "hparams is NULL"; return false; }
+  const nep_hparams& h = *hp;
+  if (h.n_types < 1 || h.n_types > kMaxTypes) { why = "n_types must be in [1, 8]"; return false; }
+  if (!(h.rc_radial > 0) || !(h.rc_angular > 0) || !(h.rc_angular <= h.rc_radial) ||
+      !std::isfinite(h.rc_radial)) {
+    why = "need 0 < rc_angular <= rc_radial (finite)";
+    return false;
+  }
+  if (h.n_max_radial < 0 || h.n_max_radial >= kMaxBasis || h.n_max_angular < 0 ||
+      h.n_max_angular >= kMaxBasis || h.basis_radial < 0 || h.basis_radial >= kMaxBasis ||
+      h.basis_angular < 0 || h.basis_angular >= kMaxBasis) {
+    why = "n_max and basis sizes must be in [0, 15]";
+    return false;
+  }
+  if (h.l_max_3b < 1 || h.l_max_3b > kMaxL) { why = "l_max_3b must be in [1, 6]"; return false; }
+  if (!(h.l_max_4b == 0 || h.l_max_4b == 2 || h.l_max_4b == 3)) {
+    why = "l_max_4b must be 0, 2 or 3";
+    return false;
+  }
+  if (h.l_max_4b >= 2 && h.l_max_3b < 2) { why = "4-body terms need l_max_3b >= 2"; return false; }
+  if (!(h.l_max_5b == 0 || h.l_max_5b == 1)) { why = "l_max_5b must be 0 or 1"; return false; }
+  if (h.n_neurons < 1 || h.n_neurons > 128) { why = "n_neurons must be in [1, 128]"; return false; }
+  if (!(h.nn_per_type == 0 || h.nn_per_type == 1)) { why = "nn_per_type must be 0 or 1"; return false; }
+  if (!(h.mlp_precision == NEP_MLP_FP32 || h.mlp_precision == NEP_MLP_BF16)) {
+    why = "mlp_precision must be NEP_MLP_FP32 or NEP_MLP_BF16";
+    return false;
+  }
+  if (h.max_nb_radial < 0 || h.max_nb_angular < 0) { why = "negative neighbour capacity"; return false; }
+  if (!(h.skin >= 0) || !std::isfinite(h.skin)) { why = "skin must be >= 0"; return false; }
+  return true;
+}
+
+// ---- angular constants (Sec. II.D) ----
+// The library's polynomials for l <= 4 are the paper's b_k; each equals
+// alpha_{lm} P_l^{(m)}(z) {Re, Im}(x+iy)^m on the unit sphere.  The addition
+// theorem gives C = (2l+1)/(4 pi) (2 - delta_m0) (l-m)!/(l+m)! for the
+// unscaled harmonics, hence C^3b = that / alpha^2; l = 5, 6 use alpha = 1.
+// C^4b and C^5b are the printed S-form coefficients.
+void angular_constants(int L, double* C3, double* C4, double* C5) {
+  static const double alpha[5][5] = {
+      {0, 0, 0, 0, 0},
+      {1.0, 1.0, 0, 0, 0},
+      {2.0, 1.0 / 3.0, 1.0 / 3.0, 0, 0},
+      {2.0, 2.0 / 3.0, 1.0 / 15.0, 1.0 / 15.0, 0},
+      {8.0, 2.0 / 5.0, 2.0 / 15.0, 1.0 / 105.0, 1.0 / 105.0}};
+  auto fact = [](int n) {
+    double f = 1;
+    for (int i = 2; i <= n; ++i) f *= i;
+    return f;
+  };
+  for (int l = 1; l <= L; ++l) {
+    int k = l * l - 1;
+    for (int m = 0; m <= l; ++m) {
+      double c = (2 * l + 1) / (4 * kPi) * (m ? 2.0 : 1.0) * fact(l - m) / fact(l + m);
+      if (l <= 4) c /= alpha[l][m] * alpha[l][m];
+      C3[k++] = c;
+      if (m) C3[k++] = c;
+    }
+  }
+  const double y20 = 0.25 * std::sqrt(5 / kPi), y21 = 0.5 * std::sqrt(15 / (2 * kPi)),
+               y22 = 0.25 * std::sqrt(15 / (2 * kPi));
+  C4[0] = -std::sqrt(2.0 / 35) * y20 * y20 * y20;
+  C4[1] = -6 * std::sqrt(1.0 / 70) * y20 * y21 * y21;
+  C4[2] = 6 * std::sqrt(2.0 / 35) * y20 * y22 * y22;
+  C4[3] = 6 * std::sqrt(3.0 / 35) * y21 * y21 * y22;
+  C4[4] = -12 * std::sqrt(3.0 / 35) * y21 * y21 * y22;
+  C5[0] = 21 / (80 * kPi * kPi);
+  C5[1] = 21 / (40 * kPi * kPi);
+  C5[2] = 21 / (80 * kPi * kPi);
+}
+
+uint16_t to_bf16(float f) {
+  uint32_t u;
+  std::memcpy(&u, &f, 4);
+  if ((u & 0x7f800000u) == 0x7f800000u) return (uint16_t)(u >> 16);  // inf / nan
+  u += 0x7fffu + ((u >> 16) & 1u);                                    // round to nearest even
+  return (uint16_t)(u >> 16);
+}
+
+template <class T>
+void dev_alloc(T*& p, size_t n) {
+  if (p) HIPCHK(hipFree(p));
+  p = nullptr;
+  if (n == 0) return;
+  hipError_t e = hipMalloc((void**)&p, n * sizeof(T));
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    p = nullptr;
+    throw Failure{NEP_E_OOM, "device allocation of " + std::to_string(n * sizeof(T)) + " bytes failed"};
+  }
+}
+
+template <class T>
+void dev_free(T*& p) {
+  if (p) (void)hipFree(p);
+  p = nullptr;
+}
+
+struct Geometry {
+  StructInfo st;
+  int32_t n_cells;
+  double volume;
+};
+
+// Cell inverse, face widths and the neighbour-search mode of one structure.
+Geometry make_geometry(const double* box, const int32_t* pbc, int64_t n_atoms, double r_list) {
+  Geometry g{};
+  StructInfo& st = g.st;
+  for (int k = 0; k < 9; ++k) {
+    if (!std::isfinite(box[k])) throw Failure{NEP_E_BOX, "box has a non-finite entry"};
+    st.H[k] = box[k];
+  }
+  const double a = box[0], b = box[1], c = box[2], d = box[3], e = box[4], f = box[5], gg = box[6],
+               hh = box[7], kk = box[8];
+  const double det = a * (e * kk - f * hh) - b * (d * kk - f * gg) + c * (d * hh - e * gg);
+  if (!(det > 0)) throw Failure{NEP_E_BOX, "det(box) must be positive"};
+  st.Hi[0] = (e * kk - f * hh) / det;
+  st.Hi[1] = (c * hh - b * kk) / det;
+  st.Hi[2] = (b * f - c * e) / det;
+  st.Hi[3] = (f * gg - d * kk) / det;
+  st.Hi[4] = (a * kk - c * gg) / det;
+  st.Hi[5] = (c * d - a * f) / det;
+  st.Hi[6] = (d * hh - e * gg) / det;
+  st.Hi[7] = (b * gg - a * hh) / det;
+  st.Hi[8] = (a * e - b * d) / det;
+  g.volume = det;
+  // face width along cell vector k = volume / |(other two) cross product|
+  double w[3];
+  for (int k = 0; k < 3; ++k) {
+    const double* u = box + 3 * ((k + 1) % 3);
+    const double* v = box + 3 * ((k + 2) % 3);
+    const double cx = u[1] * v[2] - u[2] * v[1], cy = u[2] * v[0] - u[0] * v[2],
+                 cz = u[0] * v[1] - u[1] * v[0];
+    w[k] = det / std::sqrt(cx * cx + cy * cy + cz * cz);
+  }
+  bool min_image_ok = true;
+  for (int k = 0; k < 3; ++k) {
+    st.pbc[k] = pbc ? (pbc[k] != 0) : 1;
+    if (st.pbc[k] && !(w[k] > 2.0 * r_list * (1.0 + 1e-9))) min_image_ok = false;
+  }
+  st.start = 0;
+  st.count = n_atoms;
+  st.cell_off = 0;
+  if (min_image_ok) {
+    int32_t nc[3];
+    int64_t total = 1;
+    for (int k = 0; k < 3; ++k) {
+      nc[k] = std::max(1, (int)std::floor(w[k] / (r_list * (1.0 + 1e-9))));
+      nc[k] = std::min(nc[k], 1024);
+      total *= nc[k];
+    }
+    if (n_atoms > 256 && total > 1 && total < (1 << 28)) {
+      st.mode = kModeCells;
+      for (int k = 0; k < 3; ++k) st.ncell[k] = nc[k];
+      g.n_cells = (int32_t)total;
+    } else {
+      st.mode = kModeAllPairs;
+      st.ncell[0] = st.ncell[1] = st.ncell[2] = 1;
+      g.n_cells = 1;
+    }
+  } else {
+    st.mode = kModeImages;
+    for (int k = 0; k < 3; ++k) {
+      st.reach[k] = st.pbc[k] ? (int)std::floor(r_list / w[k] + 0.5) + 1 : 0;
+      if (st.reach[k] > 7)
+        throw Failure{NEP_E_BOX, "cell too thin: a face width is below r_c / 6.5; replicate it"};
+    }
+    st.ncell[0] = st.ncell[1] = st.ncell[2] = 1;
+    g.n_cells = 1;
+  }
+  return g;
+}
+
+struct StageTimes {
+  std::vector<const char*> names;
+  std::vector<double> ms;
+  std::vector<int64_t> calls;
+  void add(const char* n, double t) {
+    for (size_t k = 0; k < names.size(); ++k)
+      if (names[k] == n || std::strcmp(names[k], n) == 0) {
+        ms[k] += t;
+        calls[k] += 1;
+        return;
+      }
+    names.push_back(n);
+    ms.push_back(t);
+    calls.push_back(1);
+  }
+};
+
+}  // namespace
+
+struct nep_handle {
+  nep_hparams hp{};
+  int device = 0;
+  std::string err;
+  int nd = 0, nets = 1;
+  int NG_desc = 0, ng_desc = 0, NG_force = 0, ng_force = 0;
+  DevModel M{};
+  // model tables
+  float *cR = nullptr, *cA = nullptr, *w0 = nullptr, *w0t = nullptr, *b0 = nullptr, *w1 = nullptr;
+  uint16_t *w0b = nullptr, *w0tb = nullptr;
+  // workspace
+  int64_t capN = 0, cap_part = 0, rows_cap = 0;
+  int32_t MR = 0, MA = 0, cap_cells = 0;
+  double *pos_ext = nullptr, *pos = nullptr, *pos2 = nullptr, *vel = nullptr, *vel2 = nullptr;
+  double *vel_ext = nullptr, *out_e = nullptr, *out_f = nullptr, *out_w = nullptr;
+  double *partial = nullptr, *totals = nullptr, *thermo = nullptr, *mass = nullptr, *inv_mass = nullptr;
+  int64_t thermo_cap = 0;
+  int32_t *types_ext = nullptr, *types = nullptr, *types2 = nullptr, *sid_ext = nullptr, *sid = nullptr;
+  int32_t *key = nullptr, *perm = nullptr, *ext_id = nullptr, *ext_id2 = nullptr, *inv = nullptr;
+  int32_t *cell_count = nullptr, *cell_fill = nullptr, *cell_start = nullptr;
+  int32_t *rows = nullptr, *tcount = nullptr, *toff = nullptr, *tcursor = nullptr, *flags = nullptr;
+  StructInfo* structs = nullptr;
+  Lists L{};
+  float *q = nullptr, *fp = nullptr, *U = nullptr, *sums = nullptr, *pr = nullptr, *pa = nullptr;
+  float *F = nullptr, *W = nullptr, *F_save = nullptr;
+  double *pos_save = nullptr, *vel_save = nullptr;
+  int32_t *types_save = nullptr, *ext_save = nullptr;
+  // pinned host staging for small stream-ordered copies:
+  // [0, 256) structure table, [256, 384) masses, [384, 416) flags
+  unsigned char* pinned = nullptr;
+  // timing
+  bool timing = false;
+  StageTimes times;
+  std::vector<std::pair<const char*, std::pair<hipEvent_t, hipEvent_t>>> pending;
+
+  ~nep_handle() { release(); }
+
+  void release() {
+    if (pinned) (void)hipHostFree(pinned);
+    pinned = nullptr;
+    dev_free(cR); dev_free(cA); dev_free(w0); dev_free(w0t); dev_free(b0); dev_free(w1);
+    dev_free(w0b); dev_free(w0tb);
+    free_workspace();
+    for (auto& p : pending) {
+      (void)hipEventDestroy(p.second.first);
+      (void)hipEventDestroy(p.second.second);
+    }
+    pending.clear();
+  }
+
+  void free_workspace() {
+    dev_free(pos_ext); dev_free(pos); dev_free(pos2); dev_free(vel); dev_free(vel2);
+    dev_free(vel_ext); dev_free(out_e); dev_free(out_f); dev_free(out_w);
+    dev_free(partial); dev_free(totals); dev_free(thermo); dev_free(mass); dev_free(inv_mass);
+    dev_free(types_ext); dev_free(types); dev_free(types2); dev_free(sid_ext); dev_free(sid);
+    dev_free(key); dev_free(perm); dev_free(ext_id); dev_free(ext_id2); dev_free(inv);
+    dev_free(cell_count); dev_free(cell_fill); dev_free(cell_start);
+    dev_free(rows); dev_free(tcount); dev_free(toff); dev_free(tcursor); dev_free(flags);
+    dev_free(structs);
+    free_lists();
+    dev_free(q); dev_free(fp); dev_free(U); dev_free(sums); dev_free(F); dev_free(W);
+    dev_free(F_save); dev_free(pos_save); dev_free(vel_save); dev_free(types_save);
+    dev_free(ext_save);
+    capN = 0; cap_cells = 0; thermo_cap = 0; MR = MA = 0;
+  }
+
+  void free_lists() {
+    dev_free(L.nnR); dev_free(L.nlR); dev_free(L.cdR); dev_free(L.revR);
+    dev_free(L.nnA); dev_free(L.nlA); dev_free(L.cdA); dev_free(L.revA);
+    dev_free(pr); dev_free(pa);
+  }
+
+  // ---- timing helpers ----
+  void stage_begin(hipStream_t s, hipEvent_t& a) {
+    a = nullptr;
+    if (!timing) return;
+    if (hipEventCreate(&a) != hipSuccess || hipEventRecord(a, s) != hipSuccess) a = nullptr;
+  }
+  void stage_end(const char* name, hipStream_t s, hipEvent_t a) noexcept {
+    if (!timing || !a) return;
+    hipEvent_t b = nullptr;
+    if (hipEventCreate(&b) != hipSuccess || hipEventRecord(b, s) != hipSuccess) {
+      (void)hipEventDestroy(a);
+      return;
+    }
+    pending.push_back({name, {a, b}});
+  }
+  void drop_timing() noexcept {
+    for (auto& p : pending) {
+      (void)hipEventDestroy(p.second.first);
+      (void)hipEventDestroy(p.second.second);
+    }
+    pending.clear();
+  }
+  void resolve_timing() {
+    for (auto& p : pending) {
+      float ms = 0;
+      HIPCHK(hipEventSynchronize(p.second.second));
+      HIPCHK(hipEventElapsedTime(&ms, p.second.first, p.second.second));
+      times.add(p.first, ms);
+      (void)hipEventDestroy(p.second.first);
+      (void)hipEventDestroy(p.second.second);
+    }
+    pending.clear();
+  }
+};
+
+namespace {
+
+struct Stage {
+  nep_handle* h;
+  const char* name;
+  hipStream_t s;
+  hipEvent_t a = nullptr;
+  Stage(nep_handle* h_, const char* n, hipStream_t s_) : h(h_), name(n), s(s_) { h->stage_begin(s, a); }
+  ~Stage() { h->stage_end(name, s, a); }
+};
+
+void upload_model(nep_handle* h, const double* p) {
+  const nep_hparams& hp = h->hp;
+  const int T = hp.n_types, nd = h->nd, NN = hp.n_neurons, nets = h->nets;
+  const int nR = hp.n_max_radial + 1, KR = hp.basis_radial + 1;
+  const int nA = hp.n_max_angular + 1, KA = hp.basis_angular + 1;
+  const int NNp = (NN + 31) / 32 * 32;
+  const int NDp32 = (nd + 31) / 32 * 32;
+  const int nA_pad = std::max(h->NG_desc * h->ng_desc, h->NG_force * h->ng_force);
+  for (size_t k = 0; k < n_params(hp); ++k)
+    if (!std::isfinite(p[k])) throw Failure{NEP_E_INVALID_ARG, "parameter vector has a non-finite entry"};
+  std::vector<float> w0((size_t)nets * NNp * nd, 0.f), w0t((size_t)nets * nd * NNp, 0.f);
+  std::vector<float> b0((size_t)nets * NNp, 0.f), w1((size_t)nets * NNp, 0.f);
+  std::vector<uint16_t> w0b((size_t)nets * NNp * NDp32, 0), w0tb((size_t)nets * NDp32 * NNp, 0);
+  size_t off = 0;
+  for (int t = 0; t < nets; ++t) {
+    for (int mu = 0; mu < NN; ++mu)
+      for (int v = 0; v < nd; ++v) {
+        const float x = (float)p[off + (size_t)mu * nd + v];
+        w0[((size_t)t * NNp + mu) * nd + v] = x;
+        w0t[((size_t)t * nd + v) * NNp + mu] = x;
+        w0b[((size_t)t * NNp + mu) * NDp32 + v] = to_bf16(x);
+        w0tb[((size_t)t * NDp32 + v) * NNp + mu] = to_bf16(x);
+      }
+    off += (size_t)NN * nd;
+    for (int mu = 0; mu < NN; ++mu) b0[(size_t)t * NNp + mu] = (float)p[off + mu];
+    off += NN;
+    for (int mu = 0; mu < NN; ++mu) w1[(size_t)t * NNp + mu] = (float)p[off + mu];
+    off += NN;
+  }
+  const float b1 = (float)p[off++];
+  std::vector<float> cR((size_t)T * T * nR * KR);
+  for (size_t k = 0; k < cR.size(); ++k) cR[k] = (float)p[off + k];
+  off += cR.size();
+  std::vector<float> cA((size_t)T * T * nA_pad * KA, 0.f);
+  for (int a = 0; a < T * T; ++a)
+    for (int n = 0; n < nA; ++n)
+      for (int k = 0; k < KA; ++k)
+        cA[((size_t)a * nA_pad + n) * KA + k] = (float)p[off + ((size_t)a * nA + n) * KA + k];
+  off += (size_t)T * T * nA * KA;
+
+  auto put = [](auto*& dst, const auto& v) {
+    using E = std::remove_reference_t<decltype(*dst)>;
+    dev_alloc(dst, v.size());
+    HIPCHK(hipMemcpy(dst, v.data(), v.size() * sizeof(E), hipMemcpyHostToDevice));
+  };
+  put(h->w0, w0); put(h->w0t, w0t); put(h->b0, b0); put(h->w1, w1);
+  put(h->w0b, w0b); put(h->w0tb, w0tb); put(h->cR, cR); put(h->cA, cA);
+
+  DevModel& M = h->M;
+  M.T = T; M.nR = nR; M.KR = KR; M.nA = nA; M.KA = KA; M.L = hp.l_max_3b;
+  M.NB = (hp.l_max_3b + 1) * (hp.l_max_3b + 1) - 1;
+  M.ND = nd; M.NDp = (nd + 7) / 8 * 8; M.NN = NN; M.nets = nets;
+  M.has4b = hp.l_max_4b >= 2; M.has5b = hp.l_max_5b >= 1; M.nA_pad = nA_pad;
+  M.rcR = (float)hp.rc_radial; M.rcA = (float)hp.rc_angular; M.b1 = b1;
+  M.cR = h->cR; M.cA = h->cA; M.NNp = NNp; M.NDp32 = NDp32;
+  M.w0 = h->w0; M.w0t = h->w0t; M.b0 = h->b0; M.w1 = h->w1; M.w0b = h->w0b; M.w0tb = h->w0tb;
+  double C3[kMaxNB] = {0}, C4[5], C5[3];
+  angular_constants(hp.l_max_3b, C3, C4, C5);
+  for (int k = 0; k < kMaxNB; ++k) M.C3[k] = (float)C3[k];
+  for (int k = 0; k < 5; ++k) M.C4[k] = (float)C4[k];
+  for (int k = 0; k < 3; ++k) M.C5[k] = (float)C5[k];
+}
+
+// Length of the species-grouped row order: every species segment is padded
+// to whole 16-row tiles, so it never exceeds round16(N) + 16 T.
+int64_t rows_length(int64_t N, int T) { return (N + 15) / 16 * 16 + 16 * (int64_t)T; }
+
+int64_t num_partials(int64_t N) { return std::min<int64_t>(512, std::max<int64_t>(1, (N + 1023) / 1024)); }
+
+int32_t estimate_capacity(double rc, double density) {
+  const double expect = 4.0 / 3.0 * kPi * rc * rc * rc * density;
+  int32_t m = (int32_t)std::ceil(1.3 * expect + 24);
+  return (m + 3) / 4 * 4;
+}
+
+void ensure_lists(nep_handle* h, int64_t N, int32_t MR, int32_t MA) {
+  if (N <= h->capN && MR <= h->MR && MA <= h->MA && h->L.nlR) return;
+  h->free_lists();
+  const int64_t cap = std::max(N, h->capN);
+  dev_alloc(h->L.nnR, cap); dev_alloc(h->L.nnA, cap);
+  dev_alloc(h->L.nlR, (size_t)MR * cap); dev_alloc(h->L.cdR, (size_t)MR * cap);
+  dev_alloc(h->L.revR, (size_t)MR * cap);
+  dev_alloc(h->L.nlA, (size_t)MA * cap); dev_alloc(h->L.cdA, (size_t)MA * cap);
+  dev_alloc(h->L.revA, (size_t)MA * cap);
+  dev_alloc(h->pr, (size_t)3 * MR * cap); dev_alloc(h->pa, (size_t)3 * MA * cap);
+  h->MR = MR;
+  h->MA = MA;
+  h->L.MR = MR;
+  h->L.MA = MA;
+}
+
+// Per-atom buffers sized for N atoms (contents are not preserved).
+void ensure_atoms(nep_handle* h, int64_t N, int32_t n_cells, bool md) {
+  const DevModel& M = h->M;
+  if (N > h->capN) {
+    const int32_t MR = h->MR, MA = h->MA;
+    h->free_workspace();
+    const int64_t c = N;
+    dev_alloc(h->pos_ext, 3 * c); dev_alloc(h->pos, 3 * c);
+    dev_alloc(h->types_ext, c); dev_alloc(h->types, c); dev_alloc(h->sid_ext, c); dev_alloc(h->sid, c);
+    dev_alloc(h->key, c); dev_alloc(h->perm, c); dev_alloc(h->inv, c);
+    dev_alloc(h->out_e, c); dev_alloc(h->out_f, 3 * c); dev_alloc(h->out_w, 9 * c);
+    dev_alloc(h->q, (size_t)c * M.NDp); dev_alloc(h->fp, (size_t)c * M.NDp);
+    dev_alloc(h->U, c); dev_alloc(h->sums, (size_t)M.nA * M.NB * c);
+    dev_alloc(h->F, 3 * c); dev_alloc(h->W, 9 * c);
+    h->rows_cap = rows_length(c, M.T);
+    dev_alloc(h->rows, h->rows_cap);
+    dev_alloc(h->tcount, kMaxTypes + 1); dev_alloc(h->toff, kMaxTypes + 1);
+    dev_alloc(h->tcursor, kMaxTypes + 1); dev_alloc(h->flags, 8);
+    h->cap_part = num_partials(c);
+    dev_alloc(h->partial, 11 * h->cap_part); dev_alloc(h->totals, 16);
+    dev_alloc(h->structs, 1);
+    h->capN = c;
+    h->MR = MR;
+    h->MA = MA;
+  }
+  if (n_cells > h->cap_cells) {
+    dev_alloc(h->cell_count, n_cells); dev_alloc(h->cell_fill, n_cells);
+    dev_alloc(h->cell_start, n_cells);
+    h->cap_cells = n_cells;
+  }
+  if (md && !h->vel) {
+    const int64_t c = h->capN;
+    dev_alloc(h->pos2, 3 * c); dev_alloc(h->vel, 3 * c); dev_alloc(h->vel2, 3 * c);
+    dev_alloc(h->vel_ext, 3 * c); dev_alloc(h->types2, c); dev_alloc(h->ext_id, c);
+    dev_alloc(h->ext_id2, c); dev_alloc(h->F_save, 3 * c); dev_alloc(h->pos_save, 3 * c);
+    dev_alloc(h->vel_save, 3 * c); dev_alloc(h->types_save, c); dev_alloc(h->ext_save, c);
+    dev_alloc(h->mass, kMaxTypes); dev_alloc(h->inv_mass, kMaxTypes);
+  }
+}
+
+struct Prepared {
+  Geometry geo;
+  int64_t N;
+};
+
+BuildArgs build_args(nep_handle* h, const Prepared& pp, const double* pos_src, const int32_t* types_src,
+                     double* pos_dst, int32_t* types_dst) {
+  BuildArgs b{};
+  b.N = pp.N;
+  b.n_cells = pp.geo.n_cells;
+  b.pos_ext = pos_src;
+  b.types_ext = types_src;
+  b.sid_ext = h->sid_ext;
+  b.structs = h->structs;
+  b.key = h->key;
+  b.cell_count = h->cell_count;
+  b.cell_fill = h->cell_fill;
+  b.cell_start = h->cell_start;
+  b.perm = h->perm;
+  b.pos = pos_dst;
+  b.types = types_dst;
+  b.sid = h->sid;
+  b.rcR2 = h->hp.rc_radial * h->hp.rc_radial;
+  b.rcA2 = h->hp.rc_angular * h->hp.rc_angular;
+  b.overflow = h->flags;
+  return b;
+}
+
+EvalArgs eval_args(nep_handle* h, const Prepared& pp) {
+  EvalArgs a{};
+  a.pos = h->pos;
+  a.N = pp.N;
+  a.types = h->types;
+  a.sid = h->sid;
+  a.structs = h->structs;
+  a.L = h->L;
+  a.M = h->M;
+  a.q = h->q;
+  a.fp = h->fp;
+  a.U = h->U;
+  a.sums = h->sums;
+  a.pr = h->pr;
+  a.pa = h->pa;
+  a.F = h->F;
+  a.W = h->W;
+  a.rows = h->rows;
+  a.rows_len = rows_length(pp.N, h->M.T);
+  a.mlp_bf16 = h->hp.mlp_precision == NEP_MLP_BF16;
+  a.batch = 0;
+  a.st0 = pp.geo.st;
+  return a;
+}
+
+// Geometry, buffers and the structure table for one structure of N atoms.
+Prepared prepare(nep_handle* h, int64_t N, const double* box, const int32_t* pbc, double r_list,
+                 bool md, hipStream_t s) {
+  if (N < 1 || N > (int64_t)1 << 30) throw Failure{NEP_E_INVALID_ARG, "n_atoms must be in [1, 2^30]"};
+  Prepared pp;
+  pp.N = N;
+  pp.geo = make_geometry(box, pbc, N, r_list);
+  ensure_atoms(h, N, pp.geo.n_cells, md);
+  const double density = (double)N / pp.geo.volume;
+  int32_t MR = h->hp.max_nb_radial ? h->hp.max_nb_radial : estimate_capacity(h->hp.rc_radial, density);
+  int32_t MA = h->hp.max_nb_angular ? h->hp.max_nb_angular : estimate_capacity(h->hp.rc_angular, density);
+  MR = std::max(MR, h->MR);
+  MA = std::max(MA, h->MA);
+  ensure_lists(h, N, MR, MA);
+  static_assert(sizeof(StructInfo) <= 256, "staging slot");
+  std::memcpy(h->pinned, &pp.geo.st, sizeof(StructInfo));
+  HIPCHK(hipMemcpyAsync(h->structs, h->pinned, sizeof(StructInfo), hipMemcpyHostToDevice, s));
+  launch_fill_i32(h->sid_ext, N, 0, s);
+  return pp;
+}
+
+// Rows for the current internal positions; grows the capacities (auto mode)
+// or fails (fixed capacities) when a row overflows.  Synchronises once.
+void build_rows_checked(nep_handle* h, const Prepared& pp, const BuildArgs& b, hipStream_t s,
+                        bool check_types) {
+  for (int attempt = 0; attempt < 3; ++attempt) {
+    launch_fill_i32(h->flags, 8, 0, s);
+    if (check_types) {
+      // flags[3]: species out of range, flags[4]: non-finite position
+      launch_check_types(h->types, pp.N, h->M.T, h->flags + 3, s);
+      launch_check_finite(h->pos, 3 * pp.N, h->flags + 4, s);
+    }
+    {
+      Stage st(h, "neighbor_rows", s);
+      launch_build_rows(b, h->L, s);
+    }
+    int32_t* fl = (int32_t*)(h->pinned + 384);
+    HIPCHK(hipMemcpyAsync(fl, h->flags, 8 * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    if (fl[3]) throw Failure{NEP_E_INVALID_ARG, "an atom type is out of range"};
+    if (fl[4]) throw Failure{NEP_E_NONFINITE, "positions contain NaN or Inf"};
+    if (fl[2]) throw Failure{NEP_E_HIP, "internal error: neighbour rows are not symmetric"};
+    if (fl[0] == 0 && fl[1] == 0) return;
+    const bool fixed = h->hp.max_nb_radial || h->hp.max_nb_angular;
+    if (fixed) {
+      char msg[160];
+      std::snprintf(msg, sizeof msg,
+                    "neighbour row overflow: need max_nb_radial >= %d and max_nb_angular >= %d",
+                    std::max(fl[0], h->MR), std::max(fl[1], h->MA));
+      throw Failure{NEP_E_NEIGHBOR_OVERFLOW, msg};
+    }
+    const int32_t MR = std::max(h->MR, (int32_t)((fl[0] * 1.2 + 8) / 4 * 4 + 4));
+    const int32_t MA = std::max(h->MA, (int32_t)((fl[1] * 1.2 + 8) / 4 * 4 + 4));
+    ensure_lists(h, pp.N, MR, MA);
+  }
+  throw Failure{NEP_E_NEIGHBOR_OVERFLOW, "neighbour rows kept overflowing"};
+}
+
+void order_and_build(nep_handle* h, const Prepared& pp, const double* pos_src, const int32_t* types_src,
+                     hipStream_t s, bool check) {
+  BuildArgs b = build_args(h, pp, pos_src, types_src, h->pos, h->types);
+  {
+    Stage st(h, "order_atoms", s);
+    launch_order_atoms(b, s);
+    launch_type_rows(h->types, pp.N, h->M.T, h->hp.nn_per_type, h->tcount, h->toff, h->tcursor,
+                     h->rows, rows_length(pp.N, h->M.T), s);
+  }
+  build_rows_checked(h, pp, b, s, check);
+}
+
+void forces(nep_handle* h, const Prepared& pp, hipStream_t s) {
+  EvalArgs a = eval_args(h, pp);
+  a.NG = h->NG_desc;
+  a.ngroups = h->ng_desc;
+  {
+    Stage st(h, "descriptor", s);
+    if (!launch_descriptor(a, s)) throw Failure{NEP_E_UNSUPPORTED, "no descriptor kernel for this shape"};
+  }
+  {
+    Stage st(h, "mlp", s);
+    launch_mlp(a, s);
+  }
+  a.NG = h->NG_force;
+  a.ngroups = h->ng_force;
+  {
+    Stage st(h, "partial_forces", s);
+    if (!launch_partial_forces(a, s)) throw Failure{NEP_E_UNSUPPORTED, "no force kernel for this shape"};
+  }
+  {
+    Stage st(h, "gather", s);
+    launch_gather_forces(a, s);
+  }
+}
+
+int fail(nep_handle* h, const Failure& f) {
+  if (h) {
+    h->err = f.msg;
+    h->drop_timing();
+  } else {
+    g_thread_error = f.msg;
+  }
+  return f.code;
+}
+
+void set_device(nep_handle* h) { HIPCHK(hipSetDevice(h->device)); }
+
+void check_host_types(const nep_handle* h, int64_t N, const int32_t* types) {
+  for (int64_t i = 0; i < N; ++i)
+    if (types[i] < 0 || types[i] >= h->hp.n_types)
+      throw Failure{NEP_E_INVALID_ARG, "type of atom " + std::to_string(i) + " out of range"};
+}
+
+void check_host_finite(int64_t n, const double* a, const char* what) {
+  for (int64_t i = 0; i < n; ++i)
+    if (!std::isfinite(a[i])) throw Failure{NEP_E_NONFINITE, std::string(what) + " contain NaN or Inf"};
+}
+
+int compute_impl(nep_handle* h, int64_t N, const double* d_pos, const int32_t* d_types, const double* box,
+                 const int32_t* pbc, double* d_energy, double* d_force, double* d_virial, double* d_totals,
+                 hipStream_t s) {
+  Prepared pp = prepare(h, N, box, pbc, h->hp.rc_radial, false, s);
+  order_and_build(h, pp, d_pos, d_types, s, true);
+  forces(h, pp, s);
+  EvalArgs a = eval_args(h, pp);
+  {
+    Stage st(h, "outputs", s);
+    launch_scatter_outputs(a, h->perm, d_energy, d_force, d_virial, s);
+    if (d_totals) launch_totals(h->U, h->W, N, h->partial, num_partials(N), d_totals, s);
+  }
+  return NEP_OK;
+}
+
+}  // namespace
+
+// ===========================================================================
+// C ABI
+// ===========================================================================
+
+extern "C" {
+
+int nep_num_descriptors(const nep_hparams* hp) {
+  std::string why;
+  if (!check_hparams(hp, why)) return -1;
+  return n_descriptors(*hp);
+}
+
+size_t nep_num_params(const nep_hparams* hp) {
+  std::string why;
+  if (!check_hparams(hp, why)) return 0;
+  return n_params(*hp);
+}
+
+const char* nep_last_error(const nep_handle* h) {
+  return h ? h->err.c_str() : g_thread_error.c_str();
+}
+
+int nep_create(const nep_hparams* hp, const double* params, size_t n, nep_handle** out) {
+  if (!out) return fail(nullptr, {NEP_E_INVALID_ARG, "out is NULL"});
+  *out = nullptr;
+  std::string why;
+  if (!check_hparams(hp, why)) return fail(nullptr, {NEP_E_INVALID_ARG, why});
+  if (!params || n != n_params(*hp))
+    return fail(nullptr, {NEP_E_INVALID_ARG, "params must hold nep_num_params(hp) = " +
+                                                 std::to_string(n_params(*hp)) + " doubles"});
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) {
+    (void)hipGetLastError();
+    return fail(nullptr, {NEP_E_UNSUPPORTED, "no HIP device available"});
+  }
+  nep_handle* h = new nep_handle();
+  try {
+    h->hp = *hp;
+    HIPCHK(hipGetDevice(&h->device));
+    HIPCHK(hipHostMalloc((void**)&h->pinned, 4096, hipHostMallocDefault));
+    h->nd = n_descriptors(*hp);
+    h->nets = hp->nn_per_type ? hp->n_types : 1;
+    const int nA = hp->n_max_angular + 1, L = hp->l_max_3b;
+    h->NG_desc = angular_group_size(nA, L);
+    h->ng_desc = (nA + h->NG_desc - 1) / h->NG_desc;
+    h->NG_force = h->NG_desc;
+    h->ng_force = h->ng_desc;
+    upload_model(h, params);
+    // LDS budget of the pair kernels: coefficient tables + per-thread slots
+    if (eval_lds_bytes(h->M, kBlock) > 64 * 1024)
+      throw Failure{NEP_E_UNSUPPORTED, "n_types x basis sizes too large for the LDS budget"};
+  } catch (const Failure& f) {
+    delete h;
+    return fail(nullptr, f);
+  }
+  *out = h;
+  return NEP_OK;
+}
+
+int nep_set_params(nep_handle* h, const double* params, size_t n) {
+  if (!h) return fail(nullptr, {NEP_E_INVALID_ARG, "handle is NULL"});
+  if (!params || n != n_params(h->hp)) return fail(h, {NEP_E_INVALID_ARG, "wrong parameter count"});
+  try {
+    set_device(h);
+    upload_model(h, params);
+  } catch (const Failure& f) {
+    return fail(h, f);
+  }
+  return NEP_OK;
+}
+
+void nep_destroy(nep_handle* h) {
+  if (!h) return;
+  (void)hipSetDevice(h->device);
+  delete h;
+}
+
+int nep_compute(nep_handle* h, int64_t N, const double* pos, const int32_t* types, const double box[9],
+                const int32_t pbc[3], double* energy, double* force, double* virial, double totals[10]) {
+  if (!h) return fail(nullptr, {NEP_E_INVALID_ARG, "handle is NULL"});
+  if (!pos || !types || !box) return fail(h, {NEP_E_INVALID_ARG, "pos, types and box are required"});
+  try {
+    set_device(h);
+    if (N < 1) throw Failure{NEP_E_INVALID_ARG, "n_atoms must be >= 1"};
+    check_host_types(h, N, types);
+    check_host_finite(3 * N, pos, "positions");
+    hipStream_t s = nullptr;
+    Prepared pp = prepare(h, N, box, pbc, h->hp.rc_radial, false, s);
+    (void)pp;
+    HIPCHK(hipMemcpyAsync(h->pos_ext, pos, 3 * N * sizeof(double), hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(h->types_ext, types, N * sizeof(int32_t), hipMemcpyHostToDevice, s));
+    compute_impl(h, N, h->pos_ext, h->types_ext, box, pbc, energy ? h->out_e : nullptr,
+                 force ? h->out_f : nullptr, virial ? h->out_w : nullptr, totals ? h->totals : nullptr, s);
+    if (energy) HIPCHK(hipMemcpyAsync(energy, h->out_e, N * sizeof(double), hipMemcpyDeviceToHost, s));
+    if (force) HIPCHK(hipMemcpyAsync(force, h->out_f, 3 * N * sizeof(double), hipMemcpyDeviceToHost, s));
+    if (virial) HIPCHK(hipMemcpyAsync(virial, h->out_w, 9 * N * sizeof(double), hipMemcpyDeviceToHost, s));
+    if (totals) HIPCHK(hipMemcpyAsync(totals, h->totals, 10 * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    h->resolve_timing();
+  } catch (const Failure& f) {
+    return fail(h, f);
+  }
+  return NEP_OK;
+}
+
+int nep_compute_dev(nep_handle* h, int64_t N, const double* pos, const int32_t* types, const double box[9],
+                    const int32_t pbc[3], double* energy, double* force, double* virial, double* totals,
+                    void* stream) {
+  if (!h) return fail(nullptr, {NEP_E_INVALID_ARG, "handle is NULL"});
+  if (!pos || !types || !box) return fail(h, {NEP_E_INVALID_ARG, "pos, types and box are required"});
+  try {
+    set_device(h);
+    hipStream_t s = (hipStream_t)stream;
+    compute_impl(h, N, pos, types, box, pbc, energy, force, virial, totals, s);
+    h->resolve_timing();
+  } catch (const Failure& f) {
+    return fail(h, f);
+  }
+  return NEP_OK;
+}
+
+int nep_neighbors(nep_handle* h, int64_t N, const double* pos, const double box[9], const int32_t pbc[3],
+                  int32_t which, int32_t cap, int32_t* count, int32_t* nbr, int32_t* shift) {
+  if (!h) return fail(nullptr, {NEP_E_INVALID_ARG, "handle is NULL"});
+  if (!pos || !box || !count || !nbr || !shift || cap < 1 || (which != 0 && which != 1))
+    return fail(h, {NEP_E_INVALID_ARG, "bad arguments"});
+  try {
+    set_device(h);
+    if (N < 1) throw Failure{NEP_E_INVALID_ARG, "n_atoms must be >= 1"};
+    check_host_finite(3 * N, pos, "positions");
+    hipStream_t s = nullptr;
+    Prepared pp = prepare(h, N, box, pbc, h->hp.rc_radial, false, s);
+    HIPCHK(hipMemcpyAsync(h->pos_ext, pos, 3 * N * sizeof(double), hipMemcpyHostToDevice, s));
+    launch_fill_i32(h->types_ext, N, 0, s);
+    order_and_build(h, pp, h->pos_ext, h->types_ext, s, true);
+    int32_t *d_count = nullptr, *d_nbr = nullptr, *d_shift = nullptr;
+    dev_alloc(d_count, N);
+    dev_alloc(d_nbr, (size_t)N * cap);
+    dev_alloc(d_shift, (size_t)N * cap * 3);
+    launch_inverse_perm(h->perm, N, h->inv, s);
+    launch_neighbors_out(h->L, which, N, h->perm, h->inv, h->pos, h->sid, h->structs, cap, d_count, d_nbr,
+                         d_shift, s);
+    HIPCHK(hipMemcpyAsync(count, d_count, N * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(nbr, d_nbr, (size_t)N * cap * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(shift, d_shift, (size_t)N * cap * 3 * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    dev_free(d_count);
+    dev_free(d_nbr);
+    dev_free(d_shift);
+    int32_t need = 0;
+    for (int64_t i = 0; i < N; ++i) need = std::max(need, count[i]);
+    if (need > cap)
+      throw Failure{NEP_E_NEIGHBOR_OVERFLOW, "a row has " + std::to_string(need) + " entries > cap"};
+    std::vector<std::array<int32_t, 4>> row;
+    for (int64_t i = 0; i < N; ++i) {
+      row.resize(count[i]);
+      for (int m = 0; m < count[i]; ++m)
+        row[m] = {nbr[i * cap + m], shift[(i * cap + m) * 3], shift[(i * cap + m) * 3 + 1],
+                  shift[(i * cap + m) * 3 + 2]};
+      std::sort(row.begin(), row.end());
+      for (int m = 0; m < count[i]; ++m) {
+        nbr[i * cap + m] = row[m][0];
+        for (int c = 0; c < 3; ++c) shift[(i * cap + m) * 3 + c] = row[m][1 + c];
+      }
+    }
+  } catch (const Failure& f) {
+    return fail(h, f);
+  }
+  return NEP_OK;
+}
+
+int nep_descriptors(nep_handle* h, int64_t N, const double* pos, const int32_t* types, const double box[9],
+                    const int32_t pbc[3], double* q) {
+  if (!h) return fail(nullptr, {NEP_E_INVALID_ARG, "handle is NULL"});
+  if (!pos || !types || !box || !q) return fail(h, {NEP_E_INVALID_ARG, "bad arguments"});
+  try {
+    set_device(h);
+    if (N < 1) throw Failure{NEP_E_INVALID_ARG, "n_atoms must be >= 1"};
+    check_host_types(h, N, types);
+    check_host_finite(3 * N, pos, "positions");
+    hipStream_t s = nullptr;
+    Prepared pp = prepare(h, N, box, pbc, h->hp.rc_radial, false, s);
+    HIPCHK(hipMemcpyAsync(h->pos_ext, pos, 3 * N * sizeof(double), hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(h->types_ext, types, N * sizeof(int32_t), hipMemcpyHostToDevice, s));
+    order_and_build(h, pp, h->pos_ext, h->types_ext, s, true);
+    EvalArgs a = eval_args(h, pp);
+    a.NG = h->NG_desc;
+    a.ngroups = h->ng_desc;
+    if (!launch_descriptor(a, s)) throw Failure{NEP_E_UNSUPPORTED, "no descriptor kernel for this shape"};
+    double* d_q = nullptr;
+    dev_alloc(d_q, (size_t)N * h->nd);
+    launch_descriptors_out(h->q, N, h->M.NDp, h->nd, h->perm, d_q, s);
+    HIPCHK(hipMemcpyAsync(q, d_q, (size_t)N * h->nd * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    dev_free(d_q);
+  } catch (const Failure& f) {
+    return fail(h, f);
+  }
+  return NEP_OK;
+}
+
+static int md_impl(nep_handle* h, int64_t N, double* d_pos, double* d_vel, const int32_t* d_types,
+                   const double* mass_per_type, const double* box, const int32_t* pbc, double dt,
+                   int64_t n_steps, int64_t thermo_every, double* thermo_out, bool thermo_on_host,
+                   hipStream_t s) {
+  if (!mass_per_type) throw Failure{NEP_E_INVALID_ARG, "mass_per_type is required"};
+  for (int t = 0; t < h->hp.n_types; ++t)
+    if (!(mass_per_type[t] > 0) || !std::isfinite(mass_per_type[t]))
+      throw Failure{NEP_E_INVALID_ARG, "masses must be positive"};
+  if (!(dt > 0) || !std::isfinite(dt)) throw Failure{NEP_E_INVALID_ARG, "dt must be positive"};
+  if (n_steps < 0 || thermo_every < 0) throw Failure{NEP_E_INVALID_ARG, "negative step counts"};
+  const int64_t n_rows = thermo_every > 0 ? n_steps / thermo_every : 0;
+  if (n_rows > 0 && !thermo_out) throw Failure{NEP_E_INVALID_ARG, "thermo buffer is required"};
+  Prepared pp = prepare(h, N, box, pbc, h->hp.rc_radial, true, s);
+  if (n_rows > h->thermo_cap) {
+    dev_alloc(h->thermo, 13 * n_rows);
+    h->thermo_cap = n_rows;
+  }
+  double m[kMaxTypes] = {0}, im[kMaxTypes] = {0};
+  for (int t = 0; t < h->hp.n_types; ++t) {
+    m[t] = mass_per_type[t];
+    im[t] = 1.0 / (mass_per_type[t] * kAmuA2fs2);
+  }
+  std::memcpy(h->pinned + 256, m, sizeof m);
+  std::memcpy(h->pinned + 320, im, sizeof im);
+  HIPCHK(hipMemcpyAsync(h->mass, h->pinned + 256, sizeof m, hipMemcpyHostToDevice, s));
+  HIPCHK(hipMemcpyAsync(h->inv_mass, h->pinned + 320, sizeof im, hipMemcpyHostToDevice, s));
+  // initial order: internal <- caller, velocities follow
+  order_and_build(h, pp, d_pos, d_types, s, true);
+  launch_permute_md(h->perm, N, d_pos, d_vel, h->pos2, h->vel, s);  // pos2 is scratch here
+  HIPCHK(hipMemcpyAsync(h->ext_id, h->perm, N * sizeof(int32_t), hipMemcpyDeviceToDevice, s));
+  forces(h, pp, s);
+
+  MDArgs md{};
+  md.N = N;
+  md.F = h->F;
+  md.inv_mass = h->inv_mass;
+  md.dt = dt;
+  const int64_t chunk = 50;
+  int64_t row = 0;
+  for (int64_t c0 = 0; c0 < n_steps;) {
+    const int64_t c1 = std::min(n_steps, c0 + chunk);
+    // state at the chunk start, restored if a row overflows inside the chunk
+    HIPCHK(hipMemcpyAsync(h->pos_save, h->pos, 3 * N * sizeof(double), hipMemcpyDeviceToDevice, s));
+    HIPCHK(hipMemcpyAsync(h->vel_save, h->vel, 3 * N * sizeof(double), hipMemcpyDeviceToDevice, s));
+    HIPCHK(hipMemcpyAsync(h->types_save, h->types, N * sizeof(int32_t), hipMemcpyDeviceToDevice, s));
+    HIPCHK(hipMemcpyAsync(h->ext_save, h->ext_id, N * sizeof(int32_t), hipMemcpyDeviceToDevice, s));
+    HIPCHK(hipMemcpyAsync(h->F_save, h->F, 3 * N * sizeof(float), hipMemcpyDeviceToDevice, s));
+    const int64_t row0 = row;
+    launch_fill_i32(h->flags, 8, 0, s);
+    for (int64_t step = c0 + 1; step <= c1; ++step) {
+      md.pos = h->pos;
+      md.vel = h->vel;
+      md.types = h->types;
+      {
+        Stage st(h, "integrate", s);
+        launch_kick_drift(md, s);
+      }
+      // re-sort into cell order and rebuild the rows at the new positions
+      BuildArgs b = build_args(h, pp, h->pos, h->types, h->pos2, h->types2);
+      {
+        Stage st(h, "order_atoms", s);
+        launch_order_atoms(b, s);
+        launch_permute_md(h->perm, N, h->pos, h->vel, h->pos2, h->vel2, s);
+        launch_type_rows(h->types2, N, h->M.T, h->hp.nn_per_type, h->tcount, h->toff, h->tcursor, h->rows,
+                         rows_length(N, h->M.T), s);
+      }
+      std::swap(h->pos, h->pos2);
+      std::swap(h->vel, h->vel2);
+      std::swap(h->types, h->types2);
+      // caller index of every atom in the new order: ext_id2[k] = ext_id[perm[k]]
+      {
+        Stage st(h, "order_atoms", s);
+        launch_gather_i32(h->perm, N, h->ext_id, h->ext_id2, s);
+      }
+      std::swap(h->ext_id, h->ext_id2);
+      {
+        Stage st(h, "neighbor_rows", s);
+        BuildArgs b2 = build_args(h, pp, nullptr, nullptr, h->pos, h->types);
+        launch_build_rows(b2, h->L, s);
+      }
+      forces(h, pp, s);
+      md.pos = h->pos;
+      md.vel = h->vel;
+      md.types = h->types;
+      {
+        Stage st(h, "integrate", s);
+        launch_kick(md, s);
+      }
+      if (thermo_every > 0 && step % thermo_every == 0) {
+        Stage st(h, "thermo", s);
+        launch_thermo(h->U, h->W, h->vel, h->types, h->mass, N, h->partial, num_partials(N),
+                      h->thermo + 13 * row, (double)step, kAmuA2fs2, kBoltzmann, s);
+        ++row;
+      }
+    }
+    launch_check_finite(h->pos, 3 * N, h->flags + 4, s);
+    int32_t* fl = (int32_t*)(h->pinned + 384);
+    HIPCHK(hipMemcpyAsync(fl, h->flags, 8 * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    if (fl[4]) throw Failure{NEP_E_NONFINITE, "positions became non-finite during the run"};
+    if (fl[2]) throw Failure{NEP_E_HIP, "internal error: neighbour rows are not symmetric"};
+    if (fl[0] || fl[1]) {
+      if (h->hp.max_nb_radial || h->hp.max_nb_angular)
+        throw Failure{NEP_E_NEIGHBOR_OVERFLOW, "neighbour row overflow during the run"};
+      const int32_t MR = std::max(h->MR, (int32_t)((fl[0] * 1.2 + 8) / 4 * 4 + 4));
+      const int32_t MA = std::max(h->MA, (int32_t)((fl[1] * 1.2 + 8) / 4 * 4 + 4));
+      ensure_lists(h, N, MR, MA);
+      HIPCHK(hipMemcpyAsync(h->pos, h->pos_save, 3 * N * sizeof(double), hipMemcpyDeviceToDevice, s));
+      HIPCHK(hipMemcpyAsync(h->vel, h->vel_save, 3 * N * sizeof(double), hipMemcpyDeviceToDevice, s));
+      HIPCHK(hipMemcpyAsync(h->types, h->types_save, N * sizeof(int32_t), hipMemcpyDeviceToDevice, s));
+      HIPCHK(hipMemcpyAsync(h->ext_id, h->ext_save, N * sizeof(int32_t), hipMemcpyDeviceToDevice, s));
+      HIPCHK(hipMemcpyAsync(h->F, h->F_save, 3 * N * sizeof(float), hipMemcpyDeviceToDevice, s));
+      row = row0;
+      continue;  // redo the chunk with larger rows
+    }
+    c0 = c1;
+  }
+  launch_unpermute_md(h->ext_id, N, h->pos, h->vel, d_pos, d_vel, s);
+  if (n_rows > 0)
+    HIPCHK(hipMemcpyAsync(thermo_out, h->thermo, 13 * n_rows * sizeof(double),
+                          thermo_on_host ? hipMemcpyDeviceToHost : hipMemcpyDeviceToDevice, s));
+  HIPCHK(hipStreamSynchronize(s));
+  return NEP_OK;
+}
+
+int nep_md_run(nep_handle* h, int64_t N, double* pos, double* vel, const int32_t* types,
+               const double* mass_per_type, const double box[9], const int32_t pbc[3], double dt_fs,
+               int64_t n_steps, int64_t thermo_every, double* thermo) {
+  if (!h) return fail(nullptr, {NEP_E_INVALID_ARG, "handle is NULL"});
+  if (!pos || !vel || !types || !box) return fail(h, {NEP_E_INVALID_ARG, "bad arguments"});
+  try {
+    set_device(h);
+    if (N < 1) throw Failure{NEP_E_INVALID_ARG, "n_atoms must be >= 1"};
+    check_host_types(h, N, types);
+    check_host_finite(3 * N, pos, "positions");
+    check_host_finite(3 * N, vel, "velocities");
+    hipStream_t s = nullptr;
+    prepare(h, N, box, pbc, h->hp.rc_radial, true, s);
+    HIPCHK(hipMemcpyAsync(h->pos_ext, pos, 3 * N * sizeof(double), hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(h->vel_ext, vel, 3 * N * sizeof(double), hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(h->types_ext, types, N * sizeof(int32_t), hipMemcpyHostToDevice, s));
+    md_impl(h, N, h->pos_ext, h->vel_ext, h->types_ext, mass_per_type, box, pbc, dt_fs, n_steps, thermo_every,
+            thermo, true, s);
+    HIPCHK(hipMemcpy(pos, h->pos_ext, 3 * N * sizeof(double), hipMemcpyDeviceToHost));
+    HIPCHK(hipMemcpy(vel, h->vel_ext, 3 * N * sizeof(double), hipMemcpyDeviceToHost));
+    h->resolve_timing();
+  } catch (const Failure& f) {
+    return fail(h, f);
+  }
+  return NEP_OK;
+}
+
+int nep_md_run_dev(nep_handle* h, int64_t N, double* pos, double* vel, const int32_t* types,
+                   const double* mass_per_type, const double box[9], const int32_t pbc[3], double dt_fs,
+                   int64_t n_steps, int64_t thermo_every, double* thermo, void* stream) {
+  if (!h) return fail(nullptr, {NEP_E_INVALID_ARG, "handle is NULL"});
+  if (!pos || !vel || !types || !box) return fail(h, {NEP_E_INVALID_ARG, "bad arguments"});
+  try {
+    set_device(h);
+    md_impl(h, N, pos, vel, types, mass_per_type, box, pbc, dt_fs, n_steps, thermo_every, thermo, false,
+            (hipStream_t)stream);
+    h->resolve_timing();
+  } catch (const Failure& f) {
+    return fail(h, f);
+  }
+  return NEP_OK;
+}
+
+int nep_set_timing(nep_handle* h, int32_t enable) {
+  if (!h) return fail(nullptr, {NEP_E_INVALID_ARG, "handle is NULL"});
+  h->timing = enable != 0;
+  h->times = StageTimes{};
+  return NEP_OK;
+}
+
+int nep_get_timing(const nep_handle* h, int32_t max, const char** names, double* ms, int64_t* calls) {
+  if (!h || max < 0) return 0;
+  const int n = std::min<int>(max, (int)h->times.names.size());
+  for (int k = 0; k < n; ++k) {
+    if (names) names[k] = h->times.names[k];
+    if (ms) ms[k] = h->times.ms[k];
+    if (calls) calls[k] = h->times.calls[k];
+  }
+  return n;
+}
+
+}  // extern "C"

@@ -1,0 +1,486 @@
+// descriptor.hip -- descriptor pass, partial-force pass and force/virial
+// gather of NEP3 (Sec. II.B-II.F), one thread per atom.
+//
+// Descriptor pass (eqs. qin, g_n, f_n, S_nk and the explicit q_{nl},
+// q_{n222}, q_{n1111}):
+//   * radial: q_n = sum_j sum_k c^{t_i t_j}_{nk} f_k(r_ij) is regrouped as
+//     sum_t sum_k c^{t_i t}_{nk} F_{t,k} with F_{t,k} = sum_{j of species t}
+//     f_k(r_ij), accumulated in a per-thread LDS slot: K adds per bond instead
+//     of n_R K multiply-adds;
+//   * angular: g_n(r) for a group of NG radial functions and S_{n,k} += g_n b_k
+//     held in registers (NG x NB accumulators), then q_{nl}, q_{n222},
+//     q_{n1111} from S; S is kept (SoA) for the force pass.
+// Partial-force pass (eq. partial_force): dU_i/dr_ij for every list entry,
+//   radial and angular separately; the radial part uses per-atom tables
+//   A_{t,k} = sum_n dU/dq_n c^{t_i t}_{nk}.
+// Gather (eqs. F_ij, F_i, virial): F_i = sum_j dU_i/dr_ij - dU_j/dr_ji and
+//   W_i = sum_j r_ij (x) dU_j/dr_ji, reading dU_j/dr_ji through the reverse
+//   index: no atomics, so results are bitwise reproducible.
+#include "angular.h"
+#include "nep_kernels.h"
+
+namespace nep {
+
+namespace {
+
+// Cutoff function and Chebyshev basis state for one bond.
+struct Basis {
+  float fc, dfc, x, dxdr;
+};
+
+__device__ __forceinline__ Basis make_basis(float r, float rc) {
+  Basis b;
+  const float rr = r * (1.0f / rc);
+  // cos(pi r / rc) with the hardware cosine (argument in revolutions)
+  b.fc = 0.5f + 0.5f * __builtin_amdgcn_cosf(0.5f * rr);
+  b.dfc = -0.5f * (3.14159265358979f / rc) * __builtin_amdgcn_sinf(0.5f * rr);
+  const float t = rr - 1.0f;
+  b.x = 2.0f * t * t - 1.0f;
+  b.dxdr = 4.0f * t * (1.0f / rc);
+  return b;
+}
+
+template <bool BATCH>
+__device__ __forceinline__ const StructInfo& struct_of(const EvalArgs& a, const StructInfo& st0,
+                                                       int64_t i) {
+  if constexpr (BATCH) return a.structs[a.sid[i]];
+  else return st0;
+}
+
+__device__ __forceinline__ void load_tables(const DevModel& M, float* sR, float* sA) {
+  const int nRt = M.T * M.T * M.nR * M.KR;
+  const int nAt = M.T * M.T * M.nA_pad * M.KA;
+  for (int k = threadIdx.x; k < nRt; k += blockDim.x) sR[k] = M.cR[k];
+  for (int k = threadIdx.x; k < nAt; k += blockDim.x) sA[k] = M.cA[k];
+}
+
+}  // namespace
+
+size_t eval_lds_bytes(const DevModel& M, int block) {
+  size_t t = (size_t)M.T * M.T * M.nR * M.KR + (size_t)M.T * M.T * M.nA_pad * M.KA;
+  return (t + (size_t)M.T * M.KR * block) * sizeof(float);
+}
+
+// ---------------------------------------------------------------------------
+// descriptor pass
+// ---------------------------------------------------------------------------
+
+template <int NG, int L, bool BATCH>
+__global__ void __launch_bounds__(kBlock, 2) k_descriptor(EvalArgs a, StructInfo st0) {
+  constexpr int NB = num_poly(L);
+  extern __shared__ float lds[];
+  const DevModel& M = a.M;
+  const int T = M.T, KR = M.KR, KA = M.KA, nR = M.nR, nA = M.nA;
+  float* sR = lds;
+  float* sA = sR + T * T * nR * KR;
+  float* acc = sA + T * T * M.nA_pad * KA;
+  load_tables(M, sR, sA);
+  const int tid = threadIdx.x, B = blockDim.x;
+  for (int k = 0; k < T * KR; ++k) acc[k * B + tid] = 0.f;
+  __syncthreads();
+  const int64_t N = a.N;
+  const int64_t i = (int64_t)blockIdx.x * B + tid;
+  if (i >= N) return;
+  const StructInfo& st = struct_of<BATCH>(a, st0, i);
+  const int ti = a.types[i];
+  const double* __restrict__ pos = a.pos;
+  float* __restrict__ qrow = a.q + i * M.NDp;
+
+  // ---- radial: F_{t,k} = sum_{j of species t} f_k(r_ij) ----
+  const float rcR = M.rcR;
+  const int nnR = min(a.L.nnR[i], a.L.MR);
+  for (int m = 0; m < nnR; ++m) {
+    const int64_t e = (int64_t)m * N + i;
+    const int32_t j = a.L.nlR[e];
+    const uint16_t code = st.mode == kModeImages ? a.L.cdR[e] : kCodeCenter;
+    double dx, dy, dz;
+    entry_disp(pos, N, i, j, st, code, dx, dy, dz);
+    const float fx = (float)dx, fy = (float)dy, fz = (float)dz;
+    const float r = sqrtf(fx * fx + fy * fy + fz * fz);
+    const Basis bs = make_basis(r, rcR);
+    float* slot = acc + (a.types[j] * KR) * B + tid;
+    slot[0] += bs.fc;
+    float Tm1 = 1.f, Tk = bs.x;
+    for (int k = 1; k < KR; ++k) {
+      slot[k * B] += 0.5f * (Tk + 1.f) * bs.fc;
+      const float Tn = 2.f * bs.x * Tk - Tm1;
+      Tm1 = Tk;
+      Tk = Tn;
+    }
+  }
+  for (int n = 0; n < nR; ++n) {
+    float s = 0.f;
+    for (int t = 0; t < T; ++t) {
+      const float* c = sR + ((ti * T + t) * nR + n) * KR;
+      for (int k = 0; k < KR; ++k) s += c[k] * acc[(t * KR + k) * B + tid];
+    }
+    qrow[n] = s;
+  }
+
+  // ---- angular: S_{n,k} = sum_j g_n(r_ij) b_k(u_ij), NG radial functions at a time ----
+  const float rcA = M.rcA;
+  const int nnA = min(a.L.nnA[i], a.L.MA);
+  for (int g = 0; g < a.ngroups; ++g) {
+    float S[NG][NB];
+#pragma unroll
+    for (int q = 0; q < NG; ++q)
+#pragma unroll
+      for (int k = 0; k < NB; ++k) S[q][k] = 0.f;
+    for (int m = 0; m < nnA; ++m) {
+      const int64_t e = (int64_t)m * N + i;
+      const int32_t j = a.L.nlA[e];
+      const uint16_t code = st.mode == kModeImages ? a.L.cdA[e] : kCodeCenter;
+      double dx, dy, dz;
+      entry_disp(pos, N, i, j, st, code, dx, dy, dz);
+      const float fx = (float)dx, fy = (float)dy, fz = (float)dz;
+      const float r = sqrtf(fx * fx + fy * fy + fz * fz);
+      const float rinv = 1.0f / r;
+      const Basis bs = make_basis(r, rcA);
+      const float* c = sA + ((ti * T + a.types[j]) * M.nA_pad + g * NG) * KA;
+      float gq[NG];
+#pragma unroll
+      for (int q = 0; q < NG; ++q) gq[q] = c[q * KA] * bs.fc;
+      float Tm1 = 1.f, Tk = bs.x;
+      for (int k = 1; k < KA; ++k) {
+        const float f = 0.5f * (Tk + 1.f) * bs.fc;
+#pragma unroll
+        for (int q = 0; q < NG; ++q) gq[q] += c[q * KA + k] * f;
+        const float Tn = 2.f * bs.x * Tk - Tm1;
+        Tm1 = Tk;
+        Tk = Tn;
+      }
+      angular_values<L>(fx * rinv, fy * rinv, fz * rinv,
+                        [&](int k, float b) __attribute__((always_inline)) {
+#pragma unroll
+                          for (int q = 0; q < NG; ++q) S[q][k] += gq[q] * b;
+                        });
+    }
+    // q_{nl} = sum_{k in l} C3_k S_{nk}^2 ; q_{n222} ; q_{n1111}
+#pragma unroll
+    for (int q = 0; q < NG; ++q) {
+      const int n = g * NG + q;
+      if (n >= nA) break;
+      float* sums = a.sums + (int64_t)(n * NB) * N + i;
+#pragma unroll
+      for (int k = 0; k < NB; ++k) sums[(int64_t)k * N] = S[q][k];
+      float v[L];
+#pragma unroll
+      for (int l = 0; l < L; ++l) v[l] = 0.f;
+#pragma unroll
+      for (int k = 0; k < NB; ++k) v[degree_of(k) - 1] += M.C3[k] * S[q][k] * S[q][k];
+#pragma unroll
+      for (int l = 1; l <= L; ++l) qrow[nR + (l - 1) * nA + n] = v[l - 1];
+      if constexpr (L >= 2) {
+        if (M.has4b) {
+          const float* s = S[q];
+          const float v = M.C4[0] * s[3] * s[3] * s[3] + M.C4[1] * s[3] * (s[4] * s[4] + s[5] * s[5]) +
+                          M.C4[2] * s[3] * (s[6] * s[6] + s[7] * s[7]) +
+                          M.C4[3] * s[6] * (s[5] * s[5] - s[4] * s[4]) + M.C4[4] * s[4] * s[5] * s[7];
+          qrow[nR + L * nA + n] = v;
+        }
+      }
+      if (M.has5b) {
+        const float* s = S[q];
+        const float s12 = s[1] * s[1] + s[2] * s[2];
+        const float v = M.C5[0] * s[0] * s[0] * s[0] * s[0] + M.C5[1] * s[0] * s[0] * s12 +
+                        M.C5[2] * s12 * s12;
+        qrow[nR + (L + M.has4b) * nA + n] = v;
+      }
+    }
+  }
+  for (int c = M.ND; c < M.NDp; ++c) qrow[c] = 0.f;
+}
+
+// ---------------------------------------------------------------------------
+// partial forces dU_i/dr_ij (eq. partial_force)
+// ---------------------------------------------------------------------------
+
+// Large accumulator blocks (NG x NB > 120 floats) run at one wave per SIMD so
+// the compiler can keep the D block in AGPRs instead of spilling to memory.
+template <int NG, int L, bool BATCH>
+__global__ void __launch_bounds__(kBlock, (NG * num_poly(L) > 120) ? 1 : 2)
+    k_partial_forces(EvalArgs a, StructInfo st0) {
+  constexpr int NB = num_poly(L);
+  extern __shared__ float lds[];
+  const DevModel& M = a.M;
+  const int T = M.T, KR = M.KR, KA = M.KA, nR = M.nR, nA = M.nA;
+  float* sR = lds;
+  float* sA = sR + T * T * nR * KR;
+  float* At = sA + T * T * M.nA_pad * KA;
+  load_tables(M, sR, sA);
+  __syncthreads();
+  const int tid = threadIdx.x, B = blockDim.x;
+  const int64_t N = a.N;
+  const int64_t i = (int64_t)blockIdx.x * B + tid;
+  if (i >= N) return;
+  const StructInfo& st = struct_of<BATCH>(a, st0, i);
+  const int ti = a.types[i];
+  const double* __restrict__ pos = a.pos;
+  const float* __restrict__ fprow = a.fp + i * M.NDp;
+
+  // ---- radial: A_{t,k} = sum_n dU/dq_n c^{t_i t}_{nk}; dU_i/dr_ij = (sum_k A f'_k) u ----
+  for (int t = 0; t < T; ++t)
+    for (int k = 0; k < KR; ++k) {
+      float s = 0.f;
+      for (int n = 0; n < nR; ++n) s += fprow[n] * sR[((ti * T + t) * nR + n) * KR + k];
+      At[(t * KR + k) * B + tid] = s;
+    }
+  const float rcR = M.rcR;
+  const int MR = a.L.MR;
+  const int nnR = min(a.L.nnR[i], MR);
+  for (int m = 0; m < nnR; ++m) {
+    const int64_t e = (int64_t)m * N + i;
+    const int32_t j = a.L.nlR[e];
+    const uint16_t code = st.mode == kModeImages ? a.L.cdR[e] : kCodeCenter;
+    double dx, dy, dz;
+    entry_disp(pos, N, i, j, st, code, dx, dy, dz);
+    const float fx = (float)dx, fy = (float)dy, fz = (float)dz;
+    const float r = sqrtf(fx * fx + fy * fy + fz * fz);
+    const float rinv = 1.0f / r;
+    const Basis bs = make_basis(r, rcR);
+    const float* At_j = At + (a.types[j] * KR) * B + tid;
+    // f'_k = 1/2 T'_k x' f_c + 1/2 (T_k + 1) f_c'
+    float s = At_j[0] * bs.dfc;
+    float Tm1 = 1.f, Tk = bs.x, dTm1 = 0.f, dTk = 1.f;
+    for (int k = 1; k < KR; ++k) {
+      const float df = 0.5f * dTk * bs.dxdr * bs.fc + 0.5f * (Tk + 1.f) * bs.dfc;
+      s += At_j[k * B] * df;
+      const float Tn = 2.f * bs.x * Tk - Tm1;
+      const float dTn = 2.f * Tk + 2.f * bs.x * dTk - dTm1;
+      Tm1 = Tk;
+      Tk = Tn;
+      dTm1 = dTk;
+      dTk = dTn;
+    }
+    s *= rinv;
+    float* p = a.pr + e;
+    p[0] = s * fx;
+    p[(int64_t)MR * N] = s * fy;
+    p[(int64_t)2 * MR * N] = s * fz;
+  }
+
+  // ---- angular: sum_{n,k} D_{nk} [g'_n u b_k + g_n d b_k / d r_ij] ----
+  const float rcA = M.rcA;
+  const int MA = a.L.MA;
+  const int nnA = min(a.L.nnA[i], MA);
+  for (int g = 0; g < a.ngroups; ++g) {
+    // D_{nk} = dU/dS_{nk} through q_{nl}, q_{n222}, q_{n1111}
+    float D[NG][NB];
+#pragma unroll
+    for (int q = 0; q < NG; ++q) {
+      const int n = min(g * NG + q, nA - 1);
+      const bool live = g * NG + q < nA;
+      const float* sums = a.sums + (int64_t)(n * NB) * N + i;
+      float s[NB];
+#pragma unroll
+      for (int k = 0; k < NB; ++k) s[k] = sums[(int64_t)k * N];
+      float f3[L];
+#pragma unroll
+      for (int l = 1; l <= L; ++l) f3[l - 1] = live ? fprow[nR + (l - 1) * nA + n] : 0.f;
+#pragma unroll
+      for (int k = 0; k < NB; ++k) D[q][k] = 2.f * M.C3[k] * f3[degree_of(k) - 1] * s[k];
+      if constexpr (L >= 2) {
+        if (M.has4b) {
+          const float f = live ? fprow[nR + L * nA + n] : 0.f;
+          const float* C = M.C4;
+          D[q][3] += f * (3.f * C[0] * s[3] * s[3] + C[1] * (s[4] * s[4] + s[5] * s[5]) +
+                          C[2] * (s[6] * s[6] + s[7] * s[7]));
+          D[q][4] += f * (2.f * C[1] * s[3] * s[4] - 2.f * C[3] * s[6] * s[4] + C[4] * s[5] * s[7]);
+          D[q][5] += f * (2.f * C[1] * s[3] * s[5] + 2.f * C[3] * s[6] * s[5] + C[4] * s[4] * s[7]);
+          D[q][6] += f * (2.f * C[2] * s[3] * s[6] + C[3] * (s[5] * s[5] - s[4] * s[4]));
+          D[q][7] += f * (2.f * C[2] * s[3] * s[7] + C[4] * s[4] * s[5]);
+        }
+      }
+      if (M.has5b) {
+        const float f = live ? fprow[nR + (L + M.has4b) * nA + n] : 0.f;
+        const float* C = M.C5;
+        const float s12 = s[1] * s[1] + s[2] * s[2];
+        D[q][0] += f * (4.f * C[0] * s[0] * s[0] * s[0] + 2.f * C[1] * s[0] * s12);
+        D[q][1] += f * (2.f * C[1] * s[0] * s[0] * s[1] + 4.f * C[2] * s12 * s[1]);
+        D[q][2] += f * (2.f * C[1] * s[0] * s[0] * s[2] + 4.f * C[2] * s12 * s[2]);
+      }
+    }
+    for (int m = 0; m < nnA; ++m) {
+      const int64_t e = (int64_t)m * N + i;
+      const int32_t j = a.L.nlA[e];
+      const uint16_t code = st.mode == kModeImages ? a.L.cdA[e] : kCodeCenter;
+      double dx, dy, dz;
+      entry_disp(pos, N, i, j, st, code, dx, dy, dz);
+      const float fx = (float)dx, fy = (float)dy, fz = (float)dz;
+      const float r = sqrtf(fx * fx + fy * fy + fz * fz);
+      const float rinv = 1.0f / r;
+      const float ux = fx * rinv, uy = fy * rinv, uz = fz * rinv;
+      const Basis bs = make_basis(r, rcA);
+      const float* c = sA + ((ti * T + a.types[j]) * M.nA_pad + g * NG) * KA;
+      float gq[NG], dgq[NG];
+#pragma unroll
+      for (int q = 0; q < NG; ++q) {
+        gq[q] = c[q * KA] * bs.fc;
+        dgq[q] = c[q * KA] * bs.dfc;
+      }
+      float Tm1 = 1.f, Tk = bs.x, dTm1 = 0.f, dTk = 1.f;
+      for (int k = 1; k < KA; ++k) {
+        const float f = 0.5f * (Tk + 1.f) * bs.fc;
+        const float df = 0.5f * dTk * bs.dxdr * bs.fc + 0.5f * (Tk + 1.f) * bs.dfc;
+#pragma unroll
+        for (int q = 0; q < NG; ++q) {
+          gq[q] += c[q * KA + k] * f;
+          dgq[q] += c[q * KA + k] * df;
+        }
+        const float Tn = 2.f * bs.x * Tk - Tm1;
+        const float dTn = 2.f * Tk + 2.f * bs.x * dTk - dTm1;
+        Tm1 = Tk;
+        Tk = Tn;
+        dTm1 = dTk;
+        dTk = dTn;
+      }
+      float E[NG];
+#pragma unroll
+      for (int q = 0; q < NG; ++q) E[q] = 0.f;
+      float Vx = 0.f, Vy = 0.f, Vz = 0.f;
+      angular_terms<L>(ux, uy, uz,
+                       [&](int k, float b, float gx, float gy, float gz)
+                           __attribute__((always_inline)) {
+                             float w = 0.f;
+#pragma unroll
+                             for (int q = 0; q < NG; ++q) {
+                               w += gq[q] * D[q][k];
+                               E[q] += D[q][k] * b;
+                             }
+                             Vx += w * gx;
+                             Vy += w * gy;
+                             Vz += w * gz;
+                           });
+      float s = 0.f;
+#pragma unroll
+      for (int q = 0; q < NG; ++q) s += dgq[q] * E[q];
+      const float uV = ux * Vx + uy * Vy + uz * Vz;
+      const float px = s * ux + (Vx - uV * ux) * rinv;
+      const float py = s * uy + (Vy - uV * uy) * rinv;
+      const float pz = s * uz + (Vz - uV * uz) * rinv;
+      float* p = a.pa + e;
+      if (g == 0) {
+        p[0] = px;
+        p[(int64_t)MA * N] = py;
+        p[(int64_t)2 * MA * N] = pz;
+      } else {
+        p[0] += px;
+        p[(int64_t)MA * N] += py;
+        p[(int64_t)2 * MA * N] += pz;
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// force and virial gather (eqs. F_ij, F_i, virial)
+// ---------------------------------------------------------------------------
+
+template <bool BATCH>
+__global__ void __launch_bounds__(kBlock) k_gather(EvalArgs a, StructInfo st0) {
+  const int64_t N = a.N;
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= N) return;
+  const StructInfo& st = struct_of<BATCH>(a, st0, i);
+  float F[3] = {0.f, 0.f, 0.f}, W[9] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+  for (int list = 0; list < 2; ++list) {
+    const int M = list ? a.L.MA : a.L.MR;
+    const int nn = min(list ? a.L.nnA[i] : a.L.nnR[i], M);
+    const int32_t* nl = list ? a.L.nlA : a.L.nlR;
+    const uint16_t* cd = list ? a.L.cdA : a.L.cdR;
+    const int32_t* rev = list ? a.L.revA : a.L.revR;
+    const float* P = list ? a.pa : a.pr;
+    const int64_t cs = (int64_t)M * N;
+    for (int m = 0; m < nn; ++m) {
+      const int64_t e = (int64_t)m * N + i;
+      const int32_t j = nl[e];
+      const uint16_t code = st.mode == kModeImages ? cd[e] : kCodeCenter;
+      const int64_t er = (int64_t)rev[e] * N + j;
+      const float pij[3] = {P[e], P[cs + e], P[2 * cs + e]};
+      const float pji[3] = {P[er], P[cs + er], P[2 * cs + er]};
+      double dx, dy, dz;
+      entry_disp(a.pos, N, i, j, st, code, dx, dy, dz);
+      const float d[3] = {(float)dx, (float)dy, (float)dz};
+#pragma unroll
+      for (int c = 0; c < 3; ++c) F[c] += pij[c] - pji[c];
+#pragma unroll
+      for (int x = 0; x < 3; ++x)
+#pragma unroll
+        for (int y = 0; y < 3; ++y) W[x * 3 + y] += d[x] * pji[y];
+    }
+  }
+#pragma unroll
+  for (int c = 0; c < 3; ++c) a.F[(int64_t)c * N + i] = F[c];
+#pragma unroll
+  for (int v = 0; v < 9; ++v) a.W[(int64_t)v * N + i] = W[v];
+}
+
+// ---------------------------------------------------------------------------
+// dispatch
+// ---------------------------------------------------------------------------
+
+// Group size NG for n_A radial functions at a given l_max: as many as fit the
+// register budget of the accumulator block (NG x NB floats), in two or more
+// equal groups otherwise.
+int angular_group_size(int nA, int L) {
+  const int cap = L <= 4 ? 7 : (L == 5 ? 5 : 4);
+  static const int allowed[] = {2, 4, 5, 7};
+  int best = -1, best_cost = 1 << 30;
+  for (int ng : allowed) {
+    if (ng > cap) continue;
+    int groups = (nA + ng - 1) / ng;
+    int cost = groups * ng * 4 + groups;  // padded work, then fewer passes
+    if (cost < best_cost) {
+      best_cost = cost;
+      best = ng;
+    }
+  }
+  return best;
+}
+
+template <int NG, int L, bool BATCH>
+static void launch_pair(const EvalArgs& a, const StructInfo& st0, bool force, hipStream_t s) {
+  const size_t lds = eval_lds_bytes(a.M, kBlock);
+  dim3 grid((unsigned)div_up(a.N, kBlock));
+  if (force)
+    hipLaunchKernelGGL((k_partial_forces<NG, L, BATCH>), grid, dim3(kBlock), lds, s, a, st0);
+  else
+    hipLaunchKernelGGL((k_descriptor<NG, L, BATCH>), grid, dim3(kBlock), lds, s, a, st0);
+}
+
+template <bool BATCH>
+static bool dispatch(const EvalArgs& a, const StructInfo& st0, bool force, hipStream_t s) {
+  const int L = a.M.L, NG = a.NG;
+#define NEP_CASE(ng, l)                                  \
+  if (NG == ng && L == l) {                              \
+    launch_pair<ng, l, BATCH>(a, st0, force, s);         \
+    return true;                                         \
+  }
+  NEP_CASE(2, 1) NEP_CASE(4, 1) NEP_CASE(5, 1) NEP_CASE(7, 1)
+  NEP_CASE(2, 2) NEP_CASE(4, 2) NEP_CASE(5, 2) NEP_CASE(7, 2)
+  NEP_CASE(2, 3) NEP_CASE(4, 3) NEP_CASE(5, 3) NEP_CASE(7, 3)
+  NEP_CASE(2, 4) NEP_CASE(4, 4) NEP_CASE(5, 4) NEP_CASE(7, 4)
+  NEP_CASE(2, 5) NEP_CASE(4, 5) NEP_CASE(5, 5)
+  NEP_CASE(2, 6) NEP_CASE(4, 6)
+#undef NEP_CASE
+  return false;
+}
+
+bool launch_descriptor(const EvalArgs& a, hipStream_t s) {
+  return a.batch ? dispatch<true>(a, a.st0, false, s) : dispatch<false>(a, a.st0, false, s);
+}
+
+bool launch_partial_forces(const EvalArgs& a, hipStream_t s) {
+  return a.batch ? dispatch<true>(a, a.st0, true, s) : dispatch<false>(a, a.st0, true, s);
+}
+
+void launch_gather_forces(const EvalArgs& a, hipStream_t s) {
+  dim3 grid((unsigned)div_up(a.N, kBlock));
+  if (a.batch)
+    hipLaunchKernelGGL((k_gather<true>), grid, dim3(kBlock), 0, s, a, a.st0);
+  else
+    hipLaunchKernelGGL((k_gather<false>), grid, dim3(kBlock), 0, s, a, a.st0);
+}
+
+}  // namespace nep

@@ -1,0 +1,163 @@
+// md.hip -- velocity-Verlet NVE (the 'nve' ensemble of the paper) in float64:
+//   v += dt/2 F/m;  r += dt v;  (rebuild, forces);  v += dt/2 F/m
+// plus the thermo row [step, E_pot, E_kin, T, W_xx..W_zz] as a fixed-order
+// float64 reduction.  State is kept in the internal atom order.
+#include "nep_kernels.h"
+
+namespace nep {
+
+__global__ void k_kick_drift(MDArgs a) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= a.N) return;
+  const double s = 0.5 * a.dt * a.inv_mass[a.types[i]];
+  for (int c = 0; c < 3; ++c) {
+    const int64_t k = (int64_t)c * a.N + i;
+    const double v = a.vel[k] + s * (double)a.F[k];
+    a.vel[k] = v;
+    a.pos[k] += a.dt * v;
+  }
+}
+
+__global__ void k_kick(MDArgs a) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= a.N) return;
+  const double s = 0.5 * a.dt * a.inv_mass[a.types[i]];
+  for (int c = 0; c < 3; ++c) {
+    const int64_t k = (int64_t)c * a.N + i;
+    a.vel[k] += s * (double)a.F[k];
+  }
+}
+
+void launch_kick_drift(const MDArgs& a, hipStream_t s) {
+  hipLaunchKernelGGL(k_kick_drift, dim3(div_up(a.N, kBlock)), dim3(kBlock), 0, s, a);
+}
+
+void launch_kick(const MDArgs& a, hipStream_t s) {
+  hipLaunchKernelGGL(k_kick, dim3(div_up(a.N, kBlock)), dim3(kBlock), 0, s, a);
+}
+
+constexpr int kRed = 256;
+
+// partial[b][11]: U, m v^2, W_0..8 over a fixed slice, fixed tree.
+__global__ void __launch_bounds__(kRed) k_thermo_partial(const float* __restrict__ U,
+                                                         const float* __restrict__ W,
+                                                         const double* __restrict__ vel,
+                                                         const int32_t* __restrict__ types,
+                                                         const double* __restrict__ mass,
+                                                         int64_t N, int64_t chunk,
+                                                         double* __restrict__ partial) {
+  __shared__ double sh[11][kRed];
+  const int t = threadIdx.x;
+  const int64_t lo = (int64_t)blockIdx.x * chunk, hi = min(N, lo + chunk);
+  double acc[11] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+  for (int64_t k = lo + t; k < hi; k += kRed) {
+    acc[0] += (double)U[k];
+    const double vx = vel[k], vy = vel[N + k], vz = vel[2 * N + k];
+    acc[1] += mass[types[k]] * (vx * vx + vy * vy + vz * vz);
+    for (int v = 0; v < 9; ++v) acc[2 + v] += (double)W[(int64_t)v * N + k];
+  }
+  for (int v = 0; v < 11; ++v) sh[v][t] = acc[v];
+  __syncthreads();
+  for (int off = kRed / 2; off > 0; off >>= 1) {
+    if (t < off)
+      for (int v = 0; v < 11; ++v) sh[v][t] += sh[v][t + off];
+    __syncthreads();
+  }
+  if (t < 11) partial[blockIdx.x * 11 + t] = sh[t][0];
+}
+
+__global__ void k_thermo_final(const double* __restrict__ partial, int64_t n_part, int64_t N,
+                               double step, double kin_conv, double kB, double* __restrict__ row) {
+  if (threadIdx.x != 0) return;
+  double s[11] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+  for (int64_t b = 0; b < n_part; ++b)
+    for (int v = 0; v < 11; ++v) s[v] += partial[b * 11 + v];
+  const double ek = 0.5 * s[1] * kin_conv;
+  row[0] = step;
+  row[1] = s[0];
+  row[2] = ek;
+  row[3] = N > 1 ? 2.0 * ek / ((3.0 * (double)N - 3.0) * kB) : 0.0;
+  for (int v = 0; v < 9; ++v) row[4 + v] = s[2 + v];
+}
+
+void launch_thermo(const float* U, const float* W, const double* vel, const int32_t* types,
+                   const double* mass, int64_t N, double* partial, int64_t n_part, double* row,
+                   double step, double kin_conv, double kB, hipStream_t s) {
+  const int64_t chunk = (N + n_part - 1) / n_part;
+  hipLaunchKernelGGL(k_thermo_partial, dim3((unsigned)n_part), dim3(kRed), 0, s, U, W, vel, types,
+                     mass, N, chunk, partial);
+  hipLaunchKernelGGL(k_thermo_final, dim3(1), dim3(64), 0, s, partial, n_part, N, step, kin_conv,
+                     kB, row);
+}
+
+// new[k] = old[src[k]] for positions and velocities ([3][N] each)
+__global__ void k_permute_md(const int32_t* __restrict__ src, int64_t N,
+                             const double* __restrict__ pos_old, const double* __restrict__ vel_old,
+                             double* __restrict__ pos_new, double* __restrict__ vel_new) {
+  int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= N) return;
+  const int64_t o = src[k];
+  for (int c = 0; c < 3; ++c) {
+    pos_new[(int64_t)c * N + k] = pos_old[(int64_t)c * N + o];
+    vel_new[(int64_t)c * N + k] = vel_old[(int64_t)c * N + o];
+  }
+}
+
+void launch_permute_md(const int32_t* src, int64_t N, const double* src_pos,
+                       const double* src_vel, double* dst_pos, double* dst_vel, hipStream_t s) {
+  hipLaunchKernelGGL(k_permute_md, dim3(div_up(N, kBlock)), dim3(kBlock), 0, s, src, N, src_pos,
+                     src_vel, dst_pos, dst_vel);
+}
+
+// caller order out: ext[perm[k]] = int[k]
+__global__ void k_unpermute_md(const int32_t* __restrict__ perm, int64_t N,
+                               const double* __restrict__ pos_int, const double* __restrict__ vel_int,
+                               double* __restrict__ pos_ext, double* __restrict__ vel_ext) {
+  int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= N) return;
+  const int64_t e = perm[k];
+  for (int c = 0; c < 3; ++c) {
+    pos_ext[(int64_t)c * N + e] = pos_int[(int64_t)c * N + k];
+    vel_ext[(int64_t)c * N + e] = vel_int[(int64_t)c * N + k];
+  }
+}
+
+void launch_unpermute_md(const int32_t* perm, int64_t N, const double* pos_int,
+                         const double* vel_int, double* pos_ext, double* vel_ext, hipStream_t s) {
+  hipLaunchKernelGGL(k_unpermute_md, dim3(div_up(N, kBlock)), dim3(kBlock), 0, s, perm, N, pos_int,
+                     vel_int, pos_ext, vel_ext);
+}
+
+__global__ void k_check_finite(const double* __restrict__ a, int64_t n, int32_t* __restrict__ flag) {
+  int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < n && !isfinite(a[k])) atomicExch(flag, 1);
+}
+
+void launch_check_finite(const double* a, int64_t n, int32_t* flag, hipStream_t s) {
+  if (n > 0)
+    hipLaunchKernelGGL(k_check_finite, dim3(div_up(n, kBlock)), dim3(kBlock), 0, s, a, n, flag);
+}
+
+__global__ void k_check_types(const int32_t* __restrict__ t, int64_t n, int32_t T,
+                              int32_t* __restrict__ flag) {
+  int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < n && (t[k] < 0 || t[k] >= T)) atomicExch(flag, 1);
+}
+
+void launch_check_types(const int32_t* types, int64_t n, int32_t T, int32_t* flag, hipStream_t s) {
+  if (n > 0)
+    hipLaunchKernelGGL(k_check_types, dim3(div_up(n, kBlock)), dim3(kBlock), 0, s, types, n, T, flag);
+}
+
+// out[k] = in[src[k]]
+__global__ void k_gather_i32(const int32_t* __restrict__ src, int64_t N, const int32_t* __restrict__ in,
+                             int32_t* __restrict__ out) {
+  int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < N) out[k] = in[src[k]];
+}
+
+void launch_gather_i32(const int32_t* src, int64_t N, const int32_t* in, int32_t* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_gather_i32, dim3(div_up(N, kBlock)), dim3(kBlock), 0, s, src, N, in, out);
+}
+
+}  // namespace nep

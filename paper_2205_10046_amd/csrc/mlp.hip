@@ -1,0 +1,173 @@
+// mlp.hip -- the per-atom network of eq. (Ui) as two batched GEMMs on MFMA.
+//
+// For a tile of 16 atoms of one species (rows of q in the species-grouped
+// order built with the neighbour lists):
+//   GEMM 1   H^T = w0 q^T            [N_neu x N_des] x [N_des x 16]
+//            h = tanh(H - b0),  U = sum_mu w1_mu h_mu - b1
+//   GEMM 2   dU/dq = G w0,  G = w1 (1 - h^2)     [16 x N_neu] x [N_neu x N_des]
+// (the derivative is the back-propagation of the printed apply_ann routine,
+// App. B).  GEMM 1 is laid out so that its accumulator tile, lane l holding
+// neurons 4(l/16)+r of atom l%16, is directly the A operand of GEMM 2 once
+// the reduction index is read as "neuron 16 nb + 4 (l/16) + r": the B operand
+// of GEMM 2 loads w0 rows in that same order, so no transpose through LDS is
+// needed.  Every output element is accumulated in a fixed order that does not
+// depend on the other rows of the tile, so results do not depend on how
+// atoms are grouped into tiles.
+//
+// FP32: v_mfma_f32_16x16x4_f32.  BF16: v_mfma_f32_16x16x32_bf16 with bf16
+// operands (q, w0, G) and float32 accumulation; b0, tanh and the w1 products
+// stay float32.
+#include "nep_kernels.h"
+
+namespace nep {
+
+namespace {
+typedef float v4f __attribute__((ext_vector_type(4)));
+typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
+
+__device__ __forceinline__ v8bf bf16x8_from_bits(uint4 u) {
+  v8bf r;
+  const uint32_t w[4] = {u.x, u.y, u.z, u.w};
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    r[2 * k] = __builtin_bit_cast(__bf16, (uint16_t)(w[k] & 0xffffu));
+    r[2 * k + 1] = __builtin_bit_cast(__bf16, (uint16_t)(w[k] >> 16));
+  }
+  return r;
+}
+
+__device__ __forceinline__ void bf16x4_from_bits(uint2 u, v8bf& r, int off) {
+  r[off + 0] = __builtin_bit_cast(__bf16, (uint16_t)(u.x & 0xffffu));
+  r[off + 1] = __builtin_bit_cast(__bf16, (uint16_t)(u.x >> 16));
+  r[off + 2] = __builtin_bit_cast(__bf16, (uint16_t)(u.y & 0xffffu));
+  r[off + 3] = __builtin_bit_cast(__bf16, (uint16_t)(u.y >> 16));
+}
+}  // namespace
+
+template <int NNB, bool BF16>
+__global__ void __launch_bounds__(256) k_mlp(EvalArgs a) {
+  const DevModel& M = a.M;
+  const int lane = threadIdx.x & 63;
+  const int64_t base = ((int64_t)blockIdx.x * 4 + (threadIdx.x >> 6)) * 16;
+  if (base >= a.rows_len) return;
+  const int first = a.rows[base];
+  if (first < 0) return;  // tiles never mix species; a tile starting with padding is all padding
+  const int net = M.nets > 1 ? a.types[first] : 0;
+  const int col = lane & 15, grp = lane >> 4;
+  const int atom = a.rows[base + col];
+  const int ND = M.ND, NNp = M.NNp;
+  const float* __restrict__ qrow = a.q + (int64_t)(atom < 0 ? 0 : atom) * M.NDp;
+  const float* __restrict__ b0 = M.b0 + net * NNp;
+  const float* __restrict__ w1 = M.w1 + net * NNp;
+
+  // ---- GEMM 1: acc[nb][r] = sum_d w0[16 nb + 4 grp + r][d] q[atom col][d] ----
+  v4f acc[NNB];
+#pragma unroll
+  for (int nb = 0; nb < NNB; ++nb) acc[nb] = v4f{0.f, 0.f, 0.f, 0.f};
+  if constexpr (!BF16) {
+    const float* __restrict__ w0t = M.w0t + (int64_t)net * ND * NNp;
+    const int steps = (ND + 3) / 4;
+    for (int s = 0; s < steps; ++s) {
+      const int d = 4 * s + grp;
+      const float bq = (atom >= 0 && d < ND) ? qrow[d] : 0.f;
+#pragma unroll
+      for (int nb = 0; nb < NNB; ++nb) {
+        const float aw = d < ND ? w0t[(int64_t)d * NNp + 16 * nb + col] : 0.f;
+        acc[nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(aw, bq, acc[nb], 0, 0, 0);
+      }
+    }
+  } else {
+    const uint16_t* __restrict__ w0b = M.w0b + (int64_t)net * NNp * M.NDp32;
+    const int steps = M.NDp32 / 32;
+    for (int s = 0; s < steps; ++s) {
+      const int d0 = 32 * s + 8 * grp;
+      v8bf bq;
+      if (atom >= 0 && d0 < M.NDp) {
+        const float4 x0 = *reinterpret_cast<const float4*>(qrow + d0);
+        const float4 x1 = *reinterpret_cast<const float4*>(qrow + d0 + 4);
+        bq[0] = (__bf16)x0.x; bq[1] = (__bf16)x0.y; bq[2] = (__bf16)x0.z; bq[3] = (__bf16)x0.w;
+        bq[4] = (__bf16)x1.x; bq[5] = (__bf16)x1.y; bq[6] = (__bf16)x1.z; bq[7] = (__bf16)x1.w;
+      } else {
+#pragma unroll
+        for (int k = 0; k < 8; ++k) bq[k] = (__bf16)0.f;
+      }
+#pragma unroll
+      for (int nb = 0; nb < NNB; ++nb) {
+        const uint4 u = *reinterpret_cast<const uint4*>(w0b + (int64_t)(16 * nb + col) * M.NDp32 + d0);
+        acc[nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bf16x8_from_bits(u), bq, acc[nb], 0, 0, 0);
+      }
+    }
+  }
+
+  // ---- activation, site energy and G = w1 (1 - h^2) ----
+  float u = 0.f;
+  float g[NNB][4];
+#pragma unroll
+  for (int nb = 0; nb < NNB; ++nb)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int mu = 16 * nb + 4 * grp + r;
+      const float h = tanhf(acc[nb][r] - b0[mu]);
+      u += w1[mu] * h;
+      g[nb][r] = w1[mu] * (1.f - h * h);
+    }
+  u += __shfl_xor(u, 16);
+  u += __shfl_xor(u, 32);
+  if (grp == 0 && atom >= 0) a.U[atom] = u - M.b1;
+
+  // ---- GEMM 2: dU/dq[atom][d] = sum_mu G[atom][mu] w0[mu][d] ----
+  const int dblocks = (ND + 15) / 16;
+  for (int db = 0; db < dblocks; ++db) {
+    const int d = 16 * db + col;
+    v4f c = v4f{0.f, 0.f, 0.f, 0.f};
+    if constexpr (!BF16) {
+      const float* __restrict__ w0 = M.w0 + (int64_t)net * NNp * ND;
+#pragma unroll
+      for (int nb = 0; nb < NNB; ++nb)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int mu = 16 * nb + 4 * grp + r;
+          const float bw = d < ND ? w0[(int64_t)mu * ND + d] : 0.f;
+          c = __builtin_amdgcn_mfma_f32_16x16x4f32(g[nb][r], bw, c, 0, 0, 0);
+        }
+    } else {
+      const uint16_t* __restrict__ w0tb = M.w0tb + (int64_t)net * M.NDp32 * NNp;
+      const uint16_t* wrow = w0tb + (int64_t)(d < M.NDp32 ? d : 0) * NNp;
+#pragma unroll
+      for (int p = 0; p < NNB / 2; ++p) {
+        v8bf av, bv;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          av[r] = (__bf16)g[2 * p][r];
+          av[4 + r] = (__bf16)g[2 * p + 1][r];
+        }
+        const uint2 lo = *reinterpret_cast<const uint2*>(wrow + 32 * p + 4 * grp);
+        const uint2 hi = *reinterpret_cast<const uint2*>(wrow + 32 * p + 16 + 4 * grp);
+        bf16x4_from_bits(lo, bv, 0);
+        bf16x4_from_bits(hi, bv, 4);
+        c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, c, 0, 0, 0);
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int at = a.rows[base + 4 * grp + r];
+      if (at >= 0 && d < ND) a.fp[(int64_t)at * M.NDp + d] = c[r];
+    }
+  }
+}
+
+void launch_mlp(const EvalArgs& a, hipStream_t s) {
+  const int64_t tiles = a.rows_len / 16;
+  dim3 grid((unsigned)div_up(tiles, 4)), block(256);
+  const int nnb = a.M.NNp / 16;
+#define NEP_MLP(n)                                                              \
+  if (nnb == n) {                                                               \
+    if (a.mlp_bf16) hipLaunchKernelGGL((k_mlp<n, true>), grid, block, 0, s, a); \
+    else hipLaunchKernelGGL((k_mlp<n, false>), grid, block, 0, s, a);           \
+    return;                                                                     \
+  }
+  NEP_MLP(2) NEP_MLP(4) NEP_MLP(6) NEP_MLP(8)
+#undef NEP_MLP
+}
+
+}  // namespace nep

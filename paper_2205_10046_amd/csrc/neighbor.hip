@@ -1,0 +1,364 @@
+// neighbor.hip -- neighbour rows for the sums over j != i of Sec. II.B/II.C.
+//
+// The paper assumes neighbour counts NN_i and rows NL_im are given and uses
+// the minimum image; it does not say how they are built.  Here:
+//   1. atoms are binned into cells at least r_c wide along every cell vector
+//      (fractional coordinates, float64), one cell per small structure;
+//   2. a deterministic counting sort gives the internal atom order
+//      (structure, cell, caller index): the atoms of a cell are contiguous;
+//   3. one thread per atom scans the stencil cells in increasing cell index,
+//      so candidate j arrive in increasing internal index and every row comes
+//      out sorted by (j, image) without a sort;
+//   4. membership is the strict float64 test |d|^2 < r_c^2 on the canonical
+//      displacement (no fused multiply-add), the same test for both cutoffs;
+//   5. rev[m][i] locates i in the row of its m-th neighbour by binary search,
+//      so the force pass can gather dU_j/dr_ji without atomics.
+#include "nep_kernels.h"
+
+namespace nep {
+
+__global__ void k_fill_i32(int32_t* a, int64_t n, int32_t v) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) a[i] = v;
+}
+
+// Structure id of every caller-order atom from the offsets array.
+__global__ void k_assign_struct(const int64_t* __restrict__ offs, int32_t n_struct, int64_t N,
+                                int32_t* __restrict__ sid) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= N) return;
+  int lo = 0, hi = n_struct - 1;
+  while (lo < hi) {  // last s with offs[s] <= i
+    int mid = (lo + hi + 1) >> 1;
+    if (offs[mid] <= i) lo = mid; else hi = mid - 1;
+  }
+  sid[i] = lo;
+}
+
+// Cell coordinates of a position inside structure st (fractional, wrapped
+// along periodic directions, clamped along open ones).
+__device__ inline void cell_coords(const StructInfo& st, double x, double y, double z,
+                                   int& cx, int& cy, int& cz) {
+  double s[3];
+  s[0] = x * st.Hi[0] + y * st.Hi[3] + z * st.Hi[6];
+  s[1] = x * st.Hi[1] + y * st.Hi[4] + z * st.Hi[7];
+  s[2] = x * st.Hi[2] + y * st.Hi[5] + z * st.Hi[8];
+  int c[3];
+  for (int k = 0; k < 3; ++k) {
+    double f = s[k];
+    if (st.pbc[k]) f -= floor(f);
+    f = fmin(fmax(f, 0.0), 1.0);
+    int v = (int)(f * st.ncell[k]);
+    c[k] = v < 0 ? 0 : (v >= st.ncell[k] ? st.ncell[k] - 1 : v);
+  }
+  cx = c[0];
+  cy = c[1];
+  cz = c[2];
+}
+
+__global__ void k_cell_key(const double* __restrict__ pos, int64_t N,
+                           const int32_t* __restrict__ sid, const StructInfo* __restrict__ structs,
+                           int32_t* __restrict__ key, int32_t* __restrict__ cell_count) {
+  int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= N) return;
+  const StructInfo& st = structs[sid[e]];
+  int k = st.cell_off;
+  if (st.mode == kModeCells) {
+    int cx, cy, cz;
+    cell_coords(st, pos[e], pos[N + e], pos[2 * N + e], cx, cy, cz);
+    k += (cz * st.ncell[1] + cy) * st.ncell[0] + cx;
+  }
+  key[e] = k;
+  atomicAdd(&cell_count[k], 1);
+}
+
+// Exclusive scan of n int32 counts by one block of 1024 threads.
+__global__ void __launch_bounds__(1024) k_scan_1block(const int32_t* __restrict__ in,
+                                                      int32_t* __restrict__ out, int32_t n) {
+  __shared__ int32_t part[1024];
+  int t = threadIdx.x;
+  int chunk = (n + 1023) / 1024;
+  int lo = t * chunk, hi = min(n, lo + chunk);
+  int32_t s = 0;
+  for (int i = lo; i < hi; ++i) s += in[i];
+  part[t] = s;
+  __syncthreads();
+  for (int off = 1; off < 1024; off <<= 1) {
+    int32_t v = t >= off ? part[t - off] : 0;
+    __syncthreads();
+    part[t] += v;
+    __syncthreads();
+  }
+  int32_t run = part[t] - s;
+  for (int i = lo; i < hi; ++i) {
+    int32_t c = in[i];
+    out[i] = run;
+    run += c;
+  }
+}
+
+__global__ void k_cell_scatter(const int32_t* __restrict__ key, int64_t N,
+                               const int32_t* __restrict__ cell_start,
+                               int32_t* __restrict__ cell_fill, int32_t* __restrict__ perm) {
+  int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= N) return;
+  int k = key[e];
+  int slot = atomicAdd(&cell_fill[k], 1);
+  perm[cell_start[k] + slot] = (int32_t)e;
+}
+
+// Order the atoms of each cell by caller index (makes the order independent
+// of the atomic slot assignment above).
+__global__ void k_cell_sort(const int32_t* __restrict__ cell_start,
+                            const int32_t* __restrict__ cell_count, int32_t n_cells,
+                            int32_t* __restrict__ perm) {
+  int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= n_cells) return;
+  int32_t* p = perm + cell_start[c];
+  int n = cell_count[c];
+  for (int a = 1; a < n; ++a) {
+    int32_t v = p[a];
+    int b = a - 1;
+    while (b >= 0 && p[b] > v) {
+      p[b + 1] = p[b];
+      --b;
+    }
+    p[b + 1] = v;
+  }
+}
+
+__global__ void k_gather_atoms(const int32_t* __restrict__ perm, int64_t N,
+                               const double* __restrict__ pos_ext,
+                               const int32_t* __restrict__ types_ext,
+                               const int32_t* __restrict__ sid_ext, double* __restrict__ pos,
+                               int32_t* __restrict__ types, int32_t* __restrict__ sid) {
+  int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= N) return;
+  int64_t e = perm[k];
+  pos[k] = pos_ext[e];
+  pos[N + k] = pos_ext[N + e];
+  pos[2 * N + k] = pos_ext[2 * N + e];
+  types[k] = types_ext[e];
+  sid[k] = sid_ext[e];
+}
+
+// The up-to-3 stencil cells along one cell vector in increasing order.
+__device__ inline int stencil_1d(int c, int n, int periodic, int* out) {
+  if (periodic) {
+    if (n < 3) {
+      for (int v = 0; v < n; ++v) out[v] = v;
+      return n;
+    }
+    if (c == 0) {
+      out[0] = 0; out[1] = 1; out[2] = n - 1;
+    } else if (c == n - 1) {
+      out[0] = 0; out[1] = n - 2; out[2] = n - 1;
+    } else {
+      out[0] = c - 1; out[1] = c; out[2] = c + 1;
+    }
+    return 3;
+  }
+  int k = 0;
+  for (int v = c - 1; v <= c + 1; ++v)
+    if (v >= 0 && v < n) out[k++] = v;
+  return k;
+}
+
+struct RowWriter {
+  int32_t* nl;
+  uint16_t* cd;
+  int32_t cap;
+  int32_t count;
+  __device__ inline void push(int64_t N, int64_t i, int32_t j, uint16_t code) {
+    if (count < cap) {
+      nl[(int64_t)count * N + i] = j;
+      cd[(int64_t)count * N + i] = code;
+    }
+    ++count;
+  }
+};
+
+__global__ void __launch_bounds__(kBlock) k_build_rows(
+    const double* __restrict__ pos, int64_t N, const int32_t* __restrict__ sid,
+    const StructInfo* __restrict__ structs, const int32_t* __restrict__ cell_start,
+    const int32_t* __restrict__ cell_count, double rcR2, double rcA2, Lists L,
+    int32_t* __restrict__ overflow) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= N) return;
+  const StructInfo st = structs[sid[i]];
+  const double xi = pos[i], yi = pos[N + i], zi = pos[2 * N + i];
+  RowWriter R{L.nlR, L.cdR, L.MR, 0}, A{L.nlA, L.cdA, L.MA, 0};
+
+  auto consider = [&](int64_t j, int o0, int o1, int o2) {
+    double Dx, Dy, Dz;
+    {
+#pragma clang fp contract(off)
+      Dx = pos[j] - xi;
+      Dy = pos[N + j] - yi;
+      Dz = pos[2 * N + j] - zi;
+    }
+    int n0, n1, n2;
+    min_image(st, Dx, Dy, Dz, n0, n1, n2);
+    n0 += o0;
+    n1 += o1;
+    n2 += o2;
+    if (j == i && n0 == 0 && n1 == 0 && n2 == 0) return;
+    double dx, dy, dz;
+    image_disp(st, Dx, Dy, Dz, n0, n1, n2, dx, dy, dz);
+    double r2 = norm2_exact(dx, dy, dz);
+    if (r2 < rcR2) {
+      uint16_t code = make_code(o0, o1, o2);
+      R.push(N, i, (int32_t)j, code);
+      if (r2 < rcA2) A.push(N, i, (int32_t)j, code);
+    }
+  };
+
+  if (st.mode == kModeCells) {
+    int cx, cy, cz;
+    cell_coords(st, xi, yi, zi, cx, cy, cz);
+    int sx[3], sy[3], sz[3];
+    int nx = stencil_1d(cx, st.ncell[0], st.pbc[0], sx);
+    int ny = stencil_1d(cy, st.ncell[1], st.pbc[1], sy);
+    int nz = stencil_1d(cz, st.ncell[2], st.pbc[2], sz);
+    for (int a = 0; a < nz; ++a)
+      for (int b = 0; b < ny; ++b)
+        for (int c = 0; c < nx; ++c) {
+          int cell = st.cell_off + (sz[a] * st.ncell[1] + sy[b]) * st.ncell[0] + sx[c];
+          int s0 = cell_start[cell], cnt = cell_count[cell];
+          for (int k = 0; k < cnt; ++k) consider(s0 + k, 0, 0, 0);
+        }
+  } else if (st.mode == kModeAllPairs) {
+    for (int64_t j = st.start; j < st.start + st.count; ++j) consider(j, 0, 0, 0);
+  } else {
+    const int R0 = st.reach[0], R1 = st.reach[1], R2 = st.reach[2];
+    for (int64_t j = st.start; j < st.start + st.count; ++j)
+      for (int o0 = -R0; o0 <= R0; ++o0)
+        for (int o1 = -R1; o1 <= R1; ++o1)
+          for (int o2 = -R2; o2 <= R2; ++o2) consider(j, o0, o1, o2);
+  }
+  L.nnR[i] = R.count;
+  L.nnA[i] = A.count;
+  if (R.count > L.MR) atomicMax(&overflow[0], R.count);
+  if (A.count > L.MA) atomicMax(&overflow[1], A.count);
+}
+
+// rev[m][i] = position of (i, -offset) in the row of j = nl[m][i].
+__global__ void k_reverse(int64_t N, const int32_t* __restrict__ nn, const int32_t* __restrict__ nl,
+                          const uint16_t* __restrict__ cd, int32_t cap, int32_t* __restrict__ rev,
+                          int32_t* __restrict__ err) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= N) return;
+  int cnt = min(nn[i], cap);
+  for (int m = 0; m < cnt; ++m) {
+    int32_t j = nl[(int64_t)m * N + i];
+    int a, b, c;
+    split_code(cd[(int64_t)m * N + i], a, b, c);
+    uint32_t key = ((uint32_t)make_code(-a, -b, -c));
+    int lo = 0, hi = min(nn[j], cap) - 1, found = -1;
+    while (lo <= hi) {
+      int mid = (lo + hi) >> 1;
+      int32_t jj = nl[(int64_t)mid * N + j];
+      uint32_t kk = cd[(int64_t)mid * N + j];
+      if (jj == (int32_t)i && kk == key) {
+        found = mid;
+        break;
+      }
+      if (jj < (int32_t)i || (jj == (int32_t)i && kk < key)) lo = mid + 1;
+      else hi = mid - 1;
+    }
+    if (found < 0) {
+      atomicExch(err, 1);
+      found = 0;
+    }
+    rev[(int64_t)m * N + i] = found;
+  }
+}
+
+// ---- row order for the network pass: atoms grouped by species, each group
+// padded to whole 16-row tiles (padding rows hold -1) ----
+
+__global__ void k_type_count(const int32_t* __restrict__ types, int64_t N,
+                             int32_t* __restrict__ tcount) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < N) atomicAdd(&tcount[types[i]], 1);
+}
+
+__global__ void k_type_offsets(const int32_t* __restrict__ tcount, int32_t T, int32_t per_type,
+                               int32_t* __restrict__ toff, int32_t* __restrict__ tcursor) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  int32_t o = 0;
+  for (int t = 0; t < T; ++t) {
+    toff[t] = o;
+    tcursor[t] = 0;
+    int32_t c = per_type ? tcount[t] : (t == 0 ? tcount[T] : 0);
+    o += (c + 15) / 16 * 16;
+  }
+  toff[T] = o;
+}
+
+__global__ void k_type_scatter(const int32_t* __restrict__ types, int64_t N, int32_t per_type,
+                               const int32_t* __restrict__ toff, int32_t* __restrict__ tcursor,
+                               int32_t* __restrict__ rows) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= N) return;
+  int t = per_type ? types[i] : 0;
+  int slot = atomicAdd(&tcursor[t], 1);
+  rows[toff[t] + slot] = (int32_t)i;
+}
+
+// ---------------------------------------------------------------------------
+// host side
+// ---------------------------------------------------------------------------
+
+static inline dim3 grid_for(int64_t n, int b = kBlock) { return dim3((unsigned)div_up(n, b)); }
+
+void launch_fill_i32(int32_t* a, int64_t n, int32_t v, hipStream_t s) {
+  if (n > 0) hipLaunchKernelGGL(k_fill_i32, grid_for(n), dim3(kBlock), 0, s, a, n, v);
+}
+
+void launch_assign_struct(const int64_t* offs, int32_t n_struct, int64_t N, int32_t* sid,
+                          hipStream_t s) {
+  hipLaunchKernelGGL(k_assign_struct, grid_for(N), dim3(kBlock), 0, s, offs, n_struct, N, sid);
+}
+
+void launch_order_atoms(const BuildArgs& b, hipStream_t s) {
+  launch_fill_i32(b.cell_count, b.n_cells, 0, s);
+  launch_fill_i32(b.cell_fill, b.n_cells, 0, s);
+  hipLaunchKernelGGL(k_cell_key, grid_for(b.N), dim3(kBlock), 0, s, b.pos_ext, b.N, b.sid_ext,
+                     b.structs, b.key, b.cell_count);
+  hipLaunchKernelGGL(k_scan_1block, dim3(1), dim3(1024), 0, s, b.cell_count, b.cell_start,
+                     b.n_cells);
+  hipLaunchKernelGGL(k_cell_scatter, grid_for(b.N), dim3(kBlock), 0, s, b.key, b.N,
+                     b.cell_start, b.cell_fill, b.perm);
+  hipLaunchKernelGGL(k_cell_sort, grid_for(b.n_cells), dim3(kBlock), 0, s, b.cell_start,
+                     b.cell_count, b.n_cells, b.perm);
+  hipLaunchKernelGGL(k_gather_atoms, grid_for(b.N), dim3(kBlock), 0, s, b.perm, b.N, b.pos_ext,
+                     b.types_ext, b.sid_ext, b.pos, b.types, b.sid);
+}
+
+void launch_build_rows(const BuildArgs& b, const Lists& L, hipStream_t s) {
+  hipLaunchKernelGGL(k_build_rows, grid_for(b.N), dim3(kBlock), 0, s, b.pos, b.N, b.sid,
+                     b.structs, b.cell_start, b.cell_count, b.rcR2, b.rcA2, L, b.overflow);
+  hipLaunchKernelGGL(k_reverse, grid_for(b.N), dim3(kBlock), 0, s, b.N, L.nnR, L.nlR, L.cdR,
+                     L.MR, L.revR, b.overflow + 2);
+  hipLaunchKernelGGL(k_reverse, grid_for(b.N), dim3(kBlock), 0, s, b.N, L.nnA, L.nlA, L.cdA,
+                     L.MA, L.revA, b.overflow + 2);
+}
+
+void launch_type_rows(const int32_t* types, int64_t N, int32_t T, int32_t per_type,
+                      int32_t* tcount, int32_t* toff, int32_t* tcursor, int32_t* rows,
+                      int64_t rows_len, hipStream_t s) {
+  launch_fill_i32(tcount, T + 1, 0, s);
+  launch_fill_i32(rows, rows_len, -1, s);
+  if (per_type) {
+    hipLaunchKernelGGL(k_type_count, grid_for(N), dim3(kBlock), 0, s, types, N, tcount);
+  } else {
+    // a single network: every atom counts as species 0
+    hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(1), 0, s, tcount + T, (int64_t)1, (int32_t)N);
+  }
+  hipLaunchKernelGGL(k_type_offsets, dim3(1), dim3(1), 0, s, tcount, T, per_type, toff, tcursor);
+  hipLaunchKernelGGL(k_type_scatter, grid_for(N), dim3(kBlock), 0, s, types, N, per_type, toff,
+                     tcursor, rows);
+}
+
+}  // namespace nep

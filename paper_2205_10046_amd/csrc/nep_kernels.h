@@ -1,0 +1,108 @@
+// nep_kernels.h -- argument blocks and launchers of the NEP kernels.
+#pragma once
+#include "nep_internal.h"
+
+namespace nep {
+
+struct BuildArgs {
+  int64_t N;
+  int32_t n_cells;
+  const double* pos_ext;      // caller order [3][N]
+  const int32_t* types_ext;
+  const int32_t* sid_ext;
+  const StructInfo* structs;
+  int32_t* key;               // [N]
+  int32_t* cell_count;        // [n_cells]
+  int32_t* cell_fill;         // [n_cells]
+  int32_t* cell_start;        // [n_cells]
+  int32_t* perm;              // [N] internal -> caller index
+  double* pos;                // internal [3][N]
+  int32_t* types;             // internal
+  int32_t* sid;               // internal
+  double rcR2, rcA2;
+  int32_t* overflow;          // [3]: max radial row, max angular row, rev error
+};
+
+struct EvalArgs {
+  const double* pos;          // internal [3][N]
+  int64_t N;
+  const int32_t* types;
+  const int32_t* sid;
+  const StructInfo* structs;
+  Lists L;
+  DevModel M;
+  float* q;                   // [N][NDp]
+  float* fp;                  // [N][NDp]
+  float* U;                   // [N]
+  float* sums;                // [nA_pad * NB][N]
+  float* pr;                  // [3][MR][N]
+  float* pa;                  // [3][MA][N]
+  float* F;                   // [3][N] internal
+  float* W;                   // [9][N] internal
+  const int32_t* rows;        // network row order, [rows_len]
+  int64_t rows_len;
+  int32_t ngroups;            // angular radial-function groups
+  int32_t NG;                 // group size
+  int32_t mlp_bf16;
+  int32_t batch;              // several structures: geometry from structs[sid]
+  StructInfo st0;             // the geometry when batch == 0
+};
+
+// neighbor.hip
+void launch_fill_i32(int32_t* a, int64_t n, int32_t v, hipStream_t s);
+void launch_assign_struct(const int64_t* offs, int32_t n_struct, int64_t N, int32_t* sid,
+                          hipStream_t s);
+void launch_order_atoms(const BuildArgs& b, hipStream_t s);
+void launch_build_rows(const BuildArgs& b, const Lists& L, hipStream_t s);
+void launch_type_rows(const int32_t* types, int64_t N, int32_t T, int32_t per_type,
+                      int32_t* tcount, int32_t* toff, int32_t* tcursor, int32_t* rows,
+                      int64_t rows_len, hipStream_t s);
+
+// descriptor.hip / force.hip: return false if no kernel exists for (NG, L)
+bool launch_descriptor(const EvalArgs& a, hipStream_t s);
+bool launch_partial_forces(const EvalArgs& a, hipStream_t s);
+void launch_gather_forces(const EvalArgs& a, hipStream_t s);
+size_t eval_lds_bytes(const DevModel& M, int block);
+int angular_group_size(int nA, int L);
+
+// mlp.hip
+void launch_mlp(const EvalArgs& a, hipStream_t s);
+
+// output.hip
+void launch_scatter_outputs(const EvalArgs& a, const int32_t* perm, double* energy,
+                            double* force, double* virial, hipStream_t s);
+void launch_totals(const float* U, const float* W, int64_t N, double* partial, int64_t n_part,
+                   double* totals, hipStream_t s);
+void launch_descriptors_out(const float* q, int64_t N, int NDp, int ND, const int32_t* perm,
+                            double* out, hipStream_t s);
+void launch_neighbors_out(const Lists& L, int which, int64_t N, const int32_t* perm,
+                          const int32_t* inv_perm, const double* pos, const int32_t* sid,
+                          const StructInfo* structs, int32_t cap, int32_t* count, int32_t* nbr,
+                          int32_t* shift, hipStream_t s);
+void launch_inverse_perm(const int32_t* perm, int64_t N, int32_t* inv, hipStream_t s);
+
+// md.hip
+struct MDArgs {
+  int64_t N;
+  double* pos;                // internal [3][N]
+  double* vel;                // internal [3][N]
+  const float* F;             // internal [3][N]
+  const int32_t* types;
+  const double* inv_mass;     // [T] 1 / (m * amu(A/fs)^2 in eV)
+  double dt;
+};
+void launch_kick_drift(const MDArgs& a, hipStream_t s);
+void launch_kick(const MDArgs& a, hipStream_t s);
+void launch_thermo(const float* U, const float* W, const double* vel, const int32_t* types,
+                   const double* mass, int64_t N, double* partial, int64_t n_part,
+                   double* row, double step, double kin_conv, double kB, hipStream_t s);
+void launch_permute_md(const int32_t* perm_old_to_new_src, int64_t N, const double* src_pos,
+                       const double* src_vel, double* dst_pos, double* dst_vel, hipStream_t s);
+void launch_unpermute_md(const int32_t* perm, int64_t N, const double* pos_int,
+                         const double* vel_int, double* pos_ext, double* vel_ext,
+                         hipStream_t s);
+void launch_check_finite(const double* a, int64_t n, int32_t* flag, hipStream_t s);
+void launch_check_types(const int32_t* types, int64_t n, int32_t T, int32_t* flag, hipStream_t s);
+void launch_gather_i32(const int32_t* src, int64_t N, const int32_t* in, int32_t* out, hipStream_t s);
+
+}  // namespace nep

@@ -1,0 +1,258 @@
+"""Thin ctypes binding of the HIP library ``libnep_hip.so`` (include/nep.h).
+
+Argument marshalling only: every step of the computation runs in the HIP
+kernels behind the C ABI.  Host-array calls take numpy arrays; the ``*_dev``
+calls take torch tensors on the GPU (torch is used for device memory and the
+current stream only).  Loading fails loudly when the library is missing.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libnep_hip.so")
+
+NEP_OK = 0
+NEP_E_INVALID_ARG = 1
+NEP_E_BOX = 2
+NEP_E_NONFINITE = 3
+NEP_E_NEIGHBOR_OVERFLOW = 4
+NEP_E_OOM = 5
+NEP_E_HIP = 6
+NEP_E_UNSUPPORTED = 7
+NEP_E_BUDGET = 8
+NEP_PENDING = 9
+NEP_MLP_FP32 = 0
+NEP_MLP_BF16 = 1
+
+# every entry point declared in include/nep.h
+EXPORTS = ["nep_num_descriptors", "nep_num_params", "nep_create", "nep_set_params",
+           "nep_destroy", "nep_last_error", "nep_compute", "nep_compute_dev",
+           "nep_neighbors", "nep_descriptors", "nep_md_run", "nep_md_run_dev",
+           "nep_set_timing", "nep_get_timing"]
+
+
+class NepError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"NEP error {code}: {msg}")
+        self.code = code
+
+
+class nep_hparams(C.Structure):
+    _fields_ = [("n_types", C.c_int32), ("rc_radial", C.c_double),
+                ("rc_angular", C.c_double), ("n_max_radial", C.c_int32),
+                ("n_max_angular", C.c_int32), ("basis_radial", C.c_int32),
+                ("basis_angular", C.c_int32), ("l_max_3b", C.c_int32),
+                ("l_max_4b", C.c_int32), ("l_max_5b", C.c_int32),
+                ("n_neurons", C.c_int32), ("nn_per_type", C.c_int32),
+                ("mlp_precision", C.c_int32), ("max_nb_radial", C.c_int32),
+                ("max_nb_angular", C.c_int32), ("skin", C.c_double)]
+
+
+def make_hparams(h: dict, mlp_precision=NEP_MLP_FP32, max_nb_radial=0,
+                 max_nb_angular=0, skin=0.0) -> nep_hparams:
+    return nep_hparams(
+        n_types=h["n_types"], rc_radial=h["rc_radial"], rc_angular=h["rc_angular"],
+        n_max_radial=h["n_max_radial"], n_max_angular=h["n_max_angular"],
+        basis_radial=h["basis_radial"], basis_angular=h["basis_angular"],
+        l_max_3b=h["l_max_3b"], l_max_4b=h["l_max_4b"], l_max_5b=h["l_max_5b"],
+        n_neurons=h["n_neurons"], nn_per_type=h.get("nn_per_type", 0),
+        mlp_precision=h.get("mlp_precision", mlp_precision),
+        max_nb_radial=h.get("max_nb_radial", max_nb_radial),
+        max_nb_angular=h.get("max_nb_angular", max_nb_angular),
+        skin=h.get("skin", skin))
+
+
+_lib = None
+
+
+def load():
+    """Load libnep_hip.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: run __graft_entry__.build() first")
+    L = C.CDLL(LIB_PATH)
+    P = C.POINTER
+    d, i32, i64, vp = C.c_double, C.c_int32, C.c_int64, C.c_void_p
+    pd, pi32 = P(d), P(i32)
+    hp = P(nep_hparams)
+    L.nep_num_descriptors.argtypes = [hp]
+    L.nep_num_descriptors.restype = C.c_int
+    L.nep_num_params.argtypes = [hp]
+    L.nep_num_params.restype = C.c_size_t
+    L.nep_create.argtypes = [hp, pd, C.c_size_t, P(vp)]
+    L.nep_set_params.argtypes = [vp, pd, C.c_size_t]
+    L.nep_destroy.argtypes = [vp]
+    L.nep_destroy.restype = None
+    L.nep_last_error.argtypes = [vp]
+    L.nep_last_error.restype = C.c_char_p
+    L.nep_compute.argtypes = [vp, i64, pd, pi32, pd, pi32, pd, pd, pd, pd]
+    L.nep_compute_dev.argtypes = [vp, i64, vp, vp, pd, pi32, vp, vp, vp, vp, vp]
+    L.nep_neighbors.argtypes = [vp, i64, pd, pd, pi32, i32, i32, pi32, pi32, pi32]
+    L.nep_descriptors.argtypes = [vp, i64, pd, pi32, pd, pi32, pd]
+    L.nep_md_run.argtypes = [vp, i64, pd, pd, pi32, pd, pd, pi32, d, i64, i64, pd]
+    L.nep_md_run_dev.argtypes = [vp, i64, vp, vp, vp, pd, pd, pi32, d, i64, i64, vp, vp]
+    L.nep_set_timing.argtypes = [vp, i32]
+    L.nep_get_timing.argtypes = [vp, i32, P(C.c_char_p), pd, P(i64)]
+    for name in EXPORTS:
+        getattr(L, name).restype = getattr(L, name).restype or C.c_int
+    _lib = L
+    return L
+
+
+def _ptr(a, ct):
+    return None if a is None else a.ctypes.data_as(C.POINTER(ct))
+
+
+def _f64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def _i32(a):
+    return np.ascontiguousarray(a, dtype=np.int32)
+
+
+def nep_num_params(h: dict) -> int:
+    return int(load().nep_num_params(C.byref(make_hparams(h))))
+
+
+def nep_num_descriptors(h: dict) -> int:
+    return int(load().nep_num_descriptors(C.byref(make_hparams(h))))
+
+
+def last_error(handle=None) -> str:
+    m = load().nep_last_error(handle)
+    return m.decode() if m else ""
+
+
+def _torch_stream():
+    import torch
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+class Handle:
+    """One nep_handle: hyper-parameters + parameter vector on the current GPU."""
+
+    def __init__(self, h: dict, params, mlp_precision=NEP_MLP_FP32,
+                 max_nb_radial=0, max_nb_angular=0, skin=0.0):
+        L = load()
+        self.h = dict(h)
+        self._hp = make_hparams(h, mlp_precision, max_nb_radial, max_nb_angular, skin)
+        params = _f64(params)
+        out = C.c_void_p()
+        rc = L.nep_create(C.byref(self._hp), _ptr(params, C.c_double), params.shape[0],
+                          C.byref(out))
+        if rc != NEP_OK:
+            raise NepError(rc, last_error(None))
+        self._h = out
+        self.n_types = h["n_types"]
+        self.n_des = nep_num_descriptors(h)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load().nep_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, rc):
+        if rc != NEP_OK:
+            raise NepError(rc, last_error(self._h))
+
+    def set_params(self, params):
+        params = _f64(params)
+        self._check(load().nep_set_params(self._h, _ptr(params, C.c_double), params.shape[0]))
+
+    def compute(self, pos, types, box, pbc=None):
+        """nep_compute on host arrays: dict U (N,), F (3,N), W (9,N), totals (10,)."""
+        pos, types, box = _f64(pos), _i32(types), _f64(box)
+        pbc = _i32(np.ones(3) if pbc is None else pbc)
+        n = pos.shape[1]
+        U, F, W, T = np.zeros(n), np.zeros((3, n)), np.zeros((9, n)), np.zeros(10)
+        self._check(load().nep_compute(
+            self._h, n, _ptr(pos, C.c_double), _ptr(types, C.c_int32), _ptr(box, C.c_double),
+            _ptr(pbc, C.c_int32), _ptr(U, C.c_double), _ptr(F, C.c_double),
+            _ptr(W, C.c_double), _ptr(T, C.c_double)))
+        return dict(U=U, F=F, W=W, totals=T)
+
+    def compute_dev(self, pos, types, box, pbc=None, energy=None, force=None, virial=None,
+                    totals=None):
+        """nep_compute_dev on torch CUDA tensors (float64 pos (3,N), int32 types)."""
+        box, pbc = _f64(box), _i32(np.ones(3) if pbc is None else pbc)
+        n = int(pos.shape[1])
+        p = lambda t: None if t is None else C.c_void_p(t.data_ptr())  # noqa: E731
+        self._check(load().nep_compute_dev(
+            self._h, n, p(pos), p(types), _ptr(box, C.c_double), _ptr(pbc, C.c_int32),
+            p(energy), p(force), p(virial), p(totals), _torch_stream()))
+
+    def neighbors(self, pos, box, which=0, pbc=None, cap=256):
+        """Rows at the radial (0) or angular (1) cutoff: list of (j, shift (m,3))."""
+        pos, box = _f64(pos), _f64(box)
+        pbc = _i32(np.ones(3) if pbc is None else pbc)
+        n = pos.shape[1]
+        cnt = np.zeros(n, np.int32)
+        nbr = np.zeros(n * cap, np.int32)
+        sh = np.zeros(n * cap * 3, np.int32)
+        self._check(load().nep_neighbors(
+            self._h, n, _ptr(pos, C.c_double), _ptr(box, C.c_double), _ptr(pbc, C.c_int32),
+            which, cap, _ptr(cnt, C.c_int32), _ptr(nbr, C.c_int32), _ptr(sh, C.c_int32)))
+        nbr = nbr.reshape(n, cap)
+        sh = sh.reshape(n, cap, 3)
+        return [(nbr[i, :cnt[i]].copy(), sh[i, :cnt[i]].copy()) for i in range(n)]
+
+    def descriptors(self, pos, types, box, pbc=None):
+        pos, types, box = _f64(pos), _i32(types), _f64(box)
+        pbc = _i32(np.ones(3) if pbc is None else pbc)
+        n = pos.shape[1]
+        q = np.zeros((n, self.n_des))
+        self._check(load().nep_descriptors(
+            self._h, n, _ptr(pos, C.c_double), _ptr(types, C.c_int32), _ptr(box, C.c_double),
+            _ptr(pbc, C.c_int32), _ptr(q, C.c_double)))
+        return q
+
+    def md_run(self, pos, vel, types, masses, box, dt, n_steps, thermo_every, pbc=None):
+        """nep_md_run on host arrays; returns (pos, vel, thermo (rows, 13))."""
+        pos, vel = _f64(pos).copy(), _f64(vel).copy()
+        types, box, m = _i32(types), _f64(box), _f64(masses)
+        pbc = _i32(np.ones(3) if pbc is None else pbc)
+        rows = n_steps // thermo_every if thermo_every > 0 else 0
+        th = np.zeros((max(rows, 1), 13))
+        self._check(load().nep_md_run(
+            self._h, pos.shape[1], _ptr(pos, C.c_double), _ptr(vel, C.c_double),
+            _ptr(types, C.c_int32), _ptr(m, C.c_double), _ptr(box, C.c_double),
+            _ptr(pbc, C.c_int32), float(dt), int(n_steps), int(thermo_every),
+            _ptr(th, C.c_double)))
+        return pos, vel, th[:rows]
+
+    def md_run_dev(self, pos, vel, types, masses, box, dt, n_steps, thermo_every, thermo,
+                   pbc=None):
+        """nep_md_run_dev on torch CUDA tensors; thermo is a (rows, 13) float64 tensor."""
+        box, m = _f64(box), _f64(masses)
+        pbc = _i32(np.ones(3) if pbc is None else pbc)
+        p = lambda t: None if t is None else C.c_void_p(t.data_ptr())  # noqa: E731
+        self._check(load().nep_md_run_dev(
+            self._h, int(pos.shape[1]), p(pos), p(vel), p(types), _ptr(m, C.c_double),
+            _ptr(box, C.c_double), _ptr(pbc, C.c_int32), float(dt), int(n_steps),
+            int(thermo_every), p(thermo), _torch_stream()))
+
+    def set_timing(self, enable=True):
+        self._check(load().nep_set_timing(self._h, 1 if enable else 0))
+
+    def timing(self):
+        """{stage: (total ms, launches)} of the calls since set_timing(True)."""
+        n = 32
+        names = (C.c_char_p * n)()
+        ms = np.zeros(n)
+        calls = np.zeros(n, np.int64)
+        k = load().nep_get_timing(self._h, n, names, _ptr(ms, C.c_double),
+                                  _ptr(calls, C.c_int64))
+        return {names[i].decode(): (float(ms[i]), int(calls[i])) for i in range(k)}
