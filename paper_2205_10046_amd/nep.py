@@ -76,6 +76,13 @@ def load():
         return _lib
     if not os.path.exists(LIB_PATH):
         raise RuntimeError(f"{LIB_PATH} is missing: run __graft_entry__.build() first")
+    # torch bundles its own HIP runtime under the same soname; loading it first
+    # makes the library bind to that one, so the process holds a single HIP/HSA
+    # runtime shared with the torch tensors and streams passed to *_dev calls.
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     L = C.CDLL(LIB_PATH)
     P = C.POINTER
     d, i32, i64, vp = C.c_double, C.c_int32, C.c_int64, C.c_void_p
