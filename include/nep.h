@@ -158,6 +158,87 @@ int nep_md_run_dev(nep_handle *h, int64_t n_atoms, double *pos, double *vel,
                    int64_t n_steps, int64_t thermo_every, double *thermo,
                    void *stream);
 
+/* Energies, forces and virials of n_struct structures for n_param_sets
+ * parameter vectors in one call: the population evaluation of the SNES
+ * trainer (Sec. II.E) on a training-style batch.  Structure s holds atoms
+ * [offsets[s], offsets[s+1]) of pos/types (device, [3][N] and [N],
+ * N = offsets[n_struct]); offsets (int64[n_struct+1]), boxes ([n_struct][9])
+ * and pbc ([n_struct][3], NULL = all periodic) are host arrays.  params is a
+ * host array [n_param_sets][nep_num_params] (NULL: the handle's own vector,
+ * n_param_sets must then be 1).  Outputs, device, each may be NULL:
+ * energy [P][N], force [P][3][N], virial [P][9][N], totals [P][n_struct][10].
+ * Neighbour rows are built once for all sets; the per-set passes run as one
+ * captured HIP graph.  Synchronous.  Each structure's results equal those of
+ * the same structure in a batch of one (bitwise). */
+int nep_compute_batch(nep_handle *h, int32_t n_struct, const int64_t *offsets,
+                      const double *pos, const int32_t *types, const double *boxes,
+                      const int32_t *pbc, int32_t n_param_sets, const double *params,
+                      double *energy, double *force, double *virial, double *totals,
+                      void *stream);
+
+/* ---- serving: continuous batching ----
+ * A server owns a handle and a worker thread.  Requests (single energy/force/
+ * virial evaluations, or short NVE runs) are copied at submission and queued;
+ * at every tick the worker admits queued requests while slots are free and
+ * their device-memory estimate fits the budget, then advances every active
+ * request by one batched evaluation (and one velocity-Verlet step for MD
+ * requests past their initial evaluation) over the concatenated structures.
+ * Finished requests leave the batch at the end of the tick; requests that
+ * arrive meanwhile join at the next tick.  Per-request results do not depend
+ * on the other requests in the batch (bitwise).  While a server exists, the
+ * handle must not be used directly. */
+#define NEP_REQ_EVAL 0
+#define NEP_REQ_MD 1
+
+typedef struct nep_server nep_server;
+
+typedef struct nep_request {
+  int32_t kind;                 /* NEP_REQ_EVAL or NEP_REQ_MD */
+  int64_t n_atoms;
+  const double *pos;            /* host [3][N], copied */
+  const double *vel;            /* host [3][N] (MD), copied */
+  const int32_t *types;         /* host [N], copied */
+  double box[9];
+  int32_t pbc[3];
+  int64_t n_steps;              /* MD: velocity-Verlet steps */
+  double dt_fs;                 /* MD */
+  const double *mass_per_type;  /* MD: amu [n_types], copied */
+} nep_request;
+
+typedef struct nep_result {
+  int32_t status;               /* NEP_OK or the request's error */
+  int64_t n_atoms;
+  double *energy;               /* caller buffers ([N], [3][N], [9][N], [3][N], [3][N]) or NULL; */
+  double *force;                /* for MD requests: values after the last step */
+  double *virial;
+  double *pos;
+  double *vel;
+  double totals[10];            /* E, W_xx .. W_zz of the structure */
+  double latency_ms;            /* completion - submission */
+  double queue_ms;              /* admission - submission */
+} nep_result;
+
+typedef struct nep_server_stats_t {
+  int64_t submitted, completed, active, queued, ticks;
+  double p50_ms, p99_ms, mean_ms, max_ms;   /* request latency */
+  double wall_s, busy_s;                    /* first submission to last completion; time in ticks */
+  double requests_per_s, atom_steps_per_s;  /* over wall_s */
+  double mean_batch_atoms, mean_batch_requests;
+  size_t bytes_in_use, hbm_budget;
+} nep_server_stats_t;
+
+int nep_server_create(nep_handle *h, size_t hbm_budget_bytes, int32_t max_slots,
+                      nep_server **out);
+/* Non-blocking; fails with NEP_E_BUDGET if the request alone exceeds the budget. */
+int nep_server_submit(nep_server *s, const nep_request *req, uint64_t *ticket);
+/* NEP_PENDING until the request is done; wait_ms: 0 = do not wait, < 0 = wait
+ * until done.  A result is returned once and then forgotten. */
+int nep_server_poll(nep_server *s, uint64_t ticket, int32_t wait_ms, nep_result *out);
+int nep_server_stats(nep_server *s, nep_server_stats_t *out);
+int nep_server_reset_stats(nep_server *s);
+/* Finishes every queued and active request, then stops the worker. */
+void nep_server_destroy(nep_server *s);
+
 /* Per-stage timing of the last nep_compute / nep_md_run call, filled when
  * timing was enabled with nep_set_timing(h, 1).  names[i] are static
  * strings; ms[i] is the summed time of that stage, calls[i] its launch

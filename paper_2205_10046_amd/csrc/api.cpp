@@ -10,6 +10,13 @@
 
 #include <algorithm>
 #include <array>
+#include <chrono>
+#include <condition_variable>
+#include <deque>
+#include <memory>
+#include <mutex>
+#include <thread>
+#include <unordered_map>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -246,6 +253,23 @@ struct StageTimes {
   }
 };
 
+// Device tables of one parameter vector (float32 / bf16 copies).
+struct ModelTables {
+  DevModel M{};
+  float *cR = nullptr, *cA = nullptr, *w0 = nullptr, *w0t = nullptr, *b0 = nullptr, *w1 = nullptr;
+  uint16_t *w0b = nullptr, *w0tb = nullptr;
+  void release() {
+    dev_free(cR); dev_free(cA); dev_free(w0); dev_free(w0t); dev_free(b0); dev_free(w1);
+    dev_free(w0b); dev_free(w0tb);
+  }
+};
+
+// Kernel shape picked for one problem shape (see autotune()).
+struct Tuning {
+  bool done = false;
+  int NG_desc = 0, NG_force = 0, block_desc = 256, block_force = 256;
+};
+
 }  // namespace
 
 struct nep_handle {
@@ -253,11 +277,13 @@ struct nep_handle {
   int device = 0;
   std::string err;
   int nd = 0, nets = 1;
-  int NG_desc = 0, ng_desc = 0, NG_force = 0, ng_force = 0;
-  DevModel M{};
-  // model tables
-  float *cR = nullptr, *cA = nullptr, *w0 = nullptr, *w0t = nullptr, *b0 = nullptr, *w1 = nullptr;
-  uint16_t *w0b = nullptr, *w0tb = nullptr;
+  int nA_pad = 0;
+  Tuning tune[2];                   // [single structure, batch]
+  ModelTables main;                 // the handle's own parameter vector
+  std::vector<ModelTables> pop;     // parameter sets of the last batch call
+  int64_t* offs = nullptr;          // structure offsets of a batch (device)
+  int32_t cap_struct = 0;
+  DevModel& M = main.M;
   // workspace
   int64_t capN = 0, cap_part = 0, rows_cap = 0;
   int32_t MR = 0, MA = 0, cap_cells = 0;
@@ -288,8 +314,9 @@ struct nep_handle {
   void release() {
     if (pinned) (void)hipHostFree(pinned);
     pinned = nullptr;
-    dev_free(cR); dev_free(cA); dev_free(w0); dev_free(w0t); dev_free(b0); dev_free(w1);
-    dev_free(w0b); dev_free(w0tb);
+    main.release();
+    for (auto& t : pop) t.release();
+    pop.clear();
     free_workspace();
     for (auto& p : pending) {
       (void)hipEventDestroy(p.second.first);
@@ -306,7 +333,8 @@ struct nep_handle {
     dev_free(key); dev_free(perm); dev_free(ext_id); dev_free(ext_id2); dev_free(inv);
     dev_free(cell_count); dev_free(cell_fill); dev_free(cell_start);
     dev_free(rows); dev_free(tcount); dev_free(toff); dev_free(tcursor); dev_free(flags);
-    dev_free(structs);
+    dev_free(structs); dev_free(offs);
+    cap_struct = 0;
     free_lists();
     dev_free(q); dev_free(fp); dev_free(U); dev_free(sums); dev_free(F); dev_free(W);
     dev_free(F_save); dev_free(pos_save); dev_free(vel_save); dev_free(types_save);
@@ -366,14 +394,14 @@ struct Stage {
   ~Stage() { h->stage_end(name, s, a); }
 };
 
-void upload_model(nep_handle* h, const double* p) {
+void upload_model(nep_handle* h, const double* p, ModelTables& mt) {
   const nep_hparams& hp = h->hp;
   const int T = hp.n_types, nd = h->nd, NN = hp.n_neurons, nets = h->nets;
   const int nR = hp.n_max_radial + 1, KR = hp.basis_radial + 1;
   const int nA = hp.n_max_angular + 1, KA = hp.basis_angular + 1;
   const int NNp = (NN + 31) / 32 * 32;
   const int NDp32 = (nd + 31) / 32 * 32;
-  const int nA_pad = std::max(h->NG_desc * h->ng_desc, h->NG_force * h->ng_force);
+  const int nA_pad = h->nA_pad;
   for (size_t k = 0; k < n_params(hp); ++k)
     if (!std::isfinite(p[k])) throw Failure{NEP_E_INVALID_ARG, "parameter vector has a non-finite entry"};
   std::vector<float> w0((size_t)nets * NNp * nd, 0.f), w0t((size_t)nets * nd * NNp, 0.f);
@@ -411,17 +439,17 @@ void upload_model(nep_handle* h, const double* p) {
     dev_alloc(dst, v.size());
     HIPCHK(hipMemcpy(dst, v.data(), v.size() * sizeof(E), hipMemcpyHostToDevice));
   };
-  put(h->w0, w0); put(h->w0t, w0t); put(h->b0, b0); put(h->w1, w1);
-  put(h->w0b, w0b); put(h->w0tb, w0tb); put(h->cR, cR); put(h->cA, cA);
+  put(mt.w0, w0); put(mt.w0t, w0t); put(mt.b0, b0); put(mt.w1, w1);
+  put(mt.w0b, w0b); put(mt.w0tb, w0tb); put(mt.cR, cR); put(mt.cA, cA);
 
-  DevModel& M = h->M;
+  DevModel& M = mt.M;
   M.T = T; M.nR = nR; M.KR = KR; M.nA = nA; M.KA = KA; M.L = hp.l_max_3b;
   M.NB = (hp.l_max_3b + 1) * (hp.l_max_3b + 1) - 1;
   M.ND = nd; M.NDp = (nd + 7) / 8 * 8; M.NN = NN; M.nets = nets;
   M.has4b = hp.l_max_4b >= 2; M.has5b = hp.l_max_5b >= 1; M.nA_pad = nA_pad;
   M.rcR = (float)hp.rc_radial; M.rcA = (float)hp.rc_angular; M.b1 = b1;
-  M.cR = h->cR; M.cA = h->cA; M.NNp = NNp; M.NDp32 = NDp32;
-  M.w0 = h->w0; M.w0t = h->w0t; M.b0 = h->b0; M.w1 = h->w1; M.w0b = h->w0b; M.w0tb = h->w0tb;
+  M.cR = mt.cR; M.cA = mt.cA; M.NNp = NNp; M.NDp32 = NDp32;
+  M.w0 = mt.w0; M.w0t = mt.w0t; M.b0 = mt.b0; M.w1 = mt.w1; M.w0b = mt.w0b; M.w0tb = mt.w0tb;
   double C3[kMaxNB] = {0}, C4[5], C5[3];
   angular_constants(hp.l_max_3b, C3, C4, C5);
   for (int k = 0; k < kMaxNB; ++k) M.C3[k] = (float)C3[k];
@@ -498,15 +526,18 @@ void ensure_atoms(nep_handle* h, int64_t N, int32_t n_cells, bool md) {
 }
 
 struct Prepared {
-  Geometry geo;
-  int64_t N;
+  std::vector<StructInfo> sts;   // one per structure; start/count in internal order
+  Geometry geo;                  // of structure 0 (the single-structure kernels)
+  int32_t n_cells = 0;
+  int64_t N = 0;
+  bool batch = false;
 };
 
 BuildArgs build_args(nep_handle* h, const Prepared& pp, const double* pos_src, const int32_t* types_src,
                      double* pos_dst, int32_t* types_dst) {
   BuildArgs b{};
   b.N = pp.N;
-  b.n_cells = pp.geo.n_cells;
+  b.n_cells = pp.n_cells;
   b.pos_ext = pos_src;
   b.types_ext = types_src;
   b.sid_ext = h->sid_ext;
@@ -525,7 +556,7 @@ BuildArgs build_args(nep_handle* h, const Prepared& pp, const double* pos_src, c
   return b;
 }
 
-EvalArgs eval_args(nep_handle* h, const Prepared& pp) {
+EvalArgs eval_args(nep_handle* h, const Prepared& pp, const DevModel& M) {
   EvalArgs a{};
   a.pos = h->pos;
   a.N = pp.N;
@@ -533,7 +564,7 @@ EvalArgs eval_args(nep_handle* h, const Prepared& pp) {
   a.sid = h->sid;
   a.structs = h->structs;
   a.L = h->L;
-  a.M = h->M;
+  a.M = M;
   a.q = h->q;
   a.fp = h->fp;
   a.U = h->U;
@@ -543,32 +574,71 @@ EvalArgs eval_args(nep_handle* h, const Prepared& pp) {
   a.F = h->F;
   a.W = h->W;
   a.rows = h->rows;
-  a.rows_len = rows_length(pp.N, h->M.T);
+  a.rows_len = rows_length(pp.N, M.T);
   a.mlp_bf16 = h->hp.mlp_precision == NEP_MLP_BF16;
-  a.batch = 0;
+  a.batch = pp.batch ? 1 : 0;
   a.st0 = pp.geo.st;
   return a;
 }
 
-// Geometry, buffers and the structure table for one structure of N atoms.
-Prepared prepare(nep_handle* h, int64_t N, const double* box, const int32_t* pbc, double r_list,
-                 bool md, hipStream_t s) {
+// Geometry, buffers and the structure table for structures s = 0..S-1 holding
+// atoms [offs[s], offs[s+1]) (S = 1: one structure of N atoms).
+Prepared prepare_batch(nep_handle* h, int32_t S, const int64_t* offs, const double* boxes,
+                       const int32_t* pbcs, double r_list, bool md, bool force_batch, hipStream_t s) {
+  if (S < 1) throw Failure{NEP_E_INVALID_ARG, "n_struct must be >= 1"};
+  const int64_t N = offs ? offs[S] : 0;
   if (N < 1 || N > (int64_t)1 << 30) throw Failure{NEP_E_INVALID_ARG, "n_atoms must be in [1, 2^30]"};
   Prepared pp;
   pp.N = N;
-  pp.geo = make_geometry(box, pbc, N, r_list);
-  ensure_atoms(h, N, pp.geo.n_cells, md);
-  const double density = (double)N / pp.geo.volume;
-  int32_t MR = h->hp.max_nb_radial ? h->hp.max_nb_radial : estimate_capacity(h->hp.rc_radial, density);
-  int32_t MA = h->hp.max_nb_angular ? h->hp.max_nb_angular : estimate_capacity(h->hp.rc_angular, density);
+  pp.sts.resize(S);
+  double max_density = 0;
+  int32_t cells = 0;
+  for (int32_t k = 0; k < S; ++k) {
+    const int64_t n = offs[k + 1] - offs[k];
+    if (n < 1) throw Failure{NEP_E_INVALID_ARG, "every structure needs at least one atom"};
+    Geometry g = make_geometry(boxes + 9 * k, pbcs ? pbcs + 3 * k : nullptr, n, r_list);
+    g.st.start = offs[k];
+    g.st.count = n;
+    g.st.cell_off = cells;
+    if ((int64_t)cells + g.n_cells > (1 << 30)) throw Failure{NEP_E_INVALID_ARG, "too many cells"};
+    cells += g.n_cells;
+    max_density = std::max(max_density, (double)n / g.volume);
+    pp.sts[k] = g.st;
+    if (k == 0) pp.geo = g;
+  }
+  pp.n_cells = cells;
+  pp.batch = force_batch || S > 1;
+  ensure_atoms(h, N, cells, md);
+  int32_t MR = h->hp.max_nb_radial ? h->hp.max_nb_radial : estimate_capacity(h->hp.rc_radial, max_density);
+  int32_t MA = h->hp.max_nb_angular ? h->hp.max_nb_angular : estimate_capacity(h->hp.rc_angular, max_density);
   MR = std::max(MR, h->MR);
   MA = std::max(MA, h->MA);
   ensure_lists(h, N, MR, MA);
-  static_assert(sizeof(StructInfo) <= 256, "staging slot");
-  std::memcpy(h->pinned, &pp.geo.st, sizeof(StructInfo));
-  HIPCHK(hipMemcpyAsync(h->structs, h->pinned, sizeof(StructInfo), hipMemcpyHostToDevice, s));
-  launch_fill_i32(h->sid_ext, N, 0, s);
+  if (S > h->cap_struct) {
+    dev_alloc(h->structs, S);
+    dev_alloc(h->offs, S + 1);
+    h->cap_struct = S;
+  }
+  if (S == 1) {
+    static_assert(sizeof(StructInfo) <= 256, "staging slot");
+    std::memcpy(h->pinned, &pp.sts[0], sizeof(StructInfo));
+    HIPCHK(hipMemcpyAsync(h->structs, h->pinned, sizeof(StructInfo), hipMemcpyHostToDevice, s));
+    launch_fill_i32(h->sid_ext, N, 0, s);
+  } else {
+    // larger tables go through a synchronous copy (the call synchronises later anyway)
+    HIPCHK(hipStreamSynchronize(s));
+    HIPCHK(hipMemcpy(h->structs, pp.sts.data(), S * sizeof(StructInfo), hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(h->offs, offs, (S + 1) * sizeof(int64_t), hipMemcpyHostToDevice));
+    launch_assign_struct(h->offs, S, N, h->sid_ext, s);
+  }
   return pp;
+}
+
+Prepared prepare(nep_handle* h, int64_t N, const double* box, const int32_t* pbc, double r_list,
+                 bool md, hipStream_t s) {
+  if (N < 1 || N > (int64_t)1 << 30) throw Failure{NEP_E_INVALID_ARG, "n_atoms must be in [1, 2^30]"};
+  const int64_t offs[2] = {0, N};
+  return prepare_batch(h, 1, offs, box, pbc, r_list, md, false, s);
 }
 
 // Rows for the current internal positions; grows the capacities (auto mode)
@@ -620,10 +690,85 @@ void order_and_build(nep_handle* h, const Prepared& pp, const double* pos_src, c
   build_rows_checked(h, pp, b, s, check);
 }
 
-void forces(nep_handle* h, const Prepared& pp, hipStream_t s) {
-  EvalArgs a = eval_args(h, pp);
-  a.NG = h->NG_desc;
-  a.ngroups = h->ng_desc;
+void set_groups(EvalArgs& a, int NG, int block, int nA) {
+  a.NG = NG;
+  a.ngroups = (nA + NG - 1) / NG;
+  a.block = block;
+}
+
+bool autotune_enabled() {
+  const char* e = std::getenv("NEP_AUTOTUNE");
+  return !(e && e[0] == '0');
+}
+
+// Project autotuner: on the first evaluation of a shape, time every admissible
+// (angular group size, block size) of the descriptor and partial-force kernels
+// on the actual rows (one warm-up and two timed launches each, HIP events on
+// the work stream) and keep the fastest.  The choice is fixed per handle
+// afterwards, so repeated calls stay bitwise reproducible.
+void autotune(nep_handle* h, const Prepared& pp, hipStream_t s) {
+  Tuning& t = h->tune[pp.batch ? 1 : 0];
+  if (t.done) return;
+  const int nA = h->M.nA, L = h->M.L;
+  t.NG_desc = t.NG_force = angular_group_size(nA, L);
+  t.block_desc = t.block_force = kBlock;
+  t.done = true;
+  if (!autotune_enabled()) return;
+  EvalArgs a = eval_args(h, pp, h->M);
+  hipEvent_t e0, e1;
+  HIPCHK(hipEventCreate(&e0));
+  HIPCHK(hipEventCreate(&e1));
+  auto time_it = [&](bool force, int ng, int block) {
+    set_groups(a, ng, block, nA);
+    float best = 1e30f;
+    for (int rep = 0; rep < 3; ++rep) {
+      HIPCHK(hipEventRecord(e0, s));
+      bool ok = force ? launch_partial_forces(a, s) : launch_descriptor(a, s);
+      HIPCHK(hipEventRecord(e1, s));
+      HIPCHK(hipEventSynchronize(e1));
+      if (!ok) return 1e30f;
+      float ms = 0;
+      HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+      if (rep > 0) best = std::min(best, ms);
+    }
+    return best;
+  };
+  const int blocks[] = {128, 256};
+  float best = 1e30f;
+  for (int ng : angular_group_options(nA, L))
+    for (int bl : blocks) {
+      if (eval_lds_bytes(h->M, bl) > 64 * 1024) continue;
+      float ms = time_it(false, ng, bl);
+      if (ms < best) {
+        best = ms;
+        t.NG_desc = ng;
+        t.block_desc = bl;
+      }
+    }
+  // the partial-force kernel reads dU/dq: run the chosen descriptor pass and the network once
+  set_groups(a, t.NG_desc, t.block_desc, nA);
+  launch_descriptor(a, s);
+  launch_mlp(a, s);
+  best = 1e30f;
+  for (int ng : angular_group_options(nA, L))
+    for (int bl : blocks) {
+      if (eval_lds_bytes(h->M, bl) > 64 * 1024) continue;
+      float ms = time_it(true, ng, bl);
+      if (ms < best) {
+        best = ms;
+        t.NG_force = ng;
+        t.block_force = bl;
+      }
+    }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+}
+
+void forces(nep_handle* h, const Prepared& pp, hipStream_t s, const DevModel* model = nullptr) {
+  autotune(h, pp, s);
+  const Tuning& t = h->tune[pp.batch ? 1 : 0];
+  EvalArgs a = eval_args(h, pp, model ? *model : h->M);
+  set_groups(a, t.NG_desc, t.block_desc, h->M.nA);
   {
     Stage st(h, "descriptor", s);
     if (!launch_descriptor(a, s)) throw Failure{NEP_E_UNSUPPORTED, "no descriptor kernel for this shape"};
@@ -632,8 +777,7 @@ void forces(nep_handle* h, const Prepared& pp, hipStream_t s) {
     Stage st(h, "mlp", s);
     launch_mlp(a, s);
   }
-  a.NG = h->NG_force;
-  a.ngroups = h->ng_force;
+  set_groups(a, t.NG_force, t.block_force, h->M.nA);
   {
     Stage st(h, "partial_forces", s);
     if (!launch_partial_forces(a, s)) throw Failure{NEP_E_UNSUPPORTED, "no force kernel for this shape"};
@@ -673,13 +817,374 @@ int compute_impl(nep_handle* h, int64_t N, const double* d_pos, const int32_t* d
   Prepared pp = prepare(h, N, box, pbc, h->hp.rc_radial, false, s);
   order_and_build(h, pp, d_pos, d_types, s, true);
   forces(h, pp, s);
-  EvalArgs a = eval_args(h, pp);
+  EvalArgs a = eval_args(h, pp, h->M);
   {
     Stage st(h, "outputs", s);
     launch_scatter_outputs(a, h->perm, d_energy, d_force, d_virial, s);
     if (d_totals) launch_totals(h->U, h->W, N, h->partial, num_partials(N), d_totals, s);
   }
   return NEP_OK;
+}
+
+// Batch of structures x parameter sets (device pointers).  Rows are built once
+// and shared by every parameter set; the per-set passes are captured once
+// into a HIP graph and launched as one graph.
+int batch_impl(nep_handle* h, int32_t S, const int64_t* offs, const double* d_pos, const int32_t* d_types,
+               const double* boxes, const int32_t* pbcs, int32_t P, const double* params, double* d_energy,
+               double* d_force, double* d_virial, double* d_totals, hipStream_t s) {
+  if (!offs || !boxes) throw Failure{NEP_E_INVALID_ARG, "offsets and boxes are required"};
+  if (P < 1) throw Failure{NEP_E_INVALID_ARG, "n_param_sets must be >= 1"};
+  Prepared pp = prepare_batch(h, S, offs, boxes, pbcs, h->hp.rc_radial, false, true, s);
+  const int64_t N = pp.N;
+  std::vector<const DevModel*> models;
+  if (params) {
+    if ((int32_t)h->pop.size() < P) h->pop.resize(P);
+    for (int32_t p = 0; p < P; ++p) {
+      upload_model(h, params + (size_t)p * n_params(h->hp), h->pop[p]);
+      models.push_back(&h->pop[p].M);
+    }
+  } else {
+    if (P != 1) throw Failure{NEP_E_INVALID_ARG, "params is NULL: use n_param_sets = 1"};
+    models.push_back(&h->M);
+  }
+  order_and_build(h, pp, d_pos, d_types, s, true);
+  autotune(h, pp, s);
+  // capture the per-set passes (descriptor, network, forces, gather, outputs)
+  const bool timing = h->timing;
+  hipStream_t cs = s;
+  hipStream_t own = nullptr;
+  if (!cs) {  // the legacy null stream cannot be captured: use a private stream
+    HIPCHK(hipStreamCreateWithFlags(&own, hipStreamNonBlocking));
+    HIPCHK(hipStreamSynchronize(s));
+    cs = own;
+  }
+  h->timing = false;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  try {
+    HIPCHK(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+    for (int32_t p = 0; p < P; ++p) {
+      forces(h, pp, cs, models[p]);
+      EvalArgs a = eval_args(h, pp, *models[p]);
+      launch_scatter_outputs(a, h->perm, d_energy ? d_energy + (size_t)p * N : nullptr,
+                             d_force ? d_force + (size_t)p * 3 * N : nullptr,
+                             d_virial ? d_virial + (size_t)p * 9 * N : nullptr, cs);
+      if (d_totals) launch_struct_totals(h->U, h->W, N, h->structs, S, d_totals + (size_t)p * S * 10, cs);
+    }
+    HIPCHK(hipStreamEndCapture(cs, &graph));
+    HIPCHK(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
+  } catch (...) {
+    hipGraph_t g2 = nullptr;
+    (void)hipStreamEndCapture(cs, &g2);
+    if (g2) (void)hipGraphDestroy(g2);
+    if (graph) (void)hipGraphDestroy(graph);
+    if (own) (void)hipStreamDestroy(own);
+    h->timing = timing;
+    throw;
+  }
+  h->timing = timing;
+  {
+    Stage st(h, "batch_graph", cs);
+    HIPCHK(hipGraphLaunch(exec, cs));
+  }
+  HIPCHK(hipStreamSynchronize(cs));
+  (void)hipGraphExecDestroy(exec);
+  (void)hipGraphDestroy(graph);
+  if (own) (void)hipStreamDestroy(own);
+  return NEP_OK;
+}
+
+
+// ===========================================================================
+// serving: continuous batching of evaluation and short-MD requests
+// ===========================================================================
+
+double now_s() {
+  using namespace std::chrono;
+  return duration<double>(steady_clock::now().time_since_epoch()).count();
+}
+
+struct ServerReq {
+  uint64_t ticket = 0;
+  int32_t kind = NEP_REQ_EVAL;
+  int64_t n = 0;
+  std::vector<double> pos, vel, mass;
+  std::vector<int32_t> types;
+  double box[9];
+  int32_t pbc[3];
+  int64_t n_steps = 0;
+  double dt = 1.0;
+  size_t bytes = 0;
+  double t_submit = 0, t_admit = 0, t_done = 0;
+  int64_t steps_done = -1;  // -1: initial forces not yet evaluated
+  int64_t off = 0;          // offset in the batch state while active
+  int32_t status = NEP_OK;
+  std::string error;
+  std::vector<double> energy, force, virial, out_pos, out_vel;
+  double totals[10] = {0};
+};
+
+// Device state of the active requests, concatenated in admission order.
+struct BatchState {
+  int64_t cap = 0;
+  int64_t ld = 0;  // current atom count: arrays are [3][ld], [9][ld]
+  double *pos = nullptr, *vel = nullptr, *F = nullptr, *E = nullptr, *W = nullptr;
+  double *hdm = nullptr, *dta = nullptr, *totals = nullptr, *inv_mass = nullptr;
+  int32_t* types = nullptr;
+  uint8_t* move = nullptr;
+  int32_t cap_req = 0;
+  void ensure(int64_t n, int32_t nreq) {
+    if (n > cap) {
+      release_atoms();
+      cap = std::max<int64_t>(n, 1024);
+      dev_alloc(pos, 3 * cap); dev_alloc(vel, 3 * cap); dev_alloc(F, 3 * cap); dev_alloc(E, cap);
+      dev_alloc(W, 9 * cap); dev_alloc(hdm, cap); dev_alloc(dta, cap); dev_alloc(types, cap);
+      dev_alloc(move, cap);
+    }
+    if (nreq > cap_req) {
+      dev_free(totals); dev_free(inv_mass);
+      cap_req = std::max(nreq, 16);
+      dev_alloc(totals, 10 * (size_t)cap_req);
+      dev_alloc(inv_mass, (size_t)kMaxTypes * cap_req);
+    }
+  }
+  void release_atoms() {
+    dev_free(pos); dev_free(vel); dev_free(F); dev_free(E); dev_free(W); dev_free(hdm); dev_free(dta);
+    dev_free(types); dev_free(move);
+    cap = 0;
+  }
+  void release() {
+    release_atoms();
+    dev_free(totals); dev_free(inv_mass);
+    cap_req = 0;
+  }
+};
+
+}  // namespace
+
+struct nep_server {
+  nep_handle* h = nullptr;
+  size_t budget = 0;
+  int32_t max_slots = 0;
+  std::thread worker;
+  std::mutex mu;
+  std::condition_variable cv, done_cv;
+  bool stop = false;
+  std::deque<std::shared_ptr<ServerReq>> queue;
+  std::vector<std::shared_ptr<ServerReq>> active;
+  std::unordered_map<uint64_t, std::shared_ptr<ServerReq>> done;
+  uint64_t next_ticket = 1;
+  hipStream_t stream = nullptr;
+  BatchState st, st2;
+  size_t bytes_active = 0;
+  // statistics
+  std::vector<double> latencies;
+  int64_t submitted = 0, completed = 0, ticks = 0, atom_steps = 0, batch_atoms = 0, batch_reqs = 0;
+  double t_first = -1, t_last = 0, busy = 0;
+  std::string fatal;
+};
+
+namespace {
+
+// Bytes one request of n atoms needs on the device while active: its share of
+// the handle's workspace (rows at the density of its box, descriptor and
+// partial-force buffers) plus its state in the batch.
+size_t request_bytes(const nep_handle* h, int64_t n, double density) {
+  const double rc = h->hp.rc_radial, ra = h->hp.rc_angular;
+  const size_t MR = estimate_capacity(rc, density), MA = estimate_capacity(ra, density);
+  const DevModel& M = h->M;
+  const size_t per_atom = (MR + MA) * (4 + 2 + 4 + 12) + 8 + (size_t)M.NDp * 8 +
+                          (size_t)M.nA * M.NB * 4 + 48 + 40 + 64 + 24 * 2 + 24 + 8 + 72 + 16 + 8 + 1;
+  return per_atom * (size_t)n + 4096;
+}
+
+// One tick: every active request advances by one evaluation (and, for MD
+// requests past their initial evaluation, one velocity-Verlet step).
+void server_tick(nep_server* sv) {
+  nep_handle* h = sv->h;
+  hipStream_t s = sv->stream;
+  auto& act = sv->active;
+  const int32_t S = (int32_t)act.size();
+  int64_t N = 0;
+  for (auto& r : act) N += r->n;
+  BatchState& st = sv->st;
+  // layout: keep the order of admission; re-pack when the set changed
+  bool repack = false;
+  {
+    int64_t o = 0;
+    for (auto& r : act) {
+      if (r->off != o || r->t_admit == 0) repack = true;
+      o += r->n;
+    }
+  }
+  if (st.ld != N) repack = true;
+  if (repack) {
+    BatchState& nx = sv->st2;
+    nx.ensure(N, S);
+    nx.ld = N;
+    int64_t o = 0;
+    int k = 0;
+    for (auto& r : act) {
+      const size_t n = r->n;
+      if (r->t_admit == 0) {  // newly admitted: upload its state
+        HIPCHK(hipMemcpyAsync(nx.types + o, r->types.data(), n * sizeof(int32_t), hipMemcpyHostToDevice, s));
+        for (int c = 0; c < 3; ++c) {
+          HIPCHK(hipMemcpyAsync(nx.pos + c * N + o, r->pos.data() + c * n, n * sizeof(double),
+                                hipMemcpyHostToDevice, s));
+          if (r->kind == NEP_REQ_MD)
+            HIPCHK(hipMemcpyAsync(nx.vel + c * N + o, r->vel.data() + c * n, n * sizeof(double),
+                                  hipMemcpyHostToDevice, s));
+        }
+        double im[kMaxTypes] = {0};
+        if (r->kind == NEP_REQ_MD)
+          for (int t = 0; t < h->hp.n_types; ++t) im[t] = 1.0 / (r->mass[t] * kAmuA2fs2);
+        HIPCHK(hipMemcpy(nx.inv_mass + (size_t)kMaxTypes * k, im, sizeof im, hipMemcpyHostToDevice));
+        launch_srv_factors(n, nx.types + o, nx.inv_mass + (size_t)kMaxTypes * k, 0.5 * r->dt, r->dt, nx.hdm + o,
+                           nx.dta + o, s);
+        launch_fill_u8(nx.move + o, n, 0, s);
+        r->t_admit = now_s();
+      } else {  // carried over: copy its device state to the new offset
+        const int64_t src = r->off;
+        HIPCHK(hipMemcpyAsync(nx.types + o, st.types + src, n * sizeof(int32_t), hipMemcpyDeviceToDevice, s));
+        HIPCHK(hipMemcpyAsync(nx.hdm + o, st.hdm + src, n * sizeof(double), hipMemcpyDeviceToDevice, s));
+        HIPCHK(hipMemcpyAsync(nx.dta + o, st.dta + src, n * sizeof(double), hipMemcpyDeviceToDevice, s));
+        HIPCHK(hipMemcpyAsync(nx.move + o, st.move + src, n, hipMemcpyDeviceToDevice, s));
+        for (int c = 0; c < 3; ++c) {
+          HIPCHK(hipMemcpyAsync(nx.pos + c * N + o, st.pos + c * st.ld + src, n * sizeof(double),
+                                hipMemcpyDeviceToDevice, s));
+          HIPCHK(hipMemcpyAsync(nx.vel + c * N + o, st.vel + c * st.ld + src, n * sizeof(double),
+                                hipMemcpyDeviceToDevice, s));
+          HIPCHK(hipMemcpyAsync(nx.F + c * N + o, st.F + c * st.ld + src, n * sizeof(double),
+                                hipMemcpyDeviceToDevice, s));
+        }
+      }
+      r->off = o;
+      o += n;
+      ++k;
+    }
+    std::swap(sv->st, sv->st2);
+  }
+  BatchState& b = sv->st;
+  std::vector<int64_t> offs(S + 1, 0);
+  std::vector<double> boxes(9 * (size_t)S);
+  std::vector<int32_t> pbcs(3 * (size_t)S);
+  for (int32_t k = 0; k < S; ++k) {
+    offs[k + 1] = offs[k] + act[k]->n;
+    std::memcpy(&boxes[9 * k], act[k]->box, sizeof act[k]->box);
+    std::memcpy(&pbcs[3 * k], act[k]->pbc, sizeof act[k]->pbc);
+  }
+  launch_srv_kick_drift(N, b.pos, b.vel, b.F, b.hdm, b.dta, b.move, s);
+  Prepared pp = prepare_batch(h, S, offs.data(), boxes.data(), pbcs.data(), h->hp.rc_radial, false, true, s);
+  order_and_build(h, pp, b.pos, b.types, s, true);
+  forces(h, pp, s);
+  EvalArgs a = eval_args(h, pp, h->M);
+  launch_scatter_outputs(a, h->perm, b.E, b.F, b.W, s);
+  launch_struct_totals(h->U, h->W, N, h->structs, S, b.totals, s);
+  launch_srv_kick(N, b.vel, b.F, b.hdm, b.move, s);
+  // bookkeeping: finished requests copy their results out
+  std::vector<std::shared_ptr<ServerReq>> finished;
+  std::vector<double> tot(10 * (size_t)S);
+  HIPCHK(hipMemcpyAsync(tot.data(), b.totals, tot.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+  for (int32_t k = 0; k < S; ++k) {
+    auto& r = act[k];
+    bool fin = false;
+    if (r->kind == NEP_REQ_EVAL) {
+      fin = true;
+    } else if (r->steps_done < 0) {
+      r->steps_done = 0;
+      launch_fill_u8(b.move + r->off, r->n, 1, s);
+      fin = r->n_steps == 0;
+    } else {
+      r->steps_done += 1;
+      fin = r->steps_done >= r->n_steps;
+    }
+    sv->atom_steps += r->n;
+    if (fin) {
+      const size_t n = r->n;
+      r->energy.resize(n);
+      r->force.resize(3 * n);
+      r->virial.resize(9 * n);
+      HIPCHK(hipMemcpyAsync(r->energy.data(), b.E + r->off, n * sizeof(double), hipMemcpyDeviceToHost, s));
+      for (int c = 0; c < 3; ++c)
+        HIPCHK(hipMemcpyAsync(r->force.data() + c * n, b.F + c * N + r->off, n * sizeof(double),
+                              hipMemcpyDeviceToHost, s));
+      for (int v = 0; v < 9; ++v)
+        HIPCHK(hipMemcpyAsync(r->virial.data() + v * n, b.W + v * N + r->off, n * sizeof(double),
+                              hipMemcpyDeviceToHost, s));
+      if (r->kind == NEP_REQ_MD) {
+        r->out_pos.resize(3 * n);
+        r->out_vel.resize(3 * n);
+        for (int c = 0; c < 3; ++c) {
+          HIPCHK(hipMemcpyAsync(r->out_pos.data() + c * n, b.pos + c * N + r->off, n * sizeof(double),
+                                hipMemcpyDeviceToHost, s));
+          HIPCHK(hipMemcpyAsync(r->out_vel.data() + c * n, b.vel + c * N + r->off, n * sizeof(double),
+                                hipMemcpyDeviceToHost, s));
+        }
+      }
+      finished.push_back(r);
+    }
+  }
+  HIPCHK(hipStreamSynchronize(s));
+  const double t = now_s();
+  sv->ticks += 1;
+  sv->batch_atoms += N;
+  sv->batch_reqs += S;
+  for (int32_t k = 0; k < S; ++k) std::memcpy(act[k]->totals, &tot[10 * k], 10 * sizeof(double));
+  std::lock_guard<std::mutex> lk(sv->mu);
+  for (auto& r : finished) {
+    r->t_done = t;
+    sv->bytes_active -= r->bytes;
+    sv->latencies.push_back(r->t_done - r->t_submit);
+    sv->completed += 1;
+    sv->t_last = t;
+    sv->done[r->ticket] = r;
+  }
+  act.erase(std::remove_if(act.begin(), act.end(), [](const std::shared_ptr<ServerReq>& r) { return r->t_done > 0; }),
+            act.end());
+  // the remaining requests are re-packed next tick if their offsets moved
+  sv->done_cv.notify_all();
+}
+
+void server_loop(nep_server* sv) {
+  try {
+    HIPCHK(hipSetDevice(sv->h->device));
+    for (;;) {
+      {
+        std::unique_lock<std::mutex> lk(sv->mu);
+        sv->cv.wait(lk, [&] { return sv->stop || !sv->queue.empty() || !sv->active.empty(); });
+        if (sv->stop && sv->queue.empty() && sv->active.empty()) return;
+        // admission: free slots and HBM budget, first come first served
+        while (!sv->queue.empty() && (int32_t)sv->active.size() < sv->max_slots &&
+               sv->bytes_active + sv->queue.front()->bytes <= sv->budget) {
+          sv->bytes_active += sv->queue.front()->bytes;
+          sv->active.push_back(sv->queue.front());
+          sv->queue.pop_front();
+        }
+      }
+      if (sv->active.empty()) continue;
+      const double t0 = now_s();
+      server_tick(sv);
+      sv->busy += now_s() - t0;
+    }
+  } catch (const Failure& f) {
+    std::lock_guard<std::mutex> lk(sv->mu);
+    sv->fatal = f.msg;
+    for (auto& r : sv->active) {
+      r->status = f.code;
+      r->error = f.msg;
+      r->t_done = now_s();
+      sv->done[r->ticket] = r;
+    }
+    for (auto& r : sv->queue) {
+      r->status = f.code;
+      r->error = f.msg;
+      r->t_done = now_s();
+      sv->done[r->ticket] = r;
+    }
+    sv->active.clear();
+    sv->queue.clear();
+    sv->done_cv.notify_all();
+  }
 }
 
 }  // namespace
@@ -727,11 +1232,10 @@ int nep_create(const nep_hparams* hp, const double* params, size_t n, nep_handle
     h->nd = n_descriptors(*hp);
     h->nets = hp->nn_per_type ? hp->n_types : 1;
     const int nA = hp->n_max_angular + 1, L = hp->l_max_3b;
-    h->NG_desc = angular_group_size(nA, L);
-    h->ng_desc = (nA + h->NG_desc - 1) / h->NG_desc;
-    h->NG_force = h->NG_desc;
-    h->ng_force = h->ng_desc;
-    upload_model(h, params);
+    // c^A rows padded to whole groups for every admissible group size
+    h->nA_pad = nA;
+    for (int ng : angular_group_options(nA, L)) h->nA_pad = std::max(h->nA_pad, (nA + ng - 1) / ng * ng);
+    upload_model(h, params, h->main);
     // LDS budget of the pair kernels: coefficient tables + per-thread slots
     if (eval_lds_bytes(h->M, kBlock) > 64 * 1024)
       throw Failure{NEP_E_UNSUPPORTED, "n_types x basis sizes too large for the LDS budget"};
@@ -748,7 +1252,7 @@ int nep_set_params(nep_handle* h, const double* params, size_t n) {
   if (!params || n != n_params(h->hp)) return fail(h, {NEP_E_INVALID_ARG, "wrong parameter count"});
   try {
     set_device(h);
-    upload_model(h, params);
+    upload_model(h, params, h->main);
   } catch (const Failure& f) {
     return fail(h, f);
   }
@@ -869,9 +1373,9 @@ int nep_descriptors(nep_handle* h, int64_t N, const double* pos, const int32_t* 
     HIPCHK(hipMemcpyAsync(h->pos_ext, pos, 3 * N * sizeof(double), hipMemcpyHostToDevice, s));
     HIPCHK(hipMemcpyAsync(h->types_ext, types, N * sizeof(int32_t), hipMemcpyHostToDevice, s));
     order_and_build(h, pp, h->pos_ext, h->types_ext, s, true);
-    EvalArgs a = eval_args(h, pp);
-    a.NG = h->NG_desc;
-    a.ngroups = h->ng_desc;
+    autotune(h, pp, s);
+    EvalArgs a = eval_args(h, pp, h->M);
+    set_groups(a, h->tune[0].NG_desc, h->tune[0].block_desc, h->M.nA);
     if (!launch_descriptor(a, s)) throw Failure{NEP_E_UNSUPPORTED, "no descriptor kernel for this shape"};
     double* d_q = nullptr;
     dev_alloc(d_q, (size_t)N * h->nd);
@@ -1053,6 +1557,23 @@ int nep_md_run_dev(nep_handle* h, int64_t N, double* pos, double* vel, const int
   return NEP_OK;
 }
 
+int nep_compute_batch(nep_handle* h, int32_t n_struct, const int64_t* offsets, const double* pos,
+                      const int32_t* types, const double* boxes, const int32_t* pbc, int32_t n_param_sets,
+                      const double* params, double* energy, double* force, double* virial, double* totals,
+                      void* stream) {
+  if (!h) return fail(nullptr, {NEP_E_INVALID_ARG, "handle is NULL"});
+  if (!pos || !types) return fail(h, {NEP_E_INVALID_ARG, "pos and types are required"});
+  try {
+    set_device(h);
+    batch_impl(h, n_struct, offsets, pos, types, boxes, pbc, n_param_sets, params, energy, force, virial,
+               totals, (hipStream_t)stream);
+    h->resolve_timing();
+  } catch (const Failure& f) {
+    return fail(h, f);
+  }
+  return NEP_OK;
+}
+
 int nep_set_timing(nep_handle* h, int32_t enable) {
   if (!h) return fail(nullptr, {NEP_E_INVALID_ARG, "handle is NULL"});
   h->timing = enable != 0;
@@ -1069,6 +1590,163 @@ int nep_get_timing(const nep_handle* h, int32_t max, const char** names, double*
     if (calls) calls[k] = h->times.calls[k];
   }
   return n;
+}
+
+int nep_server_create(nep_handle* h, size_t hbm_budget_bytes, int32_t max_slots, nep_server** out) {
+  if (!h || !out) return fail(h, {NEP_E_INVALID_ARG, "handle and out are required"});
+  if (max_slots < 1 || hbm_budget_bytes == 0) return fail(h, {NEP_E_INVALID_ARG, "need max_slots >= 1 and a budget"});
+  *out = nullptr;
+  nep_server* sv = new nep_server();
+  try {
+    set_device(h);
+    sv->h = h;
+    sv->budget = hbm_budget_bytes;
+    sv->max_slots = max_slots;
+    HIPCHK(hipStreamCreateWithFlags(&sv->stream, hipStreamNonBlocking));
+    sv->worker = std::thread(server_loop, sv);
+  } catch (const Failure& f) {
+    if (sv->stream) (void)hipStreamDestroy(sv->stream);
+    delete sv;
+    return fail(h, f);
+  }
+  *out = sv;
+  return NEP_OK;
+}
+
+int nep_server_submit(nep_server* sv, const nep_request* rq, uint64_t* ticket) {
+  if (!sv || !rq || !ticket) return fail(nullptr, {NEP_E_INVALID_ARG, "server, request and ticket are required"});
+  nep_handle* h = sv->h;
+  try {
+    if (rq->kind != NEP_REQ_EVAL && rq->kind != NEP_REQ_MD) throw Failure{NEP_E_INVALID_ARG, "unknown request kind"};
+    if (rq->n_atoms < 1 || !rq->pos || !rq->types) throw Failure{NEP_E_INVALID_ARG, "bad request arrays"};
+    if (rq->kind == NEP_REQ_MD && (!rq->vel || !rq->mass_per_type || rq->n_steps < 0 || !(rq->dt_fs > 0)))
+      throw Failure{NEP_E_INVALID_ARG, "an MD request needs vel, masses, n_steps >= 0 and dt > 0"};
+    const int64_t n = rq->n_atoms;
+    check_host_types(h, n, rq->types);
+    check_host_finite(3 * n, rq->pos, "positions");
+    Geometry g = make_geometry(rq->box, rq->pbc, n, h->hp.rc_radial);
+    auto r = std::make_shared<ServerReq>();
+    r->kind = rq->kind;
+    r->n = n;
+    r->pos.assign(rq->pos, rq->pos + 3 * n);
+    r->types.assign(rq->types, rq->types + n);
+    if (rq->kind == NEP_REQ_MD) {
+      check_host_finite(3 * n, rq->vel, "velocities");
+      r->vel.assign(rq->vel, rq->vel + 3 * n);
+      r->mass.assign(rq->mass_per_type, rq->mass_per_type + h->hp.n_types);
+      for (double m : r->mass)
+        if (!(m > 0)) throw Failure{NEP_E_INVALID_ARG, "masses must be positive"};
+      r->n_steps = rq->n_steps;
+      r->dt = rq->dt_fs;
+    }
+    std::memcpy(r->box, rq->box, sizeof r->box);
+    for (int k = 0; k < 3; ++k) r->pbc[k] = g.st.pbc[k];
+    r->bytes = request_bytes(h, n, (double)n / g.volume);
+    if (r->bytes > sv->budget) throw Failure{NEP_E_BUDGET, "request needs more device memory than the budget"};
+    std::lock_guard<std::mutex> lk(sv->mu);
+    if (!sv->fatal.empty()) throw Failure{NEP_E_HIP, "server stopped: " + sv->fatal};
+    r->ticket = sv->next_ticket++;
+    r->t_submit = now_s();
+    if (sv->t_first < 0) sv->t_first = r->t_submit;
+    sv->submitted += 1;
+    sv->queue.push_back(r);
+    *ticket = r->ticket;
+    sv->cv.notify_one();
+  } catch (const Failure& f) {
+    return fail(h, f);
+  }
+  return NEP_OK;
+}
+
+int nep_server_poll(nep_server* sv, uint64_t ticket, int32_t wait_ms, nep_result* out) {
+  if (!sv || !out) return fail(nullptr, {NEP_E_INVALID_ARG, "server and out are required"});
+  std::shared_ptr<ServerReq> r;
+  {
+    std::unique_lock<std::mutex> lk(sv->mu);
+    auto ready = [&] { return sv->done.count(ticket) > 0; };
+    if (!ready() && wait_ms != 0) {
+      if (wait_ms < 0) sv->done_cv.wait(lk, ready);
+      else sv->done_cv.wait_for(lk, std::chrono::milliseconds(wait_ms), ready);
+    }
+    auto it = sv->done.find(ticket);
+    if (it == sv->done.end()) return NEP_PENDING;
+    r = it->second;
+    sv->done.erase(it);
+  }
+  out->status = r->status;
+  out->n_atoms = r->n;
+  out->latency_ms = (r->t_done - r->t_submit) * 1e3;
+  out->queue_ms = r->t_admit > 0 ? (r->t_admit - r->t_submit) * 1e3 : out->latency_ms;
+  std::memcpy(out->totals, r->totals, sizeof r->totals);
+  if (r->status != NEP_OK) return fail(sv->h, {r->status, r->error});
+  const size_t n = r->n;
+  if (out->energy) std::memcpy(out->energy, r->energy.data(), n * sizeof(double));
+  if (out->force) std::memcpy(out->force, r->force.data(), 3 * n * sizeof(double));
+  if (out->virial) std::memcpy(out->virial, r->virial.data(), 9 * n * sizeof(double));
+  if (out->pos && !r->out_pos.empty()) std::memcpy(out->pos, r->out_pos.data(), 3 * n * sizeof(double));
+  if (out->vel && !r->out_vel.empty()) std::memcpy(out->vel, r->out_vel.data(), 3 * n * sizeof(double));
+  return NEP_OK;
+}
+
+int nep_server_stats(nep_server* sv, nep_server_stats_t* out) {
+  if (!sv || !out) return fail(nullptr, {NEP_E_INVALID_ARG, "server and out are required"});
+  std::lock_guard<std::mutex> lk(sv->mu);
+  std::memset(out, 0, sizeof *out);
+  out->submitted = sv->submitted;
+  out->completed = sv->completed;
+  out->active = (int64_t)sv->active.size();
+  out->queued = (int64_t)sv->queue.size();
+  out->ticks = sv->ticks;
+  std::vector<double> l = sv->latencies;
+  std::sort(l.begin(), l.end());
+  auto pct = [&](double q) {
+    if (l.empty()) return 0.0;
+    const double x = q * (l.size() - 1);
+    const size_t a = (size_t)std::floor(x), b = std::min(l.size() - 1, a + 1);
+    return (l[a] + (x - a) * (l[b] - l[a])) * 1e3;
+  };
+  out->p50_ms = pct(0.5);
+  out->p99_ms = pct(0.99);
+  out->max_ms = l.empty() ? 0 : l.back() * 1e3;
+  double sum = 0;
+  for (double v : l) sum += v;
+  out->mean_ms = l.empty() ? 0 : sum / l.size() * 1e3;
+  const double span = sv->t_first >= 0 ? sv->t_last - sv->t_first : 0;
+  out->wall_s = span;
+  out->busy_s = sv->busy;
+  out->requests_per_s = span > 0 ? sv->completed / span : 0;
+  out->atom_steps_per_s = span > 0 ? sv->atom_steps / span : 0;
+  out->mean_batch_atoms = sv->ticks ? (double)sv->batch_atoms / sv->ticks : 0;
+  out->mean_batch_requests = sv->ticks ? (double)sv->batch_reqs / sv->ticks : 0;
+  out->bytes_in_use = sv->bytes_active;
+  out->hbm_budget = sv->budget;
+  return NEP_OK;
+}
+
+int nep_server_reset_stats(nep_server* sv) {
+  if (!sv) return fail(nullptr, {NEP_E_INVALID_ARG, "server is NULL"});
+  std::lock_guard<std::mutex> lk(sv->mu);
+  sv->latencies.clear();
+  sv->completed = sv->submitted = sv->ticks = sv->atom_steps = sv->batch_atoms = sv->batch_reqs = 0;
+  sv->t_first = -1;
+  sv->t_last = 0;
+  sv->busy = 0;
+  return NEP_OK;
+}
+
+void nep_server_destroy(nep_server* sv) {
+  if (!sv) return;
+  {
+    std::lock_guard<std::mutex> lk(sv->mu);
+    sv->stop = true;
+  }
+  sv->cv.notify_all();
+  if (sv->worker.joinable()) sv->worker.join();
+  (void)hipSetDevice(sv->h->device);
+  sv->st.release();
+  sv->st2.release();
+  if (sv->stream) (void)hipStreamDestroy(sv->stream);
+  delete sv;
 }
 
 }  // extern "C"

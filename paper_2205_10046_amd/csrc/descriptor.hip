@@ -16,6 +16,8 @@
 // Gather (eqs. F_ij, F_i, virial): F_i = sum_j dU_i/dr_ij - dU_j/dr_ji and
 //   W_i = sum_j r_ij (x) dU_j/dr_ji, reading dU_j/dr_ji through the reverse
 //   index: no atomics, so results are bitwise reproducible.
+#include <vector>
+
 #include "angular.h"
 #include "nep_kernels.h"
 
@@ -420,15 +422,23 @@ __global__ void __launch_bounds__(kBlock) k_gather(EvalArgs a, StructInfo st0) {
 // dispatch
 // ---------------------------------------------------------------------------
 
-// Group size NG for n_A radial functions at a given l_max: as many as fit the
-// register budget of the accumulator block (NG x NB floats), in two or more
-// equal groups otherwise.
-int angular_group_size(int nA, int L) {
+// Admissible group sizes NG for n_A radial functions at a given l_max: the
+// accumulator block NG x NB must fit the register budget.  The default is the
+// one with the least padded work, then the fewest passes over the bonds; the
+// autotuner in api.cpp may pick another one by timing.
+std::vector<int> angular_group_options(int nA, int L) {
   const int cap = L <= 4 ? 7 : (L == 5 ? 5 : 4);
   static const int allowed[] = {2, 4, 5, 7};
+  std::vector<int> out;
+  for (int ng : allowed)
+    if (ng <= cap && (ng <= nA || ng == 2)) out.push_back(ng);
+  if (out.empty()) out.push_back(2);
+  return out;
+}
+
+int angular_group_size(int nA, int L) {
   int best = -1, best_cost = 1 << 30;
-  for (int ng : allowed) {
-    if (ng > cap) continue;
+  for (int ng : angular_group_options(nA, L)) {
     int groups = (nA + ng - 1) / ng;
     int cost = groups * ng * 4 + groups;  // padded work, then fewer passes
     if (cost < best_cost) {
@@ -441,12 +451,13 @@ int angular_group_size(int nA, int L) {
 
 template <int NG, int L, bool BATCH>
 static void launch_pair(const EvalArgs& a, const StructInfo& st0, bool force, hipStream_t s) {
-  const size_t lds = eval_lds_bytes(a.M, kBlock);
-  dim3 grid((unsigned)div_up(a.N, kBlock));
+  const int block = a.block > 0 ? a.block : kBlock;
+  const size_t lds = eval_lds_bytes(a.M, block);
+  dim3 grid((unsigned)div_up(a.N, block));
   if (force)
-    hipLaunchKernelGGL((k_partial_forces<NG, L, BATCH>), grid, dim3(kBlock), lds, s, a, st0);
+    hipLaunchKernelGGL((k_partial_forces<NG, L, BATCH>), grid, dim3(block), lds, s, a, st0);
   else
-    hipLaunchKernelGGL((k_descriptor<NG, L, BATCH>), grid, dim3(kBlock), lds, s, a, st0);
+    hipLaunchKernelGGL((k_descriptor<NG, L, BATCH>), grid, dim3(block), lds, s, a, st0);
 }
 
 template <bool BATCH>

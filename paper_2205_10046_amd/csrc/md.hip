@@ -160,4 +160,68 @@ void launch_gather_i32(const int32_t* src, int64_t N, const int32_t* in, int32_t
   hipLaunchKernelGGL(k_gather_i32, dim3(div_up(N, kBlock)), dim3(kBlock), 0, s, src, N, in, out);
 }
 
+// ---- serving: velocity Verlet on the concatenated request state (request
+// order, caller order inside each request), forces in float64 ----
+
+// v += hdm F; r += dt v   for atoms with move != 0
+__global__ void k_srv_kick_drift(int64_t N, double* __restrict__ pos, double* __restrict__ vel,
+                                 const double* __restrict__ F, const double* __restrict__ hdm,
+                                 const double* __restrict__ dta, const uint8_t* __restrict__ move) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= N || !move[i]) return;
+  for (int c = 0; c < 3; ++c) {
+    const int64_t k = (int64_t)c * N + i;
+    const double v = vel[k] + hdm[i] * F[k];
+    vel[k] = v;
+    pos[k] += dta[i] * v;
+  }
+}
+
+__global__ void k_srv_kick(int64_t N, double* __restrict__ vel, const double* __restrict__ F,
+                           const double* __restrict__ hdm, const uint8_t* __restrict__ move) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= N || !move[i]) return;
+  for (int c = 0; c < 3; ++c) {
+    const int64_t k = (int64_t)c * N + i;
+    vel[k] += hdm[i] * F[k];
+  }
+}
+
+void launch_srv_kick_drift(int64_t N, double* pos, double* vel, const double* F, const double* hdm,
+                           const double* dta, const uint8_t* move, hipStream_t s) {
+  hipLaunchKernelGGL(k_srv_kick_drift, dim3(div_up(N, kBlock)), dim3(kBlock), 0, s, N, pos, vel, F, hdm,
+                     dta, move);
+}
+
+void launch_srv_kick(int64_t N, double* vel, const double* F, const double* hdm, const uint8_t* move,
+                     hipStream_t s) {
+  hipLaunchKernelGGL(k_srv_kick, dim3(div_up(N, kBlock)), dim3(kBlock), 0, s, N, vel, F, hdm, move);
+}
+
+__global__ void k_fill_u8(uint8_t* __restrict__ a, int64_t n, uint8_t v) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) a[i] = v;
+}
+
+void launch_fill_u8(uint8_t* a, int64_t n, uint8_t v, hipStream_t s) {
+  if (n > 0) hipLaunchKernelGGL(k_fill_u8, dim3(div_up(n, kBlock)), dim3(kBlock), 0, s, a, n, v);
+}
+
+// Per-atom half-step factor 0.5 dt / (m c) and dt of one request segment.
+__global__ void k_srv_factors(int64_t n, const int32_t* __restrict__ types, const double* __restrict__ inv_mass,
+                              double half_dt, double dt, double* __restrict__ hdm,
+                              double* __restrict__ dta) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  hdm[i] = half_dt * inv_mass[types[i]];
+  dta[i] = dt;
+}
+
+void launch_srv_factors(int64_t n, const int32_t* types, const double* inv_mass, double half_dt, double dt,
+                        double* hdm, double* dta, hipStream_t s) {
+  if (n > 0)
+    hipLaunchKernelGGL(k_srv_factors, dim3(div_up(n, kBlock)), dim3(kBlock), 0, s, n, types, inv_mass,
+                       half_dt, dt, hdm, dta);
+}
+
 }  // namespace nep

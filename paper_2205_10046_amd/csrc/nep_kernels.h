@@ -1,5 +1,7 @@
 // nep_kernels.h -- argument blocks and launchers of the NEP kernels.
 #pragma once
+#include <vector>
+
 #include "nep_internal.h"
 
 namespace nep {
@@ -44,6 +46,7 @@ struct EvalArgs {
   int32_t ngroups;            // angular radial-function groups
   int32_t NG;                 // group size
   int32_t mlp_bf16;
+  int32_t block;              // threads per block of the pair kernels (0 = 256)
   int32_t batch;              // several structures: geometry from structs[sid]
   StructInfo st0;             // the geometry when batch == 0
 };
@@ -64,6 +67,7 @@ bool launch_partial_forces(const EvalArgs& a, hipStream_t s);
 void launch_gather_forces(const EvalArgs& a, hipStream_t s);
 size_t eval_lds_bytes(const DevModel& M, int block);
 int angular_group_size(int nA, int L);
+std::vector<int> angular_group_options(int nA, int L);
 
 // mlp.hip
 void launch_mlp(const EvalArgs& a, hipStream_t s);
@@ -73,6 +77,8 @@ void launch_scatter_outputs(const EvalArgs& a, const int32_t* perm, double* ener
                             double* force, double* virial, hipStream_t s);
 void launch_totals(const float* U, const float* W, int64_t N, double* partial, int64_t n_part,
                    double* totals, hipStream_t s);
+void launch_struct_totals(const float* U, const float* W, int64_t N, const StructInfo* structs,
+                          int32_t n_struct, double* totals, hipStream_t s);
 void launch_descriptors_out(const float* q, int64_t N, int NDp, int ND, const int32_t* perm,
                             double* out, hipStream_t s);
 void launch_neighbors_out(const Lists& L, int which, int64_t N, const int32_t* perm,
@@ -103,6 +109,13 @@ void launch_unpermute_md(const int32_t* perm, int64_t N, const double* pos_int,
                          hipStream_t s);
 void launch_check_finite(const double* a, int64_t n, int32_t* flag, hipStream_t s);
 void launch_check_types(const int32_t* types, int64_t n, int32_t T, int32_t* flag, hipStream_t s);
+void launch_srv_kick_drift(int64_t N, double* pos, double* vel, const double* F, const double* hdm,
+                           const double* dta, const uint8_t* move, hipStream_t s);
+void launch_srv_kick(int64_t N, double* vel, const double* F, const double* hdm, const uint8_t* move,
+                     hipStream_t s);
+void launch_fill_u8(uint8_t* a, int64_t n, uint8_t v, hipStream_t s);
+void launch_srv_factors(int64_t n, const int32_t* types, const double* inv_mass, double half_dt, double dt,
+                        double* hdm, double* dta, hipStream_t s);
 void launch_gather_i32(const int32_t* src, int64_t N, const int32_t* in, int32_t* out, hipStream_t s);
 
 }  // namespace nep

@@ -68,6 +68,36 @@ void launch_totals(const float* U, const float* W, int64_t N, double* partial, i
   hipLaunchKernelGGL(k_totals_final, dim3(1), dim3(64), 0, s, partial, n_part, totals);
 }
 
+// totals[s][10] of every structure s: one block per structure, fixed tree
+__global__ void __launch_bounds__(kRedBlock) k_struct_totals(const float* __restrict__ U,
+                                                             const float* __restrict__ W, int64_t N,
+                                                             const StructInfo* __restrict__ structs,
+                                                             double* __restrict__ totals) {
+  __shared__ double sh[10][kRedBlock];
+  const int t = threadIdx.x;
+  const StructInfo& st = structs[blockIdx.x];
+  const int64_t lo = st.start, hi = st.start + st.count;
+  double acc[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+  for (int64_t k = lo + t; k < hi; k += kRedBlock) {
+    acc[0] += (double)U[k];
+    for (int v = 0; v < 9; ++v) acc[1 + v] += (double)W[(int64_t)v * N + k];
+  }
+  for (int v = 0; v < 10; ++v) sh[v][t] = acc[v];
+  __syncthreads();
+  for (int off = kRedBlock / 2; off > 0; off >>= 1) {
+    if (t < off)
+      for (int v = 0; v < 10; ++v) sh[v][t] += sh[v][t + off];
+    __syncthreads();
+  }
+  if (t < 10) totals[(int64_t)blockIdx.x * 10 + t] = sh[t][0];
+}
+
+void launch_struct_totals(const float* U, const float* W, int64_t N, const StructInfo* structs,
+                          int32_t n_struct, double* totals, hipStream_t s) {
+  hipLaunchKernelGGL(k_struct_totals, dim3((unsigned)n_struct), dim3(kRedBlock), 0, s, U, W, N,
+                     structs, totals);
+}
+
 __global__ void k_descriptors_out(const float* __restrict__ q, int64_t N, int NDp, int ND,
                                   const int32_t* __restrict__ perm, double* __restrict__ out) {
   int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;

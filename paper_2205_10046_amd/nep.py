@@ -32,7 +32,12 @@ NEP_MLP_BF16 = 1
 EXPORTS = ["nep_num_descriptors", "nep_num_params", "nep_create", "nep_set_params",
            "nep_destroy", "nep_last_error", "nep_compute", "nep_compute_dev",
            "nep_neighbors", "nep_descriptors", "nep_md_run", "nep_md_run_dev",
-           "nep_set_timing", "nep_get_timing"]
+           "nep_compute_batch", "nep_set_timing", "nep_get_timing", "nep_server_create",
+           "nep_server_submit", "nep_server_poll", "nep_server_stats", "nep_server_reset_stats",
+           "nep_server_destroy"]
+
+NEP_REQ_EVAL = 0
+NEP_REQ_MD = 1
 
 
 class NepError(RuntimeError):
@@ -64,6 +69,30 @@ def make_hparams(h: dict, mlp_precision=NEP_MLP_FP32, max_nb_radial=0,
         max_nb_radial=h.get("max_nb_radial", max_nb_radial),
         max_nb_angular=h.get("max_nb_angular", max_nb_angular),
         skin=h.get("skin", skin))
+
+
+class nep_request(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("n_atoms", C.c_int64),
+                ("pos", C.POINTER(C.c_double)), ("vel", C.POINTER(C.c_double)),
+                ("types", C.POINTER(C.c_int32)), ("box", C.c_double * 9),
+                ("pbc", C.c_int32 * 3), ("n_steps", C.c_int64), ("dt_fs", C.c_double),
+                ("mass_per_type", C.POINTER(C.c_double))]
+
+
+class nep_result(C.Structure):
+    _fields_ = [("status", C.c_int32), ("n_atoms", C.c_int64),
+                ("energy", C.POINTER(C.c_double)), ("force", C.POINTER(C.c_double)),
+                ("virial", C.POINTER(C.c_double)), ("pos", C.POINTER(C.c_double)),
+                ("vel", C.POINTER(C.c_double)), ("totals", C.c_double * 10),
+                ("latency_ms", C.c_double), ("queue_ms", C.c_double)]
+
+
+class nep_server_stats_t(C.Structure):
+    _fields_ = [(k, C.c_int64) for k in ("submitted", "completed", "active", "queued", "ticks")] + \
+               [(k, C.c_double) for k in ("p50_ms", "p99_ms", "mean_ms", "max_ms", "wall_s",
+                                          "busy_s", "requests_per_s", "atom_steps_per_s",
+                                          "mean_batch_atoms", "mean_batch_requests")] + \
+               [("bytes_in_use", C.c_size_t), ("hbm_budget", C.c_size_t)]
 
 
 _lib = None
@@ -104,6 +133,15 @@ def load():
     L.nep_descriptors.argtypes = [vp, i64, pd, pi32, pd, pi32, pd]
     L.nep_md_run.argtypes = [vp, i64, pd, pd, pi32, pd, pd, pi32, d, i64, i64, pd]
     L.nep_md_run_dev.argtypes = [vp, i64, vp, vp, vp, pd, pd, pi32, d, i64, i64, vp, vp]
+    L.nep_compute_batch.argtypes = [vp, i32, P(i64), vp, vp, pd, pi32, i32, pd, vp, vp, vp,
+                                    vp, vp]
+    L.nep_server_create.argtypes = [vp, C.c_size_t, i32, P(vp)]
+    L.nep_server_submit.argtypes = [vp, P(nep_request), P(C.c_uint64)]
+    L.nep_server_poll.argtypes = [vp, C.c_uint64, i32, P(nep_result)]
+    L.nep_server_stats.argtypes = [vp, P(nep_server_stats_t)]
+    L.nep_server_reset_stats.argtypes = [vp]
+    L.nep_server_destroy.argtypes = [vp]
+    L.nep_server_destroy.restype = None
     L.nep_set_timing.argtypes = [vp, i32]
     L.nep_get_timing.argtypes = [vp, i32, P(C.c_char_p), pd, P(i64)]
     for name in EXPORTS:
@@ -251,6 +289,22 @@ class Handle:
             _ptr(box, C.c_double), _ptr(pbc, C.c_int32), float(dt), int(n_steps),
             int(thermo_every), p(thermo), _torch_stream()))
 
+    def compute_batch(self, offsets, pos, types, boxes, params=None, energy=None, force=None,
+                      virial=None, totals=None, pbc=None):
+        """nep_compute_batch: pos/types and outputs are torch CUDA tensors; offsets
+        (S+1), boxes (S, 9), params (P, N_par) and pbc (S, 3) are numpy arrays."""
+        offsets = np.ascontiguousarray(offsets, dtype=np.int64)
+        boxes = _f64(boxes)
+        S = offsets.shape[0] - 1
+        P = 1 if params is None else int(np.asarray(params).shape[0])
+        params = None if params is None else _f64(params)
+        pbc = None if pbc is None else _i32(pbc)
+        p = lambda t: None if t is None else C.c_void_p(t.data_ptr())  # noqa: E731
+        self._check(load().nep_compute_batch(
+            self._h, S, _ptr(offsets, C.c_int64), p(pos), p(types), _ptr(boxes, C.c_double),
+            _ptr(pbc, C.c_int32), P, _ptr(params, C.c_double), p(energy), p(force), p(virial),
+            p(totals), _torch_stream()))
+
     def set_timing(self, enable=True):
         self._check(load().nep_set_timing(self._h, 1 if enable else 0))
 
@@ -263,3 +317,76 @@ class Handle:
         k = load().nep_get_timing(self._h, n, names, _ptr(ms, C.c_double),
                                   _ptr(calls, C.c_int64))
         return {names[i].decode(): (float(ms[i]), int(calls[i])) for i in range(k)}
+
+
+class Server:
+    """A continuous-batching server (nep_server_*) on a Handle it owns."""
+
+    def __init__(self, handle: Handle, hbm_budget_bytes: int, max_slots: int = 64):
+        self.handle = handle
+        out = C.c_void_p()
+        rc = load().nep_server_create(handle._h, int(hbm_budget_bytes), int(max_slots),
+                                      C.byref(out))
+        if rc != NEP_OK:
+            raise NepError(rc, last_error(handle._h))
+        self._s = out
+        self._keep = {}
+
+    def submit(self, pos, types, box, kind=NEP_REQ_EVAL, vel=None, masses=None, n_steps=0,
+               dt=1.0, pbc=None):
+        pos, types, box = _f64(pos), _i32(types), _f64(box)
+        vel = None if vel is None else _f64(vel)
+        masses = None if masses is None else _f64(masses)
+        r = nep_request(kind=kind, n_atoms=pos.shape[1], pos=_ptr(pos, C.c_double),
+                        vel=_ptr(vel, C.c_double), types=_ptr(types, C.c_int32),
+                        n_steps=int(n_steps), dt_fs=float(dt),
+                        mass_per_type=_ptr(masses, C.c_double))
+        r.box[:] = list(box)
+        r.pbc[:] = [1, 1, 1] if pbc is None else [int(x) for x in pbc]
+        t = C.c_uint64()
+        rc = load().nep_server_submit(self._s, C.byref(r), C.byref(t))
+        if rc != NEP_OK:
+            raise NepError(rc, last_error(self.handle._h))
+        self._keep[t.value] = (pos.shape[1], kind)
+        return t.value
+
+    def poll(self, ticket, wait_ms=0):
+        """None while pending, else dict U, F, W, totals, latency_ms [, pos, vel]."""
+        n, kind = self._keep[ticket]
+        U, F, W = np.zeros(n), np.zeros((3, n)), np.zeros((9, n))
+        P, V = (np.zeros((3, n)), np.zeros((3, n))) if kind == NEP_REQ_MD else (None, None)
+        r = nep_result(energy=_ptr(U, C.c_double), force=_ptr(F, C.c_double),
+                       virial=_ptr(W, C.c_double), pos=_ptr(P, C.c_double),
+                       vel=_ptr(V, C.c_double))
+        rc = load().nep_server_poll(self._s, C.c_uint64(ticket), int(wait_ms), C.byref(r))
+        if rc == NEP_PENDING:
+            return None
+        del self._keep[ticket]
+        if rc != NEP_OK:
+            raise NepError(rc, last_error(self.handle._h))
+        out = dict(U=U, F=F, W=W, totals=np.array(r.totals[:]), latency_ms=r.latency_ms,
+                   queue_ms=r.queue_ms)
+        if kind == NEP_REQ_MD:
+            out.update(pos=P, vel=V)
+        return out
+
+    def stats(self):
+        st = nep_server_stats_t()
+        rc = load().nep_server_stats(self._s, C.byref(st))
+        if rc != NEP_OK:
+            raise NepError(rc, last_error(self.handle._h))
+        return {k: getattr(st, k) for k, _ in st._fields_}
+
+    def reset_stats(self):
+        load().nep_server_reset_stats(self._s)
+
+    def close(self):
+        if getattr(self, "_s", None):
+            load().nep_server_destroy(self._s)
+            self._s = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

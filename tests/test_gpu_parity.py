@@ -270,3 +270,63 @@ def test_device_path_checks_types(handles):
     with pytest.raises(nep.NepError) as e:
         handle.compute_dev(tp, tt, box, force=f)
     assert e.value.code == nep.NEP_E_INVALID_ARG
+
+
+# --------------------------------------------------------------------------
+# batches of structures x parameter sets (training-style population eval)
+# --------------------------------------------------------------------------
+
+def _batch_setup(n_struct=12, seed=21):
+    h = synth.WORKLOADS["train3"]
+    structs = synth.random_structures(n_struct, 8, 96, seed=seed)
+    pos, types, boxes, offs = synth.concat_structures(structs)
+    return h, structs, pos, types, boxes, offs
+
+
+def _run_batch(handle, pos, types, boxes, offs, params):
+    import torch
+    dev = torch.device("cuda:0")
+    n, S = pos.shape[1], boxes.shape[0]
+    P = 1 if params is None else params.shape[0]
+    e = torch.zeros(P, n, dtype=torch.float64, device=dev)
+    f = torch.zeros(P, 3, n, dtype=torch.float64, device=dev)
+    w = torch.zeros(P, 9, n, dtype=torch.float64, device=dev)
+    t = torch.zeros(P, S, 10, dtype=torch.float64, device=dev)
+    handle.compute_batch(offs, torch.tensor(pos, device=dev), torch.tensor(types, device=dev),
+                         boxes, params, e, f, w, t)
+    torch.cuda.synchronize()
+    return e.cpu().numpy(), f.cpu().numpy(), w.cpu().numpy(), t.cpu().numpy()
+
+
+def test_batch_population_matches_oracle():
+    h, structs, pos, types, boxes, offs = _batch_setup()
+    mean = synth.random_params(O.num_params(h))
+    pop = synth.population(mean, 3)
+    handle = nep.Handle(h, mean)
+    e, f, w, t = _run_batch(handle, pos, types, boxes, offs, pop)
+    worst = 0.0
+    for p in range(pop.shape[0]):
+        for s, (ps, ts, bs) in enumerate(structs):
+            a, b = offs[s], offs[s + 1]
+            ref = O.evaluate(h, pop[p], ps, ts, bs)
+            dU = np.abs(e[p, a:b] - ref["U"]).max()
+            dF = np.abs(f[p, :, a:b] - ref["F"]).max()
+            dW = np.abs(w[p, :, a:b] - ref["W"]).max()
+            worst = max(worst, dF)
+            assert dU <= TOL_U and dF <= TOL_F and dW <= TOL_W, (p, s, dU, dF, dW)
+            np.testing.assert_allclose(t[p, s, 0], ref["U"].sum(), atol=TOL_U * (b - a))
+            np.testing.assert_allclose(t[p, s, 1:], w[p, :, a:b].sum(1), atol=1e-9 * (b - a))
+    log(f"[batch] {len(structs)} structures x {pop.shape[0]} sets: worst |dF| {worst:.2e}")
+
+
+def test_batch_invariance_bitwise():
+    """A structure's result alone (batch of one) equals its result in the batch."""
+    h, structs, pos, types, boxes, offs = _batch_setup(8, seed=5)
+    params = synth.random_params(O.num_params(h))
+    handle = nep.Handle(h, params)
+    e, f, w, _ = _run_batch(handle, pos, types, boxes, offs, None)
+    for s, (ps, ts, bs) in enumerate(structs):
+        a, b = offs[s], offs[s + 1]
+        e1, f1, w1, _ = _run_batch(handle, ps, ts, bs[None, :], np.array([0, b - a]), None)
+        assert np.array_equal(e1[0], e[0, a:b]) and np.array_equal(f1[0], f[0, :, a:b])
+        assert np.array_equal(w1[0], w[0, :, a:b])
