@@ -69,6 +69,9 @@ def parse():
     ap.add_argument("--no-bf16", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--serve-requests", type=int, default=200)
+    ap.add_argument("--serve-budget-gb", type=float, default=2.0)
     return ap.parse_args()
 
 
@@ -86,6 +89,59 @@ def run_md(handle, pos_d, vel_d, types_d, masses, box, steps, warmup, torch):
     stages = handle.timing()
     handle.set_timing(False)
     return dt, stages, th.cpu().numpy()
+
+
+def serving_leg(nep, synth, params_of, n_req, budget_gb, prec):
+    """Poisson stream of eval / 100-step NVE requests (log-uniform 64..100k atoms,
+    2 species, FCC or BCC): saturation throughput with every request queued at
+    once, then p50/p99 latency at 0.5 and 0.8 of that request rate."""
+    h = synth.WORKLOADS["serve2"]
+    masses = np.array(synth.MASSES["serve2"])
+    reqs = synth.serving_stream(n_requests=n_req, rate_hz=1.0, seed=synth.SEED_STRUCT + 7)
+    handle = nep.Handle(h, params_of(h), mlp_precision=prec)
+    srv = nep.Server(handle, int(budget_gb * (1 << 30)), max_slots=64)
+
+    def submit(r):
+        if r.kind == "eval":
+            return srv.submit(r.pos, r.types, r.box)
+        return srv.submit(r.pos, r.types, r.box, kind=nep.NEP_REQ_MD, vel=r.vel,
+                          masses=masses, n_steps=r.n_steps, dt=1.0)
+
+    # warm-up (autotuner, workspace growth) on a few requests
+    for r in reqs[:4]:
+        srv.poll(submit(r), wait_ms=-1)
+    srv.reset_stats()
+    tickets = [submit(r) for r in reqs]
+    for t in tickets:
+        srv.poll(t, wait_ms=-1)
+    sat = srv.stats()
+    out = {"requests": n_req, "atoms_mean": float(np.mean([r.pos.shape[1] for r in reqs])),
+           "saturation": {"requests_per_s": sat["requests_per_s"],
+                          "atom_steps_per_s": sat["atom_steps_per_s"],
+                          "p50_ms": sat["p50_ms"], "p99_ms": sat["p99_ms"],
+                          "mean_batch_requests": sat["mean_batch_requests"]}}
+    base_t = np.array([r.arrival_s for r in reqs])
+    for frac in (0.5, 0.8):
+        rate = frac * sat["requests_per_s"]
+        arrivals = base_t * (1.0 / rate)       # the stream was drawn at 1 Hz
+        srv.reset_stats()
+        t0 = time.perf_counter()
+        tickets = []
+        for r, ta in zip(reqs, arrivals):
+            dt = ta - (time.perf_counter() - t0)
+            if dt > 0:
+                time.sleep(dt)
+            tickets.append(submit(r))
+        for t in tickets:
+            srv.poll(t, wait_ms=-1)
+        st = srv.stats()
+        out[f"load_{frac}"] = {"rate_hz": rate, "p50_ms": st["p50_ms"], "p99_ms": st["p99_ms"],
+                               "requests_per_s": st["requests_per_s"],
+                               "atom_steps_per_s": st["atom_steps_per_s"],
+                               "mean_batch_requests": st["mean_batch_requests"]}
+    srv.close()
+    handle.close()
+    return out
 
 
 def cpu_baseline(h, params, seconds):
@@ -191,6 +247,13 @@ def main():
                                         "avg_launch_ms": avgb["mlp"]}}
     out["paper_context"] = {"A100_NEP3_MgAlCu": 1.5e7, "V100_NEP_carbon_4.2A": 3.6e6,
                             "unit": "atom-step/s", "note": "other hardware and models"}
+    if not args.no_serve:
+        pof = lambda hh: synth.random_params(nep.nep_num_params(hh))  # noqa: E731
+        out["serving"] = {"fp32": serving_leg(nep, synth, pof, args.serve_requests,
+                                              args.serve_budget_gb, nep.NEP_MLP_FP32)}
+        if not args.no_bf16:
+            out["serving"]["bf16"] = serving_leg(nep, synth, pof, args.serve_requests,
+                                                 args.serve_budget_gb, nep.NEP_MLP_BF16)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(h, params, args.cpu_seconds)
     print(json.dumps(out), flush=True)

@@ -297,6 +297,9 @@ struct nep_handle {
   int32_t *rows = nullptr, *tcount = nullptr, *toff = nullptr, *tcursor = nullptr, *flags = nullptr;
   StructInfo* structs = nullptr;
   Lists L{};
+  Lists V{};                       // candidate rows at r_c^R + skin (MD with a skin)
+  double* pos_ref = nullptr;       // positions at the last candidate-row build
+  double* ref_save = nullptr;
   float *q = nullptr, *fp = nullptr, *U = nullptr, *sums = nullptr, *pr = nullptr, *pa = nullptr;
   float *F = nullptr, *W = nullptr, *F_save = nullptr;
   double *pos_save = nullptr, *vel_save = nullptr;
@@ -338,8 +341,14 @@ struct nep_handle {
     free_lists();
     dev_free(q); dev_free(fp); dev_free(U); dev_free(sums); dev_free(F); dev_free(W);
     dev_free(F_save); dev_free(pos_save); dev_free(vel_save); dev_free(types_save);
-    dev_free(ext_save);
+    dev_free(ext_save); dev_free(pos_ref); dev_free(ref_save);
+    free_verlet();
     capN = 0; cap_cells = 0; thermo_cap = 0; MR = MA = 0;
+  }
+
+  void free_verlet() {
+    dev_free(V.nnR); dev_free(V.nlR); dev_free(V.cdR); dev_free(V.nnA);
+    V = Lists{};
   }
 
   void free_lists() {
@@ -661,8 +670,11 @@ void build_rows_checked(nep_handle* h, const Prepared& pp, const BuildArgs& b, h
     HIPCHK(hipStreamSynchronize(s));
     if (fl[3]) throw Failure{NEP_E_INVALID_ARG, "an atom type is out of range"};
     if (fl[4]) throw Failure{NEP_E_NONFINITE, "positions contain NaN or Inf"};
-    if (fl[2]) throw Failure{NEP_E_HIP, "internal error: neighbour rows are not symmetric"};
-    if (fl[0] == 0 && fl[1] == 0) return;
+    if (fl[0] == 0 && fl[1] == 0) {
+      // without truncated rows every entry has its reverse entry
+      if (fl[2]) throw Failure{NEP_E_HIP, "internal error: neighbour rows are not symmetric"};
+      return;
+    }
     const bool fixed = h->hp.max_nb_radial || h->hp.max_nb_angular;
     if (fixed) {
       char msg[160];
@@ -1389,6 +1401,188 @@ int nep_descriptors(nep_handle* h, int64_t N, const double* pos, const int32_t* 
   return NEP_OK;
 }
 
+namespace {
+
+void ensure_verlet(nep_handle* h, int64_t N, int32_t MV) {
+  if (h->V.nlR && MV <= h->V.MR && N <= h->capN) return;
+  h->free_verlet();
+  const int64_t cap = h->capN;
+  dev_alloc(h->V.nnR, cap);
+  dev_alloc(h->V.nnA, cap);
+  dev_alloc(h->V.nlR, (size_t)MV * cap);
+  dev_alloc(h->V.cdR, (size_t)MV * cap);
+  h->V.MR = MV;
+  h->V.MA = 0;
+  if (!h->pos_ref) {
+    dev_alloc(h->pos_ref, 3 * cap);
+    dev_alloc(h->ref_save, 3 * cap);
+  }
+}
+
+// Rebuild now from the current internal state: re-sort into cell order
+// (velocities and caller indices follow), remember the positions, and build
+// the candidate rows.  gate = NULL runs unconditionally.
+void skin_rebuild(nep_handle* h, const Prepared& pp, double rl, const int32_t* gate, hipStream_t s) {
+  const int64_t N = pp.N;
+  BuildArgs br = build_args(h, pp, h->pos, h->types, h->pos2, h->types2);
+  br.ext_src = h->ext_id;
+  br.gate = gate;
+  launch_order_atoms(br, s);
+  launch_gather3_gated(h->perm, N, h->vel, h->vel2, gate, s);
+  launch_gather_i32_gated(h->perm, N, h->ext_id, h->ext_id2, gate, s);
+  launch_copy_gated_f64(h->pos, h->pos2, 3 * N, gate, s);
+  launch_copy_gated_f64(h->vel, h->vel2, 3 * N, gate, s);
+  launch_copy_gated_i32(h->types, h->types2, N, gate, s);
+  launch_copy_gated_i32(h->ext_id, h->ext_id2, N, gate, s);
+  launch_copy_gated_f64(h->pos_ref, h->pos, 3 * N, gate, s);
+  BuildArgs bv = build_args(h, pp, nullptr, nullptr, h->pos, h->types);
+  bv.rcR2 = rl * rl;
+  bv.gate = gate;
+  launch_build_verlet(bv, h->V, s);
+}
+
+void skin_filter(nep_handle* h, const Prepared& pp, hipStream_t s) {
+  BuildArgs bf = build_args(h, pp, nullptr, nullptr, h->pos, h->types);
+  launch_type_rows(h->types, pp.N, h->M.T, h->hp.nn_per_type, h->tcount, h->toff, h->tcursor, h->rows,
+                   rows_length(pp.N, h->M.T), s);
+  launch_filter_rows(bf, pp.geo.st, pp.batch, h->V, h->L, s);
+}
+
+// Grow whichever rows overflowed (flags [0] radial, [1] angular, [5]
+// candidate); returns false if nothing overflowed.
+bool grow_rows(nep_handle* h, int64_t N, const int32_t* fl) {
+  if (!fl[0] && !fl[1] && !fl[5]) return false;
+  if ((fl[0] || fl[1]) && (h->hp.max_nb_radial || h->hp.max_nb_angular))
+    throw Failure{NEP_E_NEIGHBOR_OVERFLOW, "neighbour row overflow during the run"};
+  if (fl[0] || fl[1])
+    ensure_lists(h, N, std::max(h->MR, (int32_t)((fl[0] * 1.2 + 8) / 4 * 4 + 4)),
+                 std::max(h->MA, (int32_t)((fl[1] * 1.2 + 8) / 4 * 4 + 4)));
+  if (fl[5]) ensure_verlet(h, N, std::max(h->V.MR, (int32_t)((fl[5] * 1.2 + 8) / 4 * 4 + 4)));
+  return true;
+}
+
+int32_t* read_flags(nep_handle* h, hipStream_t s) {
+  int32_t* fl = (int32_t*)(h->pinned + 384);
+  HIPCHK(hipMemcpyAsync(fl, h->flags, 8 * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  return fl;
+}
+
+// Velocity Verlet with candidate rows at r_c^R + skin, rebuilt on the device
+// when an atom has moved more than skin / 2 since the last build; the exact
+// rows are filtered from them every step.
+int md_skin(nep_handle* h, const Prepared& pp, double* d_pos, double* d_vel, const int32_t* d_types,
+            double dt, int64_t n_steps, int64_t thermo_every, double* thermo_out, bool thermo_on_host,
+            int64_t n_rows, hipStream_t s) {
+  const int64_t N = pp.N;
+  const double skin = h->hp.skin, rl = h->hp.rc_radial + skin;
+  const double thr2 = 0.25 * skin * skin;
+  int32_t* gate = h->flags + 7;
+  ensure_verlet(h, N, std::max(h->V.MR, estimate_capacity(rl, (double)N / pp.geo.volume)));
+  // initial order from the caller arrays
+  {
+    BuildArgs b0 = build_args(h, pp, d_pos, d_types, h->pos, h->types);
+    launch_order_atoms(b0, s);
+    launch_permute_md(h->perm, N, d_pos, d_vel, h->pos2, h->vel, s);
+    HIPCHK(hipMemcpyAsync(h->ext_id, h->perm, N * sizeof(int32_t), hipMemcpyDeviceToDevice, s));
+    launch_fill_i32(h->flags, 8, 0, s);
+    launch_check_types(h->types, N, h->M.T, h->flags + 3, s);
+    launch_check_finite(h->pos, 3 * N, h->flags + 4, s);
+  }
+  for (int attempt = 0;; ++attempt) {
+    launch_fill_i32(h->flags, 3, 0, s);
+    launch_fill_i32(h->flags + 5, 1, 0, s);
+    skin_rebuild(h, pp, rl, nullptr, s);
+    skin_filter(h, pp, s);
+    const int32_t* fl = read_flags(h, s);
+    if (fl[3]) throw Failure{NEP_E_INVALID_ARG, "an atom type is out of range"};
+    if (fl[4]) throw Failure{NEP_E_NONFINITE, "positions contain NaN or Inf"};
+    if (!grow_rows(h, N, fl)) {
+      if (fl[2]) throw Failure{NEP_E_HIP, "internal error: neighbour rows are not symmetric"};
+      break;
+    }
+    if (attempt == 3) throw Failure{NEP_E_NEIGHBOR_OVERFLOW, "neighbour rows kept overflowing"};
+  }
+  forces(h, pp, s);
+  MDArgs md{};
+  md.N = N;
+  md.F = h->F;
+  md.inv_mass = h->inv_mass;
+  md.dt = dt;
+  md.pos = h->pos;
+  md.vel = h->vel;
+  md.types = h->types;
+  const int64_t chunk = 50;
+  int64_t row = 0;
+  bool redo = false;
+  for (int64_t c0 = 0; c0 < n_steps;) {
+    const int64_t c1 = std::min(n_steps, c0 + chunk);
+    HIPCHK(hipMemcpyAsync(h->pos_save, h->pos, 3 * N * sizeof(double), hipMemcpyDeviceToDevice, s));
+    HIPCHK(hipMemcpyAsync(h->vel_save, h->vel, 3 * N * sizeof(double), hipMemcpyDeviceToDevice, s));
+    HIPCHK(hipMemcpyAsync(h->ref_save, h->pos_ref, 3 * N * sizeof(double), hipMemcpyDeviceToDevice, s));
+    HIPCHK(hipMemcpyAsync(h->types_save, h->types, N * sizeof(int32_t), hipMemcpyDeviceToDevice, s));
+    HIPCHK(hipMemcpyAsync(h->ext_save, h->ext_id, N * sizeof(int32_t), hipMemcpyDeviceToDevice, s));
+    HIPCHK(hipMemcpyAsync(h->F_save, h->F, 3 * N * sizeof(float), hipMemcpyDeviceToDevice, s));
+    const int64_t row0 = row;
+    launch_fill_i32(h->flags, 8, 0, s);
+    if (redo) {  // rows were grown: rebuild them for the restored state first
+      skin_rebuild(h, pp, rl, nullptr, s);
+      redo = false;
+    }
+    for (int64_t step = c0 + 1; step <= c1; ++step) {
+      {
+        Stage st(h, "integrate", s);
+        launch_kick_drift(md, s);
+      }
+      {
+        Stage st(h, "order_atoms", s);
+        launch_fill_i32(gate, 1, 0, s);
+        launch_check_displacement(h->pos, h->pos_ref, N, thr2, gate, s);
+        skin_rebuild(h, pp, rl, gate, s);
+      }
+      {
+        Stage st(h, "neighbor_rows", s);
+        skin_filter(h, pp, s);
+      }
+      forces(h, pp, s);
+      {
+        Stage st(h, "integrate", s);
+        launch_kick(md, s);
+      }
+      if (thermo_every > 0 && step % thermo_every == 0) {
+        Stage st(h, "thermo", s);
+        launch_thermo(h->U, h->W, h->vel, h->types, h->mass, N, h->partial, num_partials(N),
+                      h->thermo + 13 * row, (double)step, kAmuA2fs2, kBoltzmann, s);
+        ++row;
+      }
+    }
+    launch_check_finite(h->pos, 3 * N, h->flags + 4, s);
+    const int32_t* fl = read_flags(h, s);
+    if (fl[4]) throw Failure{NEP_E_NONFINITE, "positions became non-finite during the run"};
+    if (grow_rows(h, N, fl)) {
+      HIPCHK(hipMemcpyAsync(h->pos, h->pos_save, 3 * N * sizeof(double), hipMemcpyDeviceToDevice, s));
+      HIPCHK(hipMemcpyAsync(h->vel, h->vel_save, 3 * N * sizeof(double), hipMemcpyDeviceToDevice, s));
+      HIPCHK(hipMemcpyAsync(h->pos_ref, h->ref_save, 3 * N * sizeof(double), hipMemcpyDeviceToDevice, s));
+      HIPCHK(hipMemcpyAsync(h->types, h->types_save, N * sizeof(int32_t), hipMemcpyDeviceToDevice, s));
+      HIPCHK(hipMemcpyAsync(h->ext_id, h->ext_save, N * sizeof(int32_t), hipMemcpyDeviceToDevice, s));
+      HIPCHK(hipMemcpyAsync(h->F, h->F_save, 3 * N * sizeof(float), hipMemcpyDeviceToDevice, s));
+      row = row0;
+      redo = true;
+      continue;
+    }
+    if (fl[2]) throw Failure{NEP_E_HIP, "internal error: neighbour rows are not symmetric"};
+    c0 = c1;
+  }
+  launch_unpermute_md(h->ext_id, N, h->pos, h->vel, d_pos, d_vel, s);
+  if (n_rows > 0)
+    HIPCHK(hipMemcpyAsync(thermo_out, h->thermo, 13 * n_rows * sizeof(double),
+                          thermo_on_host ? hipMemcpyDeviceToHost : hipMemcpyDeviceToDevice, s));
+  HIPCHK(hipStreamSynchronize(s));
+  return NEP_OK;
+}
+
+}  // namespace
+
 static int md_impl(nep_handle* h, int64_t N, double* d_pos, double* d_vel, const int32_t* d_types,
                    const double* mass_per_type, const double* box, const int32_t* pbc, double dt,
                    int64_t n_steps, int64_t thermo_every, double* thermo_out, bool thermo_on_host,
@@ -1401,7 +1595,8 @@ static int md_impl(nep_handle* h, int64_t N, double* d_pos, double* d_vel, const
   if (n_steps < 0 || thermo_every < 0) throw Failure{NEP_E_INVALID_ARG, "negative step counts"};
   const int64_t n_rows = thermo_every > 0 ? n_steps / thermo_every : 0;
   if (n_rows > 0 && !thermo_out) throw Failure{NEP_E_INVALID_ARG, "thermo buffer is required"};
-  Prepared pp = prepare(h, N, box, pbc, h->hp.rc_radial, true, s);
+  const bool with_skin = h->hp.skin > 0;
+  Prepared pp = prepare(h, N, box, pbc, h->hp.rc_radial + h->hp.skin, true, s);
   if (n_rows > h->thermo_cap) {
     dev_alloc(h->thermo, 13 * n_rows);
     h->thermo_cap = n_rows;
@@ -1415,6 +1610,9 @@ static int md_impl(nep_handle* h, int64_t N, double* d_pos, double* d_vel, const
   std::memcpy(h->pinned + 320, im, sizeof im);
   HIPCHK(hipMemcpyAsync(h->mass, h->pinned + 256, sizeof m, hipMemcpyHostToDevice, s));
   HIPCHK(hipMemcpyAsync(h->inv_mass, h->pinned + 320, sizeof im, hipMemcpyHostToDevice, s));
+  if (with_skin)
+    return md_skin(h, pp, d_pos, d_vel, d_types, dt, n_steps, thermo_every, thermo_out, thermo_on_host,
+                   n_rows, s);
   // initial order: internal <- caller, velocities follow
   order_and_build(h, pp, d_pos, d_types, s, true);
   launch_permute_md(h->perm, N, d_pos, d_vel, h->pos2, h->vel, s);  // pos2 is scratch here
@@ -1448,6 +1646,7 @@ static int md_impl(nep_handle* h, int64_t N, double* d_pos, double* d_vel, const
       }
       // re-sort into cell order and rebuild the rows at the new positions
       BuildArgs b = build_args(h, pp, h->pos, h->types, h->pos2, h->types2);
+      b.ext_src = h->ext_id;
       {
         Stage st(h, "order_atoms", s);
         launch_order_atoms(b, s);
@@ -1489,7 +1688,8 @@ static int md_impl(nep_handle* h, int64_t N, double* d_pos, double* d_vel, const
     HIPCHK(hipMemcpyAsync(fl, h->flags, 8 * sizeof(int32_t), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
     if (fl[4]) throw Failure{NEP_E_NONFINITE, "positions became non-finite during the run"};
-    if (fl[2]) throw Failure{NEP_E_HIP, "internal error: neighbour rows are not symmetric"};
+    if (fl[2] && !(fl[0] || fl[1]))
+      throw Failure{NEP_E_HIP, "internal error: neighbour rows are not symmetric"};
     if (fl[0] || fl[1]) {
       if (h->hp.max_nb_radial || h->hp.max_nb_angular)
         throw Failure{NEP_E_NEIGHBOR_OVERFLOW, "neighbour row overflow during the run"};

@@ -109,6 +109,32 @@ void launch_permute_md(const int32_t* src, int64_t N, const double* src_pos,
                      src_vel, dst_pos, dst_vel);
 }
 
+// gated gathers used by a device-decided rebuild: out[k] = in[src[k]]
+__global__ void k_gather3_gated(const int32_t* __restrict__ src, int64_t N, const double* __restrict__ in,
+                                double* __restrict__ out, const int32_t* gate) {
+  int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= N || (gate && *gate == 0)) return;
+  const int64_t o = src[k];
+  for (int c = 0; c < 3; ++c) out[(int64_t)c * N + k] = in[(int64_t)c * N + o];
+}
+
+__global__ void k_gather_i32_gated(const int32_t* __restrict__ src, int64_t N, const int32_t* __restrict__ in,
+                                   int32_t* __restrict__ out, const int32_t* gate) {
+  int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < N && !(gate && *gate == 0)) out[k] = in[src[k]];
+}
+
+void launch_gather3_gated(const int32_t* src, int64_t N, const double* in, double* out,
+                          const int32_t* gate, hipStream_t s) {
+  hipLaunchKernelGGL(k_gather3_gated, dim3(div_up(N, kBlock)), dim3(kBlock), 0, s, src, N, in, out, gate);
+}
+
+void launch_gather_i32_gated(const int32_t* src, int64_t N, const int32_t* in, int32_t* out,
+                             const int32_t* gate, hipStream_t s) {
+  hipLaunchKernelGGL(k_gather_i32_gated, dim3(div_up(N, kBlock)), dim3(kBlock), 0, s, src, N, in, out,
+                     gate);
+}
+
 // caller order out: ext[perm[k]] = int[k]
 __global__ void k_unpermute_md(const int32_t* __restrict__ perm, int64_t N,
                                const double* __restrict__ pos_int, const double* __restrict__ vel_int,

@@ -17,9 +17,19 @@
 
 namespace nep {
 
+// Kernels of a rebuild take an optional gate: when it points to 0 they do
+// nothing, so an MD step can issue a fixed kernel sequence and let the device
+// decide whether the rows are rebuilt.
+__device__ __forceinline__ bool gated_off(const int32_t* gate) { return gate && *gate == 0; }
+
 __global__ void k_fill_i32(int32_t* a, int64_t n, int32_t v) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) a[i] = v;
+}
+
+__global__ void k_fill_i32_gated(int32_t* a, int64_t n, int32_t v, const int32_t* gate) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n && !gated_off(gate)) a[i] = v;
 }
 
 // Structure id of every caller-order atom from the offsets array.
@@ -58,9 +68,10 @@ __device__ inline void cell_coords(const StructInfo& st, double x, double y, dou
 
 __global__ void k_cell_key(const double* __restrict__ pos, int64_t N,
                            const int32_t* __restrict__ sid, const StructInfo* __restrict__ structs,
-                           int32_t* __restrict__ key, int32_t* __restrict__ cell_count) {
+                           int32_t* __restrict__ key, int32_t* __restrict__ cell_count,
+                           const int32_t* gate) {
   int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= N) return;
+  if (e >= N || gated_off(gate)) return;
   const StructInfo& st = structs[sid[e]];
   int k = st.cell_off;
   if (st.mode == kModeCells) {
@@ -74,8 +85,10 @@ __global__ void k_cell_key(const double* __restrict__ pos, int64_t N,
 
 // Exclusive scan of n int32 counts by one block of 1024 threads.
 __global__ void __launch_bounds__(1024) k_scan_1block(const int32_t* __restrict__ in,
-                                                      int32_t* __restrict__ out, int32_t n) {
+                                                      int32_t* __restrict__ out, int32_t n,
+                                                      const int32_t* gate) {
   __shared__ int32_t part[1024];
+  if (gated_off(gate)) return;
   int t = threadIdx.x;
   int chunk = (n + 1023) / 1024;
   int lo = t * chunk, hi = min(n, lo + chunk);
@@ -99,27 +112,32 @@ __global__ void __launch_bounds__(1024) k_scan_1block(const int32_t* __restrict_
 
 __global__ void k_cell_scatter(const int32_t* __restrict__ key, int64_t N,
                                const int32_t* __restrict__ cell_start,
-                               int32_t* __restrict__ cell_fill, int32_t* __restrict__ perm) {
+                               int32_t* __restrict__ cell_fill, int32_t* __restrict__ perm,
+                               const int32_t* gate) {
   int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= N) return;
+  if (e >= N || gated_off(gate)) return;
   int k = key[e];
   int slot = atomicAdd(&cell_fill[k], 1);
   perm[cell_start[k] + slot] = (int32_t)e;
 }
 
-// Order the atoms of each cell by caller index (makes the order independent
-// of the atomic slot assignment above).
+// Order the atoms of each cell by caller index (ext[source index], or the
+// source index itself when ext is NULL).  The internal order is then a
+// function of the positions and caller indices only: independent of the
+// atomic slot assignment above and of the order the atoms came in.
 __global__ void k_cell_sort(const int32_t* __restrict__ cell_start,
                             const int32_t* __restrict__ cell_count, int32_t n_cells,
-                            int32_t* __restrict__ perm) {
+                            const int32_t* __restrict__ ext, int32_t* __restrict__ perm,
+                            const int32_t* gate) {
   int c = blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= n_cells) return;
+  if (c >= n_cells || gated_off(gate)) return;
   int32_t* p = perm + cell_start[c];
   int n = cell_count[c];
   for (int a = 1; a < n; ++a) {
-    int32_t v = p[a];
+    const int32_t v = p[a];
+    const int32_t kv = ext ? ext[v] : v;
     int b = a - 1;
-    while (b >= 0 && p[b] > v) {
+    while (b >= 0 && (ext ? ext[p[b]] : p[b]) > kv) {
       p[b + 1] = p[b];
       --b;
     }
@@ -131,9 +149,10 @@ __global__ void k_gather_atoms(const int32_t* __restrict__ perm, int64_t N,
                                const double* __restrict__ pos_ext,
                                const int32_t* __restrict__ types_ext,
                                const int32_t* __restrict__ sid_ext, double* __restrict__ pos,
-                               int32_t* __restrict__ types, int32_t* __restrict__ sid) {
+                               int32_t* __restrict__ types, int32_t* __restrict__ sid,
+                               const int32_t* gate) {
   int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (k >= N) return;
+  if (k >= N || gated_off(gate)) return;
   int64_t e = perm[k];
   pos[k] = pos_ext[e];
   pos[N + k] = pos_ext[N + e];
@@ -182,9 +201,9 @@ __global__ void __launch_bounds__(kBlock) k_build_rows(
     const double* __restrict__ pos, int64_t N, const int32_t* __restrict__ sid,
     const StructInfo* __restrict__ structs, const int32_t* __restrict__ cell_start,
     const int32_t* __restrict__ cell_count, double rcR2, double rcA2, Lists L,
-    int32_t* __restrict__ overflow) {
+    int32_t* __restrict__ overflow, const int32_t* gate) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= N) return;
+  if (i >= N || gated_off(gate)) return;
   const StructInfo st = structs[sid[i]];
   const double xi = pos[i], yi = pos[N + i], zi = pos[2 * N + i];
   RowWriter R{L.nlR, L.cdR, L.MR, 0}, A{L.nlA, L.cdA, L.MA, 0};
@@ -322,27 +341,117 @@ void launch_assign_struct(const int64_t* offs, int32_t n_struct, int64_t N, int3
 }
 
 void launch_order_atoms(const BuildArgs& b, hipStream_t s) {
-  launch_fill_i32(b.cell_count, b.n_cells, 0, s);
-  launch_fill_i32(b.cell_fill, b.n_cells, 0, s);
+  const int32_t* g = b.gate;
+  hipLaunchKernelGGL(k_fill_i32_gated, grid_for(b.n_cells), dim3(kBlock), 0, s, b.cell_count,
+                     (int64_t)b.n_cells, 0, g);
+  hipLaunchKernelGGL(k_fill_i32_gated, grid_for(b.n_cells), dim3(kBlock), 0, s, b.cell_fill,
+                     (int64_t)b.n_cells, 0, g);
   hipLaunchKernelGGL(k_cell_key, grid_for(b.N), dim3(kBlock), 0, s, b.pos_ext, b.N, b.sid_ext,
-                     b.structs, b.key, b.cell_count);
+                     b.structs, b.key, b.cell_count, g);
   hipLaunchKernelGGL(k_scan_1block, dim3(1), dim3(1024), 0, s, b.cell_count, b.cell_start,
-                     b.n_cells);
+                     b.n_cells, g);
   hipLaunchKernelGGL(k_cell_scatter, grid_for(b.N), dim3(kBlock), 0, s, b.key, b.N,
-                     b.cell_start, b.cell_fill, b.perm);
+                     b.cell_start, b.cell_fill, b.perm, g);
   hipLaunchKernelGGL(k_cell_sort, grid_for(b.n_cells), dim3(kBlock), 0, s, b.cell_start,
-                     b.cell_count, b.n_cells, b.perm);
+                     b.cell_count, b.n_cells, b.ext_src, b.perm, g);
   hipLaunchKernelGGL(k_gather_atoms, grid_for(b.N), dim3(kBlock), 0, s, b.perm, b.N, b.pos_ext,
-                     b.types_ext, b.sid_ext, b.pos, b.types, b.sid);
+                     b.types_ext, b.sid_ext, b.pos, b.types, b.sid, g);
 }
 
 void launch_build_rows(const BuildArgs& b, const Lists& L, hipStream_t s) {
   hipLaunchKernelGGL(k_build_rows, grid_for(b.N), dim3(kBlock), 0, s, b.pos, b.N, b.sid,
-                     b.structs, b.cell_start, b.cell_count, b.rcR2, b.rcA2, L, b.overflow);
-  hipLaunchKernelGGL(k_reverse, grid_for(b.N), dim3(kBlock), 0, s, b.N, L.nnR, L.nlR, L.cdR,
-                     L.MR, L.revR, b.overflow + 2);
-  hipLaunchKernelGGL(k_reverse, grid_for(b.N), dim3(kBlock), 0, s, b.N, L.nnA, L.nlA, L.cdA,
-                     L.MA, L.revA, b.overflow + 2);
+                     b.structs, b.cell_start, b.cell_count, b.rcR2, b.rcA2, L, b.overflow,
+                     (const int32_t*)nullptr);
+  launch_reverse(b.N, L, b.overflow + 2, s);
+}
+
+void launch_reverse(int64_t N, const Lists& L, int32_t* err, hipStream_t s) {
+  hipLaunchKernelGGL(k_reverse, grid_for(N), dim3(kBlock), 0, s, N, L.nnR, L.nlR, L.cdR, L.MR,
+                     L.revR, err);
+  hipLaunchKernelGGL(k_reverse, grid_for(N), dim3(kBlock), 0, s, N, L.nnA, L.nlA, L.cdA, L.MA,
+                     L.revA, err);
+}
+
+// Candidate rows at r_c^R + skin (radial slots of V only), rebuilt when the
+// gate is set.
+void launch_build_verlet(const BuildArgs& b, const Lists& V, hipStream_t s) {
+  hipLaunchKernelGGL(k_build_rows, grid_for(b.N), dim3(kBlock), 0, s, b.pos, b.N, b.sid,
+                     b.structs, b.cell_start, b.cell_count, b.rcR2, -1.0, V, b.overflow + 5,
+                     b.gate);
+}
+
+// Exact rows at r_c^R and r_c^A from the candidate rows, order preserved (so
+// still sorted by (j, image)), with the same float64 membership test.
+template <bool BATCH>
+__global__ void __launch_bounds__(kBlock) k_filter_rows(const double* __restrict__ pos, int64_t N,
+                                                        const int32_t* __restrict__ sid,
+                                                        const StructInfo* __restrict__ structs,
+                                                        StructInfo st0, Lists V, double rcR2,
+                                                        double rcA2, Lists L,
+                                                        int32_t* __restrict__ overflow) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= N) return;
+  const StructInfo& st = BATCH ? structs[sid[i]] : st0;
+  RowWriter R{L.nlR, L.cdR, L.MR, 0}, A{L.nlA, L.cdA, L.MA, 0};
+  const int nv = min(V.nnR[i], V.MR);
+  for (int m = 0; m < nv; ++m) {
+    const int64_t e = (int64_t)m * N + i;
+    const int32_t j = V.nlR[e];
+    const uint16_t code = V.cdR[e];
+    double dx, dy, dz;
+    entry_disp(pos, N, i, j, st, code, dx, dy, dz);
+    const double r2 = norm2_exact(dx, dy, dz);
+    if (r2 < rcR2) {
+      R.push(N, i, j, code);
+      if (r2 < rcA2) A.push(N, i, j, code);
+    }
+  }
+  L.nnR[i] = R.count;
+  L.nnA[i] = A.count;
+  if (R.count > L.MR) atomicMax(&overflow[0], R.count);
+  if (A.count > L.MA) atomicMax(&overflow[1], A.count);
+}
+
+void launch_filter_rows(const BuildArgs& b, const StructInfo& st0, bool batch, const Lists& V,
+                        const Lists& L, hipStream_t s) {
+  if (batch)
+    hipLaunchKernelGGL(k_filter_rows<true>, grid_for(b.N), dim3(kBlock), 0, s, b.pos, b.N, b.sid,
+                       b.structs, st0, V, b.rcR2, b.rcA2, L, b.overflow);
+  else
+    hipLaunchKernelGGL(k_filter_rows<false>, grid_for(b.N), dim3(kBlock), 0, s, b.pos, b.N, b.sid,
+                       b.structs, st0, V, b.rcR2, b.rcA2, L, b.overflow);
+  launch_reverse(b.N, L, b.overflow + 2, s);
+}
+
+// gate = any |r_i - r_i(at last build)|^2 > thr2
+__global__ void k_check_displacement(const double* __restrict__ pos, const double* __restrict__ ref,
+                                     int64_t N, double thr2, int32_t* __restrict__ gate) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= N) return;
+  const double dx = pos[i] - ref[i], dy = pos[N + i] - ref[N + i], dz = pos[2 * N + i] - ref[2 * N + i];
+  if (dx * dx + dy * dy + dz * dz > thr2) atomicExch(gate, 1);
+}
+
+void launch_check_displacement(const double* pos, const double* ref, int64_t N, double thr2,
+                               int32_t* gate, hipStream_t s) {
+  hipLaunchKernelGGL(k_check_displacement, grid_for(N), dim3(kBlock), 0, s, pos, ref, N, thr2, gate);
+}
+
+template <class T>
+__global__ void k_copy_gated(T* __restrict__ dst, const T* __restrict__ src, int64_t n,
+                             const int32_t* gate) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n && !gated_off(gate)) dst[i] = src[i];
+}
+
+void launch_copy_gated_f64(double* dst, const double* src, int64_t n, const int32_t* gate,
+                           hipStream_t s) {
+  hipLaunchKernelGGL(k_copy_gated<double>, grid_for(n), dim3(kBlock), 0, s, dst, src, n, gate);
+}
+
+void launch_copy_gated_i32(int32_t* dst, const int32_t* src, int64_t n, const int32_t* gate,
+                           hipStream_t s) {
+  hipLaunchKernelGGL(k_copy_gated<int32_t>, grid_for(n), dim3(kBlock), 0, s, dst, src, n, gate);
 }
 
 void launch_type_rows(const int32_t* types, int64_t N, int32_t T, int32_t per_type,

@@ -12,6 +12,7 @@ struct BuildArgs {
   const double* pos_ext;      // caller order [3][N]
   const int32_t* types_ext;
   const int32_t* sid_ext;
+  const int32_t* ext_src;     // caller index of each source atom (NULL: the source index)
   const StructInfo* structs;
   int32_t* key;               // [N]
   int32_t* cell_count;        // [n_cells]
@@ -22,7 +23,9 @@ struct BuildArgs {
   int32_t* types;             // internal
   int32_t* sid;               // internal
   double rcR2, rcA2;
-  int32_t* overflow;          // [3]: max radial row, max angular row, rev error
+  int32_t* overflow;          // flags: [0] radial row, [1] angular row, [2] rev error,
+                              // [5] candidate row overflow (max counts)
+  const int32_t* gate;        // rebuild kernels run only when *gate != 0 (NULL: always)
 };
 
 struct EvalArgs {
@@ -57,6 +60,16 @@ void launch_assign_struct(const int64_t* offs, int32_t n_struct, int64_t N, int3
                           hipStream_t s);
 void launch_order_atoms(const BuildArgs& b, hipStream_t s);
 void launch_build_rows(const BuildArgs& b, const Lists& L, hipStream_t s);
+void launch_reverse(int64_t N, const Lists& L, int32_t* err, hipStream_t s);
+void launch_build_verlet(const BuildArgs& b, const Lists& V, hipStream_t s);
+void launch_filter_rows(const BuildArgs& b, const StructInfo& st0, bool batch, const Lists& V,
+                        const Lists& L, hipStream_t s);
+void launch_check_displacement(const double* pos, const double* ref, int64_t N, double thr2,
+                               int32_t* gate, hipStream_t s);
+void launch_copy_gated_f64(double* dst, const double* src, int64_t n, const int32_t* gate,
+                           hipStream_t s);
+void launch_copy_gated_i32(int32_t* dst, const int32_t* src, int64_t n, const int32_t* gate,
+                           hipStream_t s);
 void launch_type_rows(const int32_t* types, int64_t N, int32_t T, int32_t per_type,
                       int32_t* tcount, int32_t* toff, int32_t* tcursor, int32_t* rows,
                       int64_t rows_len, hipStream_t s);
@@ -116,6 +129,10 @@ void launch_srv_kick(int64_t N, double* vel, const double* F, const double* hdm,
 void launch_fill_u8(uint8_t* a, int64_t n, uint8_t v, hipStream_t s);
 void launch_srv_factors(int64_t n, const int32_t* types, const double* inv_mass, double half_dt, double dt,
                         double* hdm, double* dta, hipStream_t s);
+void launch_gather3_gated(const int32_t* src, int64_t N, const double* in, double* out,
+                          const int32_t* gate, hipStream_t s);
+void launch_gather_i32_gated(const int32_t* src, int64_t N, const int32_t* in, int32_t* out,
+                             const int32_t* gate, hipStream_t s);
 void launch_gather_i32(const int32_t* src, int64_t N, const int32_t* in, int32_t* out, hipStream_t s);
 
 }  // namespace nep
