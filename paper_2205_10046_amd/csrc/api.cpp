@@ -299,6 +299,7 @@ struct nep_handle {
   Lists L{};
   Lists V{};                       // candidate rows at r_c^R + skin (MD with a skin)
   double* pos_ref = nullptr;       // positions at the last candidate-row build
+  int32_t* row_counter = nullptr;  // thermo row of graph-replayed MD steps
   double* ref_save = nullptr;
   float *q = nullptr, *fp = nullptr, *U = nullptr, *sums = nullptr, *pr = nullptr, *pa = nullptr;
   float *F = nullptr, *W = nullptr, *F_save = nullptr;
@@ -341,7 +342,7 @@ struct nep_handle {
     free_lists();
     dev_free(q); dev_free(fp); dev_free(U); dev_free(sums); dev_free(F); dev_free(W);
     dev_free(F_save); dev_free(pos_save); dev_free(vel_save); dev_free(types_save);
-    dev_free(ext_save); dev_free(pos_ref); dev_free(ref_save);
+    dev_free(ext_save); dev_free(pos_ref); dev_free(ref_save); dev_free(row_counter);
     free_verlet();
     capN = 0; cap_cells = 0; thermo_cap = 0; MR = MA = 0;
   }
@@ -1512,11 +1513,78 @@ int md_skin(nep_handle* h, const Prepared& pp, double* d_pos, double* d_vel, con
   md.pos = h->pos;
   md.vel = h->vel;
   md.types = h->types;
-  const int64_t chunk = 50;
+  // one MD step with a device-decided rebuild (a fixed kernel sequence)
+  auto step_body = [&](hipStream_t cs) {
+    {
+      Stage st(h, "integrate", cs);
+      launch_kick_drift(md, cs);
+    }
+    {
+      Stage st(h, "order_atoms", cs);
+      launch_fill_i32(gate, 1, 0, cs);
+      launch_check_displacement(h->pos, h->pos_ref, N, thr2, gate, cs);
+      skin_rebuild(h, pp, rl, gate, cs);
+    }
+    {
+      Stage st(h, "neighbor_rows", cs);
+      skin_filter(h, pp, cs);
+    }
+    forces(h, pp, cs);
+    {
+      Stage st(h, "integrate", cs);
+      launch_kick(md, cs);
+    }
+  };
+  // Replay groups of G steps (+ their thermo row) from a captured HIP graph;
+  // per-stage event timing (nep_set_timing) uses direct launches instead.
+  const int64_t G = thermo_every > 0 ? thermo_every : 10;
+  const char* genv = std::getenv("NEP_MD_GRAPH");
+  const bool use_graph = !h->timing && !(genv && genv[0] == '0') && n_steps >= G && G <= 1000;
+  if (!h->row_counter) dev_alloc(h->row_counter, 1);
+  hipStream_t gs = s;
+  hipStream_t own = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  if (use_graph) {
+    if (!gs) {
+      HIPCHK(hipStreamCreateWithFlags(&own, hipStreamNonBlocking));
+      gs = own;
+    }
+    HIPCHK(hipStreamSynchronize(s));
+    try {
+      HIPCHK(hipStreamBeginCapture(gs, hipStreamCaptureModeThreadLocal));
+      for (int64_t k = 0; k < G; ++k) step_body(gs);
+      if (thermo_every > 0)
+        launch_thermo_counted(h->U, h->W, h->vel, h->types, h->mass, N, h->partial, num_partials(N),
+                              h->thermo, h->row_counter, (double)thermo_every, kAmuA2fs2, kBoltzmann, gs);
+      HIPCHK(hipStreamEndCapture(gs, &graph));
+      HIPCHK(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
+    } catch (...) {
+      hipGraph_t g2 = nullptr;
+      (void)hipStreamEndCapture(gs, &g2);
+      if (g2) (void)hipGraphDestroy(g2);
+      if (graph) (void)hipGraphDestroy(graph);
+      if (own) (void)hipStreamDestroy(own);
+      throw;
+    }
+  }
+  struct GraphGuard {
+    hipGraph_t g;
+    hipGraphExec_t e;
+    hipStream_t own;
+    ~GraphGuard() {
+      if (e) (void)hipGraphExecDestroy(e);
+      if (g) (void)hipGraphDestroy(g);
+      if (own) (void)hipStreamDestroy(own);
+    }
+  } guard{graph, exec, own};
+  hipStream_t ws = use_graph ? gs : s;   // the stream every step runs on
+  const int64_t chunk = use_graph ? G * std::max<int64_t>(1, 50 / G) : 50;
   int64_t row = 0;
   bool redo = false;
   for (int64_t c0 = 0; c0 < n_steps;) {
     const int64_t c1 = std::min(n_steps, c0 + chunk);
+    s = ws;
     HIPCHK(hipMemcpyAsync(h->pos_save, h->pos, 3 * N * sizeof(double), hipMemcpyDeviceToDevice, s));
     HIPCHK(hipMemcpyAsync(h->vel_save, h->vel, 3 * N * sizeof(double), hipMemcpyDeviceToDevice, s));
     HIPCHK(hipMemcpyAsync(h->ref_save, h->pos_ref, 3 * N * sizeof(double), hipMemcpyDeviceToDevice, s));
@@ -1529,26 +1597,19 @@ int md_skin(nep_handle* h, const Prepared& pp, double* d_pos, double* d_vel, con
       skin_rebuild(h, pp, rl, nullptr, s);
       redo = false;
     }
+    if (use_graph) {
+      int32_t* rc = (int32_t*)(h->pinned + 416);
+      *rc = (int32_t)row;
+      HIPCHK(hipMemcpyAsync(h->row_counter, rc, sizeof(int32_t), hipMemcpyHostToDevice, s));
+    }
     for (int64_t step = c0 + 1; step <= c1; ++step) {
-      {
-        Stage st(h, "integrate", s);
-        launch_kick_drift(md, s);
+      if (use_graph && (step - 1) % G == 0 && step - 1 + G <= c1) {
+        HIPCHK(hipGraphLaunch(exec, s));
+        if (thermo_every > 0) ++row;
+        step += G - 1;
+        continue;
       }
-      {
-        Stage st(h, "order_atoms", s);
-        launch_fill_i32(gate, 1, 0, s);
-        launch_check_displacement(h->pos, h->pos_ref, N, thr2, gate, s);
-        skin_rebuild(h, pp, rl, gate, s);
-      }
-      {
-        Stage st(h, "neighbor_rows", s);
-        skin_filter(h, pp, s);
-      }
-      forces(h, pp, s);
-      {
-        Stage st(h, "integrate", s);
-        launch_kick(md, s);
-      }
+      step_body(s);
       if (thermo_every > 0 && step % thermo_every == 0) {
         Stage st(h, "thermo", s);
         launch_thermo(h->U, h->W, h->vel, h->types, h->mass, N, h->partial, num_partials(N),

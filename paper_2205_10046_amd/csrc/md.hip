@@ -67,8 +67,15 @@ __global__ void __launch_bounds__(kRed) k_thermo_partial(const float* __restrict
 }
 
 __global__ void k_thermo_final(const double* __restrict__ partial, int64_t n_part, int64_t N,
-                               double step, double kin_conv, double kB, double* __restrict__ row) {
+                               double step, double kin_conv, double kB, double* __restrict__ row,
+                               int32_t* __restrict__ counter, double every) {
   if (threadIdx.x != 0) return;
+  if (counter) {  // row and step number from a device counter (graph replays)
+    const int32_t r = *counter;
+    *counter = r + 1;
+    row += 13 * (int64_t)r;
+    step = (double)(r + 1) * every;
+  }
   double s[11] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
   for (int64_t b = 0; b < n_part; ++b)
     for (int v = 0; v < 11; ++v) s[v] += partial[b * 11 + v];
@@ -87,7 +94,18 @@ void launch_thermo(const float* U, const float* W, const double* vel, const int3
   hipLaunchKernelGGL(k_thermo_partial, dim3((unsigned)n_part), dim3(kRed), 0, s, U, W, vel, types,
                      mass, N, chunk, partial);
   hipLaunchKernelGGL(k_thermo_final, dim3(1), dim3(64), 0, s, partial, n_part, N, step, kin_conv,
-                     kB, row);
+                     kB, row, (int32_t*)nullptr, 0.0);
+}
+
+void launch_thermo_counted(const float* U, const float* W, const double* vel, const int32_t* types,
+                           const double* mass, int64_t N, double* partial, int64_t n_part,
+                           double* rows, int32_t* counter, double every, double kin_conv, double kB,
+                           hipStream_t s) {
+  const int64_t chunk = (N + n_part - 1) / n_part;
+  hipLaunchKernelGGL(k_thermo_partial, dim3((unsigned)n_part), dim3(kRed), 0, s, U, W, vel, types,
+                     mass, N, chunk, partial);
+  hipLaunchKernelGGL(k_thermo_final, dim3(1), dim3(64), 0, s, partial, n_part, N, 0.0, kin_conv, kB,
+                     rows, counter, every);
 }
 
 // new[k] = old[src[k]] for positions and velocities ([3][N] each)

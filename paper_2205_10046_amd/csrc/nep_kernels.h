@@ -115,6 +115,10 @@ void launch_kick(const MDArgs& a, hipStream_t s);
 void launch_thermo(const float* U, const float* W, const double* vel, const int32_t* types,
                    const double* mass, int64_t N, double* partial, int64_t n_part,
                    double* row, double step, double kin_conv, double kB, hipStream_t s);
+void launch_thermo_counted(const float* U, const float* W, const double* vel, const int32_t* types,
+                           const double* mass, int64_t N, double* partial, int64_t n_part,
+                           double* rows, int32_t* counter, double every, double kin_conv, double kB,
+                           hipStream_t s);
 void launch_permute_md(const int32_t* perm_old_to_new_src, int64_t N, const double* src_pos,
                        const double* src_vel, double* dst_pos, double* dst_vel, hipStream_t s);
 void launch_unpermute_md(const int32_t* perm, int64_t N, const double* pos_int,
