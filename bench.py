@@ -25,6 +25,7 @@ sys.path.insert(0, ROOT)
 
 WORKLOAD = "fcc131k"
 THERMO_EVERY = 10
+SKIN = 1.0   # Angstrom: rows at r_c + 1 A, rebuilt after a 0.5 A displacement
 # MI355X: FP32 vector peak without packed-FP32 instructions (all device code is
 # built with packed FP32 disabled): 256 CU x 64 lanes x 2 flop x 2.4 GHz
 PEAK_FP32_VALU = 256 * 64 * 2 * 2.4e9 / 1e12
@@ -70,25 +71,33 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--no-2m", action="store_true")
+    ap.add_argument("--steps-2m", type=int, default=20)
     ap.add_argument("--serve-requests", type=int, default=200)
     ap.add_argument("--serve-budget-gb", type=float, default=2.0)
     return ap.parse_args()
 
 
 def run_md(handle, pos_d, vel_d, types_d, masses, box, steps, warmup, torch):
+    """Time `steps` NVE steps (graph-replayed, no instrumentation); then run the
+    same number of steps again with HIP-event timing of every stage on the work
+    stream, for the per-kernel averages."""
     th = torch.zeros((max(steps // THERMO_EVERY, 1), 13), dtype=torch.float64,
                      device=pos_d.device)
     if warmup:
         handle.md_run_dev(pos_d, vel_d, types_d, masses, box, 1.0, warmup, 0, th)
     torch.cuda.synchronize()
-    handle.set_timing(True)
     t0 = time.perf_counter()
     handle.md_run_dev(pos_d, vel_d, types_d, masses, box, 1.0, steps, THERMO_EVERY, th)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
+    rows = th.cpu().numpy()
+    handle.set_timing(True)
+    handle.md_run_dev(pos_d, vel_d, types_d, masses, box, 1.0, steps, THERMO_EVERY, th)
+    torch.cuda.synchronize()
     stages = handle.timing()
     handle.set_timing(False)
-    return dt, stages, th.cpu().numpy()
+    return dt, stages, rows
 
 
 def serving_leg(nep, synth, params_of, n_req, budget_gb, prec):
@@ -189,7 +198,7 @@ def main():
 
     results = {}
     for prec in ([nep.NEP_MLP_FP32] + ([] if args.no_bf16 else [nep.NEP_MLP_BF16])):
-        handle = nep.Handle(h, params, mlp_precision=prec)
+        handle = nep.Handle(h, params, mlp_precision=prec, skin=SKIN)
         pos_d = torch.tensor(pos, device=dev)
         vel_d = torch.tensor(vel, device=dev)
         types_d = torch.tensor(types, device=dev)
@@ -224,7 +233,8 @@ def main():
         "config": {"workload": "fcc131k: 131,072-atom 4-species random FCC alloy "
                                "(32^3 cells, a=4.05 A), NEP r_c 6/5 A, n_max 8/6, "
                                "N_bas 8/6, l_max 4 + 4-body, 50 neurons per species, "
-                               "NVE dt=1 fs from 300 K, thermo every 10 steps",
+                               "NVE dt=1 fs from 300 K, thermo every 10 steps, "
+                               "rows at r_c + 1 A rebuilt after a 0.5 A displacement",
                    "atoms": n, "mlp": "fp32"},
         "roofline": {"bound": "alu", "kernel": dom, "achieved": achieved,
                      "peak": PEAK_FP32_VALU, "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_VALU,
@@ -247,6 +257,29 @@ def main():
                                         "avg_launch_ms": avgb["mlp"]}}
     out["paper_context"] = {"A100_NEP3_MgAlCu": 1.5e7, "V100_NEP_carbon_4.2A": 3.6e6,
                             "unit": "atom-step/s", "note": "other hardware and models"}
+    if not args.no_2m:
+        # 2,000,000-atom BCC, l_max = 6 with 4-body and 5-body terms: FP32 vs BF16
+        h2 = synth.WORKLOADS["bcc2m"]
+        p2 = synth.random_params(nep.nep_num_params(h2))
+        pos2, types2, box2 = synth.bcc2m()
+        m2 = np.array(synth.MASSES["bcc2m"])
+        vel2 = synth.maxwell_velocities(m2[types2], 300.0)
+        out["bcc2m"] = {"atoms": pos2.shape[1], "steps": args.steps_2m}
+        for prec, tag in ((nep.NEP_MLP_FP32, "fp32"), (nep.NEP_MLP_BF16, "bf16")):
+            if tag == "bf16" and args.no_bf16:
+                continue
+            hd = nep.Handle(h2, p2, mlp_precision=prec, skin=SKIN)
+            pd_ = torch.tensor(pos2, device=dev)
+            vd_ = torch.tensor(vel2, device=dev)
+            td_ = torch.tensor(types2, device=dev)
+            t2, st2, _ = run_md(hd, pd_, vd_, td_, m2, box2, args.steps_2m, 2, torch)
+            out["bcc2m"][tag] = {"value": pos2.shape[1] * args.steps_2m / t2,
+                                 "ms_per_step": t2 / args.steps_2m * 1e3,
+                                 "stages_ms_per_step": {k: v[0] / args.steps_2m
+                                                        for k, v in st2.items()}}
+            hd.close()
+            del pd_, vd_, td_
+            torch.cuda.empty_cache()
     if not args.no_serve:
         pof = lambda hh: synth.random_params(nep.nep_num_params(hh))  # noqa: E731
         out["serving"] = {"fp32": serving_leg(nep, synth, pof, args.serve_requests,

@@ -190,6 +190,22 @@ def test_full_size_fcc131k_sampled(handles):
     assert np.abs(res["F"].sum(axis=1)).max() < 1e-3
 
 
+def test_full_size_bcc2m_sampled(handles):
+    """The 2,000,000-atom BCC workload (l_max = 6, 4-body, 5-body): sampled atoms."""
+    h = synth.WORKLOADS["bcc2m"]
+    pos, types, box = synth.bcc2m()
+    handle, p = handles("bcc2m", h)
+    log(f"[full] bcc2m N={pos.shape[1]}")
+    res = handle.compute(pos, types, box)
+    idx = np.random.default_rng(6).choice(pos.shape[1], 6, replace=False)
+    ref = O.evaluate_atoms(h, p, pos, types, box, idx)
+    dU = np.abs(res["U"][idx] - ref["U"]).max()
+    dF = np.abs(res["F"][:, idx].T - ref["F"]).max()
+    dW = np.abs(res["W"][:, idx].T - ref["W"]).max()
+    log(f"[full] bcc2m sampled: max|dU|={dU:.2e} max|dF|={dF:.2e} max|dW|={dW:.2e}")
+    assert dU <= TOL_SITE and dF <= TOL_F and dW <= TOL_W
+
+
 def test_md_short_trajectory_matches_oracle(handles):
     h = synth.WORKLOADS["diamond216"]
     pos, types, box = synth.diamond216()
