@@ -294,14 +294,15 @@ struct nep_handle {
   int32_t *types_ext = nullptr, *types = nullptr, *types2 = nullptr, *sid_ext = nullptr, *sid = nullptr;
   int32_t *key = nullptr, *perm = nullptr, *ext_id = nullptr, *ext_id2 = nullptr, *inv = nullptr;
   int32_t *cell_count = nullptr, *cell_fill = nullptr, *cell_start = nullptr;
-  int32_t *rows = nullptr, *tcount = nullptr, *toff = nullptr, *tcursor = nullptr, *flags = nullptr;
+  int32_t *rows = nullptr, *tblk = nullptr, *tex = nullptr, *toff = nullptr, *flags = nullptr;
   StructInfo* structs = nullptr;
   Lists L{};
   Lists V{};                       // candidate rows at r_c^R + skin (MD with a skin)
   double* pos_ref = nullptr;       // positions at the last candidate-row build
   int32_t* row_counter = nullptr;  // thermo row of graph-replayed MD steps
   double* ref_save = nullptr;
-  float *q = nullptr, *fp = nullptr, *U = nullptr, *sums = nullptr, *pr = nullptr, *pa = nullptr;
+  float *q = nullptr, *fp = nullptr, *U = nullptr, *sums = nullptr;
+  float4* P = nullptr;
   float *F = nullptr, *W = nullptr, *F_save = nullptr;
   double *pos_save = nullptr, *vel_save = nullptr;
   int32_t *types_save = nullptr, *ext_save = nullptr;
@@ -336,7 +337,7 @@ struct nep_handle {
     dev_free(types_ext); dev_free(types); dev_free(types2); dev_free(sid_ext); dev_free(sid);
     dev_free(key); dev_free(perm); dev_free(ext_id); dev_free(ext_id2); dev_free(inv);
     dev_free(cell_count); dev_free(cell_fill); dev_free(cell_start);
-    dev_free(rows); dev_free(tcount); dev_free(toff); dev_free(tcursor); dev_free(flags);
+    dev_free(rows); dev_free(tblk); dev_free(tex); dev_free(toff); dev_free(flags);
     dev_free(structs); dev_free(offs);
     cap_struct = 0;
     free_lists();
@@ -349,13 +350,14 @@ struct nep_handle {
 
   void free_verlet() {
     dev_free(V.nnR); dev_free(V.nlR); dev_free(V.cdR); dev_free(V.nnA);
+    dev_free(V.revR); dev_free(V.fmap);
     V = Lists{};
   }
 
   void free_lists() {
     dev_free(L.nnR); dev_free(L.nlR); dev_free(L.cdR); dev_free(L.revR);
-    dev_free(L.nnA); dev_free(L.nlA); dev_free(L.cdA); dev_free(L.revA);
-    dev_free(pr); dev_free(pa);
+    dev_free(L.nnA); dev_free(L.nlA); dev_free(L.cdA); dev_free(L.amap);
+    dev_free(P);
   }
 
   // ---- timing helpers ----
@@ -481,14 +483,16 @@ int32_t estimate_capacity(double rc, double density) {
 
 void ensure_lists(nep_handle* h, int64_t N, int32_t MR, int32_t MA) {
   if (N <= h->capN && MR <= h->MR && MA <= h->MA && h->L.nlR) return;
+  if (MR > kMaxRow || MA > kMaxRow)
+    throw Failure{NEP_E_NEIGHBOR_OVERFLOW, "neighbour rows longer than 65535 entries"};
   h->free_lists();
   const int64_t cap = std::max(N, h->capN);
   dev_alloc(h->L.nnR, cap); dev_alloc(h->L.nnA, cap);
   dev_alloc(h->L.nlR, (size_t)MR * cap); dev_alloc(h->L.cdR, (size_t)MR * cap);
   dev_alloc(h->L.revR, (size_t)MR * cap);
   dev_alloc(h->L.nlA, (size_t)MA * cap); dev_alloc(h->L.cdA, (size_t)MA * cap);
-  dev_alloc(h->L.revA, (size_t)MA * cap);
-  dev_alloc(h->pr, (size_t)3 * MR * cap); dev_alloc(h->pa, (size_t)3 * MA * cap);
+  dev_alloc(h->L.amap, (size_t)MA * cap);
+  dev_alloc(h->P, (size_t)MR * cap);
   h->MR = MR;
   h->MA = MA;
   h->L.MR = MR;
@@ -511,8 +515,8 @@ void ensure_atoms(nep_handle* h, int64_t N, int32_t n_cells, bool md) {
     dev_alloc(h->F, 3 * c); dev_alloc(h->W, 9 * c);
     h->rows_cap = rows_length(c, M.T);
     dev_alloc(h->rows, h->rows_cap);
-    dev_alloc(h->tcount, kMaxTypes + 1); dev_alloc(h->toff, kMaxTypes + 1);
-    dev_alloc(h->tcursor, kMaxTypes + 1); dev_alloc(h->flags, 8);
+    dev_alloc(h->tblk, kMaxTypes * type_row_blocks(c)); dev_alloc(h->tex, kMaxTypes * type_row_blocks(c));
+    dev_alloc(h->toff, kMaxTypes + 1); dev_alloc(h->flags, 8);
     h->cap_part = num_partials(c);
     dev_alloc(h->partial, 11 * h->cap_part); dev_alloc(h->totals, 16);
     dev_alloc(h->structs, 1);
@@ -579,8 +583,7 @@ EvalArgs eval_args(nep_handle* h, const Prepared& pp, const DevModel& M) {
   a.fp = h->fp;
   a.U = h->U;
   a.sums = h->sums;
-  a.pr = h->pr;
-  a.pa = h->pa;
+  a.P = h->P;
   a.F = h->F;
   a.W = h->W;
   a.rows = h->rows;
@@ -697,8 +700,8 @@ void order_and_build(nep_handle* h, const Prepared& pp, const double* pos_src, c
   {
     Stage st(h, "order_atoms", s);
     launch_order_atoms(b, s);
-    launch_type_rows(h->types, pp.N, h->M.T, h->hp.nn_per_type, h->tcount, h->toff, h->tcursor,
-                     h->rows, rows_length(pp.N, h->M.T), s);
+    launch_type_rows(h->types, pp.N, h->M.T, h->hp.nn_per_type, h->tblk, h->tex, h->toff, h->rows,
+                     rows_length(pp.N, h->M.T), nullptr, s);
   }
   build_rows_checked(h, pp, b, s, check);
 }
@@ -1406,12 +1409,15 @@ namespace {
 
 void ensure_verlet(nep_handle* h, int64_t N, int32_t MV) {
   if (h->V.nlR && MV <= h->V.MR && N <= h->capN) return;
+  if (MV > kMaxRow) throw Failure{NEP_E_NEIGHBOR_OVERFLOW, "candidate rows longer than 65535 entries"};
   h->free_verlet();
   const int64_t cap = h->capN;
   dev_alloc(h->V.nnR, cap);
   dev_alloc(h->V.nnA, cap);
   dev_alloc(h->V.nlR, (size_t)MV * cap);
   dev_alloc(h->V.cdR, (size_t)MV * cap);
+  dev_alloc(h->V.revR, (size_t)MV * cap);
+  dev_alloc(h->V.fmap, (size_t)MV * cap);
   h->V.MR = MV;
   h->V.MA = 0;
   if (!h->pos_ref) {
@@ -1440,12 +1446,12 @@ void skin_rebuild(nep_handle* h, const Prepared& pp, double rl, const int32_t* g
   bv.rcR2 = rl * rl;
   bv.gate = gate;
   launch_build_verlet(bv, h->V, s);
+  launch_type_rows(h->types, N, h->M.T, h->hp.nn_per_type, h->tblk, h->tex, h->toff, h->rows,
+                   rows_length(N, h->M.T), gate, s);
 }
 
 void skin_filter(nep_handle* h, const Prepared& pp, hipStream_t s) {
   BuildArgs bf = build_args(h, pp, nullptr, nullptr, h->pos, h->types);
-  launch_type_rows(h->types, pp.N, h->M.T, h->hp.nn_per_type, h->tcount, h->toff, h->tcursor, h->rows,
-                   rows_length(pp.N, h->M.T), s);
   launch_filter_rows(bf, pp.geo.st, pp.batch, h->V, h->L, s);
 }
 
@@ -1712,8 +1718,8 @@ static int md_impl(nep_handle* h, int64_t N, double* d_pos, double* d_vel, const
         Stage st(h, "order_atoms", s);
         launch_order_atoms(b, s);
         launch_permute_md(h->perm, N, h->pos, h->vel, h->pos2, h->vel2, s);
-        launch_type_rows(h->types2, N, h->M.T, h->hp.nn_per_type, h->tcount, h->toff, h->tcursor, h->rows,
-                         rows_length(N, h->M.T), s);
+        launch_type_rows(h->types2, N, h->M.T, h->hp.nn_per_type, h->tblk, h->tex, h->toff, h->rows,
+                         rows_length(N, h->M.T), nullptr, s);
       }
       std::swap(h->pos, h->pos2);
       std::swap(h->vel, h->vel2);

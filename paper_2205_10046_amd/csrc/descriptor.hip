@@ -10,12 +10,14 @@
 //   * angular: g_n(r) for a group of NG radial functions and S_{n,k} += g_n b_k
 //     held in registers (NG x NB accumulators), then q_{nl}, q_{n222},
 //     q_{n1111} from S; S is kept (SoA) for the force pass.
-// Partial-force pass (eq. partial_force): dU_i/dr_ij for every list entry,
-//   radial and angular separately; the radial part uses per-atom tables
-//   A_{t,k} = sum_n dU/dq_n c^{t_i t}_{nk}.
+// Partial-force pass (eq. partial_force): dU_i/dr_ij for every radial entry;
+//   the radial part uses per-atom tables A_{t,k} = sum_n dU/dq_n c^{t_i t}_{nk},
+//   and the angular part of a pair within r_c^A is added into the same slot
+//   (the angular row maps into the radial row).
 // Gather (eqs. F_ij, F_i, virial): F_i = sum_j dU_i/dr_ij - dU_j/dr_ji and
-//   W_i = sum_j r_ij (x) dU_j/dr_ji, reading dU_j/dr_ji through the reverse
-//   index: no atomics, so results are bitwise reproducible.
+//   W_i = sum_j r_ij (x) dU_j/dr_ji over the radial row, reading dU_j/dr_ji
+//   through the reverse index: no atomics, so results are bitwise
+//   reproducible.
 #include <vector>
 
 #include "angular.h"
@@ -228,8 +230,7 @@ __global__ void __launch_bounds__(kBlock, (NG * num_poly(L) > 120) ? 1 : 2)
       At[(t * KR + k) * B + tid] = s;
     }
   const float rcR = M.rcR;
-  const int MR = a.L.MR;
-  const int nnR = min(a.L.nnR[i], MR);
+  const int nnR = min(a.L.nnR[i], a.L.MR);
   for (int m = 0; m < nnR; ++m) {
     const int64_t e = (int64_t)m * N + i;
     const int32_t j = a.L.nlR[e];
@@ -255,16 +256,12 @@ __global__ void __launch_bounds__(kBlock, (NG * num_poly(L) > 120) ? 1 : 2)
       dTk = dTn;
     }
     s *= rinv;
-    float* p = a.pr + e;
-    p[0] = s * fx;
-    p[(int64_t)MR * N] = s * fy;
-    p[(int64_t)2 * MR * N] = s * fz;
+    a.P[e] = make_float4(s * fx, s * fy, s * fz, 0.f);
   }
 
   // ---- angular: sum_{n,k} D_{nk} [g'_n u b_k + g_n d b_k / d r_ij] ----
   const float rcA = M.rcA;
-  const int MA = a.L.MA;
-  const int nnA = min(a.L.nnA[i], MA);
+  const int nnA = min(a.L.nnA[i], a.L.MA);
   for (int g = 0; g < a.ngroups; ++g) {
     // D_{nk} = dU/dS_{nk} through q_{nl}, q_{n222}, q_{n1111}
     float D[NG][NB];
@@ -360,16 +357,12 @@ __global__ void __launch_bounds__(kBlock, (NG * num_poly(L) > 120) ? 1 : 2)
       const float px = s * ux + (Vx - uV * ux) * rinv;
       const float py = s * uy + (Vy - uV * uy) * rinv;
       const float pz = s * uz + (Vz - uV * uz) * rinv;
-      float* p = a.pa + e;
-      if (g == 0) {
-        p[0] = px;
-        p[(int64_t)MA * N] = py;
-        p[(int64_t)2 * MA * N] = pz;
-      } else {
-        p[0] += px;
-        p[(int64_t)MA * N] += py;
-        p[(int64_t)2 * MA * N] += pz;
-      }
+      float4* p = a.P + (int64_t)a.L.amap[e] * N + i;
+      float4 v = *p;
+      v.x += px;
+      v.y += py;
+      v.z += pz;
+      *p = v;
     }
   }
 }
@@ -385,32 +378,24 @@ __global__ void __launch_bounds__(kBlock) k_gather(EvalArgs a, StructInfo st0) {
   if (i >= N) return;
   const StructInfo& st = struct_of<BATCH>(a, st0, i);
   float F[3] = {0.f, 0.f, 0.f}, W[9] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+  const int nn = min(a.L.nnR[i], a.L.MR);
+  for (int m = 0; m < nn; ++m) {
+    const int64_t e = (int64_t)m * N + i;
+    const int32_t j = a.L.nlR[e];
+    const uint16_t code = st.mode == kModeImages ? a.L.cdR[e] : kCodeCenter;
+    const float4 pij = a.P[e];
+    const float4 pji = a.P[(int64_t)a.L.revR[e] * N + j];
+    double dx, dy, dz;
+    entry_disp(a.pos, N, i, j, st, code, dx, dy, dz);
+    const float d[3] = {(float)dx, (float)dy, (float)dz};
+    const float q[3] = {pji.x, pji.y, pji.z};
+    F[0] += pij.x - pji.x;
+    F[1] += pij.y - pji.y;
+    F[2] += pij.z - pji.z;
 #pragma unroll
-  for (int list = 0; list < 2; ++list) {
-    const int M = list ? a.L.MA : a.L.MR;
-    const int nn = min(list ? a.L.nnA[i] : a.L.nnR[i], M);
-    const int32_t* nl = list ? a.L.nlA : a.L.nlR;
-    const uint16_t* cd = list ? a.L.cdA : a.L.cdR;
-    const int32_t* rev = list ? a.L.revA : a.L.revR;
-    const float* P = list ? a.pa : a.pr;
-    const int64_t cs = (int64_t)M * N;
-    for (int m = 0; m < nn; ++m) {
-      const int64_t e = (int64_t)m * N + i;
-      const int32_t j = nl[e];
-      const uint16_t code = st.mode == kModeImages ? cd[e] : kCodeCenter;
-      const int64_t er = (int64_t)rev[e] * N + j;
-      const float pij[3] = {P[e], P[cs + e], P[2 * cs + e]};
-      const float pji[3] = {P[er], P[cs + er], P[2 * cs + er]};
-      double dx, dy, dz;
-      entry_disp(a.pos, N, i, j, st, code, dx, dy, dz);
-      const float d[3] = {(float)dx, (float)dy, (float)dz};
+    for (int x = 0; x < 3; ++x)
 #pragma unroll
-      for (int c = 0; c < 3; ++c) F[c] += pij[c] - pji[c];
-#pragma unroll
-      for (int x = 0; x < 3; ++x)
-#pragma unroll
-        for (int y = 0; y < 3; ++y) W[x * 3 + y] += d[x] * pji[y];
-    }
+      for (int y = 0; y < 3; ++y) W[x * 3 + y] += d[x] * q[y];
   }
 #pragma unroll
   for (int c = 0; c < 3; ++c) a.F[(int64_t)c * N + i] = F[c];

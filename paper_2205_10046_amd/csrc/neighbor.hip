@@ -11,8 +11,13 @@
 //      out sorted by (j, image) without a sort;
 //   4. membership is the strict float64 test |d|^2 < r_c^2 on the canonical
 //      displacement (no fused multiply-add), the same test for both cutoffs;
-//   5. rev[m][i] locates i in the row of its m-th neighbour by binary search,
-//      so the force pass can gather dU_j/dr_ji without atomics.
+//   5. the angular row is the subsequence of the radial row with
+//      |d|^2 < (r_c^A)^2; amap[m][i] is the radial position of angular entry m;
+//   6. rev[m][i] locates i in the radial row of its m-th neighbour (binary
+//      search), so the force pass can gather dU_j/dr_ji without atomics.
+//      With candidate rows (MD with a skin) the binary search runs on the
+//      candidate rows at each rebuild only, and the exact rows take their
+//      reverse positions through the candidate -> exact position map.
 #include "nep_kernels.h"
 
 namespace nep {
@@ -197,6 +202,15 @@ struct RowWriter {
   }
 };
 
+// Angular row entry that is also entry `rpos` of the radial row (clamped
+// into the radial capacity: an overflowing build is redone anyway, but the
+// kernels that run before the host sees the flag stay in bounds).
+__device__ inline void push_angular(RowWriter& A, uint16_t* amap, int32_t MR, int64_t N,
+                                    int64_t i, int32_t j, uint16_t code, int32_t rpos) {
+  if (A.count < A.cap) amap[(int64_t)A.count * N + i] = (uint16_t)min(rpos, MR - 1);
+  A.push(N, i, j, code);
+}
+
 __global__ void __launch_bounds__(kBlock) k_build_rows(
     const double* __restrict__ pos, int64_t N, const int32_t* __restrict__ sid,
     const StructInfo* __restrict__ structs, const int32_t* __restrict__ cell_start,
@@ -227,8 +241,8 @@ __global__ void __launch_bounds__(kBlock) k_build_rows(
     double r2 = norm2_exact(dx, dy, dz);
     if (r2 < rcR2) {
       uint16_t code = make_code(o0, o1, o2);
+      if (r2 < rcA2) push_angular(A, L.amap, L.MR, N, i, (int32_t)j, code, R.count);
       R.push(N, i, (int32_t)j, code);
-      if (r2 < rcA2) A.push(N, i, (int32_t)j, code);
     }
   };
 
@@ -264,9 +278,9 @@ __global__ void __launch_bounds__(kBlock) k_build_rows(
 // rev[m][i] = position of (i, -offset) in the row of j = nl[m][i].
 __global__ void k_reverse(int64_t N, const int32_t* __restrict__ nn, const int32_t* __restrict__ nl,
                           const uint16_t* __restrict__ cd, int32_t cap, int32_t* __restrict__ rev,
-                          int32_t* __restrict__ err) {
+                          int32_t* __restrict__ err, const int32_t* gate) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= N) return;
+  if (i >= N || gated_off(gate)) return;
   int cnt = min(nn[i], cap);
   for (int m = 0; m < cnt; ++m) {
     int32_t j = nl[(int64_t)m * N + i];
@@ -293,36 +307,69 @@ __global__ void k_reverse(int64_t N, const int32_t* __restrict__ nn, const int32
   }
 }
 
-// ---- row order for the network pass: atoms grouped by species, each group
-// padded to whole 16-row tiles (padding rows hold -1) ----
+// ---- row order for the network pass: atoms grouped by species in
+// increasing internal index, each group padded to whole 16-row tiles
+// (padding rows hold -1).  Counting sort by blocks of kBlock atoms:
+// per-block species counts, one exclusive scan over [species][block], then
+// every atom takes its rank inside the block from wave ballots. ----
 
-__global__ void k_type_count(const int32_t* __restrict__ types, int64_t N,
-                             int32_t* __restrict__ tcount) {
-  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < N) atomicAdd(&tcount[types[i]], 1);
+// Species of atom i for the row order, clamped into [0, Tn): a type out of
+// range is reported by its own check, and the rows stay in bounds meanwhile.
+__device__ __forceinline__ int row_species(const int32_t* types, int64_t i, int32_t Tn,
+                                           int32_t per_type) {
+  return per_type ? min(max(types[i], 0), Tn - 1) : 0;
 }
 
-__global__ void k_type_offsets(const int32_t* __restrict__ tcount, int32_t T, int32_t per_type,
-                               int32_t* __restrict__ toff, int32_t* __restrict__ tcursor) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+__global__ void __launch_bounds__(kBlock) k_type_block_count(const int32_t* __restrict__ types,
+                                                             int64_t N, int32_t Tn, int32_t per_type,
+                                                             int32_t nb, int32_t* __restrict__ tblk,
+                                                             const int32_t* gate) {
+  __shared__ int32_t hist[kMaxTypes];
+  if (gated_off(gate)) return;
+  const int t = threadIdx.x;
+  if (t < kMaxTypes) hist[t] = 0;
+  __syncthreads();
+  const int64_t i = (int64_t)blockIdx.x * kBlock + t;
+  if (i < N) atomicAdd(&hist[row_species(types, i, Tn, per_type)], 1);
+  __syncthreads();
+  if (t < Tn) tblk[(int64_t)t * nb + blockIdx.x] = hist[t];
+}
+
+// shift[t] = (padded start of species t) - (exclusive count before species t)
+__global__ void k_type_shift(const int32_t* __restrict__ tex, int64_t N, int32_t Tn, int32_t nb,
+                             int32_t* __restrict__ shift, const int32_t* gate) {
+  if (threadIdx.x != 0 || blockIdx.x != 0 || gated_off(gate)) return;
   int32_t o = 0;
-  for (int t = 0; t < T; ++t) {
-    toff[t] = o;
-    tcursor[t] = 0;
-    int32_t c = per_type ? tcount[t] : (t == 0 ? tcount[T] : 0);
-    o += (c + 15) / 16 * 16;
+  for (int t = 0; t < Tn; ++t) {
+    const int32_t first = tex[(int64_t)t * nb];
+    const int32_t next = t + 1 < Tn ? tex[(int64_t)(t + 1) * nb] : (int32_t)N;
+    shift[t] = o - first;
+    o += (next - first + 15) / 16 * 16;
   }
-  toff[T] = o;
 }
 
-__global__ void k_type_scatter(const int32_t* __restrict__ types, int64_t N, int32_t per_type,
-                               const int32_t* __restrict__ toff, int32_t* __restrict__ tcursor,
-                               int32_t* __restrict__ rows) {
-  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= N) return;
-  int t = per_type ? types[i] : 0;
-  int slot = atomicAdd(&tcursor[t], 1);
-  rows[toff[t] + slot] = (int32_t)i;
+__global__ void __launch_bounds__(kBlock) k_type_block_scatter(
+    const int32_t* __restrict__ types, int64_t N, int32_t Tn, int32_t per_type, int32_t nb,
+    const int32_t* __restrict__ tex, const int32_t* __restrict__ shift, int32_t* __restrict__ rows,
+    const int32_t* gate) {
+  constexpr int kWaves = kBlock / 64;
+  __shared__ int32_t wcount[kWaves][kMaxTypes];
+  if (gated_off(gate)) return;
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  const int64_t i = (int64_t)blockIdx.x * kBlock + t;
+  const bool live = i < N;
+  const int sp = live ? row_species(types, i, Tn, per_type) : -1;
+  const uint64_t below = lane ? (~0ull >> (64 - lane)) : 0ull;
+  int rank = 0;
+  for (int q = 0; q < Tn; ++q) {
+    const uint64_t m = __ballot(sp == q);
+    if (sp == q) rank = __popcll(m & below);
+    if (lane == 0) wcount[w][q] = __popcll(m);
+  }
+  __syncthreads();
+  if (!live) return;
+  for (int v = 0; v < w; ++v) rank += wcount[v][sp];
+  rows[tex[(int64_t)sp * nb + blockIdx.x] + shift[sp] + rank] = (int32_t)i;
 }
 
 // ---------------------------------------------------------------------------
@@ -362,14 +409,12 @@ void launch_build_rows(const BuildArgs& b, const Lists& L, hipStream_t s) {
   hipLaunchKernelGGL(k_build_rows, grid_for(b.N), dim3(kBlock), 0, s, b.pos, b.N, b.sid,
                      b.structs, b.cell_start, b.cell_count, b.rcR2, b.rcA2, L, b.overflow,
                      (const int32_t*)nullptr);
-  launch_reverse(b.N, L, b.overflow + 2, s);
+  launch_reverse(b.N, L, b.overflow + 2, nullptr, s);
 }
 
-void launch_reverse(int64_t N, const Lists& L, int32_t* err, hipStream_t s) {
+void launch_reverse(int64_t N, const Lists& L, int32_t* err, const int32_t* gate, hipStream_t s) {
   hipLaunchKernelGGL(k_reverse, grid_for(N), dim3(kBlock), 0, s, N, L.nnR, L.nlR, L.cdR, L.MR,
-                     L.revR, err);
-  hipLaunchKernelGGL(k_reverse, grid_for(N), dim3(kBlock), 0, s, N, L.nnA, L.nlA, L.cdA, L.MA,
-                     L.revA, err);
+                     L.revR, err, gate);
 }
 
 // Candidate rows at r_c^R + skin (radial slots of V only), rebuilt when the
@@ -378,10 +423,12 @@ void launch_build_verlet(const BuildArgs& b, const Lists& V, hipStream_t s) {
   hipLaunchKernelGGL(k_build_rows, grid_for(b.N), dim3(kBlock), 0, s, b.pos, b.N, b.sid,
                      b.structs, b.cell_start, b.cell_count, b.rcR2, -1.0, V, b.overflow + 5,
                      b.gate);
+  launch_reverse(b.N, V, b.overflow + 2, b.gate, s);
 }
 
 // Exact rows at r_c^R and r_c^A from the candidate rows, order preserved (so
-// still sorted by (j, image)), with the same float64 membership test.
+// still sorted by (j, image)), with the same float64 membership test;
+// V.fmap[m][i] = radial position of candidate m, or -1.
 template <bool BATCH>
 __global__ void __launch_bounds__(kBlock) k_filter_rows(const double* __restrict__ pos, int64_t N,
                                                         const int32_t* __restrict__ sid,
@@ -401,15 +448,40 @@ __global__ void __launch_bounds__(kBlock) k_filter_rows(const double* __restrict
     double dx, dy, dz;
     entry_disp(pos, N, i, j, st, code, dx, dy, dz);
     const double r2 = norm2_exact(dx, dy, dz);
+    int32_t f = -1;
     if (r2 < rcR2) {
+      f = R.count;
+      if (r2 < rcA2) push_angular(A, L.amap, L.MR, N, i, j, code, R.count);
       R.push(N, i, j, code);
-      if (r2 < rcA2) A.push(N, i, j, code);
     }
+    V.fmap[e] = f;
   }
   L.nnR[i] = R.count;
   L.nnA[i] = A.count;
   if (R.count > L.MR) atomicMax(&overflow[0], R.count);
   if (A.count > L.MA) atomicMax(&overflow[1], A.count);
+}
+
+// rev of the exact rows from the candidate reverse index: the entry of i in
+// the row of j sits at candidate position V.revR[m][i] there, whose exact
+// position is V.fmap of that entry.
+__global__ void __launch_bounds__(kBlock) k_reverse_from_candidates(int64_t N, Lists V, Lists L,
+                                                                    int32_t* __restrict__ err) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= N) return;
+  const int nv = min(V.nnR[i], V.MR);
+  for (int m = 0; m < nv; ++m) {
+    const int64_t e = (int64_t)m * N + i;
+    const int32_t f = V.fmap[e];
+    if (f < 0) continue;
+    const int32_t j = V.nlR[e];
+    int32_t g = V.fmap[(int64_t)V.revR[e] * N + j];
+    if (g < 0) {
+      atomicExch(err, 1);
+      g = 0;
+    }
+    if (f < L.MR) L.revR[(int64_t)f * N + i] = min(g, L.MR - 1);
+  }
 }
 
 void launch_filter_rows(const BuildArgs& b, const StructInfo& st0, bool batch, const Lists& V,
@@ -420,7 +492,8 @@ void launch_filter_rows(const BuildArgs& b, const StructInfo& st0, bool batch, c
   else
     hipLaunchKernelGGL(k_filter_rows<false>, grid_for(b.N), dim3(kBlock), 0, s, b.pos, b.N, b.sid,
                        b.structs, st0, V, b.rcR2, b.rcA2, L, b.overflow);
-  launch_reverse(b.N, L, b.overflow + 2, s);
+  hipLaunchKernelGGL(k_reverse_from_candidates, grid_for(b.N), dim3(kBlock), 0, s, b.N, V, L,
+                     b.overflow + 2);
 }
 
 // gate = any |r_i - r_i(at last build)|^2 > thr2
@@ -454,20 +527,21 @@ void launch_copy_gated_i32(int32_t* dst, const int32_t* src, int64_t n, const in
   hipLaunchKernelGGL(k_copy_gated<int32_t>, grid_for(n), dim3(kBlock), 0, s, dst, src, n, gate);
 }
 
+int64_t type_row_blocks(int64_t N) { return div_up(N, kBlock); }
+
 void launch_type_rows(const int32_t* types, int64_t N, int32_t T, int32_t per_type,
-                      int32_t* tcount, int32_t* toff, int32_t* tcursor, int32_t* rows,
-                      int64_t rows_len, hipStream_t s) {
-  launch_fill_i32(tcount, T + 1, 0, s);
-  launch_fill_i32(rows, rows_len, -1, s);
-  if (per_type) {
-    hipLaunchKernelGGL(k_type_count, grid_for(N), dim3(kBlock), 0, s, types, N, tcount);
-  } else {
-    // a single network: every atom counts as species 0
-    hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(1), 0, s, tcount + T, (int64_t)1, (int32_t)N);
-  }
-  hipLaunchKernelGGL(k_type_offsets, dim3(1), dim3(1), 0, s, tcount, T, per_type, toff, tcursor);
-  hipLaunchKernelGGL(k_type_scatter, grid_for(N), dim3(kBlock), 0, s, types, N, per_type, toff,
-                     tcursor, rows);
+                      int32_t* tblk, int32_t* tex, int32_t* toff, int32_t* rows,
+                      int64_t rows_len, const int32_t* gate, hipStream_t s) {
+  const int32_t Tn = per_type ? T : 1;
+  const int32_t nb = (int32_t)type_row_blocks(N);
+  hipLaunchKernelGGL(k_fill_i32_gated, grid_for(rows_len), dim3(kBlock), 0, s, rows, rows_len,
+                     (int32_t)-1, gate);
+  hipLaunchKernelGGL(k_type_block_count, dim3(nb), dim3(kBlock), 0, s, types, N, Tn, per_type, nb,
+                     tblk, gate);
+  hipLaunchKernelGGL(k_scan_1block, dim3(1), dim3(1024), 0, s, tblk, tex, Tn * nb, gate);
+  hipLaunchKernelGGL(k_type_shift, dim3(1), dim3(64), 0, s, tex, N, Tn, nb, toff, gate);
+  hipLaunchKernelGGL(k_type_block_scatter, dim3(nb), dim3(kBlock), 0, s, types, N, Tn, per_type,
+                     nb, tex, toff, rows, gate);
 }
 
 }  // namespace nep

@@ -6,10 +6,13 @@
 //   pos      float64 [3][N]           SoA, internal order
 //   nl_*     int32   [M][N]           neighbour m of atom i at nl[m*N + i]
 //   cd_*     uint16  [M][N]           image offset code of that entry
-//   rev_*    int32   [M][N]           position of i in the row of that j
+//   revR     int32   [MR][N]          position of i in the radial row of that j
+//   amap     uint16  [MA][N]          position of angular entry m in the radial row
+//                                     (the angular row is a subsequence of it)
 //   q, fp    float32 [N][ND_pad]      descriptor / dU/dq rows (network input)
 //   sums     float32 [NA*NB][N]       angular sums S_{n,k}, SoA
-//   pr, pa   float32 [3][M][N]        partial forces dU_i/dr_ij per entry
+//   P        float32x4 [MR][N]        dU_i/dr_ij per radial entry, radial and
+//                                     angular parts summed (w unused)
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -128,7 +131,8 @@ struct DevModel {
   float C5[3];
 };
 
-// Internal neighbour lists of one build.
+// Internal neighbour lists of one build.  Row capacities stay below 65535
+// so positions inside a row fit the uint16 maps.
 struct Lists {
   int32_t MR, MA;           // row capacities
   int32_t* nnR;
@@ -138,8 +142,11 @@ struct Lists {
   int32_t* nnA;
   int32_t* nlA;
   uint16_t* cdA;
-  int32_t* revA;
+  uint16_t* amap;           // angular entry -> radial position
+  int32_t* fmap;            // candidate rows only: candidate -> exact radial position or -1
 };
+
+constexpr int32_t kMaxRow = 65535;
 
 inline int div_up(int64_t a, int64_t b) { return (int)((a + b - 1) / b); }
 

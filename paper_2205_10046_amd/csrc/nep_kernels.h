@@ -40,8 +40,7 @@ struct EvalArgs {
   float* fp;                  // [N][NDp]
   float* U;                   // [N]
   float* sums;                // [nA_pad * NB][N]
-  float* pr;                  // [3][MR][N]
-  float* pa;                  // [3][MA][N]
+  float4* P;                  // [MR][N] dU_i/dr_ij per radial entry
   float* F;                   // [3][N] internal
   float* W;                   // [9][N] internal
   const int32_t* rows;        // network row order, [rows_len]
@@ -60,7 +59,7 @@ void launch_assign_struct(const int64_t* offs, int32_t n_struct, int64_t N, int3
                           hipStream_t s);
 void launch_order_atoms(const BuildArgs& b, hipStream_t s);
 void launch_build_rows(const BuildArgs& b, const Lists& L, hipStream_t s);
-void launch_reverse(int64_t N, const Lists& L, int32_t* err, hipStream_t s);
+void launch_reverse(int64_t N, const Lists& L, int32_t* err, const int32_t* gate, hipStream_t s);
 void launch_build_verlet(const BuildArgs& b, const Lists& V, hipStream_t s);
 void launch_filter_rows(const BuildArgs& b, const StructInfo& st0, bool batch, const Lists& V,
                         const Lists& L, hipStream_t s);
@@ -70,9 +69,12 @@ void launch_copy_gated_f64(double* dst, const double* src, int64_t n, const int3
                            hipStream_t s);
 void launch_copy_gated_i32(int32_t* dst, const int32_t* src, int64_t n, const int32_t* gate,
                            hipStream_t s);
+// Species-grouped row order of the network pass; tblk and tex hold
+// kMaxTypes * type_row_blocks(N) ints each.
+int64_t type_row_blocks(int64_t N);
 void launch_type_rows(const int32_t* types, int64_t N, int32_t T, int32_t per_type,
-                      int32_t* tcount, int32_t* toff, int32_t* tcursor, int32_t* rows,
-                      int64_t rows_len, hipStream_t s);
+                      int32_t* tblk, int32_t* tex, int32_t* toff, int32_t* rows,
+                      int64_t rows_len, const int32_t* gate, hipStream_t s);
 
 // descriptor.hip / force.hip: return false if no kernel exists for (NG, L)
 bool launch_descriptor(const EvalArgs& a, hipStream_t s);
