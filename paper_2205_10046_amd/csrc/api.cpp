@@ -268,6 +268,7 @@ struct ModelTables {
 struct Tuning {
   bool done = false;
   int NG_desc = 0, NG_force = 0, block_desc = 256, block_force = 256;
+  int lanes_desc = 1, lanes_force = 1;   // lanes per atom of the pair kernels
 };
 
 }  // namespace
@@ -277,7 +278,6 @@ struct nep_handle {
   int device = 0;
   std::string err;
   int nd = 0, nets = 1;
-  int nA_pad = 0;
   Tuning tune[2];                   // [single structure, batch]
   ModelTables main;                 // the handle's own parameter vector
   std::vector<ModelTables> pop;     // parameter sets of the last batch call
@@ -356,7 +356,7 @@ struct nep_handle {
 
   void free_lists() {
     dev_free(L.nnR); dev_free(L.nlR); dev_free(L.cdR); dev_free(L.revR);
-    dev_free(L.nnA); dev_free(L.nlA); dev_free(L.cdA); dev_free(L.amap);
+    dev_free(L.nnA);
     dev_free(P);
   }
 
@@ -413,7 +413,6 @@ void upload_model(nep_handle* h, const double* p, ModelTables& mt) {
   const int nA = hp.n_max_angular + 1, KA = hp.basis_angular + 1;
   const int NNp = (NN + 31) / 32 * 32;
   const int NDp32 = (nd + 31) / 32 * 32;
-  const int nA_pad = h->nA_pad;
   for (size_t k = 0; k < n_params(hp); ++k)
     if (!std::isfinite(p[k])) throw Failure{NEP_E_INVALID_ARG, "parameter vector has a non-finite entry"};
   std::vector<float> w0((size_t)nets * NNp * nd, 0.f), w0t((size_t)nets * nd * NNp, 0.f);
@@ -439,11 +438,23 @@ void upload_model(nep_handle* h, const double* p, ModelTables& mt) {
   std::vector<float> cR((size_t)T * T * nR * KR);
   for (size_t k = 0; k < cR.size(); ++k) cR[k] = (float)p[off + k];
   off += cR.size();
-  std::vector<float> cA((size_t)T * T * nA_pad * KA, 0.f);
-  for (int a = 0; a < T * T; ++a)
-    for (int n = 0; n < nA; ++n)
-      for (int k = 0; k < KA; ++k)
-        cA[((size_t)a * nA_pad + n) * KA + k] = (float)p[off + ((size_t)a * nA + n) * KA + k];
+  // one angular table per admissible group size NG: [T][T][groups][KA][ng_pad(NG)]
+  std::vector<float> cA;
+  int32_t cA_off[8];
+  int32_t cA_max = 0;
+  for (int ng = 0; ng < 8; ++ng) cA_off[ng] = -1;
+  for (int ng : angular_group_options(nA, hp.l_max_3b)) {
+    const int groups = (nA + ng - 1) / ng, w = ng_pad(ng);
+    const size_t base = cA.size();
+    cA_off[ng] = (int32_t)base;
+    cA.resize(base + (size_t)T * T * groups * KA * w, 0.f);
+    for (int a = 0; a < T * T; ++a)
+      for (int n = 0; n < nA; ++n)
+        for (int k = 0; k < KA; ++k)
+          cA[base + (((size_t)a * groups + n / ng) * KA + k) * w + n % ng] =
+              (float)p[off + ((size_t)a * nA + n) * KA + k];
+    cA_max = std::max(cA_max, (int32_t)(cA.size() - base));
+  }
   off += (size_t)T * T * nA * KA;
 
   auto put = [](auto*& dst, const auto& v) {
@@ -458,7 +469,8 @@ void upload_model(nep_handle* h, const double* p, ModelTables& mt) {
   M.T = T; M.nR = nR; M.KR = KR; M.nA = nA; M.KA = KA; M.L = hp.l_max_3b;
   M.NB = (hp.l_max_3b + 1) * (hp.l_max_3b + 1) - 1;
   M.ND = nd; M.NDp = (nd + 7) / 8 * 8; M.NN = NN; M.nets = nets;
-  M.has4b = hp.l_max_4b >= 2; M.has5b = hp.l_max_5b >= 1; M.nA_pad = nA_pad;
+  M.has4b = hp.l_max_4b >= 2; M.has5b = hp.l_max_5b >= 1; M.cA_max = cA_max;
+  for (int ng = 0; ng < 8; ++ng) M.cA_off[ng] = cA_off[ng];
   M.rcR = (float)hp.rc_radial; M.rcA = (float)hp.rc_angular; M.b1 = b1;
   M.cR = mt.cR; M.cA = mt.cA; M.NNp = NNp; M.NDp32 = NDp32;
   M.w0 = mt.w0; M.w0t = mt.w0t; M.b0 = mt.b0; M.w1 = mt.w1; M.w0b = mt.w0b; M.w0tb = mt.w0tb;
@@ -490,13 +502,33 @@ void ensure_lists(nep_handle* h, int64_t N, int32_t MR, int32_t MA) {
   dev_alloc(h->L.nnR, cap); dev_alloc(h->L.nnA, cap);
   dev_alloc(h->L.nlR, (size_t)MR * cap); dev_alloc(h->L.cdR, (size_t)MR * cap);
   dev_alloc(h->L.revR, (size_t)MR * cap);
-  dev_alloc(h->L.nlA, (size_t)MA * cap); dev_alloc(h->L.cdA, (size_t)MA * cap);
-  dev_alloc(h->L.amap, (size_t)MA * cap);
   dev_alloc(h->P, (size_t)MR * cap);
   h->MR = MR;
   h->MA = MA;
   h->L.MR = MR;
-  h->L.MA = MA;
+  // the angular row lives in the radial row; its length is only capped when
+  // the caller fixed max_nb_angular
+  h->L.MA = h->hp.max_nb_angular ? MA : kMaxRow;
+}
+
+// Candidate rows V of MV slots per atom (contents are not preserved).
+void ensure_verlet(nep_handle* h, int64_t N, int32_t MV) {
+  if (h->V.nlR && MV <= h->V.MR && N <= h->capN) return;
+  if (MV > kMaxRow) throw Failure{NEP_E_NEIGHBOR_OVERFLOW, "candidate rows longer than 65535 entries"};
+  h->free_verlet();
+  const int64_t cap = h->capN;
+  dev_alloc(h->V.nnR, cap);
+  dev_alloc(h->V.nnA, cap);
+  dev_alloc(h->V.nlR, (size_t)MV * cap);
+  dev_alloc(h->V.cdR, (size_t)MV * cap);
+  dev_alloc(h->V.revR, (size_t)MV * cap);
+  dev_alloc(h->V.fmap, (size_t)MV * cap);
+  h->V.MR = MV;
+  h->V.MA = 0;
+  if (!h->pos_ref) {
+    dev_alloc(h->pos_ref, 3 * cap);
+    dev_alloc(h->ref_save, 3 * cap);
+  }
 }
 
 // Per-atom buffers sized for N atoms (contents are not preserved).
@@ -627,6 +659,9 @@ Prepared prepare_batch(nep_handle* h, int32_t S, const int64_t* offs, const doub
   MR = std::max(MR, h->MR);
   MA = std::max(MA, h->MA);
   ensure_lists(h, N, MR, MA);
+  // candidate rows at r_list (= r_c^R, or r_c^R + skin)
+  const int32_t MV = r_list > h->hp.rc_radial ? estimate_capacity(r_list, max_density) : MR;
+  ensure_verlet(h, N, std::max(MV, h->V.MR));
   if (S > h->cap_struct) {
     dev_alloc(h->structs, S);
     dev_alloc(h->offs, S + 1);
@@ -667,13 +702,15 @@ void build_rows_checked(nep_handle* h, const Prepared& pp, const BuildArgs& b, h
     }
     {
       Stage st(h, "neighbor_rows", s);
-      launch_build_rows(b, h->L, s);
+      launch_build_rows(b, pp.geo.st, pp.batch, h->V, h->L, s);
     }
     int32_t* fl = (int32_t*)(h->pinned + 384);
     HIPCHK(hipMemcpyAsync(fl, h->flags, 8 * sizeof(int32_t), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
     if (fl[3]) throw Failure{NEP_E_INVALID_ARG, "an atom type is out of range"};
     if (fl[4]) throw Failure{NEP_E_NONFINITE, "positions contain NaN or Inf"};
+    // the candidate rows are at r_c^R here: their overflow count is the radial one
+    fl[0] = std::max(fl[0], fl[5]);
     if (fl[0] == 0 && fl[1] == 0) {
       // without truncated rows every entry has its reverse entry
       if (fl[2]) throw Failure{NEP_E_HIP, "internal error: neighbour rows are not symmetric"};
@@ -690,6 +727,7 @@ void build_rows_checked(nep_handle* h, const Prepared& pp, const BuildArgs& b, h
     const int32_t MR = std::max(h->MR, (int32_t)((fl[0] * 1.2 + 8) / 4 * 4 + 4));
     const int32_t MA = std::max(h->MA, (int32_t)((fl[1] * 1.2 + 8) / 4 * 4 + 4));
     ensure_lists(h, pp.N, MR, MA);
+    ensure_verlet(h, pp.N, std::max(h->V.MR, MR));
   }
   throw Failure{NEP_E_NEIGHBOR_OVERFLOW, "neighbour rows kept overflowing"};
 }
@@ -706,10 +744,11 @@ void order_and_build(nep_handle* h, const Prepared& pp, const double* pos_src, c
   build_rows_checked(h, pp, b, s, check);
 }
 
-void set_groups(EvalArgs& a, int NG, int block, int nA) {
+void set_groups(EvalArgs& a, int NG, int block, int nA, int lanes) {
   a.NG = NG;
   a.ngroups = (nA + NG - 1) / NG;
   a.block = block;
+  a.lanes = lanes;
 }
 
 bool autotune_enabled() {
@@ -718,24 +757,26 @@ bool autotune_enabled() {
 }
 
 // Project autotuner: on the first evaluation of a shape, time every admissible
-// (angular group size, block size) of the descriptor and partial-force kernels
-// on the actual rows (one warm-up and two timed launches each, HIP events on
-// the work stream) and keep the fastest.  The choice is fixed per handle
-// afterwards, so repeated calls stay bitwise reproducible.
+// (angular group size, block size, lanes per atom) of the descriptor and
+// partial-force kernels on the actual rows (one warm-up and two timed
+// launches each, HIP events on the work stream) and keep the fastest.  The
+// choice is fixed per handle afterwards, so repeated calls stay bitwise
+// reproducible.
 void autotune(nep_handle* h, const Prepared& pp, hipStream_t s) {
   Tuning& t = h->tune[pp.batch ? 1 : 0];
   if (t.done) return;
   const int nA = h->M.nA, L = h->M.L;
   t.NG_desc = t.NG_force = angular_group_size(nA, L);
   t.block_desc = t.block_force = kBlock;
+  t.lanes_desc = t.lanes_force = 4;
   t.done = true;
   if (!autotune_enabled()) return;
   EvalArgs a = eval_args(h, pp, h->M);
   hipEvent_t e0, e1;
   HIPCHK(hipEventCreate(&e0));
   HIPCHK(hipEventCreate(&e1));
-  auto time_it = [&](bool force, int ng, int block) {
-    set_groups(a, ng, block, nA);
+  auto time_it = [&](bool force, int ng, int block, int lanes) {
+    set_groups(a, ng, block, nA, lanes);
     float best = 1e30f;
     for (int rep = 0; rep < 3; ++rep) {
       HIPCHK(hipEventRecord(e0, s));
@@ -750,32 +791,28 @@ void autotune(nep_handle* h, const Prepared& pp, hipStream_t s) {
     return best;
   };
   const int blocks[] = {128, 256};
-  float best = 1e30f;
-  for (int ng : angular_group_options(nA, L))
-    for (int bl : blocks) {
-      if (eval_lds_bytes(h->M, bl) > 64 * 1024) continue;
-      float ms = time_it(false, ng, bl);
-      if (ms < best) {
-        best = ms;
-        t.NG_desc = ng;
-        t.block_desc = bl;
-      }
-    }
+  const int lane_opts[] = {1, 4};
+  auto search = [&](bool force, int& ng_out, int& block_out, int& lanes_out) {
+    float best = 1e30f;
+    for (int ng : angular_group_options(nA, L))
+      for (int bl : blocks)
+        for (int ln : lane_opts) {
+          if (eval_lds_bytes(h->M, bl) > 64 * 1024) continue;
+          float ms = time_it(force, ng, bl, ln);
+          if (ms < best) {
+            best = ms;
+            ng_out = ng;
+            block_out = bl;
+            lanes_out = ln;
+          }
+        }
+  };
+  search(false, t.NG_desc, t.block_desc, t.lanes_desc);
   // the partial-force kernel reads dU/dq: run the chosen descriptor pass and the network once
-  set_groups(a, t.NG_desc, t.block_desc, nA);
+  set_groups(a, t.NG_desc, t.block_desc, nA, t.lanes_desc);
   launch_descriptor(a, s);
   launch_mlp(a, s);
-  best = 1e30f;
-  for (int ng : angular_group_options(nA, L))
-    for (int bl : blocks) {
-      if (eval_lds_bytes(h->M, bl) > 64 * 1024) continue;
-      float ms = time_it(true, ng, bl);
-      if (ms < best) {
-        best = ms;
-        t.NG_force = ng;
-        t.block_force = bl;
-      }
-    }
+  search(true, t.NG_force, t.block_force, t.lanes_force);
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
 }
@@ -784,7 +821,7 @@ void forces(nep_handle* h, const Prepared& pp, hipStream_t s, const DevModel* mo
   autotune(h, pp, s);
   const Tuning& t = h->tune[pp.batch ? 1 : 0];
   EvalArgs a = eval_args(h, pp, model ? *model : h->M);
-  set_groups(a, t.NG_desc, t.block_desc, h->M.nA);
+  set_groups(a, t.NG_desc, t.block_desc, h->M.nA, t.lanes_desc);
   {
     Stage st(h, "descriptor", s);
     if (!launch_descriptor(a, s)) throw Failure{NEP_E_UNSUPPORTED, "no descriptor kernel for this shape"};
@@ -793,7 +830,7 @@ void forces(nep_handle* h, const Prepared& pp, hipStream_t s, const DevModel* mo
     Stage st(h, "mlp", s);
     launch_mlp(a, s);
   }
-  set_groups(a, t.NG_force, t.block_force, h->M.nA);
+  set_groups(a, t.NG_force, t.block_force, h->M.nA, t.lanes_force);
   {
     Stage st(h, "partial_forces", s);
     if (!launch_partial_forces(a, s)) throw Failure{NEP_E_UNSUPPORTED, "no force kernel for this shape"};
@@ -1247,10 +1284,6 @@ int nep_create(const nep_hparams* hp, const double* params, size_t n, nep_handle
     HIPCHK(hipHostMalloc((void**)&h->pinned, 4096, hipHostMallocDefault));
     h->nd = n_descriptors(*hp);
     h->nets = hp->nn_per_type ? hp->n_types : 1;
-    const int nA = hp->n_max_angular + 1, L = hp->l_max_3b;
-    // c^A rows padded to whole groups for every admissible group size
-    h->nA_pad = nA;
-    for (int ng : angular_group_options(nA, L)) h->nA_pad = std::max(h->nA_pad, (nA + ng - 1) / ng * ng);
     upload_model(h, params, h->main);
     // LDS budget of the pair kernels: coefficient tables + per-thread slots
     if (eval_lds_bytes(h->M, kBlock) > 64 * 1024)
@@ -1391,7 +1424,7 @@ int nep_descriptors(nep_handle* h, int64_t N, const double* pos, const int32_t* 
     order_and_build(h, pp, h->pos_ext, h->types_ext, s, true);
     autotune(h, pp, s);
     EvalArgs a = eval_args(h, pp, h->M);
-    set_groups(a, h->tune[0].NG_desc, h->tune[0].block_desc, h->M.nA);
+    set_groups(a, h->tune[0].NG_desc, h->tune[0].block_desc, h->M.nA, h->tune[0].lanes_desc);
     if (!launch_descriptor(a, s)) throw Failure{NEP_E_UNSUPPORTED, "no descriptor kernel for this shape"};
     double* d_q = nullptr;
     dev_alloc(d_q, (size_t)N * h->nd);
@@ -1406,25 +1439,6 @@ int nep_descriptors(nep_handle* h, int64_t N, const double* pos, const int32_t* 
 }
 
 namespace {
-
-void ensure_verlet(nep_handle* h, int64_t N, int32_t MV) {
-  if (h->V.nlR && MV <= h->V.MR && N <= h->capN) return;
-  if (MV > kMaxRow) throw Failure{NEP_E_NEIGHBOR_OVERFLOW, "candidate rows longer than 65535 entries"};
-  h->free_verlet();
-  const int64_t cap = h->capN;
-  dev_alloc(h->V.nnR, cap);
-  dev_alloc(h->V.nnA, cap);
-  dev_alloc(h->V.nlR, (size_t)MV * cap);
-  dev_alloc(h->V.cdR, (size_t)MV * cap);
-  dev_alloc(h->V.revR, (size_t)MV * cap);
-  dev_alloc(h->V.fmap, (size_t)MV * cap);
-  h->V.MR = MV;
-  h->V.MA = 0;
-  if (!h->pos_ref) {
-    dev_alloc(h->pos_ref, 3 * cap);
-    dev_alloc(h->ref_save, 3 * cap);
-  }
-}
 
 // Rebuild now from the current internal state: re-sort into cell order
 // (velocities and caller indices follow), remember the positions, and build
@@ -1733,7 +1747,7 @@ static int md_impl(nep_handle* h, int64_t N, double* d_pos, double* d_vel, const
       {
         Stage st(h, "neighbor_rows", s);
         BuildArgs b2 = build_args(h, pp, nullptr, nullptr, h->pos, h->types);
-        launch_build_rows(b2, h->L, s);
+        launch_build_rows(b2, pp.geo.st, pp.batch, h->V, h->L, s);
       }
       forces(h, pp, s);
       md.pos = h->pos;
@@ -1755,6 +1769,7 @@ static int md_impl(nep_handle* h, int64_t N, double* d_pos, double* d_vel, const
     HIPCHK(hipMemcpyAsync(fl, h->flags, 8 * sizeof(int32_t), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
     if (fl[4]) throw Failure{NEP_E_NONFINITE, "positions became non-finite during the run"};
+    fl[0] = std::max(fl[0], fl[5]);  // candidate rows at r_c^R: the same count
     if (fl[2] && !(fl[0] || fl[1]))
       throw Failure{NEP_E_HIP, "internal error: neighbour rows are not symmetric"};
     if (fl[0] || fl[1]) {
@@ -1763,6 +1778,7 @@ static int md_impl(nep_handle* h, int64_t N, double* d_pos, double* d_vel, const
       const int32_t MR = std::max(h->MR, (int32_t)((fl[0] * 1.2 + 8) / 4 * 4 + 4));
       const int32_t MA = std::max(h->MA, (int32_t)((fl[1] * 1.2 + 8) / 4 * 4 + 4));
       ensure_lists(h, N, MR, MA);
+      ensure_verlet(h, N, std::max(h->V.MR, MR));
       HIPCHK(hipMemcpyAsync(h->pos, h->pos_save, 3 * N * sizeof(double), hipMemcpyDeviceToDevice, s));
       HIPCHK(hipMemcpyAsync(h->vel, h->vel_save, 3 * N * sizeof(double), hipMemcpyDeviceToDevice, s));
       HIPCHK(hipMemcpyAsync(h->types, h->types_save, N * sizeof(int32_t), hipMemcpyDeviceToDevice, s));

@@ -1,6 +1,13 @@
 // descriptor.hip -- descriptor pass, partial-force pass and force/virial
 // gather of NEP3 (Sec. II.B-II.F), one thread per atom.
 //
+// Both pair kernels run G lanes per atom (G = 1 or 4, adjacent lanes): lane
+// s of an atom takes the row entries m = s, s + G, ...; the angular row is
+// the first nnA entries of the radial row, so a lane owns the same entries
+// in both loops.  More lanes per atom give more waves to hide the latency of
+// the neighbour loads when N is small against the 1024 SIMDs; the per-lane
+// partial sums are combined with DPP quad permutations.
+//
 // Descriptor pass (eqs. qin, g_n, f_n, S_nk and the explicit q_{nl},
 // q_{n222}, q_{n1111}):
 //   * radial: q_n = sum_j sum_k c^{t_i t_j}_{nk} f_k(r_ij) is regrouped as
@@ -44,6 +51,78 @@ __device__ __forceinline__ Basis make_basis(float r, float rc) {
   return b;
 }
 
+// Sum of v over the G adjacent lanes of one atom (G in {1, 2, 4}); every
+// lane of the group gets the same bits (the pairwise adds commute).
+template <int G>
+__device__ __forceinline__ float group_sum(float v) {
+  if constexpr (G >= 2)
+    v += __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0xB1, 0xF, 0xF, false));
+  if constexpr (G >= 4)
+    v += __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x4E, 0xF, 0xF, false));
+  return v;
+}
+
+// Visit row entries m = first, first + step, ... < nn of atom i with the
+// neighbour loads software-pipelined: the index j of entry m + 2 step and the
+// position and species of entry m + step are in flight while entry m is
+// computed.  body(m, e, j, tj, dx, dy, dz) gets the float32 displacement
+// rounded from the float64 one.  Entries past the row load atom 0 (always
+// in bounds) and are never visited.
+template <class Body>
+__device__ __forceinline__ void for_entries(const EvalArgs& a, const StructInfo& st, int64_t i,
+                                            int first, int nn, int step, Body&& body) {
+  const int64_t N = a.N;
+  const double* __restrict__ pos = a.pos;
+  const int32_t* __restrict__ nl = a.L.nlR;
+  const uint16_t* __restrict__ cd = a.L.cdR;
+  const bool images = st.mode == kModeImages;
+  const double xi = pos[i], yi = pos[N + i], zi = pos[2 * N + i];
+  auto index_of = [&](int m, uint16_t& code) -> int32_t {
+    if (m >= nn) {
+      code = kCodeCenter;
+      return 0;
+    }
+    const int64_t e = (int64_t)m * N + i;
+    code = images ? cd[e] : kCodeCenter;
+    return nl[e];
+  };
+  uint16_t c0, c1;
+  int32_t j0 = index_of(first, c0);
+  int32_t j1 = index_of(first + step, c1);
+  double px = pos[j0], py = pos[N + j0], pz = pos[2 * N + j0];
+  int32_t t0 = a.types[j0];
+  for (int m = first; m < nn; m += step) {
+    const int32_t jc = j0, tc = t0;
+    const uint16_t cc = c0;
+    double Dx, Dy, Dz;
+    {
+#pragma clang fp contract(off)
+      Dx = px - xi;
+      Dy = py - yi;
+      Dz = pz - zi;
+    }
+    j0 = j1;
+    c0 = c1;
+    px = pos[j0];
+    py = pos[N + j0];
+    pz = pos[2 * N + j0];
+    t0 = a.types[j0];
+    j1 = index_of(m + 2 * step, c1);
+    int n0, n1, n2;
+    min_image(st, Dx, Dy, Dz, n0, n1, n2);
+    if (cc != kCodeCenter) {
+      int oa, ob, oc;
+      split_code(cc, oa, ob, oc);
+      n0 += oa;
+      n1 += ob;
+      n2 += oc;
+    }
+    double dx, dy, dz;
+    image_disp(st, Dx, Dy, Dz, n0, n1, n2, dx, dy, dz);
+    body(m, (int64_t)m * N + i, jc, tc, (float)dx, (float)dy, (float)dz);
+  }
+}
+
 template <bool BATCH>
 __device__ __forceinline__ const StructInfo& struct_of(const EvalArgs& a, const StructInfo& st0,
                                                        int64_t i) {
@@ -51,17 +130,48 @@ __device__ __forceinline__ const StructInfo& struct_of(const EvalArgs& a, const 
   else return st0;
 }
 
-__device__ __forceinline__ void load_tables(const DevModel& M, float* sR, float* sA) {
+// LDS: radial table [T][T][nR][KR] (rounded to 16 bytes), the angular table
+// of group size NG, then per-lane slots.
+__device__ __forceinline__ int radial_table_floats(const DevModel& M) {
+  return round4(M.T * M.T * M.nR * M.KR);
+}
+
+template <int NG>
+__device__ __forceinline__ void load_tables(const DevModel& M, int ngroups, float* sR, float* sA) {
   const int nRt = M.T * M.T * M.nR * M.KR;
-  const int nAt = M.T * M.T * M.nA_pad * M.KA;
+  const int nAt = M.T * M.T * ngroups * M.KA * ng_pad(NG);
+  const float* cA = M.cA + M.cA_off[NG];
   for (int k = threadIdx.x; k < nRt; k += blockDim.x) sR[k] = M.cR[k];
-  for (int k = threadIdx.x; k < nAt; k += blockDim.x) sA[k] = M.cA[k];
+  for (int k = threadIdx.x; k < nAt; k += blockDim.x) sA[k] = cA[k];
+}
+
+// The NG coefficients of one group at one basis index (16-byte aligned rows).
+template <int NG>
+__device__ __forceinline__ void load_group(const float* p, float (&c)[NG]) {
+  constexpr int W = ng_pad(NG);
+  if constexpr (W % 4 == 0) {
+#pragma unroll
+    for (int v = 0; v < W / 4; ++v) {
+      const float4 x = reinterpret_cast<const float4*>(p)[v];
+      const float e[4] = {x.x, x.y, x.z, x.w};
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+        if (4 * v + u < NG) c[4 * v + u] = e[u];
+    }
+  } else if constexpr (W == 2) {
+    const float2 x = *reinterpret_cast<const float2*>(p);
+    c[0] = x.x;
+    c[1] = x.y;
+  } else {
+#pragma unroll
+    for (int q = 0; q < NG; ++q) c[q] = p[q];
+  }
 }
 
 }  // namespace
 
 size_t eval_lds_bytes(const DevModel& M, int block) {
-  size_t t = (size_t)M.T * M.T * M.nR * M.KR + (size_t)M.T * M.T * M.nA_pad * M.KA;
+  size_t t = (size_t)round4(M.T * M.T * M.nR * M.KR) + (size_t)round4(M.cA_max);
   return (t + (size_t)M.T * M.KR * block) * sizeof(float);
 }
 
@@ -69,50 +179,55 @@ size_t eval_lds_bytes(const DevModel& M, int block) {
 // descriptor pass
 // ---------------------------------------------------------------------------
 
-template <int NG, int L, bool BATCH>
+template <int NG, int L, bool BATCH, int G>
 __global__ void __launch_bounds__(kBlock, 2) k_descriptor(EvalArgs a, StructInfo st0) {
   constexpr int NB = num_poly(L);
-  extern __shared__ float lds[];
+  extern __shared__ float4 lds_v4[];  // 16-byte aligned base
+  float* lds = reinterpret_cast<float*>(lds_v4);
   const DevModel& M = a.M;
   const int T = M.T, KR = M.KR, KA = M.KA, nR = M.nR, nA = M.nA;
+  constexpr int W = ng_pad(NG);
   float* sR = lds;
-  float* sA = sR + T * T * nR * KR;
-  float* acc = sA + T * T * M.nA_pad * KA;
-  load_tables(M, sR, sA);
+  float* sA = sR + radial_table_floats(M);
+  float* acc = sA + round4(T * T * a.ngroups * KA * W);
+  load_tables<NG>(M, a.ngroups, sR, sA);
   const int tid = threadIdx.x, B = blockDim.x;
   for (int k = 0; k < T * KR; ++k) acc[k * B + tid] = 0.f;
   __syncthreads();
   const int64_t N = a.N;
-  const int64_t i = (int64_t)blockIdx.x * B + tid;
-  if (i >= N) return;
+  const int sub = tid & (G - 1);
+  const int64_t i = ((int64_t)blockIdx.x * B + tid) / G;
+  if (i >= N) return;  // the G lanes of an atom leave together
   const StructInfo& st = struct_of<BATCH>(a, st0, i);
   const int ti = a.types[i];
   const double* __restrict__ pos = a.pos;
+  const int32_t* __restrict__ nl = a.L.nlR;
+  const uint16_t* __restrict__ cd = a.L.cdR;
   float* __restrict__ qrow = a.q + i * M.NDp;
 
   // ---- radial: F_{t,k} = sum_{j of species t} f_k(r_ij) ----
   const float rcR = M.rcR;
   const int nnR = min(a.L.nnR[i], a.L.MR);
-  for (int m = 0; m < nnR; ++m) {
-    const int64_t e = (int64_t)m * N + i;
-    const int32_t j = a.L.nlR[e];
-    const uint16_t code = st.mode == kModeImages ? a.L.cdR[e] : kCodeCenter;
-    double dx, dy, dz;
-    entry_disp(pos, N, i, j, st, code, dx, dy, dz);
-    const float fx = (float)dx, fy = (float)dy, fz = (float)dz;
+  for_entries(a, st, i, sub, nnR, G,
+              [&](int m, int64_t e, int32_t j, int32_t tj, float fx, float fy, float fz)
+                  __attribute__((always_inline)) {
     const float r = sqrtf(fx * fx + fy * fy + fz * fz);
     const Basis bs = make_basis(r, rcR);
-    float* slot = acc + (a.types[j] * KR) * B + tid;
+    float* slot = acc + (tj * KR) * B + tid;
     slot[0] += bs.fc;
     float Tm1 = 1.f, Tk = bs.x;
-    for (int k = 1; k < KR; ++k) {
+#pragma unroll
+    for (int k = 1; k < kMaxBasis; ++k) {
+      if (k >= KR) break;
       slot[k * B] += 0.5f * (Tk + 1.f) * bs.fc;
       const float Tn = 2.f * bs.x * Tk - Tm1;
       Tm1 = Tk;
       Tk = Tn;
     }
-  }
-  for (int n = 0; n < nR; ++n) {
+  });
+  if constexpr (G > 1)
+    for (int k = 0; k < T * KR; ++k) acc[k * B + tid] = group_sum<G>(acc[k * B + tid]);
+  for (int n = sub; n < nR; n += G) {
     float s = 0.f;
     for (int t = 0; t < T; ++t) {
       const float* c = sR + ((ti * T + t) * nR + n) * KR;
@@ -123,32 +238,36 @@ __global__ void __launch_bounds__(kBlock, 2) k_descriptor(EvalArgs a, StructInfo
 
   // ---- angular: S_{n,k} = sum_j g_n(r_ij) b_k(u_ij), NG radial functions at a time ----
   const float rcA = M.rcA;
-  const int nnA = min(a.L.nnA[i], a.L.MA);
+  const int nnA = min(a.L.nnA[i], a.L.MR);
   for (int g = 0; g < a.ngroups; ++g) {
     float S[NG][NB];
 #pragma unroll
     for (int q = 0; q < NG; ++q)
 #pragma unroll
       for (int k = 0; k < NB; ++k) S[q][k] = 0.f;
-    for (int m = 0; m < nnA; ++m) {
-      const int64_t e = (int64_t)m * N + i;
-      const int32_t j = a.L.nlA[e];
-      const uint16_t code = st.mode == kModeImages ? a.L.cdA[e] : kCodeCenter;
-      double dx, dy, dz;
-      entry_disp(pos, N, i, j, st, code, dx, dy, dz);
-      const float fx = (float)dx, fy = (float)dy, fz = (float)dz;
+    for_entries(a, st, i, sub, nnA, G,
+                [&](int m, int64_t e, int32_t j, int32_t tj, float fx, float fy, float fz)
+                    __attribute__((always_inline)) {
       const float r = sqrtf(fx * fx + fy * fy + fz * fz);
       const float rinv = 1.0f / r;
       const Basis bs = make_basis(r, rcA);
-      const float* c = sA + ((ti * T + a.types[j]) * M.nA_pad + g * NG) * KA;
+      const float* c = sA + ((ti * T + tj) * a.ngroups + g) * KA * W;
       float gq[NG];
+      {
+        float cv[NG];
+        load_group<NG>(c, cv);
 #pragma unroll
-      for (int q = 0; q < NG; ++q) gq[q] = c[q * KA] * bs.fc;
+        for (int q = 0; q < NG; ++q) gq[q] = cv[q] * bs.fc;
+      }
       float Tm1 = 1.f, Tk = bs.x;
-      for (int k = 1; k < KA; ++k) {
+#pragma unroll
+      for (int k = 1; k < kMaxBasis; ++k) {
+        if (k >= KA) break;
+        float cv[NG];
+        load_group<NG>(c + k * W, cv);
         const float f = 0.5f * (Tk + 1.f) * bs.fc;
 #pragma unroll
-        for (int q = 0; q < NG; ++q) gq[q] += c[q * KA + k] * f;
+        for (int q = 0; q < NG; ++q) gq[q] += cv[q] * f;
         const float Tn = 2.f * bs.x * Tk - Tm1;
         Tm1 = Tk;
         Tk = Tn;
@@ -158,6 +277,12 @@ __global__ void __launch_bounds__(kBlock, 2) k_descriptor(EvalArgs a, StructInfo
 #pragma unroll
                           for (int q = 0; q < NG; ++q) S[q][k] += gq[q] * b;
                         });
+    });
+    if constexpr (G > 1) {
+#pragma unroll
+      for (int q = 0; q < NG; ++q)
+#pragma unroll
+        for (int k = 0; k < NB; ++k) S[q][k] = group_sum<G>(S[q][k]);
     }
     // q_{nl} = sum_{k in l} C3_k S_{nk}^2 ; q_{n222} ; q_{n1111}
 #pragma unroll
@@ -166,7 +291,9 @@ __global__ void __launch_bounds__(kBlock, 2) k_descriptor(EvalArgs a, StructInfo
       if (n >= nA) break;
       float* sums = a.sums + (int64_t)(n * NB) * N + i;
 #pragma unroll
-      for (int k = 0; k < NB; ++k) sums[(int64_t)k * N] = S[q][k];
+      for (int k = 0; k < NB; ++k)
+        if (k % G == sub) sums[(int64_t)k * N] = S[q][k];
+      if (q % G != sub) continue;
       float v[L];
 #pragma unroll
       for (int l = 0; l < L; ++l) v[l] = 0.f;
@@ -192,7 +319,8 @@ __global__ void __launch_bounds__(kBlock, 2) k_descriptor(EvalArgs a, StructInfo
       }
     }
   }
-  for (int c = M.ND; c < M.NDp; ++c) qrow[c] = 0.f;
+  if (sub == 0)
+    for (int c = M.ND; c < M.NDp; ++c) qrow[c] = 0.f;
 }
 
 // ---------------------------------------------------------------------------
@@ -200,26 +328,31 @@ __global__ void __launch_bounds__(kBlock, 2) k_descriptor(EvalArgs a, StructInfo
 // ---------------------------------------------------------------------------
 
 // Large accumulator blocks (NG x NB > 120 floats) run at one wave per SIMD so
-// the compiler can keep the D block in AGPRs instead of spilling to memory.
-template <int NG, int L, bool BATCH>
+// the compiler can keep the D block in registers instead of spilling.
+template <int NG, int L, bool BATCH, int G>
 __global__ void __launch_bounds__(kBlock, (NG * num_poly(L) > 120) ? 1 : 2)
     k_partial_forces(EvalArgs a, StructInfo st0) {
   constexpr int NB = num_poly(L);
-  extern __shared__ float lds[];
+  extern __shared__ float4 lds_v4[];  // 16-byte aligned base
+  float* lds = reinterpret_cast<float*>(lds_v4);
   const DevModel& M = a.M;
   const int T = M.T, KR = M.KR, KA = M.KA, nR = M.nR, nA = M.nA;
+  constexpr int W = ng_pad(NG);
   float* sR = lds;
-  float* sA = sR + T * T * nR * KR;
-  float* At = sA + T * T * M.nA_pad * KA;
-  load_tables(M, sR, sA);
+  float* sA = sR + radial_table_floats(M);
+  float* At = sA + round4(T * T * a.ngroups * KA * W);
+  load_tables<NG>(M, a.ngroups, sR, sA);
   __syncthreads();
   const int tid = threadIdx.x, B = blockDim.x;
   const int64_t N = a.N;
-  const int64_t i = (int64_t)blockIdx.x * B + tid;
+  const int sub = tid & (G - 1);
+  const int64_t i = ((int64_t)blockIdx.x * B + tid) / G;
   if (i >= N) return;
   const StructInfo& st = struct_of<BATCH>(a, st0, i);
   const int ti = a.types[i];
   const double* __restrict__ pos = a.pos;
+  const int32_t* __restrict__ nl = a.L.nlR;
+  const uint16_t* __restrict__ cd = a.L.cdR;
   const float* __restrict__ fprow = a.fp + i * M.NDp;
 
   // ---- radial: A_{t,k} = sum_n dU/dq_n c^{t_i t}_{nk}; dU_i/dr_ij = (sum_k A f'_k) u ----
@@ -231,21 +364,19 @@ __global__ void __launch_bounds__(kBlock, (NG * num_poly(L) > 120) ? 1 : 2)
     }
   const float rcR = M.rcR;
   const int nnR = min(a.L.nnR[i], a.L.MR);
-  for (int m = 0; m < nnR; ++m) {
-    const int64_t e = (int64_t)m * N + i;
-    const int32_t j = a.L.nlR[e];
-    const uint16_t code = st.mode == kModeImages ? a.L.cdR[e] : kCodeCenter;
-    double dx, dy, dz;
-    entry_disp(pos, N, i, j, st, code, dx, dy, dz);
-    const float fx = (float)dx, fy = (float)dy, fz = (float)dz;
+  for_entries(a, st, i, sub, nnR, G,
+              [&](int m, int64_t e, int32_t j, int32_t tj, float fx, float fy, float fz)
+                  __attribute__((always_inline)) {
     const float r = sqrtf(fx * fx + fy * fy + fz * fz);
     const float rinv = 1.0f / r;
     const Basis bs = make_basis(r, rcR);
-    const float* At_j = At + (a.types[j] * KR) * B + tid;
+    const float* At_j = At + (tj * KR) * B + tid;
     // f'_k = 1/2 T'_k x' f_c + 1/2 (T_k + 1) f_c'
     float s = At_j[0] * bs.dfc;
     float Tm1 = 1.f, Tk = bs.x, dTm1 = 0.f, dTk = 1.f;
-    for (int k = 1; k < KR; ++k) {
+#pragma unroll
+    for (int k = 1; k < kMaxBasis; ++k) {
+      if (k >= KR) break;
       const float df = 0.5f * dTk * bs.dxdr * bs.fc + 0.5f * (Tk + 1.f) * bs.dfc;
       s += At_j[k * B] * df;
       const float Tn = 2.f * bs.x * Tk - Tm1;
@@ -257,11 +388,11 @@ __global__ void __launch_bounds__(kBlock, (NG * num_poly(L) > 120) ? 1 : 2)
     }
     s *= rinv;
     a.P[e] = make_float4(s * fx, s * fy, s * fz, 0.f);
-  }
+  });
 
   // ---- angular: sum_{n,k} D_{nk} [g'_n u b_k + g_n d b_k / d r_ij] ----
   const float rcA = M.rcA;
-  const int nnA = min(a.L.nnA[i], a.L.MA);
+  const int nnA = min(a.L.nnA[i], a.L.MR);
   for (int g = 0; g < a.ngroups; ++g) {
     // D_{nk} = dU/dS_{nk} through q_{nl}, q_{n222}, q_{n1111}
     float D[NG][NB];
@@ -299,32 +430,36 @@ __global__ void __launch_bounds__(kBlock, (NG * num_poly(L) > 120) ? 1 : 2)
         D[q][2] += f * (2.f * C[1] * s[0] * s[0] * s[2] + 4.f * C[2] * s12 * s[2]);
       }
     }
-    for (int m = 0; m < nnA; ++m) {
-      const int64_t e = (int64_t)m * N + i;
-      const int32_t j = a.L.nlA[e];
-      const uint16_t code = st.mode == kModeImages ? a.L.cdA[e] : kCodeCenter;
-      double dx, dy, dz;
-      entry_disp(pos, N, i, j, st, code, dx, dy, dz);
-      const float fx = (float)dx, fy = (float)dy, fz = (float)dz;
+    for_entries(a, st, i, sub, nnA, G,
+                [&](int m, int64_t e, int32_t j, int32_t tj, float fx, float fy, float fz)
+                    __attribute__((always_inline)) {
       const float r = sqrtf(fx * fx + fy * fy + fz * fz);
       const float rinv = 1.0f / r;
       const float ux = fx * rinv, uy = fy * rinv, uz = fz * rinv;
       const Basis bs = make_basis(r, rcA);
-      const float* c = sA + ((ti * T + a.types[j]) * M.nA_pad + g * NG) * KA;
+      const float* c = sA + ((ti * T + tj) * a.ngroups + g) * KA * W;
       float gq[NG], dgq[NG];
+      {
+        float cv[NG];
+        load_group<NG>(c, cv);
 #pragma unroll
-      for (int q = 0; q < NG; ++q) {
-        gq[q] = c[q * KA] * bs.fc;
-        dgq[q] = c[q * KA] * bs.dfc;
+        for (int q = 0; q < NG; ++q) {
+          gq[q] = cv[q] * bs.fc;
+          dgq[q] = cv[q] * bs.dfc;
+        }
       }
       float Tm1 = 1.f, Tk = bs.x, dTm1 = 0.f, dTk = 1.f;
-      for (int k = 1; k < KA; ++k) {
+#pragma unroll
+      for (int k = 1; k < kMaxBasis; ++k) {
+        if (k >= KA) break;
+        float cv[NG];
+        load_group<NG>(c + k * W, cv);
         const float f = 0.5f * (Tk + 1.f) * bs.fc;
         const float df = 0.5f * dTk * bs.dxdr * bs.fc + 0.5f * (Tk + 1.f) * bs.dfc;
 #pragma unroll
         for (int q = 0; q < NG; ++q) {
-          gq[q] += c[q * KA + k] * f;
-          dgq[q] += c[q * KA + k] * df;
+          gq[q] += cv[q] * f;
+          dgq[q] += cv[q] * df;
         }
         const float Tn = 2.f * bs.x * Tk - Tm1;
         const float dTn = 2.f * Tk + 2.f * bs.x * dTk - dTm1;
@@ -357,13 +492,13 @@ __global__ void __launch_bounds__(kBlock, (NG * num_poly(L) > 120) ? 1 : 2)
       const float px = s * ux + (Vx - uV * ux) * rinv;
       const float py = s * uy + (Vy - uV * uy) * rinv;
       const float pz = s * uz + (Vz - uV * uz) * rinv;
-      float4* p = a.P + (int64_t)a.L.amap[e] * N + i;
-      float4 v = *p;
+      // the same lane wrote the radial part of entry m above
+      float4 v = a.P[e];
       v.x += px;
       v.y += py;
       v.z += pz;
-      *p = v;
-    }
+      a.P[e] = v;
+    });
   }
 }
 
@@ -379,15 +514,12 @@ __global__ void __launch_bounds__(kBlock) k_gather(EvalArgs a, StructInfo st0) {
   const StructInfo& st = struct_of<BATCH>(a, st0, i);
   float F[3] = {0.f, 0.f, 0.f}, W[9] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
   const int nn = min(a.L.nnR[i], a.L.MR);
-  for (int m = 0; m < nn; ++m) {
-    const int64_t e = (int64_t)m * N + i;
-    const int32_t j = a.L.nlR[e];
-    const uint16_t code = st.mode == kModeImages ? a.L.cdR[e] : kCodeCenter;
+  for_entries(a, st, i, 0, nn, 1,
+              [&](int m, int64_t e, int32_t j, int32_t tj, float fx, float fy, float fz)
+                  __attribute__((always_inline)) {
     const float4 pij = a.P[e];
     const float4 pji = a.P[(int64_t)a.L.revR[e] * N + j];
-    double dx, dy, dz;
-    entry_disp(a.pos, N, i, j, st, code, dx, dy, dz);
-    const float d[3] = {(float)dx, (float)dy, (float)dz};
+    const float d[3] = {fx, fy, fz};
     const float q[3] = {pji.x, pji.y, pji.z};
     F[0] += pij.x - pji.x;
     F[1] += pij.y - pji.y;
@@ -396,7 +528,7 @@ __global__ void __launch_bounds__(kBlock) k_gather(EvalArgs a, StructInfo st0) {
     for (int x = 0; x < 3; ++x)
 #pragma unroll
       for (int y = 0; y < 3; ++y) W[x * 3 + y] += d[x] * q[y];
-  }
+  });
 #pragma unroll
   for (int c = 0; c < 3; ++c) a.F[(int64_t)c * N + i] = F[c];
 #pragma unroll
@@ -434,20 +566,27 @@ int angular_group_size(int nA, int L) {
   return best;
 }
 
-template <int NG, int L, bool BATCH>
-static void launch_pair(const EvalArgs& a, const StructInfo& st0, bool force, hipStream_t s) {
+template <int NG, int L, bool BATCH, int G>
+static void launch_pair_g(const EvalArgs& a, const StructInfo& st0, bool force, hipStream_t s) {
   const int block = a.block > 0 ? a.block : kBlock;
   const size_t lds = eval_lds_bytes(a.M, block);
-  dim3 grid((unsigned)div_up(a.N, block));
+  dim3 grid((unsigned)div_up(a.N * G, block));
   if (force)
-    hipLaunchKernelGGL((k_partial_forces<NG, L, BATCH>), grid, dim3(block), lds, s, a, st0);
+    hipLaunchKernelGGL((k_partial_forces<NG, L, BATCH, G>), grid, dim3(block), lds, s, a, st0);
   else
-    hipLaunchKernelGGL((k_descriptor<NG, L, BATCH>), grid, dim3(block), lds, s, a, st0);
+    hipLaunchKernelGGL((k_descriptor<NG, L, BATCH, G>), grid, dim3(block), lds, s, a, st0);
+}
+
+template <int NG, int L, bool BATCH>
+static void launch_pair(const EvalArgs& a, const StructInfo& st0, bool force, hipStream_t s) {
+  if (a.lanes == 4) launch_pair_g<NG, L, BATCH, 4>(a, st0, force, s);
+  else launch_pair_g<NG, L, BATCH, 1>(a, st0, force, s);
 }
 
 template <bool BATCH>
 static bool dispatch(const EvalArgs& a, const StructInfo& st0, bool force, hipStream_t s) {
   const int L = a.M.L, NG = a.NG;
+  if (a.lanes != 1 && a.lanes != 4) return false;
 #define NEP_CASE(ng, l)                                  \
   if (NG == ng && L == l) {                              \
     launch_pair<ng, l, BATCH>(a, st0, force, s);         \

@@ -7,17 +7,19 @@
 //   2. a deterministic counting sort gives the internal atom order
 //      (structure, cell, caller index): the atoms of a cell are contiguous;
 //   3. one thread per atom scans the stencil cells in increasing cell index,
-//      so candidate j arrive in increasing internal index and every row comes
-//      out sorted by (j, image) without a sort;
+//      so candidate j arrive in increasing internal index and every candidate
+//      row (radius r_c^R, or r_c^R + skin in MD with a skin) comes out sorted
+//      by (j, image) without a sort;
 //   4. membership is the strict float64 test |d|^2 < r_c^2 on the canonical
 //      displacement (no fused multiply-add), the same test for both cutoffs;
-//   5. the angular row is the subsequence of the radial row with
-//      |d|^2 < (r_c^A)^2; amap[m][i] is the radial position of angular entry m;
-//   6. rev[m][i] locates i in the radial row of its m-th neighbour (binary
-//      search), so the force pass can gather dU_j/dr_ji without atomics.
-//      With candidate rows (MD with a skin) the binary search runs on the
-//      candidate rows at each rebuild only, and the exact rows take their
-//      reverse positions through the candidate -> exact position map.
+//   5. the exact radial row is filtered from the candidates with the
+//      angular-range entries (|d|^2 < (r_c^A)^2) first and the rest after,
+//      each part in candidate order: the angular row of the sums is the
+//      first nnA entries of the radial row;
+//   6. rev[m][i] locates i in the radial row of its m-th neighbour: a binary
+//      search on the sorted candidate rows (once per candidate build) and the
+//      candidate -> exact position map of every filter, so the force pass
+//      can gather dU_j/dr_ji without atomics.
 #include "nep_kernels.h"
 
 namespace nep {
@@ -202,25 +204,16 @@ struct RowWriter {
   }
 };
 
-// Angular row entry that is also entry `rpos` of the radial row (clamped
-// into the radial capacity: an overflowing build is redone anyway, but the
-// kernels that run before the host sees the flag stay in bounds).
-__device__ inline void push_angular(RowWriter& A, uint16_t* amap, int32_t MR, int64_t N,
-                                    int64_t i, int32_t j, uint16_t code, int32_t rpos) {
-  if (A.count < A.cap) amap[(int64_t)A.count * N + i] = (uint16_t)min(rpos, MR - 1);
-  A.push(N, i, j, code);
-}
-
 __global__ void __launch_bounds__(kBlock) k_build_rows(
     const double* __restrict__ pos, int64_t N, const int32_t* __restrict__ sid,
     const StructInfo* __restrict__ structs, const int32_t* __restrict__ cell_start,
-    const int32_t* __restrict__ cell_count, double rcR2, double rcA2, Lists L,
-    int32_t* __restrict__ overflow, const int32_t* gate) {
+    const int32_t* __restrict__ cell_count, double rc2, Lists V, int32_t* __restrict__ overflow,
+    const int32_t* gate) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= N || gated_off(gate)) return;
   const StructInfo st = structs[sid[i]];
   const double xi = pos[i], yi = pos[N + i], zi = pos[2 * N + i];
-  RowWriter R{L.nlR, L.cdR, L.MR, 0}, A{L.nlA, L.cdA, L.MA, 0};
+  RowWriter R{V.nlR, V.cdR, V.MR, 0};
 
   auto consider = [&](int64_t j, int o0, int o1, int o2) {
     double Dx, Dy, Dz;
@@ -239,11 +232,7 @@ __global__ void __launch_bounds__(kBlock) k_build_rows(
     double dx, dy, dz;
     image_disp(st, Dx, Dy, Dz, n0, n1, n2, dx, dy, dz);
     double r2 = norm2_exact(dx, dy, dz);
-    if (r2 < rcR2) {
-      uint16_t code = make_code(o0, o1, o2);
-      if (r2 < rcA2) push_angular(A, L.amap, L.MR, N, i, (int32_t)j, code, R.count);
-      R.push(N, i, (int32_t)j, code);
-    }
+    if (r2 < rc2) R.push(N, i, (int32_t)j, make_code(o0, o1, o2));
   };
 
   if (st.mode == kModeCells) {
@@ -269,13 +258,12 @@ __global__ void __launch_bounds__(kBlock) k_build_rows(
         for (int o1 = -R1; o1 <= R1; ++o1)
           for (int o2 = -R2; o2 <= R2; ++o2) consider(j, o0, o1, o2);
   }
-  L.nnR[i] = R.count;
-  L.nnA[i] = A.count;
-  if (R.count > L.MR) atomicMax(&overflow[0], R.count);
-  if (A.count > L.MA) atomicMax(&overflow[1], A.count);
+  V.nnR[i] = R.count;
+  if (R.count > V.MR) atomicMax(overflow, R.count);
 }
 
-// rev[m][i] = position of (i, -offset) in the row of j = nl[m][i].
+// rev[m][i] = position of (i, -offset) in the row of j = nl[m][i] (rows
+// sorted by (j, image)).
 __global__ void k_reverse(int64_t N, const int32_t* __restrict__ nn, const int32_t* __restrict__ nl,
                           const uint16_t* __restrict__ cd, int32_t cap, int32_t* __restrict__ rev,
                           int32_t* __restrict__ err, const int32_t* gate) {
@@ -405,11 +393,12 @@ void launch_order_atoms(const BuildArgs& b, hipStream_t s) {
                      b.types_ext, b.sid_ext, b.pos, b.types, b.sid, g);
 }
 
-void launch_build_rows(const BuildArgs& b, const Lists& L, hipStream_t s) {
-  hipLaunchKernelGGL(k_build_rows, grid_for(b.N), dim3(kBlock), 0, s, b.pos, b.N, b.sid,
-                     b.structs, b.cell_start, b.cell_count, b.rcR2, b.rcA2, L, b.overflow,
-                     (const int32_t*)nullptr);
-  launch_reverse(b.N, L, b.overflow + 2, nullptr, s);
+void launch_build_rows(const BuildArgs& b, const StructInfo& st0, bool batch, const Lists& V,
+                       const Lists& L, hipStream_t s) {
+  BuildArgs bv = b;
+  bv.gate = nullptr;
+  launch_build_verlet(bv, V, s);
+  launch_filter_rows(b, st0, batch, V, L, s);
 }
 
 void launch_reverse(int64_t N, const Lists& L, int32_t* err, const int32_t* gate, hipStream_t s) {
@@ -417,18 +406,18 @@ void launch_reverse(int64_t N, const Lists& L, int32_t* err, const int32_t* gate
                      L.revR, err, gate);
 }
 
-// Candidate rows at r_c^R + skin (radial slots of V only), rebuilt when the
+// Candidate rows at sqrt(b.rcR2) and their reverse index, rebuilt when the
 // gate is set.
 void launch_build_verlet(const BuildArgs& b, const Lists& V, hipStream_t s) {
   hipLaunchKernelGGL(k_build_rows, grid_for(b.N), dim3(kBlock), 0, s, b.pos, b.N, b.sid,
-                     b.structs, b.cell_start, b.cell_count, b.rcR2, -1.0, V, b.overflow + 5,
-                     b.gate);
+                     b.structs, b.cell_start, b.cell_count, b.rcR2, V, b.overflow + 5, b.gate);
   launch_reverse(b.N, V, b.overflow + 2, b.gate, s);
 }
 
-// Exact rows at r_c^R and r_c^A from the candidate rows, order preserved (so
-// still sorted by (j, image)), with the same float64 membership test;
-// V.fmap[m][i] = radial position of candidate m, or -1.
+// Exact radial row from the candidate row with the same float64 membership
+// test: the entries with |d|^2 < (r_c^A)^2 first, then the others, each part
+// in candidate order; nnA = size of the first part.  V.fmap[m][i] = radial
+// position of candidate m, or -1.
 template <bool BATCH>
 __global__ void __launch_bounds__(kBlock) k_filter_rows(const double* __restrict__ pos, int64_t N,
                                                         const int32_t* __restrict__ sid,
@@ -436,10 +425,11 @@ __global__ void __launch_bounds__(kBlock) k_filter_rows(const double* __restrict
                                                         StructInfo st0, Lists V, double rcR2,
                                                         double rcA2, Lists L,
                                                         int32_t* __restrict__ overflow) {
+  constexpr int32_t kOuter = -2;
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= N) return;
   const StructInfo& st = BATCH ? structs[sid[i]] : st0;
-  RowWriter R{L.nlR, L.cdR, L.MR, 0}, A{L.nlA, L.cdA, L.MA, 0};
+  RowWriter R{L.nlR, L.cdR, L.MR, 0};
   const int nv = min(V.nnR[i], V.MR);
   for (int m = 0; m < nv; ++m) {
     const int64_t e = (int64_t)m * N + i;
@@ -449,17 +439,25 @@ __global__ void __launch_bounds__(kBlock) k_filter_rows(const double* __restrict
     entry_disp(pos, N, i, j, st, code, dx, dy, dz);
     const double r2 = norm2_exact(dx, dy, dz);
     int32_t f = -1;
-    if (r2 < rcR2) {
+    if (r2 < rcA2) {
       f = R.count;
-      if (r2 < rcA2) push_angular(A, L.amap, L.MR, N, i, j, code, R.count);
       R.push(N, i, j, code);
+    } else if (r2 < rcR2) {
+      f = kOuter;
     }
     V.fmap[e] = f;
   }
+  const int32_t nA = R.count;
+  for (int m = 0; m < nv; ++m) {
+    const int64_t e = (int64_t)m * N + i;
+    if (V.fmap[e] != kOuter) continue;
+    V.fmap[e] = R.count;
+    R.push(N, i, V.nlR[e], V.cdR[e]);
+  }
   L.nnR[i] = R.count;
-  L.nnA[i] = A.count;
+  L.nnA[i] = nA;
   if (R.count > L.MR) atomicMax(&overflow[0], R.count);
-  if (A.count > L.MA) atomicMax(&overflow[1], A.count);
+  if (nA > L.MA) atomicMax(&overflow[1], nA);
 }
 
 // rev of the exact rows from the candidate reverse index: the entry of i in

@@ -108,16 +108,24 @@ __device__ inline void entry_disp(const double* __restrict__ pos, int64_t N, int
   image_disp(st, Dx, Dy, Dz, n0, n1, n2, dx, dy, dz);
 }
 
+// Row length of a group of NG radial functions in the angular table.
+__host__ __device__ constexpr int ng_pad(int ng) { return ng <= 2 ? ng : (ng + 3) / 4 * 4; }
+__host__ __device__ constexpr int round4(int n) { return (n + 3) / 4 * 4; }
+
 // Model tables in device memory, float32 (converted once from the float64
 // parameter vector).  c tables are zero-padded to whole groups of radial
 // functions so kernels never test n < n_max + 1.
 struct DevModel {
   int32_t T, nR, KR, nA, KA, L, NB, ND, NDp, NN, nets, has4b, has5b;
-  int32_t nA_pad;           // n_A rounded up to the angular group size
+  int32_t cA_max;           // largest angular table (floats) over the group sizes
   float rcR, rcA;
   float b1;
   const float* cR;          // [T][T][nR][KR]
-  const float* cA;          // [T][T][nA_pad][KA]
+  // angular coefficients for group size NG at cA + cA_off[NG] (-1: none):
+  // [T][T][groups][KA][ng_pad(NG)], the NG functions of a group contiguous
+  // (zero beyond n_A), so one aligned vector read serves a whole group
+  const float* cA;
+  int32_t cA_off[8];
   int32_t NNp;              // N_neu rounded up to 32 (zero-padded neurons)
   int32_t NDp32;            // N_des rounded up to 32
   const float* w0;          // [nets][NNp][ND]   network weights w0, row = neuron

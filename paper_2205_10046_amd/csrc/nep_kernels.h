@@ -47,6 +47,7 @@ struct EvalArgs {
   int64_t rows_len;
   int32_t ngroups;            // angular radial-function groups
   int32_t NG;                 // group size
+  int32_t lanes;              // lanes per atom of the pair kernels (1 or 4)
   int32_t mlp_bf16;
   int32_t block;              // threads per block of the pair kernels (0 = 256)
   int32_t batch;              // several structures: geometry from structs[sid]
@@ -58,7 +59,9 @@ void launch_fill_i32(int32_t* a, int64_t n, int32_t v, hipStream_t s);
 void launch_assign_struct(const int64_t* offs, int32_t n_struct, int64_t N, int32_t* sid,
                           hipStream_t s);
 void launch_order_atoms(const BuildArgs& b, hipStream_t s);
-void launch_build_rows(const BuildArgs& b, const Lists& L, hipStream_t s);
+// Exact rows at the cutoffs of b from candidate rows V at sqrt(b.rcR2).
+void launch_build_rows(const BuildArgs& b, const StructInfo& st0, bool batch, const Lists& V,
+                       const Lists& L, hipStream_t s);
 void launch_reverse(int64_t N, const Lists& L, int32_t* err, const int32_t* gate, hipStream_t s);
 void launch_build_verlet(const BuildArgs& b, const Lists& V, hipStream_t s);
 void launch_filter_rows(const BuildArgs& b, const StructInfo& st0, bool batch, const Lists& V,

@@ -123,8 +123,7 @@ void launch_inverse_perm(const int32_t* perm, int64_t N, int32_t* inv, hipStream
 }
 
 // Neighbour rows in caller indices with absolute integer images n.  Output
-// rows follow the internal order (sorted by internal index); the host sorts
-// them by caller index.
+// rows follow the internal order; the host sorts them by caller index.
 __global__ void k_neighbors_out(Lists L, int which, int64_t N, const int32_t* __restrict__ perm,
                                 const int32_t* __restrict__ inv, const double* __restrict__ pos,
                                 const int32_t* __restrict__ sid,
@@ -135,10 +134,10 @@ __global__ void k_neighbors_out(Lists L, int which, int64_t N, const int32_t* __
   if (e >= N) return;
   const int64_t i = inv[e];
   const StructInfo& st = structs[sid[i]];
-  const int M = which ? L.MA : L.MR;
-  const int32_t* nl = which ? L.nlA : L.nlR;
-  const uint16_t* cd = which ? L.cdA : L.cdR;
-  const int nn = min(which ? L.nnA[i] : L.nnR[i], M);
+  // the angular row is the first nnA entries of the radial row
+  const int32_t* nl = L.nlR;
+  const uint16_t* cd = L.cdR;
+  const int nn = min(which ? L.nnA[i] : L.nnR[i], L.MR);
   count[e] = nn;
   for (int m = 0; m < nn && m < cap; ++m) {
     const int64_t j = nl[(int64_t)m * N + i];
