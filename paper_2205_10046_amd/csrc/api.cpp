@@ -817,7 +817,10 @@ void autotune(nep_handle* h, const Prepared& pp, hipStream_t s) {
   (void)hipEventDestroy(e1);
 }
 
-void forces(nep_handle* h, const Prepared& pp, hipStream_t s, const DevModel* model = nullptr) {
+// Descriptors, network, partial forces and the force gather; the per-atom
+// virial only when `virial` (MD steps without a thermo row skip it).
+void forces(nep_handle* h, const Prepared& pp, hipStream_t s, const DevModel* model = nullptr,
+            bool virial = true) {
   autotune(h, pp, s);
   const Tuning& t = h->tune[pp.batch ? 1 : 0];
   EvalArgs a = eval_args(h, pp, model ? *model : h->M);
@@ -837,7 +840,7 @@ void forces(nep_handle* h, const Prepared& pp, hipStream_t s, const DevModel* mo
   }
   {
     Stage st(h, "gather", s);
-    launch_gather_forces(a, s);
+    launch_gather_forces(a, virial, s);
   }
 }
 
@@ -1534,7 +1537,7 @@ int md_skin(nep_handle* h, const Prepared& pp, double* d_pos, double* d_vel, con
   md.vel = h->vel;
   md.types = h->types;
   // one MD step with a device-decided rebuild (a fixed kernel sequence)
-  auto step_body = [&](hipStream_t cs) {
+  auto step_body = [&](hipStream_t cs, bool virial) {
     {
       Stage st(h, "integrate", cs);
       launch_kick_drift(md, cs);
@@ -1549,7 +1552,7 @@ int md_skin(nep_handle* h, const Prepared& pp, double* d_pos, double* d_vel, con
       Stage st(h, "neighbor_rows", cs);
       skin_filter(h, pp, cs);
     }
-    forces(h, pp, cs);
+    forces(h, pp, cs, nullptr, virial);
     {
       Stage st(h, "integrate", cs);
       launch_kick(md, cs);
@@ -1562,42 +1565,49 @@ int md_skin(nep_handle* h, const Prepared& pp, double* d_pos, double* d_vel, con
   const bool use_graph = !h->timing && !(genv && genv[0] == '0') && n_steps >= G && G <= 1000;
   if (!h->row_counter) dev_alloc(h->row_counter, 1);
   hipStream_t gs = s;
-  hipStream_t own = nullptr;
-  hipGraph_t graph = nullptr;
-  hipGraphExec_t exec = nullptr;
-  if (use_graph) {
-    if (!gs) {
-      HIPCHK(hipStreamCreateWithFlags(&own, hipStreamNonBlocking));
-      gs = own;
+  struct GraphGuard {
+    hipGraph_t g = nullptr;
+    hipGraphExec_t e = nullptr;
+    hipStream_t own = nullptr;
+    void drop() {
+      if (e) (void)hipGraphExecDestroy(e);
+      if (g) (void)hipGraphDestroy(g);
+      e = nullptr;
+      g = nullptr;
     }
-    HIPCHK(hipStreamSynchronize(s));
+    ~GraphGuard() {
+      drop();
+      if (own) (void)hipStreamDestroy(own);
+    }
+  } guard;
+  // (Re)capture the G-step group: kernel arguments hold the row buffers by
+  // value, so a capture is only valid until the rows are reallocated.
+  auto capture = [&]() {
+    guard.drop();
+    HIPCHK(hipStreamSynchronize(gs));
     try {
       HIPCHK(hipStreamBeginCapture(gs, hipStreamCaptureModeThreadLocal));
-      for (int64_t k = 0; k < G; ++k) step_body(gs);
+      for (int64_t k = 0; k < G; ++k) step_body(gs, thermo_every > 0 && k == G - 1);
       if (thermo_every > 0)
         launch_thermo_counted(h->U, h->W, h->vel, h->types, h->mass, N, h->partial, num_partials(N),
                               h->thermo, h->row_counter, (double)thermo_every, kAmuA2fs2, kBoltzmann, gs);
-      HIPCHK(hipStreamEndCapture(gs, &graph));
-      HIPCHK(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
+      HIPCHK(hipStreamEndCapture(gs, &guard.g));
+      HIPCHK(hipGraphInstantiate(&guard.e, guard.g, nullptr, nullptr, 0));
     } catch (...) {
       hipGraph_t g2 = nullptr;
       (void)hipStreamEndCapture(gs, &g2);
       if (g2) (void)hipGraphDestroy(g2);
-      if (graph) (void)hipGraphDestroy(graph);
-      if (own) (void)hipStreamDestroy(own);
       throw;
     }
-  }
-  struct GraphGuard {
-    hipGraph_t g;
-    hipGraphExec_t e;
-    hipStream_t own;
-    ~GraphGuard() {
-      if (e) (void)hipGraphExecDestroy(e);
-      if (g) (void)hipGraphDestroy(g);
-      if (own) (void)hipStreamDestroy(own);
+  };
+  if (use_graph) {
+    if (!gs) {
+      HIPCHK(hipStreamCreateWithFlags(&guard.own, hipStreamNonBlocking));
+      gs = guard.own;
     }
-  } guard{graph, exec, own};
+    HIPCHK(hipStreamSynchronize(s));
+    capture();
+  }
   hipStream_t ws = use_graph ? gs : s;   // the stream every step runs on
   const int64_t chunk = use_graph ? G * std::max<int64_t>(1, 50 / G) : 50;
   int64_t row = 0;
@@ -1624,12 +1634,12 @@ int md_skin(nep_handle* h, const Prepared& pp, double* d_pos, double* d_vel, con
     }
     for (int64_t step = c0 + 1; step <= c1; ++step) {
       if (use_graph && (step - 1) % G == 0 && step - 1 + G <= c1) {
-        HIPCHK(hipGraphLaunch(exec, s));
+        HIPCHK(hipGraphLaunch(guard.e, s));
         if (thermo_every > 0) ++row;
         step += G - 1;
         continue;
       }
-      step_body(s);
+      step_body(s, thermo_every > 0 && step % thermo_every == 0);
       if (thermo_every > 0 && step % thermo_every == 0) {
         Stage st(h, "thermo", s);
         launch_thermo(h->U, h->W, h->vel, h->types, h->mass, N, h->partial, num_partials(N),
@@ -1649,6 +1659,7 @@ int md_skin(nep_handle* h, const Prepared& pp, double* d_pos, double* d_vel, con
       HIPCHK(hipMemcpyAsync(h->F, h->F_save, 3 * N * sizeof(float), hipMemcpyDeviceToDevice, s));
       row = row0;
       redo = true;
+      if (use_graph) capture();  // the grown rows live at new addresses
       continue;
     }
     if (fl[2]) throw Failure{NEP_E_HIP, "internal error: neighbour rows are not symmetric"};
@@ -1749,7 +1760,7 @@ static int md_impl(nep_handle* h, int64_t N, double* d_pos, double* d_vel, const
         BuildArgs b2 = build_args(h, pp, nullptr, nullptr, h->pos, h->types);
         launch_build_rows(b2, pp.geo.st, pp.batch, h->V, h->L, s);
       }
-      forces(h, pp, s);
+      forces(h, pp, s, nullptr, thermo_every > 0 && step % thermo_every == 0);
       md.pos = h->pos;
       md.vel = h->vel;
       md.types = h->types;

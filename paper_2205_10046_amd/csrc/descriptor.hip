@@ -506,33 +506,93 @@ __global__ void __launch_bounds__(kBlock, (NG * num_poly(L) > 120) ? 1 : 2)
 // force and virial gather (eqs. F_ij, F_i, virial)
 // ---------------------------------------------------------------------------
 
-template <bool BATCH>
+// One thread per atom walks its radial row; dU_j/dr_ji sits at position
+// rev[m][i] of row j.  The index words of entry m + 2 and the partial forces
+// (and neighbour position, for the virial) of entry m + 1 are loaded while
+// entry m is accumulated.  VIRIAL = false leaves W untouched (MD steps
+// without a thermo row).
+template <bool BATCH, bool VIRIAL>
 __global__ void __launch_bounds__(kBlock) k_gather(EvalArgs a, StructInfo st0) {
   const int64_t N = a.N;
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= N) return;
   const StructInfo& st = struct_of<BATCH>(a, st0, i);
-  float F[3] = {0.f, 0.f, 0.f}, W[9] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
   const int nn = min(a.L.nnR[i], a.L.MR);
-  for_entries(a, st, i, 0, nn, 1,
-              [&](int m, int64_t e, int32_t j, int32_t tj, float fx, float fy, float fz)
-                  __attribute__((always_inline)) {
-    const float4 pij = a.P[e];
-    const float4 pji = a.P[(int64_t)a.L.revR[e] * N + j];
-    const float d[3] = {fx, fy, fz};
-    const float q[3] = {pji.x, pji.y, pji.z};
-    F[0] += pij.x - pji.x;
-    F[1] += pij.y - pji.y;
-    F[2] += pij.z - pji.z;
+  const double* __restrict__ pos = a.pos;
+  const double xi = pos[i], yi = pos[N + i], zi = pos[2 * N + i];
+  struct Words {
+    int32_t j, r;
+    uint16_t code;
+  };
+  auto words = [&](int m) -> Words {
+    Words w{0, 0, kCodeCenter};
+    if (m < nn) {
+      const int64_t e = (int64_t)m * N + i;
+      w.j = a.L.nlR[e];
+      w.r = a.L.revR[e];
+      if (VIRIAL && st.mode == kModeImages) w.code = a.L.cdR[e];
+    }
+    return w;
+  };
+  Words w0 = words(0), w1 = words(1);
+  float4 pij = a.P[i];
+  float4 pji = a.P[(int64_t)w0.r * N + w0.j];
+  double px = 0.0, py = 0.0, pz = 0.0;
+  if (VIRIAL) {
+    px = pos[w0.j];
+    py = pos[N + w0.j];
+    pz = pos[2 * N + w0.j];
+  }
+  float F[3] = {0.f, 0.f, 0.f}, W[9] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+  for (int m = 0; m < nn; ++m) {
+    const Words c = w0;
+    const float4 cij = pij, cji = pji;
+    const double cx = px, cy = py, cz = pz;
+    w0 = w1;
+    w1 = words(m + 2);
+    pij = a.P[(int64_t)min(m + 1, nn - 1) * N + i];
+    pji = a.P[(int64_t)w0.r * N + w0.j];
+    if (VIRIAL) {
+      px = pos[w0.j];
+      py = pos[N + w0.j];
+      pz = pos[2 * N + w0.j];
+    }
+    F[0] += cij.x - cji.x;
+    F[1] += cij.y - cji.y;
+    F[2] += cij.z - cji.z;
+    if constexpr (VIRIAL) {
+      double Dx, Dy, Dz;
+      {
+#pragma clang fp contract(off)
+        Dx = cx - xi;
+        Dy = cy - yi;
+        Dz = cz - zi;
+      }
+      int n0, n1, n2;
+      min_image(st, Dx, Dy, Dz, n0, n1, n2);
+      if (c.code != kCodeCenter) {
+        int oa, ob, oc;
+        split_code(c.code, oa, ob, oc);
+        n0 += oa;
+        n1 += ob;
+        n2 += oc;
+      }
+      double dx, dy, dz;
+      image_disp(st, Dx, Dy, Dz, n0, n1, n2, dx, dy, dz);
+      const float d[3] = {(float)dx, (float)dy, (float)dz};
+      const float q[3] = {cji.x, cji.y, cji.z};
 #pragma unroll
-    for (int x = 0; x < 3; ++x)
+      for (int x = 0; x < 3; ++x)
 #pragma unroll
-      for (int y = 0; y < 3; ++y) W[x * 3 + y] += d[x] * q[y];
-  });
+        for (int y = 0; y < 3; ++y) W[x * 3 + y] += d[x] * q[y];
+    }
+  }
 #pragma unroll
   for (int c = 0; c < 3; ++c) a.F[(int64_t)c * N + i] = F[c];
+  if constexpr (VIRIAL) {
 #pragma unroll
-  for (int v = 0; v < 9; ++v) a.W[(int64_t)v * N + i] = W[v];
+    for (int v = 0; v < 9; ++v) a.W[(int64_t)v * N + i] = W[v];
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -610,12 +670,15 @@ bool launch_partial_forces(const EvalArgs& a, hipStream_t s) {
   return a.batch ? dispatch<true>(a, a.st0, true, s) : dispatch<false>(a, a.st0, true, s);
 }
 
-void launch_gather_forces(const EvalArgs& a, hipStream_t s) {
+void launch_gather_forces(const EvalArgs& a, bool virial, hipStream_t s) {
   dim3 grid((unsigned)div_up(a.N, kBlock));
-  if (a.batch)
-    hipLaunchKernelGGL((k_gather<true>), grid, dim3(kBlock), 0, s, a, a.st0);
-  else
-    hipLaunchKernelGGL((k_gather<false>), grid, dim3(kBlock), 0, s, a, a.st0);
+  if (a.batch) {
+    if (virial) hipLaunchKernelGGL((k_gather<true, true>), grid, dim3(kBlock), 0, s, a, a.st0);
+    else hipLaunchKernelGGL((k_gather<true, false>), grid, dim3(kBlock), 0, s, a, a.st0);
+  } else {
+    if (virial) hipLaunchKernelGGL((k_gather<false, true>), grid, dim3(kBlock), 0, s, a, a.st0);
+    else hipLaunchKernelGGL((k_gather<false, false>), grid, dim3(kBlock), 0, s, a, a.st0);
+  }
 }
 
 }  // namespace nep

@@ -416,8 +416,9 @@ void launch_build_verlet(const BuildArgs& b, const Lists& V, hipStream_t s) {
 
 // Exact radial row from the candidate row with the same float64 membership
 // test: the entries with |d|^2 < (r_c^A)^2 first, then the others, each part
-// in candidate order; nnA = size of the first part.  V.fmap[m][i] = radial
-// position of candidate m, or -1.
+// in candidate order; nnA = size of the first part.  V.fmap[m][i] = exact
+// position of candidate m (or -1).  The neighbour index and position of the
+// next candidate are loaded while the current one is tested.
 template <bool BATCH>
 __global__ void __launch_bounds__(kBlock) k_filter_rows(const double* __restrict__ pos, int64_t N,
                                                         const int32_t* __restrict__ sid,
@@ -431,12 +432,39 @@ __global__ void __launch_bounds__(kBlock) k_filter_rows(const double* __restrict
   const StructInfo& st = BATCH ? structs[sid[i]] : st0;
   RowWriter R{L.nlR, L.cdR, L.MR, 0};
   const int nv = min(V.nnR[i], V.MR);
+  const double xi = pos[i], yi = pos[N + i], zi = pos[2 * N + i];
+  int32_t jn = nv > 0 ? V.nlR[i] : 0;
+  uint16_t cn = nv > 0 ? V.cdR[i] : kCodeCenter;
+  double px = pos[jn], py = pos[N + jn], pz = pos[2 * N + jn];
   for (int m = 0; m < nv; ++m) {
     const int64_t e = (int64_t)m * N + i;
-    const int32_t j = V.nlR[e];
-    const uint16_t code = V.cdR[e];
+    const int32_t j = jn;
+    const uint16_t code = cn;
+    double Dx, Dy, Dz;
+    {
+#pragma clang fp contract(off)
+      Dx = px - xi;
+      Dy = py - yi;
+      Dz = pz - zi;
+    }
+    if (m + 1 < nv) {
+      jn = V.nlR[e + N];
+      cn = V.cdR[e + N];
+    }
+    px = pos[jn];
+    py = pos[N + jn];
+    pz = pos[2 * N + jn];
+    int n0, n1, n2;
+    min_image(st, Dx, Dy, Dz, n0, n1, n2);
+    if (code != kCodeCenter) {
+      int oa, ob, oc;
+      split_code(code, oa, ob, oc);
+      n0 += oa;
+      n1 += ob;
+      n2 += oc;
+    }
     double dx, dy, dz;
-    entry_disp(pos, N, i, j, st, code, dx, dy, dz);
+    image_disp(st, Dx, Dy, Dz, n0, n1, n2, dx, dy, dz);
     const double r2 = norm2_exact(dx, dy, dz);
     int32_t f = -1;
     if (r2 < rcA2) {
@@ -460,26 +488,38 @@ __global__ void __launch_bounds__(kBlock) k_filter_rows(const double* __restrict
   if (nA > L.MA) atomicMax(&overflow[1], nA);
 }
 
-// rev of the exact rows from the candidate reverse index: the entry of i in
-// the row of j sits at candidate position V.revR[m][i] there, whose exact
-// position is V.fmap of that entry.
+// rev of the exact rows: the entry of i in the row of j sits at candidate
+// position V.revR[m][i] there, whose exact position is V.fmap of that entry.
+// The candidate words of entry m + 1 are loaded while entry m is resolved.
 __global__ void __launch_bounds__(kBlock) k_reverse_from_candidates(int64_t N, Lists V, Lists L,
                                                                     int32_t* __restrict__ err) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= N) return;
   const int nv = min(V.nnR[i], V.MR);
+  int32_t fn = -1, jn = 0, rn = 0;
+  if (nv > 0) {
+    fn = V.fmap[i];
+    jn = V.nlR[i];
+    rn = V.revR[i];
+  }
+  bool broken = false;
   for (int m = 0; m < nv; ++m) {
-    const int64_t e = (int64_t)m * N + i;
-    const int32_t f = V.fmap[e];
+    const int32_t f = fn, j = jn, r = rn;
+    if (m + 1 < nv) {
+      const int64_t e1 = (int64_t)(m + 1) * N + i;
+      fn = V.fmap[e1];
+      jn = V.nlR[e1];
+      rn = V.revR[e1];
+    }
     if (f < 0) continue;
-    const int32_t j = V.nlR[e];
-    int32_t g = V.fmap[(int64_t)V.revR[e] * N + j];
+    int32_t g = V.fmap[(int64_t)r * N + j];
     if (g < 0) {
-      atomicExch(err, 1);
+      broken = true;
       g = 0;
     }
     if (f < L.MR) L.revR[(int64_t)f * N + i] = min(g, L.MR - 1);
   }
+  if (broken) atomicExch(err, 1);
 }
 
 void launch_filter_rows(const BuildArgs& b, const StructInfo& st0, bool batch, const Lists& V,

@@ -7,8 +7,10 @@
 //   nl_*     int32   [M][N]           neighbour m of atom i at nl[m*N + i]
 //   cd_*     uint16  [M][N]           image offset code of that entry
 //   revR     int32   [MR][N]          position of i in the radial row of that j
-//   amap     uint16  [MA][N]          position of angular entry m in the radial row
-//                                     (the angular row is a subsequence of it)
+//   nnA                               the angular row is the first nnA[i] entries
+//                                     of the radial row
+//   V.*      int32/uint16 [MV][N]     candidate rows (radius r_c^R + skin), their
+//                                     reverse index and candidate -> exact map
 //   q, fp    float32 [N][ND_pad]      descriptor / dU/dq rows (network input)
 //   sums     float32 [NA*NB][N]       angular sums S_{n,k}, SoA
 //   P        float32x4 [MR][N]        dU_i/dr_ij per radial entry, radial and
@@ -150,8 +152,7 @@ struct Lists {
   int32_t* nnA;
   int32_t* nlA;
   uint16_t* cdA;
-  uint16_t* amap;           // angular entry -> radial position
-  int32_t* fmap;            // candidate rows only: candidate -> exact radial position or -1
+  int32_t* fmap;            // candidate rows only: candidate -> exact position, or -1
 };
 
 constexpr int32_t kMaxRow = 65535;

@@ -34,7 +34,7 @@ struct EvalArgs {
   const int32_t* types;
   const int32_t* sid;
   const StructInfo* structs;
-  Lists L;
+  Lists L;                    // exact rows
   DevModel M;
   float* q;                   // [N][NDp]
   float* fp;                  // [N][NDp]
@@ -82,7 +82,7 @@ void launch_type_rows(const int32_t* types, int64_t N, int32_t T, int32_t per_ty
 // descriptor.hip / force.hip: return false if no kernel exists for (NG, L)
 bool launch_descriptor(const EvalArgs& a, hipStream_t s);
 bool launch_partial_forces(const EvalArgs& a, hipStream_t s);
-void launch_gather_forces(const EvalArgs& a, hipStream_t s);
+void launch_gather_forces(const EvalArgs& a, bool virial, hipStream_t s);
 size_t eval_lds_bytes(const DevModel& M, int block);
 int angular_group_size(int nA, int L);
 std::vector<int> angular_group_options(int nA, int L);
