@@ -189,7 +189,8 @@ def main():
 
     dev = torch.device("cuda:0")
     h = synth.WORKLOADS[WORKLOAD]
-    params = synth.random_params(nep.nep_num_params(h))
+    # a parameter vector that keeps the lattice solid over the run (see synth)
+    params = synth.solid_params(h, nep.nep_num_descriptors(h), nep.nep_num_params(h))
     pos, types, box = synth.fcc131k()
     masses = np.array(synth.MASSES[WORKLOAD])
     vel = synth.maxwell_velocities(masses[types], 300.0)
@@ -229,7 +230,8 @@ def main():
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f32",
-        "data": "synthetic",
+        "data": "synthetic (seeded lattice, Maxwell velocities, seeded parameter vector "
+                "with a repulsive radial term so the lattice stays solid)",
         "config": {"workload": "fcc131k: 131,072-atom 4-species random FCC alloy "
                                "(32^3 cells, a=4.05 A), NEP r_c 6/5 A, n_max 8/6, "
                                "N_bas 8/6, l_max 4 + 4-body, 50 neurons per species, "
@@ -260,7 +262,7 @@ def main():
     if not args.no_2m:
         # 2,000,000-atom BCC, l_max = 6 with 4-body and 5-body terms: FP32 vs BF16
         h2 = synth.WORKLOADS["bcc2m"]
-        p2 = synth.random_params(nep.nep_num_params(h2))
+        p2 = synth.solid_params(h2, nep.nep_num_descriptors(h2), nep.nep_num_params(h2))
         pos2, types2, box2 = synth.bcc2m()
         m2 = np.array(synth.MASSES["bcc2m"])
         vel2 = synth.maxwell_velocities(m2[types2], 300.0)

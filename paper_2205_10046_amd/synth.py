@@ -212,6 +212,38 @@ def random_params(n_params, seed=SEED_WEIGHTS, sigma=0.1):
     return np.random.default_rng(seed).normal(0.0, sigma, size=n_params)
 
 
+def solid_params(h, n_des, n_params, seed=SEED_WEIGHTS, sigma=0.1):
+    """Parameters for MD benchmarks that keep a lattice solid over a run (as a
+    trained model does), where i.i.d. weights let the alloy heat up and
+    cluster.  Starting from random_params, in the parameter vector (per
+    network w0[N_neu][N_des], b0, w1; then b1; c^R[t_i][t_j][n][k]; c^A):
+      * c^R of n = 0 is the k = 1 basis function alone (coefficient 1), a
+        short-ranged positive radial function, so q_0 grows as neighbours
+        come closer;
+      * w0 weights on descriptor 0 are 0.02 (the network stays in its linear
+        range) and all other w0 weights are scaled by 0.02;
+      * w1 = 5 + |w1|, so dU_i/dq_0 > 0: a stiff repulsive term plus a small
+        random many-body part.
+    Every descriptor still enters the network, so the cost is that of any
+    parameter vector of these hyper-parameters."""
+    n_types, n_neu, per_type = h["n_types"], h["n_neurons"], h["nn_per_type"]
+    n_r, k_r = h["n_max_radial"] + 1, h["basis_radial"] + 1
+    p = random_params(n_params, seed, sigma)
+    off = 0
+    for _ in range(n_types if per_type else 1):
+        w0 = p[off:off + n_neu * n_des].reshape(n_neu, n_des)
+        w0[:, 1:] *= 0.02
+        w0[:, 0] = 0.02
+        off += n_neu * n_des + n_neu
+        p[off:off + n_neu] = 5.0 + np.abs(p[off:off + n_neu])
+        off += n_neu
+    off += 1
+    c_r = p[off:off + n_types * n_types * n_r * k_r].reshape(n_types, n_types, n_r, k_r)
+    c_r[:, :, 0, :] = 0.0
+    c_r[:, :, 0, 1] = 1.0
+    return p
+
+
 def population(mean, n_pop, seed=SEED_WEIGHTS + 1, sigma=0.1):
     """SNES-style population z_p = mean + sigma * eps_p, eps_p ~ N(0, I)."""
     rng = np.random.default_rng(seed)
