@@ -34,6 +34,24 @@ PEAK_BF16_MFMA = 2500.0
 PEAK_HBM = 8000.0  # GB/s
 
 
+def measured_traffic():
+    """HBM bytes per launch of the partial-force kernel from the committed
+    FETCH_SIZE/WRITE_SIZE counter summary, or None when the kernel source has
+    changed since those counters were taken."""
+    import hashlib
+    import json
+    here = os.path.dirname(os.path.abspath(__file__))
+    try:
+        rec = json.load(open(os.path.join(here, "profiles", "partial_forces_fcc131k_traffic.json")))
+        src = open(os.path.join(here, rec["source"]), "rb").read()
+    except (OSError, KeyError, ValueError):
+        return None
+    if hashlib.sha256(src).hexdigest() != rec["source_sha256"]:
+        return None
+    return {"bytes": rec["fetch_bytes"] + rec["write_bytes"], "fetch_bytes": rec["fetch_bytes"],
+            "write_bytes": rec["write_bytes"], "kernel": rec["kernel"]}
+
+
 def algorithmic_flops(h, p_r, p_a):
     """Useful float work per atom of each pass (flop; a multiply-add counts 2).
 
@@ -213,6 +231,7 @@ def main():
     dt, stages, th = results[nep.NEP_MLP_FP32]
     value = n * args.steps / dt
     fl = algorithmic_flops(h, p_r, p_a)
+    tr = measured_traffic()
     avg = {k: v[0] / v[1] for k, v in stages.items()}
     dom = max(("descriptor", "partial_forces"), key=lambda k: avg.get(k, 0.0))
     achieved = fl[dom] * n / (avg[dom] * 1e-3) / 1e12
@@ -240,7 +259,8 @@ def main():
                    "atoms": n, "mlp": "fp32"},
         "roofline": {"bound": "alu", "kernel": dom, "achieved": achieved,
                      "peak": PEAK_FP32_VALU, "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_VALU,
-                     "traffic": None,
+                     "traffic": (tr or {}).get("bytes"), "traffic_unit": "bytes per launch",
+                     "traffic_detail": tr,
                      "flop_per_atom": fl[dom], "avg_launch_ms": avg[dom]},
         "mlp_roofline": {"bound": "mfma", "achieved": mlp_t, "peak": PEAK_FP32_MFMA,
                          "unit": "TFLOP/s", "frac": mlp_t / PEAK_FP32_MFMA,
