@@ -269,6 +269,7 @@ struct Tuning {
   bool done = false;
   int NG_desc = 0, NG_force = 0, block_desc = 256, block_force = 256;
   int lanes_desc = 1, lanes_force = 1;   // lanes per atom of the pair kernels
+  int lanes_gather = 1;                  // lanes per atom of the force gather
 };
 
 }  // namespace
@@ -443,15 +444,19 @@ void upload_model(nep_handle* h, const double* p, ModelTables& mt) {
   int32_t cA_off[8];
   int32_t cA_max = 0;
   for (int ng = 0; ng < 8; ++ng) cA_off[ng] = -1;
+  int32_t cA_pair[8];
+  for (int ng = 0; ng < 8; ++ng) cA_pair[ng] = 0;
   for (int ng : angular_group_options(nA, hp.l_max_3b)) {
     const int groups = (nA + ng - 1) / ng, w = ng_pad(ng);
+    const int ps = pair_stride(groups * KA * w);
     const size_t base = cA.size();
     cA_off[ng] = (int32_t)base;
-    cA.resize(base + (size_t)T * T * groups * KA * w, 0.f);
+    cA_pair[ng] = ps;
+    cA.resize(base + (size_t)T * T * ps, 0.f);
     for (int a = 0; a < T * T; ++a)
       for (int n = 0; n < nA; ++n)
         for (int k = 0; k < KA; ++k)
-          cA[base + (((size_t)a * groups + n / ng) * KA + k) * w + n % ng] =
+          cA[base + (size_t)a * ps + ((size_t)(n / ng) * KA + k) * w + n % ng] =
               (float)p[off + ((size_t)a * nA + n) * KA + k];
     cA_max = std::max(cA_max, (int32_t)(cA.size() - base));
   }
@@ -470,7 +475,10 @@ void upload_model(nep_handle* h, const double* p, ModelTables& mt) {
   M.NB = (hp.l_max_3b + 1) * (hp.l_max_3b + 1) - 1;
   M.ND = nd; M.NDp = (nd + 7) / 8 * 8; M.NN = NN; M.nets = nets;
   M.has4b = hp.l_max_4b >= 2; M.has5b = hp.l_max_5b >= 1; M.cA_max = cA_max;
-  for (int ng = 0; ng < 8; ++ng) M.cA_off[ng] = cA_off[ng];
+  for (int ng = 0; ng < 8; ++ng) {
+    M.cA_off[ng] = cA_off[ng];
+    M.cA_pair[ng] = cA_pair[ng];
+  }
   M.rcR = (float)hp.rc_radial; M.rcA = (float)hp.rc_angular; M.b1 = b1;
   M.cR = mt.cR; M.cA = mt.cA; M.NNp = NNp; M.NDp32 = NDp32;
   M.w0 = mt.w0; M.w0t = mt.w0t; M.b0 = mt.b0; M.w1 = mt.w1; M.w0b = mt.w0b; M.w0tb = mt.w0tb;
@@ -813,6 +821,29 @@ void autotune(nep_handle* h, const Prepared& pp, hipStream_t s) {
   launch_descriptor(a, s);
   launch_mlp(a, s);
   search(true, t.NG_force, t.block_force, t.lanes_force);
+  // the gather reads the partial forces: run the chosen force pass once, then time lanes 1 and 4
+  set_groups(a, t.NG_force, t.block_force, nA, t.lanes_force);
+  launch_partial_forces(a, s);
+  {
+    float best = 1e30f;
+    for (int ln : lane_opts) {
+      a.lanes = ln;
+      float ms_best = 1e30f;
+      for (int rep = 0; rep < 3; ++rep) {
+        HIPCHK(hipEventRecord(e0, s));
+        launch_gather_forces(a, false, s);
+        HIPCHK(hipEventRecord(e1, s));
+        HIPCHK(hipEventSynchronize(e1));
+        float ms = 0;
+        HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+        if (rep > 0) ms_best = std::min(ms_best, ms);
+      }
+      if (ms_best < best) {
+        best = ms_best;
+        t.lanes_gather = ln;
+      }
+    }
+  }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
 }
@@ -840,6 +871,7 @@ void forces(nep_handle* h, const Prepared& pp, hipStream_t s, const DevModel* mo
   }
   {
     Stage st(h, "gather", s);
+    a.lanes = t.lanes_gather;
     launch_gather_forces(a, virial, s);
   }
 }

@@ -139,7 +139,7 @@ __device__ __forceinline__ int radial_table_floats(const DevModel& M) {
 template <int NG>
 __device__ __forceinline__ void load_tables(const DevModel& M, int ngroups, float* sR, float* sA) {
   const int nRt = M.T * M.T * M.nR * M.KR;
-  const int nAt = M.T * M.T * ngroups * M.KA * ng_pad(NG);
+  const int nAt = M.T * M.T * M.cA_pair[NG];
   const float* cA = M.cA + M.cA_off[NG];
   for (int k = threadIdx.x; k < nRt; k += blockDim.x) sR[k] = M.cR[k];
   for (int k = threadIdx.x; k < nAt; k += blockDim.x) sA[k] = cA[k];
@@ -189,7 +189,7 @@ __global__ void __launch_bounds__(kBlock, 2) k_descriptor(EvalArgs a, StructInfo
   constexpr int W = ng_pad(NG);
   float* sR = lds;
   float* sA = sR + radial_table_floats(M);
-  float* acc = sA + round4(T * T * a.ngroups * KA * W);
+  float* acc = sA + round4(T * T * M.cA_pair[NG]);
   load_tables<NG>(M, a.ngroups, sR, sA);
   const int tid = threadIdx.x, B = blockDim.x;
   for (int k = 0; k < T * KR; ++k) acc[k * B + tid] = 0.f;
@@ -251,7 +251,7 @@ __global__ void __launch_bounds__(kBlock, 2) k_descriptor(EvalArgs a, StructInfo
       const float r = sqrtf(fx * fx + fy * fy + fz * fz);
       const float rinv = 1.0f / r;
       const Basis bs = make_basis(r, rcA);
-      const float* c = sA + ((ti * T + tj) * a.ngroups + g) * KA * W;
+      const float* c = sA + (ti * T + tj) * M.cA_pair[NG] + g * KA * W;
       float gq[NG];
       {
         float cv[NG];
@@ -340,7 +340,7 @@ __global__ void __launch_bounds__(kBlock, (NG * num_poly(L) > 120) ? 1 : 2)
   constexpr int W = ng_pad(NG);
   float* sR = lds;
   float* sA = sR + radial_table_floats(M);
-  float* At = sA + round4(T * T * a.ngroups * KA * W);
+  float* At = sA + round4(T * T * M.cA_pair[NG]);
   load_tables<NG>(M, a.ngroups, sR, sA);
   __syncthreads();
   const int tid = threadIdx.x, B = blockDim.x;
@@ -437,7 +437,7 @@ __global__ void __launch_bounds__(kBlock, (NG * num_poly(L) > 120) ? 1 : 2)
       const float rinv = 1.0f / r;
       const float ux = fx * rinv, uy = fy * rinv, uz = fz * rinv;
       const Basis bs = make_basis(r, rcA);
-      const float* c = sA + ((ti * T + tj) * a.ngroups + g) * KA * W;
+      const float* c = sA + (ti * T + tj) * M.cA_pair[NG] + g * KA * W;
       float gq[NG], dgq[NG];
       {
         float cv[NG];
@@ -506,16 +506,18 @@ __global__ void __launch_bounds__(kBlock, (NG * num_poly(L) > 120) ? 1 : 2)
 // force and virial gather (eqs. F_ij, F_i, virial)
 // ---------------------------------------------------------------------------
 
-// One thread per atom walks its radial row; dU_j/dr_ji sits at position
-// rev[m][i] of row j.  The index words of entry m + 2 and the partial forces
-// (and neighbour position, for the virial) of entry m + 1 are loaded while
-// entry m is accumulated.  VIRIAL = false leaves W untouched (MD steps
-// without a thermo row).
-template <bool BATCH, bool VIRIAL>
+// G lanes per atom (1 or 4) walk its radial row (lane s takes entries
+// s, s + G, ...); dU_j/dr_ji sits at position rev[m][i] of row j.  The index
+// words of a lane's entry after next and the partial forces (and neighbour
+// position, for the virial) of its next entry are loaded while the current
+// one is accumulated; the lane sums are combined with DPP quad sums.
+// VIRIAL = false leaves W untouched (MD steps without a thermo row).
+template <bool BATCH, bool VIRIAL, int G>
 __global__ void __launch_bounds__(kBlock) k_gather(EvalArgs a, StructInfo st0) {
   const int64_t N = a.N;
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= N) return;
+  const int sub = threadIdx.x & (G - 1);
+  const int64_t i = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / G;
+  if (i >= N) return;  // the lanes of an atom leave together
   const StructInfo& st = struct_of<BATCH>(a, st0, i);
   const int nn = min(a.L.nnR[i], a.L.MR);
   const double* __restrict__ pos = a.pos;
@@ -534,8 +536,8 @@ __global__ void __launch_bounds__(kBlock) k_gather(EvalArgs a, StructInfo st0) {
     }
     return w;
   };
-  Words w0 = words(0), w1 = words(1);
-  float4 pij = a.P[i];
+  Words w0 = words(sub), w1 = words(sub + G);
+  float4 pij = a.P[(int64_t)min(sub, max(nn - 1, 0)) * N + i];
   float4 pji = a.P[(int64_t)w0.r * N + w0.j];
   double px = 0.0, py = 0.0, pz = 0.0;
   if (VIRIAL) {
@@ -544,13 +546,13 @@ __global__ void __launch_bounds__(kBlock) k_gather(EvalArgs a, StructInfo st0) {
     pz = pos[2 * N + w0.j];
   }
   float F[3] = {0.f, 0.f, 0.f}, W[9] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-  for (int m = 0; m < nn; ++m) {
+  for (int m = sub; m < nn; m += G) {
     const Words c = w0;
     const float4 cij = pij, cji = pji;
     const double cx = px, cy = py, cz = pz;
     w0 = w1;
-    w1 = words(m + 2);
-    pij = a.P[(int64_t)min(m + 1, nn - 1) * N + i];
+    w1 = words(m + 2 * G);
+    pij = a.P[(int64_t)min(m + G, nn - 1) * N + i];
     pji = a.P[(int64_t)w0.r * N + w0.j];
     if (VIRIAL) {
       px = pos[w0.j];
@@ -588,10 +590,16 @@ __global__ void __launch_bounds__(kBlock) k_gather(EvalArgs a, StructInfo st0) {
     }
   }
 #pragma unroll
-  for (int c = 0; c < 3; ++c) a.F[(int64_t)c * N + i] = F[c];
+  for (int c = 0; c < 3; ++c) {
+    const float v = group_sum<G>(F[c]);
+    if (c % G == sub) a.F[(int64_t)c * N + i] = v;
+  }
   if constexpr (VIRIAL) {
 #pragma unroll
-    for (int v = 0; v < 9; ++v) a.W[(int64_t)v * N + i] = W[v];
+    for (int v = 0; v < 9; ++v) {
+      const float x = group_sum<G>(W[v]);
+      if (v % G == sub) a.W[(int64_t)v * N + i] = x;
+    }
   }
 }
 
@@ -670,15 +678,21 @@ bool launch_partial_forces(const EvalArgs& a, hipStream_t s) {
   return a.batch ? dispatch<true>(a, a.st0, true, s) : dispatch<false>(a, a.st0, true, s);
 }
 
-void launch_gather_forces(const EvalArgs& a, bool virial, hipStream_t s) {
-  dim3 grid((unsigned)div_up(a.N, kBlock));
+template <int G>
+static void launch_gather_g(const EvalArgs& a, bool virial, hipStream_t s) {
+  dim3 grid((unsigned)div_up(a.N * G, kBlock));
   if (a.batch) {
-    if (virial) hipLaunchKernelGGL((k_gather<true, true>), grid, dim3(kBlock), 0, s, a, a.st0);
-    else hipLaunchKernelGGL((k_gather<true, false>), grid, dim3(kBlock), 0, s, a, a.st0);
+    if (virial) hipLaunchKernelGGL((k_gather<true, true, G>), grid, dim3(kBlock), 0, s, a, a.st0);
+    else hipLaunchKernelGGL((k_gather<true, false, G>), grid, dim3(kBlock), 0, s, a, a.st0);
   } else {
-    if (virial) hipLaunchKernelGGL((k_gather<false, true>), grid, dim3(kBlock), 0, s, a, a.st0);
-    else hipLaunchKernelGGL((k_gather<false, false>), grid, dim3(kBlock), 0, s, a, a.st0);
+    if (virial) hipLaunchKernelGGL((k_gather<false, true, G>), grid, dim3(kBlock), 0, s, a, a.st0);
+    else hipLaunchKernelGGL((k_gather<false, false, G>), grid, dim3(kBlock), 0, s, a, a.st0);
   }
+}
+
+void launch_gather_forces(const EvalArgs& a, bool virial, hipStream_t s) {
+  if (a.lanes == 4) launch_gather_g<4>(a, virial, s);
+  else launch_gather_g<1>(a, virial, s);
 }
 
 }  // namespace nep

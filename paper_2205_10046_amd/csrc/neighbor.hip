@@ -417,8 +417,24 @@ void launch_build_verlet(const BuildArgs& b, const Lists& V, hipStream_t s) {
 // Exact radial row from the candidate row with the same float64 membership
 // test: the entries with |d|^2 < (r_c^A)^2 first, then the others, each part
 // in candidate order; nnA = size of the first part.  V.fmap[m][i] = exact
-// position of candidate m (or -1).  The neighbour index and position of the
-// next candidate are loaded while the current one is tested.
+// position of candidate m (or -1).  kFilterLanes lanes per atom each take a
+// contiguous quarter of the candidate row: pass 1 classifies it (neighbour
+// index and position of the next candidate in flight while the current one
+// is tested) and counts its members, quad-broadcast DPP prefix sums give each
+// lane its write offsets, pass 2 writes the entries.  The rows are the same
+// as those of a single sequential pass.
+constexpr int kFilterLanes = 4;
+
+// Value of v held by lane l of this lane's quad.
+__device__ __forceinline__ int32_t quad_lane(int32_t v, int l) {
+  switch (l) {
+    case 0: return __builtin_amdgcn_mov_dpp(v, 0x00, 0xF, 0xF, false);
+    case 1: return __builtin_amdgcn_mov_dpp(v, 0x55, 0xF, 0xF, false);
+    case 2: return __builtin_amdgcn_mov_dpp(v, 0xAA, 0xF, 0xF, false);
+    default: return __builtin_amdgcn_mov_dpp(v, 0xFF, 0xF, 0xF, false);
+  }
+}
+
 template <bool BATCH>
 __global__ void __launch_bounds__(kBlock) k_filter_rows(const double* __restrict__ pos, int64_t N,
                                                         const int32_t* __restrict__ sid,
@@ -426,19 +442,23 @@ __global__ void __launch_bounds__(kBlock) k_filter_rows(const double* __restrict
                                                         StructInfo st0, Lists V, double rcR2,
                                                         double rcA2, Lists L,
                                                         int32_t* __restrict__ overflow) {
-  constexpr int32_t kOuter = -2;
-  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= N) return;
+  constexpr int G = kFilterLanes;
+  constexpr int32_t kOuter = -2, kAngular = -3;
+  const int sub = threadIdx.x & (G - 1);
+  const int64_t i = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / G;
+  if (i >= N) return;  // the lanes of an atom leave together
   const StructInfo& st = BATCH ? structs[sid[i]] : st0;
-  RowWriter R{L.nlR, L.cdR, L.MR, 0};
   const int nv = min(V.nnR[i], V.MR);
+  const int q = (nv + G - 1) / G;
+  const int m0 = min(sub * q, nv), m1 = min(m0 + q, nv);
+  const bool images = st.mode == kModeImages;
   const double xi = pos[i], yi = pos[N + i], zi = pos[2 * N + i];
-  int32_t jn = nv > 0 ? V.nlR[i] : 0;
-  uint16_t cn = nv > 0 ? V.cdR[i] : kCodeCenter;
+  int32_t jn = m0 < m1 ? V.nlR[(int64_t)m0 * N + i] : 0;
+  uint16_t cn = (images && m0 < m1) ? V.cdR[(int64_t)m0 * N + i] : kCodeCenter;
   double px = pos[jn], py = pos[N + jn], pz = pos[2 * N + jn];
-  for (int m = 0; m < nv; ++m) {
+  int32_t na = 0, no = 0;
+  for (int m = m0; m < m1; ++m) {
     const int64_t e = (int64_t)m * N + i;
-    const int32_t j = jn;
     const uint16_t code = cn;
     double Dx, Dy, Dz;
     {
@@ -447,9 +467,9 @@ __global__ void __launch_bounds__(kBlock) k_filter_rows(const double* __restrict
       Dy = py - yi;
       Dz = pz - zi;
     }
-    if (m + 1 < nv) {
+    if (m + 1 < m1) {
       jn = V.nlR[e + N];
-      cn = V.cdR[e + N];
+      if (images) cn = V.cdR[e + N];
     }
     px = pos[jn];
     py = pos[N + jn];
@@ -468,45 +488,72 @@ __global__ void __launch_bounds__(kBlock) k_filter_rows(const double* __restrict
     const double r2 = norm2_exact(dx, dy, dz);
     int32_t f = -1;
     if (r2 < rcA2) {
-      f = R.count;
-      R.push(N, i, j, code);
+      f = kAngular;
+      ++na;
     } else if (r2 < rcR2) {
       f = kOuter;
+      ++no;
     }
     V.fmap[e] = f;
   }
-  const int32_t nA = R.count;
-  for (int m = 0; m < nv; ++m) {
-    const int64_t e = (int64_t)m * N + i;
-    if (V.fmap[e] != kOuter) continue;
-    V.fmap[e] = R.count;
-    R.push(N, i, V.nlR[e], V.cdR[e]);
+  // offsets: angular entries of lanes < sub, then all angular, then outer of lanes < sub
+  int32_t a_before = 0, o_before = 0, a_all = 0, o_all = 0;
+#pragma unroll
+  for (int l = 0; l < G; ++l) {
+    const int32_t al = quad_lane(na, l), ol = quad_lane(no, l);
+    a_all += al;
+    o_all += ol;
+    if (l < sub) {
+      a_before += al;
+      o_before += ol;
+    }
   }
-  L.nnR[i] = R.count;
-  L.nnA[i] = nA;
-  if (R.count > L.MR) atomicMax(&overflow[0], R.count);
-  if (nA > L.MA) atomicMax(&overflow[1], nA);
+  int32_t pa = a_before, po = a_all + o_before;
+  for (int m = m0; m < m1; ++m) {
+    const int64_t e = (int64_t)m * N + i;
+    const int32_t c = V.fmap[e];
+    if (c >= -1) continue;
+    const int32_t p = c == kAngular ? pa++ : po++;
+    V.fmap[e] = p;
+    if (p < L.MR) {
+      L.nlR[(int64_t)p * N + i] = V.nlR[e];
+      if (images) L.cdR[(int64_t)p * N + i] = V.cdR[e];
+    }
+  }
+  if (sub == 0) {
+    const int32_t total = a_all + o_all;
+    L.nnR[i] = total;
+    L.nnA[i] = a_all;
+    if (total > L.MR) atomicMax(&overflow[0], total);
+    if (a_all > L.MA) atomicMax(&overflow[1], a_all);
+  }
 }
 
 // rev of the exact rows: the entry of i in the row of j sits at candidate
 // position V.revR[m][i] there, whose exact position is V.fmap of that entry.
-// The candidate words of entry m + 1 are loaded while entry m is resolved.
+// kRevLanes lanes per atom take candidates m = s, s + 4, ...; the words of a
+// lane's next candidate are loaded while the current one is resolved.
+constexpr int kRevLanes = 4;
+
 __global__ void __launch_bounds__(kBlock) k_reverse_from_candidates(int64_t N, Lists V, Lists L,
                                                                     int32_t* __restrict__ err) {
-  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  constexpr int G = kRevLanes;
+  const int sub = threadIdx.x & (G - 1);
+  const int64_t i = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / G;
   if (i >= N) return;
   const int nv = min(V.nnR[i], V.MR);
   int32_t fn = -1, jn = 0, rn = 0;
-  if (nv > 0) {
-    fn = V.fmap[i];
-    jn = V.nlR[i];
-    rn = V.revR[i];
+  if (sub < nv) {
+    const int64_t e0 = (int64_t)sub * N + i;
+    fn = V.fmap[e0];
+    jn = V.nlR[e0];
+    rn = V.revR[e0];
   }
   bool broken = false;
-  for (int m = 0; m < nv; ++m) {
+  for (int m = sub; m < nv; m += G) {
     const int32_t f = fn, j = jn, r = rn;
-    if (m + 1 < nv) {
-      const int64_t e1 = (int64_t)(m + 1) * N + i;
+    if (m + G < nv) {
+      const int64_t e1 = (int64_t)(m + G) * N + i;
       fn = V.fmap[e1];
       jn = V.nlR[e1];
       rn = V.revR[e1];
@@ -524,14 +571,15 @@ __global__ void __launch_bounds__(kBlock) k_reverse_from_candidates(int64_t N, L
 
 void launch_filter_rows(const BuildArgs& b, const StructInfo& st0, bool batch, const Lists& V,
                         const Lists& L, hipStream_t s) {
+  const dim3 grid = grid_for(b.N * kFilterLanes);
   if (batch)
-    hipLaunchKernelGGL(k_filter_rows<true>, grid_for(b.N), dim3(kBlock), 0, s, b.pos, b.N, b.sid,
-                       b.structs, st0, V, b.rcR2, b.rcA2, L, b.overflow);
+    hipLaunchKernelGGL(k_filter_rows<true>, grid, dim3(kBlock), 0, s, b.pos, b.N, b.sid, b.structs,
+                       st0, V, b.rcR2, b.rcA2, L, b.overflow);
   else
-    hipLaunchKernelGGL(k_filter_rows<false>, grid_for(b.N), dim3(kBlock), 0, s, b.pos, b.N, b.sid,
-                       b.structs, st0, V, b.rcR2, b.rcA2, L, b.overflow);
-  hipLaunchKernelGGL(k_reverse_from_candidates, grid_for(b.N), dim3(kBlock), 0, s, b.N, V, L,
-                     b.overflow + 2);
+    hipLaunchKernelGGL(k_filter_rows<false>, grid, dim3(kBlock), 0, s, b.pos, b.N, b.sid, b.structs,
+                       st0, V, b.rcR2, b.rcA2, L, b.overflow);
+  hipLaunchKernelGGL(k_reverse_from_candidates, grid_for(b.N * kRevLanes), dim3(kBlock), 0, s,
+                     b.N, V, L, b.overflow + 2);
 }
 
 // gate = any |r_i - r_i(at last build)|^2 > thr2

@@ -5,7 +5,8 @@
 // atom order = structure-major, then cell-major, then caller index):
 //   pos      float64 [3][N]           SoA, internal order
 //   nl_*     int32   [M][N]           neighbour m of atom i at nl[m*N + i]
-//   cd_*     uint16  [M][N]           image offset code of that entry
+//   cd_*     uint16  [M][N]           image offset code of that entry (exact rows:
+//                                     stored only for kModeImages structures)
 //   revR     int32   [MR][N]          position of i in the radial row of that j
 //   nnA                               the angular row is the first nnA[i] entries
 //                                     of the radial row
@@ -113,6 +114,8 @@ __device__ inline void entry_disp(const double* __restrict__ pos, int64_t N, int
 // Row length of a group of NG radial functions in the angular table.
 __host__ __device__ constexpr int ng_pad(int ng) { return ng <= 2 ? ng : (ng + 3) / 4 * 4; }
 __host__ __device__ constexpr int round4(int n) { return (n + 3) / 4 * 4; }
+// Smallest stride >= n floats that is 4 mod 64 (bank-spread species pairs).
+__host__ __device__ constexpr int pair_stride(int n) { return n + ((4 - n % 64) + 64) % 64; }
 
 // Model tables in device memory, float32 (converted once from the float64
 // parameter vector).  c tables are zero-padded to whole groups of radial
@@ -124,10 +127,13 @@ struct DevModel {
   float b1;
   const float* cR;          // [T][T][nR][KR]
   // angular coefficients for group size NG at cA + cA_off[NG] (-1: none):
-  // [T][T][groups][KA][ng_pad(NG)], the NG functions of a group contiguous
-  // (zero beyond n_A), so one aligned vector read serves a whole group
+  // [T x T species pairs, cA_pair[NG] floats apart][groups][KA][ng_pad(NG)],
+  // the NG functions of a group contiguous (zero beyond n_A), so one aligned
+  // vector read serves a whole group; the pair stride is 4 mod 64 floats so
+  // lanes reading different species pairs fall into different LDS banks
   const float* cA;
   int32_t cA_off[8];
+  int32_t cA_pair[8];
   int32_t NNp;              // N_neu rounded up to 32 (zero-padded neurons)
   int32_t NDp32;            // N_des rounded up to 32
   const float* w0;          // [nets][NNp][ND]   network weights w0, row = neuron

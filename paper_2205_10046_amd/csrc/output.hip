@@ -144,7 +144,8 @@ __global__ void k_neighbors_out(Lists L, int which, int64_t N, const int32_t* __
     int n0, n1, n2, a, b, c;
     min_image(st, pos[j] - pos[i], pos[N + j] - pos[N + i], pos[2 * N + j] - pos[2 * N + i], n0,
               n1, n2);
-    split_code(cd[(int64_t)m * N + i], a, b, c);
+    // image codes are stored only for structures that need several images
+    split_code(st.mode == kModeImages ? cd[(int64_t)m * N + i] : kCodeCenter, a, b, c);
     nbr[e * cap + m] = perm[j];
     shift[(e * cap + m) * 3 + 0] = n0 + a;
     shift[(e * cap + m) * 3 + 1] = n1 + b;
