@@ -364,11 +364,9 @@ __global__ void __launch_bounds__(kBlock, (NG * num_poly(L) > 120) ? 1 : 2)
     }
   const float rcR = M.rcR;
   const int nnR = min(a.L.nnR[i], a.L.MR);
-  for_entries(a, st, i, sub, nnR, G,
-              [&](int m, int64_t e, int32_t j, int32_t tj, float fx, float fy, float fz)
-                  __attribute__((always_inline)) {
-    const float r = sqrtf(fx * fx + fy * fy + fz * fz);
-    const float rinv = 1.0f / r;
+  const int nnA = min(a.L.nnA[i], a.L.MR);
+  // radial scalar s with dU_i/dr_ij (radial part) = s * r_ij
+  auto radial_scalar = [&](int32_t tj, float r, float rinv) __attribute__((always_inline)) {
     const Basis bs = make_basis(r, rcR);
     const float* At_j = At + (tj * KR) * B + tid;
     // f'_k = 1/2 T'_k x' f_c + 1/2 (T_k + 1) f_c'
@@ -386,13 +384,21 @@ __global__ void __launch_bounds__(kBlock, (NG * num_poly(L) > 120) ? 1 : 2)
       dTm1 = dTk;
       dTk = dTn;
     }
-    s *= rinv;
+    return s * rinv;
+  };
+  // entries past the angular prefix: radial part only (the prefix gets its
+  // radial part in the first angular pass below); first such m of this lane
+  const int m_outer = sub + (nnA > sub ? (nnA - sub + G - 1) / G * G : 0);
+  for_entries(a, st, i, m_outer, nnR, G,
+              [&](int m, int64_t e, int32_t j, int32_t tj, float fx, float fy, float fz)
+                  __attribute__((always_inline)) {
+    const float r = sqrtf(fx * fx + fy * fy + fz * fz);
+    const float s = radial_scalar(tj, r, 1.0f / r);
     a.P[e] = make_float4(s * fx, s * fy, s * fz, 0.f);
   });
 
   // ---- angular: sum_{n,k} D_{nk} [g'_n u b_k + g_n d b_k / d r_ij] ----
   const float rcA = M.rcA;
-  const int nnA = min(a.L.nnA[i], a.L.MR);
   for (int g = 0; g < a.ngroups; ++g) {
     // D_{nk} = dU/dS_{nk} through q_{nl}, q_{n222}, q_{n1111}
     float D[NG][NB];
@@ -492,8 +498,15 @@ __global__ void __launch_bounds__(kBlock, (NG * num_poly(L) > 120) ? 1 : 2)
       const float px = s * ux + (Vx - uV * ux) * rinv;
       const float py = s * uy + (Vy - uV * uy) * rinv;
       const float pz = s * uz + (Vz - uV * uz) * rinv;
-      // the same lane wrote the radial part of entry m above
-      float4 v = a.P[e];
+      // the first pass adds the radial part of the pair (same rounding order
+      // as radial first, then each angular group); later passes update it
+      float4 v;
+      if (g == 0) {
+        const float sr = radial_scalar(tj, r, rinv);
+        v = make_float4(sr * fx, sr * fy, sr * fz, 0.f);
+      } else {
+        v = a.P[e];
+      }
       v.x += px;
       v.y += py;
       v.z += pz;
