@@ -356,10 +356,18 @@ __global__ void __launch_bounds__(kBlock, (NG * num_poly(L) > 120) ? 1 : 2)
   const float* __restrict__ fprow = a.fp + i * M.NDp;
 
   // ---- radial: A_{t,k} = sum_n dU/dq_n c^{t_i t}_{nk}; dU_i/dr_ij = (sum_k A f'_k) u ----
+  float fpr[kMaxBasis];  // dU/dq_n of the radial descriptors, loaded once
+#pragma unroll
+  for (int n = 0; n < kMaxBasis; ++n) fpr[n] = n < nR ? fprow[n] : 0.f;
   for (int t = 0; t < T; ++t)
     for (int k = 0; k < KR; ++k) {
+      const float* c = sR + (ti * T + t) * nR * KR + k;
       float s = 0.f;
-      for (int n = 0; n < nR; ++n) s += fprow[n] * sR[((ti * T + t) * nR + n) * KR + k];
+#pragma unroll
+      for (int n = 0; n < kMaxBasis; ++n) {
+        if (n >= nR) break;
+        s += fpr[n] * c[n * KR];
+      }
       At[(t * KR + k) * B + tid] = s;
     }
   const float rcR = M.rcR;
