@@ -227,14 +227,23 @@ __global__ void __launch_bounds__(kBlock, 2) k_descriptor(EvalArgs a, StructInfo
   });
   if constexpr (G > 1)
     for (int k = 0; k < T * KR; ++k) acc[k * B + tid] = group_sum<G>(acc[k * B + tid]);
-  for (int n = sub; n < nR; n += G) {
-    float s = 0.f;
-    for (int t = 0; t < T; ++t) {
-      const float* c = sR + ((ti * T + t) * nR + n) * KR;
-      for (int k = 0; k < KR; ++k) s += c[k] * acc[(t * KR + k) * B + tid];
+  // q_n = sum_t sum_k c^{t_i t}_{nk} F_{t,k}: each F read once, all n in registers
+  float qr[kMaxBasis];
+#pragma unroll
+  for (int n = 0; n < kMaxBasis; ++n) qr[n] = 0.f;
+  for (int t = 0; t < T; ++t)
+    for (int k = 0; k < KR; ++k) {
+      const float F = acc[(t * KR + k) * B + tid];
+      const float* c = sR + (ti * T + t) * nR * KR + k;
+#pragma unroll
+      for (int n = 0; n < kMaxBasis; ++n) {
+        if (n >= nR) break;
+        qr[n] += c[n * KR] * F;
+      }
     }
-    qrow[n] = s;
-  }
+#pragma unroll
+  for (int n = 0; n < kMaxBasis; ++n)
+    if (n < nR && n % G == sub) qrow[n] = qr[n];
 
   // ---- angular: S_{n,k} = sum_j g_n(r_ij) b_k(u_ij), NG radial functions at a time ----
   const float rcA = M.rcA;
