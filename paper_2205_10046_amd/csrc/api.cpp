@@ -1483,14 +1483,13 @@ void skin_rebuild(nep_handle* h, const Prepared& pp, double rl, const int32_t* g
   BuildArgs br = build_args(h, pp, h->pos, h->types, h->pos2, h->types2);
   br.ext_src = h->ext_id;
   br.gate = gate;
+  br.vel_src = h->vel;
+  br.vel_dst = h->vel2;
+  br.ext_in = h->ext_id;
+  br.ext_out = h->ext_id2;
   launch_order_atoms(br, s);
-  launch_gather3_gated(h->perm, N, h->vel, h->vel2, gate, s);
-  launch_gather_i32_gated(h->perm, N, h->ext_id, h->ext_id2, gate, s);
-  launch_copy_gated_f64(h->pos, h->pos2, 3 * N, gate, s);
-  launch_copy_gated_f64(h->vel, h->vel2, 3 * N, gate, s);
-  launch_copy_gated_i32(h->types, h->types2, N, gate, s);
-  launch_copy_gated_i32(h->ext_id, h->ext_id2, N, gate, s);
-  launch_copy_gated_f64(h->pos_ref, h->pos, 3 * N, gate, s);
+  launch_commit_rebuild(N, h->pos2, h->vel2, h->types2, h->ext_id2, h->pos, h->vel, h->types,
+                        h->ext_id, h->pos_ref, gate, s);
   BuildArgs bv = build_args(h, pp, nullptr, nullptr, h->pos, h->types);
   bv.rcR2 = rl * rl;
   bv.gate = gate;

@@ -152,20 +152,44 @@ __global__ void k_cell_sort(const int32_t* __restrict__ cell_start,
   }
 }
 
-__global__ void k_gather_atoms(const int32_t* __restrict__ perm, int64_t N,
-                               const double* __restrict__ pos_ext,
-                               const int32_t* __restrict__ types_ext,
-                               const int32_t* __restrict__ sid_ext, double* __restrict__ pos,
-                               int32_t* __restrict__ types, int32_t* __restrict__ sid,
-                               const int32_t* gate) {
+__global__ void k_gather_atoms(BuildArgs b) {
+  const int64_t N = b.N;
+  int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= N || gated_off(b.gate)) return;
+  int64_t e = b.perm[k];
+  for (int c = 0; c < 3; ++c) b.pos[c * N + k] = b.pos_ext[c * N + e];
+  b.types[k] = b.types_ext[e];
+  b.sid[k] = b.sid_ext[e];
+  if (b.vel_src)
+    for (int c = 0; c < 3; ++c) b.vel_dst[c * N + k] = b.vel_src[c * N + e];
+  if (b.ext_in) b.ext_out[k] = b.ext_in[e];
+}
+
+__global__ void k_fill_cells(int32_t* __restrict__ a, int32_t* __restrict__ b, int64_t n,
+                             const int32_t* gate) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n && !gated_off(gate)) {
+    a[i] = 0;
+    b[i] = 0;
+  }
+}
+
+__global__ void k_commit_rebuild(int64_t N, const double* __restrict__ pos2,
+                                 const double* __restrict__ vel2, const int32_t* __restrict__ types2,
+                                 const int32_t* __restrict__ ext2, double* __restrict__ pos,
+                                 double* __restrict__ vel, int32_t* __restrict__ types,
+                                 int32_t* __restrict__ ext, double* __restrict__ pos_ref,
+                                 const int32_t* gate) {
   int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= N || gated_off(gate)) return;
-  int64_t e = perm[k];
-  pos[k] = pos_ext[e];
-  pos[N + k] = pos_ext[N + e];
-  pos[2 * N + k] = pos_ext[2 * N + e];
-  types[k] = types_ext[e];
-  sid[k] = sid_ext[e];
+  for (int c = 0; c < 3; ++c) {
+    const double x = pos2[c * N + k];
+    pos[c * N + k] = x;
+    pos_ref[c * N + k] = x;
+    vel[c * N + k] = vel2[c * N + k];
+  }
+  types[k] = types2[k];
+  ext[k] = ext2[k];
 }
 
 // The up-to-3 stencil cells along one cell vector in increasing order.
@@ -311,10 +335,13 @@ __device__ __forceinline__ int row_species(const int32_t* types, int64_t i, int3
 __global__ void __launch_bounds__(kBlock) k_type_block_count(const int32_t* __restrict__ types,
                                                              int64_t N, int32_t Tn, int32_t per_type,
                                                              int32_t nb, int32_t* __restrict__ tblk,
-                                                             const int32_t* gate) {
+                                                             int32_t* __restrict__ rows,
+                                                             int64_t rows_len, const int32_t* gate) {
   __shared__ int32_t hist[kMaxTypes];
   if (gated_off(gate)) return;
   const int t = threadIdx.x;
+  // every row slot starts as padding (-1); the scatter kernel fills the atoms
+  for (int64_t r = (int64_t)blockIdx.x * kBlock + t; r < rows_len; r += (int64_t)nb * kBlock) rows[r] = -1;
   if (t < kMaxTypes) hist[t] = 0;
   __syncthreads();
   const int64_t i = (int64_t)blockIdx.x * kBlock + t;
@@ -377,10 +404,8 @@ void launch_assign_struct(const int64_t* offs, int32_t n_struct, int64_t N, int3
 
 void launch_order_atoms(const BuildArgs& b, hipStream_t s) {
   const int32_t* g = b.gate;
-  hipLaunchKernelGGL(k_fill_i32_gated, grid_for(b.n_cells), dim3(kBlock), 0, s, b.cell_count,
-                     (int64_t)b.n_cells, 0, g);
-  hipLaunchKernelGGL(k_fill_i32_gated, grid_for(b.n_cells), dim3(kBlock), 0, s, b.cell_fill,
-                     (int64_t)b.n_cells, 0, g);
+  hipLaunchKernelGGL(k_fill_cells, grid_for(b.n_cells), dim3(kBlock), 0, s, b.cell_count,
+                     b.cell_fill, (int64_t)b.n_cells, g);
   hipLaunchKernelGGL(k_cell_key, grid_for(b.N), dim3(kBlock), 0, s, b.pos_ext, b.N, b.sid_ext,
                      b.structs, b.key, b.cell_count, g);
   hipLaunchKernelGGL(k_scan_1block, dim3(1), dim3(1024), 0, s, b.cell_count, b.cell_start,
@@ -389,8 +414,14 @@ void launch_order_atoms(const BuildArgs& b, hipStream_t s) {
                      b.cell_start, b.cell_fill, b.perm, g);
   hipLaunchKernelGGL(k_cell_sort, grid_for(b.n_cells), dim3(kBlock), 0, s, b.cell_start,
                      b.cell_count, b.n_cells, b.ext_src, b.perm, g);
-  hipLaunchKernelGGL(k_gather_atoms, grid_for(b.N), dim3(kBlock), 0, s, b.perm, b.N, b.pos_ext,
-                     b.types_ext, b.sid_ext, b.pos, b.types, b.sid, g);
+  hipLaunchKernelGGL(k_gather_atoms, grid_for(b.N), dim3(kBlock), 0, s, b);
+}
+
+void launch_commit_rebuild(int64_t N, const double* pos2, const double* vel2, const int32_t* types2,
+                           const int32_t* ext2, double* pos, double* vel, int32_t* types, int32_t* ext,
+                           double* pos_ref, const int32_t* gate, hipStream_t s) {
+  hipLaunchKernelGGL(k_commit_rebuild, grid_for(N), dim3(kBlock), 0, s, N, pos2, vel2, types2, ext2,
+                     pos, vel, types, ext, pos_ref, gate);
 }
 
 void launch_build_rows(const BuildArgs& b, const StructInfo& st0, bool batch, const Lists& V,
@@ -620,10 +651,8 @@ void launch_type_rows(const int32_t* types, int64_t N, int32_t T, int32_t per_ty
                       int64_t rows_len, const int32_t* gate, hipStream_t s) {
   const int32_t Tn = per_type ? T : 1;
   const int32_t nb = (int32_t)type_row_blocks(N);
-  hipLaunchKernelGGL(k_fill_i32_gated, grid_for(rows_len), dim3(kBlock), 0, s, rows, rows_len,
-                     (int32_t)-1, gate);
   hipLaunchKernelGGL(k_type_block_count, dim3(nb), dim3(kBlock), 0, s, types, N, Tn, per_type, nb,
-                     tblk, gate);
+                     tblk, rows, rows_len, gate);
   hipLaunchKernelGGL(k_scan_1block, dim3(1), dim3(1024), 0, s, tblk, tex, Tn * nb, gate);
   hipLaunchKernelGGL(k_type_shift, dim3(1), dim3(64), 0, s, tex, N, Tn, nb, toff, gate);
   hipLaunchKernelGGL(k_type_block_scatter, dim3(nb), dim3(kBlock), 0, s, types, N, Tn, per_type,

@@ -26,6 +26,11 @@ struct BuildArgs {
   int32_t* overflow;          // flags: [0] radial row, [1] angular row, [2] rev error,
                               // [5] candidate row overflow (max counts)
   const int32_t* gate;        // rebuild kernels run only when *gate != 0 (NULL: always)
+  // optional: velocities and caller indices permuted with the positions
+  const double* vel_src = nullptr;
+  double* vel_dst = nullptr;
+  const int32_t* ext_in = nullptr;
+  int32_t* ext_out = nullptr;
 };
 
 struct EvalArgs {
@@ -64,6 +69,10 @@ void launch_build_rows(const BuildArgs& b, const StructInfo& st0, bool batch, co
                        const Lists& L, hipStream_t s);
 void launch_reverse(int64_t N, const Lists& L, int32_t* err, const int32_t* gate, hipStream_t s);
 void launch_build_verlet(const BuildArgs& b, const Lists& V, hipStream_t s);
+// After a gated re-sort: pos/vel/types/ext <- their permuted copies, pos_ref <- pos.
+void launch_commit_rebuild(int64_t N, const double* pos2, const double* vel2, const int32_t* types2,
+                           const int32_t* ext2, double* pos, double* vel, int32_t* types, int32_t* ext,
+                           double* pos_ref, const int32_t* gate, hipStream_t s);
 void launch_filter_rows(const BuildArgs& b, const StructInfo& st0, bool batch, const Lists& V,
                         const Lists& L, hipStream_t s);
 void launch_check_displacement(const double* pos, const double* ref, int64_t N, double thr2,
