@@ -34,22 +34,23 @@ PEAK_BF16_MFMA = 2500.0
 PEAK_HBM = 8000.0  # GB/s
 
 
-def measured_traffic():
-    """HBM bytes per launch of the partial-force kernel from the committed
-    FETCH_SIZE/WRITE_SIZE counter summary, or None when the kernel source has
-    changed since those counters were taken."""
+def measured_traffic(kernel):
+    """HBM bytes per launch of the named partial-force kernel variant from the
+    committed FETCH_SIZE/WRITE_SIZE counter summary, or None when that variant
+    was not profiled or the kernel source has changed since."""
     import hashlib
     import json
     here = os.path.dirname(os.path.abspath(__file__))
     try:
         rec = json.load(open(os.path.join(here, "profiles", "partial_forces_fcc131k_traffic.json")))
         src = open(os.path.join(here, rec["source"]), "rb").read()
+        v = rec["variants"][kernel]
     except (OSError, KeyError, ValueError):
         return None
     if hashlib.sha256(src).hexdigest() != rec["source_sha256"]:
         return None
-    return {"bytes": rec["fetch_bytes"] + rec["write_bytes"], "fetch_bytes": rec["fetch_bytes"],
-            "write_bytes": rec["write_bytes"], "kernel": rec["kernel"]}
+    return {"bytes": v["fetch_bytes"] + v["write_bytes"], "fetch_bytes": v["fetch_bytes"],
+            "write_bytes": v["write_bytes"], "kernel": kernel, "dispatches": v["dispatches"]}
 
 
 def algorithmic_flops(h, p_r, p_a):
@@ -224,6 +225,8 @@ def main():
         dt, stages, th = run_md(handle, pos_d, vel_d, types_d, masses, box, args.steps,
                                 args.warmup, torch)
         results[prec] = (dt, stages, th)
+        if prec == nep.NEP_MLP_FP32:
+            tune = handle.tuning()
         handle.close()
         del pos_d, vel_d, types_d
         torch.cuda.empty_cache()
@@ -231,7 +234,8 @@ def main():
     dt, stages, th = results[nep.NEP_MLP_FP32]
     value = n * args.steps / dt
     fl = algorithmic_flops(h, p_r, p_a)
-    tr = measured_traffic()
+    force_kernel = f"k_partial_forces<{tune['ng_force']}, {h['l_max_3b']}, false, {tune['lanes_force']}>"
+    tr = measured_traffic(force_kernel)
     avg = {k: v[0] / v[1] for k, v in stages.items()}
     dom = max(("descriptor", "partial_forces"), key=lambda k: avg.get(k, 0.0))
     achieved = fl[dom] * n / (avg[dom] * 1e-3) / 1e12
@@ -260,7 +264,7 @@ def main():
         "roofline": {"bound": "alu", "kernel": dom, "achieved": achieved,
                      "peak": PEAK_FP32_VALU, "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_VALU,
                      "traffic": (tr or {}).get("bytes"), "traffic_unit": "bytes per launch",
-                     "traffic_detail": tr,
+                     "traffic_detail": tr, "variant": force_kernel, "tuning": tune,
                      "flop_per_atom": fl[dom], "avg_launch_ms": avg[dom]},
         "mlp_roofline": {"bound": "mfma", "achieved": mlp_t, "peak": PEAK_FP32_MFMA,
                          "unit": "TFLOP/s", "frac": mlp_t / PEAK_FP32_MFMA,

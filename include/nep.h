@@ -247,6 +247,13 @@ int nep_set_timing(nep_handle *h, int32_t enable);
 int nep_get_timing(const nep_handle *h, int32_t max, const char **names,
                    double *ms, int64_t *calls);
 
+/* Kernel shapes the autotuner fixed for this handle (batch = 0: single
+ * structure, 1: the batched path): out[7] = {descriptor group size, block,
+ * lanes per atom; partial-force group size, block, lanes per atom; gather
+ * lanes per atom}.  Zeros before the first evaluation of that kind.  Not
+ * from the paper: it names the variants that profiles refer to. */
+int nep_get_tuning(const nep_handle *h, int32_t batch, int32_t out[7]);
+
 #ifdef __cplusplus
 }
 #endif

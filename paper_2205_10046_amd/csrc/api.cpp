@@ -1917,6 +1917,16 @@ int nep_get_timing(const nep_handle* h, int32_t max, const char** names, double*
   return n;
 }
 
+int nep_get_tuning(const nep_handle* h, int32_t batch, int32_t out[7]) {
+  if (!h || !out || (batch != 0 && batch != 1))
+    return fail(nullptr, {NEP_E_INVALID_ARG, "handle, batch in {0, 1} and out[7] are required"});
+  const Tuning& t = h->tune[batch];
+  const int32_t v[7] = {t.NG_desc, t.block_desc, t.lanes_desc, t.NG_force, t.block_force,
+                        t.lanes_force, t.lanes_gather};
+  for (int k = 0; k < 7; ++k) out[k] = t.done ? v[k] : 0;
+  return NEP_OK;
+}
+
 int nep_server_create(nep_handle* h, size_t hbm_budget_bytes, int32_t max_slots, nep_server** out) {
   if (!h || !out) return fail(h, {NEP_E_INVALID_ARG, "handle and out are required"});
   if (max_slots < 1 || hbm_budget_bytes == 0) return fail(h, {NEP_E_INVALID_ARG, "need max_slots >= 1 and a budget"});

@@ -32,7 +32,8 @@ NEP_MLP_BF16 = 1
 EXPORTS = ["nep_num_descriptors", "nep_num_params", "nep_create", "nep_set_params",
            "nep_destroy", "nep_last_error", "nep_compute", "nep_compute_dev",
            "nep_neighbors", "nep_descriptors", "nep_md_run", "nep_md_run_dev",
-           "nep_compute_batch", "nep_set_timing", "nep_get_timing", "nep_server_create",
+           "nep_compute_batch", "nep_set_timing", "nep_get_timing", "nep_get_tuning",
+           "nep_server_create",
            "nep_server_submit", "nep_server_poll", "nep_server_stats", "nep_server_reset_stats",
            "nep_server_destroy"]
 
@@ -144,6 +145,7 @@ def load():
     L.nep_server_destroy.restype = None
     L.nep_set_timing.argtypes = [vp, i32]
     L.nep_get_timing.argtypes = [vp, i32, P(C.c_char_p), pd, P(i64)]
+    L.nep_get_tuning.argtypes = [vp, i32, P(i32)]
     for name in EXPORTS:
         getattr(L, name).restype = getattr(L, name).restype or C.c_int
     _lib = L
@@ -317,6 +319,15 @@ class Handle:
         k = load().nep_get_timing(self._h, n, names, _ptr(ms, C.c_double),
                                   _ptr(calls, C.c_int64))
         return {names[i].decode(): (float(ms[i]), int(calls[i])) for i in range(k)}
+
+
+    def tuning(self, batch=False):
+        """Kernel shapes fixed by the autotuner (zeros before the first evaluation)."""
+        out = np.zeros(7, np.int32)
+        self._check(load().nep_get_tuning(self._h, 1 if batch else 0, _ptr(out, C.c_int32)))
+        keys = ("ng_desc", "block_desc", "lanes_desc", "ng_force", "block_force", "lanes_force",
+                "lanes_gather")
+        return dict(zip(keys, (int(x) for x in out)))
 
 
 class Server:
