@@ -37,17 +37,19 @@ PEAK_HBM = 8000.0  # GB/s
 def measured_traffic(kernel):
     """HBM bytes per launch of the named partial-force kernel variant from the
     committed FETCH_SIZE/WRITE_SIZE counter summary, or None when that variant
-    was not profiled or the kernel source has changed since."""
+    was not profiled or any source it is built from has changed since."""
     import hashlib
     import json
     here = os.path.dirname(os.path.abspath(__file__))
     try:
         rec = json.load(open(os.path.join(here, "profiles", "partial_forces_fcc131k_traffic.json")))
-        src = open(os.path.join(here, rec["source"]), "rb").read()
+        digest = hashlib.sha256()
+        for f in rec["sources"]:
+            digest.update(open(os.path.join(here, f), "rb").read())
         v = rec["variants"][kernel]
     except (OSError, KeyError, ValueError):
         return None
-    if hashlib.sha256(src).hexdigest() != rec["source_sha256"]:
+    if digest.hexdigest() != rec["sources_sha256"]:
         return None
     return {"bytes": v["fetch_bytes"] + v["write_bytes"], "fetch_bytes": v["fetch_bytes"],
             "write_bytes": v["write_bytes"], "kernel": kernel, "dispatches": v["dispatches"]}

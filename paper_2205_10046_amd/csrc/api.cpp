@@ -188,6 +188,8 @@ Geometry make_geometry(const double* box, const int32_t* pbc, int64_t n_atoms, d
   st.Hi[6] = (d * hh - e * gg) / det;
   st.Hi[7] = (b * gg - a * hh) / det;
   st.Hi[8] = (a * e - b * d) / det;
+  st.ortho = (box[1] == 0.0 && box[2] == 0.0 && box[3] == 0.0 && box[5] == 0.0 && box[6] == 0.0 &&
+              box[7] == 0.0) ? 1 : 0;
   g.volume = det;
   // face width along cell vector k = volume / |(other two) cross product|
   double w[3];

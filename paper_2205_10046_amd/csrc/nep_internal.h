@@ -48,7 +48,7 @@ struct StructInfo {
   int32_t ncell[3];    // cells per cell vector (kModeCells), else 1
   int32_t cell_off;    // first global cell id
   int32_t reach[3];    // image offset range R (kModeImages)
-  int32_t pad;
+  int32_t ortho;       // 1: H is diagonal (every off-diagonal entry exactly 0)
 };
 
 __host__ __device__ inline uint16_t make_code(int a, int b, int c) {
@@ -62,9 +62,17 @@ __host__ __device__ inline void split_code(uint16_t code, int& a, int& b, int& c
 
 // Minimum-image offset n0 = -rint(s) of the fractional bond offset s along
 // each periodic cell vector (0 along open directions).
+// For a diagonal H the off-diagonal products are exact zeros, so the
+// diagonal-only forms below give the same bits as the general ones.
 __device__ inline void min_image(const StructInfo& st, double Dx, double Dy, double Dz,
                                  int& n0, int& n1, int& n2) {
   n0 = n1 = n2 = 0;
+  if (st.ortho) {
+    if (st.pbc[0]) n0 = -(int)rint(Dx * st.Hi[0]);
+    if (st.pbc[1]) n1 = -(int)rint(Dy * st.Hi[4]);
+    if (st.pbc[2]) n2 = -(int)rint(Dz * st.Hi[8]);
+    return;
+  }
   if (st.pbc[0]) n0 = -(int)rint(Dx * st.Hi[0] + Dy * st.Hi[3] + Dz * st.Hi[6]);
   if (st.pbc[1]) n1 = -(int)rint(Dx * st.Hi[1] + Dy * st.Hi[4] + Dz * st.Hi[7]);
   if (st.pbc[2]) n2 = -(int)rint(Dx * st.Hi[2] + Dy * st.Hi[5] + Dz * st.Hi[8]);
@@ -78,6 +86,12 @@ __device__ inline void image_disp(const StructInfo& st, double Dx, double Dy, do
                                   double& dz) {
 #pragma clang fp contract(off)
   const double a = (double)n0, b = (double)n1, c = (double)n2;
+  if (st.ortho) {
+    dx = Dx + a * st.H[0];
+    dy = Dy + b * st.H[4];
+    dz = Dz + c * st.H[8];
+    return;
+  }
   double tx = (a * st.H[0] + b * st.H[3]) + c * st.H[6];
   double ty = (a * st.H[1] + b * st.H[4]) + c * st.H[7];
   double tz = (a * st.H[2] + b * st.H[5]) + c * st.H[8];
