@@ -25,7 +25,7 @@ sys.path.insert(0, ROOT)
 
 WORKLOAD = "fcc131k"
 THERMO_EVERY = 10
-SKIN = 1.0   # Angstrom: rows at r_c + 1 A, rebuilt after a 0.5 A displacement
+SKIN = 0.8   # Angstrom: rows at r_c + 0.8 A, rebuilt after a 0.4 A displacement (fastest of 0.6-1.3 A measured)
 # MI355X: FP32 vector peak without packed-FP32 instructions (all device code is
 # built with packed FP32 disabled): 256 CU x 64 lanes x 2 flop x 2.4 GHz
 PEAK_FP32_VALU = 256 * 64 * 2 * 2.4e9 / 1e12
@@ -94,6 +94,8 @@ def parse():
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--no-2m", action="store_true")
     ap.add_argument("--steps-2m", type=int, default=20)
+    ap.add_argument("--skin", type=float, default=SKIN,
+                    help="Verlet skin in Angstrom (rows at r_c + skin, rebuilt after skin/2)")
     ap.add_argument("--serve-requests", type=int, default=200)
     ap.add_argument("--serve-budget-gb", type=float, default=2.0)
     return ap.parse_args()
@@ -220,7 +222,7 @@ def main():
 
     results = {}
     for prec in ([nep.NEP_MLP_FP32] + ([] if args.no_bf16 else [nep.NEP_MLP_BF16])):
-        handle = nep.Handle(h, params, mlp_precision=prec, skin=SKIN)
+        handle = nep.Handle(h, params, mlp_precision=prec, skin=args.skin)
         pos_d = torch.tensor(pos, device=dev)
         vel_d = torch.tensor(vel, device=dev)
         types_d = torch.tensor(types, device=dev)
@@ -261,7 +263,8 @@ def main():
                                "(32^3 cells, a=4.05 A), NEP r_c 6/5 A, n_max 8/6, "
                                "N_bas 8/6, l_max 4 + 4-body, 50 neurons per species, "
                                "NVE dt=1 fs from 300 K, thermo every 10 steps, "
-                               "rows at r_c + 1 A rebuilt after a 0.5 A displacement",
+                               f"rows at r_c + {args.skin:g} A rebuilt after a "
+                               f"{args.skin / 2:g} A displacement",
                    "atoms": n, "mlp": "fp32"},
         "roofline": {"bound": "alu", "kernel": dom, "achieved": achieved,
                      "peak": PEAK_FP32_VALU, "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_VALU,
@@ -296,7 +299,7 @@ def main():
         for prec, tag in ((nep.NEP_MLP_FP32, "fp32"), (nep.NEP_MLP_BF16, "bf16")):
             if tag == "bf16" and args.no_bf16:
                 continue
-            hd = nep.Handle(h2, p2, mlp_precision=prec, skin=SKIN)
+            hd = nep.Handle(h2, p2, mlp_precision=prec, skin=args.skin)
             pd_ = torch.tensor(pos2, device=dev)
             vd_ = torch.tensor(vel2, device=dev)
             td_ = torch.tensor(types2, device=dev)
