@@ -196,7 +196,7 @@ __global__ void __launch_bounds__(kBlock, 2) k_descriptor(EvalArgs a, StructInfo
   __syncthreads();
   const int64_t N = a.N;
   const int sub = tid & (G - 1);
-  const int64_t i = ((int64_t)blockIdx.x * B + tid) / G;
+  const int64_t i = (xcd_block() * B + tid) / G;
   if (i >= N) return;  // the G lanes of an atom leave together
   const StructInfo& st = struct_of<BATCH>(a, st0, i);
   const int ti = a.types[i];
@@ -355,7 +355,7 @@ __global__ void __launch_bounds__(kBlock, (NG * num_poly(L) > 120) ? 1 : 2)
   const int tid = threadIdx.x, B = blockDim.x;
   const int64_t N = a.N;
   const int sub = tid & (G - 1);
-  const int64_t i = ((int64_t)blockIdx.x * B + tid) / G;
+  const int64_t i = (xcd_block() * B + tid) / G;
   if (i >= N) return;
   const StructInfo& st = struct_of<BATCH>(a, st0, i);
   const int ti = a.types[i];
@@ -546,7 +546,7 @@ template <bool BATCH, bool VIRIAL, int G>
 __global__ void __launch_bounds__(kBlock) k_gather(EvalArgs a, StructInfo st0) {
   const int64_t N = a.N;
   const int sub = threadIdx.x & (G - 1);
-  const int64_t i = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / G;
+  const int64_t i = (xcd_block() * blockDim.x + threadIdx.x) / G;
   if (i >= N) return;  // the lanes of an atom leave together
   const StructInfo& st = struct_of<BATCH>(a, st0, i);
   const int nn = min(a.L.nnR[i], a.L.MR);

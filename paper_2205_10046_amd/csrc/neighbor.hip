@@ -233,7 +233,7 @@ __global__ void __launch_bounds__(kBlock) k_build_rows(
     const StructInfo* __restrict__ structs, const int32_t* __restrict__ cell_start,
     const int32_t* __restrict__ cell_count, double rc2, Lists V, int32_t* __restrict__ overflow,
     const int32_t* gate) {
-  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int64_t i = xcd_block() * blockDim.x + threadIdx.x;
   if (i >= N || gated_off(gate)) return;
   const StructInfo st = structs[sid[i]];
   const double xi = pos[i], yi = pos[N + i], zi = pos[2 * N + i];
@@ -291,7 +291,7 @@ __global__ void __launch_bounds__(kBlock) k_build_rows(
 __global__ void k_reverse(int64_t N, const int32_t* __restrict__ nn, const int32_t* __restrict__ nl,
                           const uint16_t* __restrict__ cd, int32_t cap, int32_t* __restrict__ rev,
                           int32_t* __restrict__ err, const int32_t* gate) {
-  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int64_t i = xcd_block() * blockDim.x + threadIdx.x;
   if (i >= N || gated_off(gate)) return;
   int cnt = min(nn[i], cap);
   for (int m = 0; m < cnt; ++m) {
@@ -476,7 +476,7 @@ __global__ void __launch_bounds__(kBlock) k_filter_rows(const double* __restrict
   constexpr int G = kFilterLanes;
   constexpr int32_t kOuter = -2, kAngular = -3;
   const int sub = threadIdx.x & (G - 1);
-  const int64_t i = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / G;
+  const int64_t i = (xcd_block() * blockDim.x + threadIdx.x) / G;
   if (i >= N) return;  // the lanes of an atom leave together
   const StructInfo& st = BATCH ? structs[sid[i]] : st0;
   const int nv = min(V.nnR[i], V.MR);
@@ -570,7 +570,7 @@ __global__ void __launch_bounds__(kBlock) k_reverse_from_candidates(int64_t N, L
                                                                     int32_t* __restrict__ err) {
   constexpr int G = kRevLanes;
   const int sub = threadIdx.x & (G - 1);
-  const int64_t i = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / G;
+  const int64_t i = (xcd_block() * blockDim.x + threadIdx.x) / G;
   if (i >= N) return;
   const int nv = min(V.nnR[i], V.MR);
   int32_t fn = -1, jn = 0, rn = 0;

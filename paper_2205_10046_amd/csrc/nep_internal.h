@@ -179,4 +179,16 @@ constexpr int32_t kMaxRow = 65535;
 
 inline int div_up(int64_t a, int64_t b) { return (int)((a + b - 1) / b); }
 
+// The chip deals the blocks of a grid to its 8 XCDs round-robin (block b
+// runs on XCD b mod 8), each XCD with its own L2.  Numbering the work so that
+// the blocks of one XCD take one contiguous range of atoms keeps the
+// neighbours that its concurrent blocks share in that L2.  A bijection on
+// [0, gridDim.x) for any grid size.
+constexpr int kXcds = 8;
+__device__ __forceinline__ int64_t xcd_block() {
+  const int64_t b = blockIdx.x, nb = gridDim.x;
+  const int64_t x = b % kXcds, k = b / kXcds, q = nb / kXcds, r = nb % kXcds;
+  return x * q + (x < r ? x : r) + k;
+}
+
 }  // namespace nep
