@@ -290,6 +290,27 @@ def test_device_path_checks_types(handles):
     assert e.value.code == nep.NEP_E_INVALID_ARG
 
 
+def test_tuning_reported_and_fixed(handles):
+    """The autotuned kernel shapes are admissible, and a second evaluation of
+    the same shape reuses them (bitwise-equal results)."""
+    name, h, (pos, types, box) = CASES[1]
+    p = synth.random_params(O.num_params(h), seed=5)
+    handle = nep.Handle(h, p)
+    assert set(handle.tuning().values()) == {0}
+    r1 = handle.compute(pos, types, box)
+    t1 = handle.tuning()
+    r2 = handle.compute(pos, types, box)
+    assert handle.tuning() == t1
+    log(f"[tuning] {t1}")
+    assert t1["ng_desc"] in (2, 4, 5, 7) and t1["ng_force"] in (2, 4, 5, 7)
+    assert t1["block_desc"] in (128, 256) and t1["block_force"] in (128, 256)
+    assert t1["lanes_desc"] in (1, 4) and t1["lanes_force"] in (1, 4)
+    assert t1["lanes_gather"] in (1, 4)
+    for k in ("U", "F", "W"):
+        assert np.array_equal(r1[k], r2[k])
+    handle.close()
+
+
 # --------------------------------------------------------------------------
 # batches of structures x parameter sets (training-style population eval)
 # --------------------------------------------------------------------------
