@@ -96,6 +96,9 @@ def parse():
     ap.add_argument("--steps-2m", type=int, default=20)
     ap.add_argument("--skin", type=float, default=SKIN,
                     help="Verlet skin in Angstrom (rows at r_c + skin, rebuilt after skin/2)")
+    ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--batch-structs", type=int, default=2000)
+    ap.add_argument("--batch-sets", type=int, default=50)
     ap.add_argument("--serve-requests", type=int, default=200)
     ap.add_argument("--serve-budget-gb", type=float, default=2.0)
     return ap.parse_args()
@@ -174,6 +177,54 @@ def serving_leg(nep, synth, params_of, n_req, budget_gb, prec):
     srv.close()
     handle.close()
     return out
+
+
+def batch_leg(nep, synth, torch, n_struct, n_sets, reps=3):
+    """Training-style population batch: n_struct periodic triclinic cells of
+    8-256 atoms, 3 species, evaluated (energy, forces, virial) for n_sets
+    parameter vectors z_p = mean + 0.1 eps_p in one nep_compute_batch call
+    (rows built once and shared; the per-set passes replayed as one HIP
+    graph).  The first call fixes the kernel shapes (autotuner); the next
+    `reps` calls are timed whole (rows, graph capture and launch included);
+    one more call with HIP-event stage timing gives the graph launch alone."""
+    dev = torch.device("cuda:0")
+    h = synth.WORKLOADS["train3"]
+    structs = synth.random_structures(n_struct)
+    pos, types, boxes, offs = synth.concat_structures(structs)
+    n, S = pos.shape[1], boxes.shape[0]
+    mean = synth.random_params(nep.nep_num_params(h))
+    pop = synth.population(mean, n_sets)
+    handle = nep.Handle(h, mean)
+    pos_d = torch.tensor(pos, device=dev)
+    types_d = torch.tensor(types, device=dev)
+    e = torch.empty(n_sets, n, dtype=torch.float64, device=dev)
+    f = torch.empty(n_sets, 3, n, dtype=torch.float64, device=dev)
+    w = torch.empty(n_sets, 9, n, dtype=torch.float64, device=dev)
+    t = torch.empty(n_sets, S, 10, dtype=torch.float64, device=dev)
+    handle.compute_batch(offs, pos_d, types_d, boxes, pop, e, f, w, t)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        handle.compute_batch(offs, pos_d, types_d, boxes, pop, e, f, w, t)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / reps
+    handle.set_timing(True)
+    handle.compute_batch(offs, pos_d, types_d, boxes, pop, e, f, w, t)
+    torch.cuda.synchronize()
+    stages = handle.timing()
+    handle.set_timing(False)
+    handle.close()
+    g = stages.get("batch_graph", (float("nan"), 1))
+    graph_ms = g[0] / max(g[1], 1)
+    del pos_d, types_d, e, f, w, t
+    torch.cuda.empty_cache()
+    return {"structures": S, "atoms": n, "param_sets": n_sets,
+            "atom_evals_per_s": n * n_sets / dt, "evals_per_s": S * n_sets / dt,
+            "ms_per_call": dt * 1e3, "graph_ms": graph_ms,
+            "graph_atom_evals_per_s": n * n_sets / (graph_ms * 1e-3),
+            "workload": ("train3: random triclinic cells, 8-256 atoms, density 0.05-0.09 "
+                         "atoms/A^3, 3 species; NEP r_c 6/3.5 A, n_max 12/8, N_bas 12/8, "
+                         "l_max 4, 100 neurons per species; E, F, W per vector")}
 
 
 def cpu_baseline(h, params, seconds):
@@ -311,6 +362,9 @@ def main():
             hd.close()
             del pd_, vd_, td_
             torch.cuda.empty_cache()
+    if not args.no_batch:
+        out["population_batch"] = batch_leg(nep, synth, torch, args.batch_structs,
+                                            args.batch_sets)
     if not args.no_serve:
         pof = lambda hh: synth.random_params(nep.nep_num_params(hh))  # noqa: E731
         out["serving"] = {"fp32": serving_leg(nep, synth, pof, args.serve_requests,

@@ -67,12 +67,29 @@ __global__ void __launch_bounds__(256) k_mlp(EvalArgs a) {
   if constexpr (!BF16) {
     const float* __restrict__ w0t = M.w0t + (int64_t)net * ND * NNp;
     const int steps = (ND + 3) / 4;
+    // the operands of step s + 1 are loaded while step s is multiplied; every
+    // load is in bounds (index clamped) and the tail is selected to zero after
+    float qn, wn[NNB];
+    {
+      const int dc = min(grp, ND - 1);
+      qn = qrow[dc];
+#pragma unroll
+      for (int nb = 0; nb < NNB; ++nb) wn[nb] = w0t[(int64_t)dc * NNp + 16 * nb + col];
+    }
     for (int s = 0; s < steps; ++s) {
       const int d = 4 * s + grp;
-      const float bq = (atom >= 0 && d < ND) ? qrow[d] : 0.f;
+      const float qv = qn;
+      float wv[NNB];
+#pragma unroll
+      for (int nb = 0; nb < NNB; ++nb) wv[nb] = wn[nb];
+      const int dn = min(d + 4, ND - 1);
+      qn = qrow[dn];
+#pragma unroll
+      for (int nb = 0; nb < NNB; ++nb) wn[nb] = w0t[(int64_t)dn * NNp + 16 * nb + col];
+      const float bq = (atom >= 0 && d < ND) ? qv : 0.f;
 #pragma unroll
       for (int nb = 0; nb < NNB; ++nb) {
-        const float aw = d < ND ? w0t[(int64_t)d * NNp + 16 * nb + col] : 0.f;
+        const float aw = d < ND ? wv[nb] : 0.f;
         acc[nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(aw, bq, acc[nb], 0, 0, 0);
       }
     }
@@ -81,16 +98,14 @@ __global__ void __launch_bounds__(256) k_mlp(EvalArgs a) {
     const int steps = M.NDp32 / 32;
     for (int s = 0; s < steps; ++s) {
       const int d0 = 32 * s + 8 * grp;
+      const int dq = min(d0, M.NDp - 8);  // NDp is a multiple of 8: the load stays in the row
+      const bool live = atom >= 0 && d0 < M.NDp;
+      const float4 x0 = *reinterpret_cast<const float4*>(qrow + dq);
+      const float4 x1 = *reinterpret_cast<const float4*>(qrow + dq + 4);
+      const float xs[8] = {x0.x, x0.y, x0.z, x0.w, x1.x, x1.y, x1.z, x1.w};
       v8bf bq;
-      if (atom >= 0 && d0 < M.NDp) {
-        const float4 x0 = *reinterpret_cast<const float4*>(qrow + d0);
-        const float4 x1 = *reinterpret_cast<const float4*>(qrow + d0 + 4);
-        bq[0] = (__bf16)x0.x; bq[1] = (__bf16)x0.y; bq[2] = (__bf16)x0.z; bq[3] = (__bf16)x0.w;
-        bq[4] = (__bf16)x1.x; bq[5] = (__bf16)x1.y; bq[6] = (__bf16)x1.z; bq[7] = (__bf16)x1.w;
-      } else {
 #pragma unroll
-        for (int k = 0; k < 8; ++k) bq[k] = (__bf16)0.f;
-      }
+      for (int k = 0; k < 8; ++k) bq[k] = (__bf16)(live ? xs[k] : 0.f);
 #pragma unroll
       for (int nb = 0; nb < NNB; ++nb) {
         const uint4 u = *reinterpret_cast<const uint4*>(w0b + (int64_t)(16 * nb + col) * M.NDp32 + d0);
@@ -101,33 +116,48 @@ __global__ void __launch_bounds__(256) k_mlp(EvalArgs a) {
 
   // ---- activation, site energy and G = w1 (1 - h^2) ----
   float u = 0.f;
-  float g[NNB][4];
+  float g[NNB][4], b0v[NNB][4], w1v[NNB][4];
+#pragma unroll
+  for (int nb = 0; nb < NNB; ++nb)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {  // all loads issued before the first tanh
+      const int mu = 16 * nb + 4 * grp + r;
+      b0v[nb][r] = b0[mu];
+      w1v[nb][r] = w1[mu];
+    }
 #pragma unroll
   for (int nb = 0; nb < NNB; ++nb)
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-      const int mu = 16 * nb + 4 * grp + r;
-      const float h = tanhf(acc[nb][r] - b0[mu]);
-      u += w1[mu] * h;
-      g[nb][r] = w1[mu] * (1.f - h * h);
+      const float h = tanhf(acc[nb][r] - b0v[nb][r]);
+      u += w1v[nb][r] * h;
+      g[nb][r] = w1v[nb][r] * (1.f - h * h);
     }
   u += __shfl_xor(u, 16);
   u += __shfl_xor(u, 32);
   if (grp == 0 && atom >= 0) a.U[atom] = u - M.b1;
 
   // ---- GEMM 2: dU/dq[atom][d] = sum_mu G[atom][mu] w0[mu][d] ----
+  int out_atom[4];
+#pragma unroll
+  for (int r = 0; r < 4; ++r) out_atom[r] = a.rows[base + 4 * grp + r];
   const int dblocks = (ND + 15) / 16;
   for (int db = 0; db < dblocks; ++db) {
     const int d = 16 * db + col;
     v4f c = v4f{0.f, 0.f, 0.f, 0.f};
     if constexpr (!BF16) {
       const float* __restrict__ w0 = M.w0 + (int64_t)net * NNp * ND;
+      const int dc = min(d, ND - 1);
+      float wv[NNB][4];
+#pragma unroll
+      for (int nb = 0; nb < NNB; ++nb)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) wv[nb][r] = w0[(int64_t)(16 * nb + 4 * grp + r) * ND + dc];
 #pragma unroll
       for (int nb = 0; nb < NNB; ++nb)
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-          const int mu = 16 * nb + 4 * grp + r;
-          const float bw = d < ND ? w0[(int64_t)mu * ND + d] : 0.f;
+          const float bw = d < ND ? wv[nb][r] : 0.f;
           c = __builtin_amdgcn_mfma_f32_16x16x4f32(g[nb][r], bw, c, 0, 0, 0);
         }
     } else {
@@ -150,7 +180,7 @@ __global__ void __launch_bounds__(256) k_mlp(EvalArgs a) {
     }
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-      const int at = a.rows[base + 4 * grp + r];
+      const int at = out_atom[r];
       if (at >= 0 && d < ND) a.fp[(int64_t)at * M.NDp + d] = c[r];
     }
   }

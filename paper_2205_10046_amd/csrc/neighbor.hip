@@ -448,12 +448,14 @@ void launch_build_verlet(const BuildArgs& b, const Lists& V, hipStream_t s) {
 // Exact radial row from the candidate row with the same float64 membership
 // test: the entries with |d|^2 < (r_c^A)^2 first, then the others, each part
 // in candidate order; nnA = size of the first part.  V.fmap[m][i] = exact
-// position of candidate m (or -1).  kFilterLanes lanes per atom each take a
-// contiguous quarter of the candidate row: pass 1 classifies it (neighbour
-// index and position of the next candidate in flight while the current one
-// is tested) and counts its members, quad-broadcast DPP prefix sums give each
-// lane its write offsets, pass 2 writes the entries.  The rows are the same
-// as those of a single sequential pass.
+// position of candidate m (or -1).  kFilterLanes lanes per atom take the
+// candidates m = s, s + 4, ..., so the 16 atoms of a wave read and write
+// whole 64-byte runs of a row.  Pass 1 classifies (neighbour index and
+// position of the lane's next candidate in flight while the current one is
+// tested) and counts the members; pass 2 walks the row four candidates at a
+// time in candidate order, and quad DPP prefix sums of the class flags give
+// each member its exact position.  The rows are the same as those of a
+// single sequential pass.
 constexpr int kFilterLanes = 4;
 
 // Value of v held by lane l of this lane's quad.
@@ -480,15 +482,13 @@ __global__ void __launch_bounds__(kBlock) k_filter_rows(const double* __restrict
   if (i >= N) return;  // the lanes of an atom leave together
   const StructInfo& st = BATCH ? structs[sid[i]] : st0;
   const int nv = min(V.nnR[i], V.MR);
-  const int q = (nv + G - 1) / G;
-  const int m0 = min(sub * q, nv), m1 = min(m0 + q, nv);
   const bool images = st.mode == kModeImages;
   const double xi = pos[i], yi = pos[N + i], zi = pos[2 * N + i];
-  int32_t jn = m0 < m1 ? V.nlR[(int64_t)m0 * N + i] : 0;
-  uint16_t cn = (images && m0 < m1) ? V.cdR[(int64_t)m0 * N + i] : kCodeCenter;
+  int32_t jn = sub < nv ? V.nlR[(int64_t)sub * N + i] : 0;
+  uint16_t cn = (images && sub < nv) ? V.cdR[(int64_t)sub * N + i] : kCodeCenter;
   double px = pos[jn], py = pos[N + jn], pz = pos[2 * N + jn];
   int32_t na = 0, no = 0;
-  for (int m = m0; m < m1; ++m) {
+  for (int m = sub; m < nv; m += G) {
     const int64_t e = (int64_t)m * N + i;
     const uint16_t code = cn;
     double Dx, Dy, Dz;
@@ -498,9 +498,9 @@ __global__ void __launch_bounds__(kBlock) k_filter_rows(const double* __restrict
       Dy = py - yi;
       Dz = pz - zi;
     }
-    if (m + 1 < m1) {
-      jn = V.nlR[e + N];
-      if (images) cn = V.cdR[e + N];
+    if (m + G < nv) {
+      jn = V.nlR[e + G * N];
+      if (images) cn = V.cdR[e + G * N];
     }
     px = pos[jn];
     py = pos[N + jn];
@@ -527,29 +527,43 @@ __global__ void __launch_bounds__(kBlock) k_filter_rows(const double* __restrict
     }
     V.fmap[e] = f;
   }
-  // offsets: angular entries of lanes < sub, then all angular, then outer of lanes < sub
-  int32_t a_before = 0, o_before = 0, a_all = 0, o_all = 0;
+  int32_t a_all = 0, o_all = 0;
 #pragma unroll
   for (int l = 0; l < G; ++l) {
-    const int32_t al = quad_lane(na, l), ol = quad_lane(no, l);
-    a_all += al;
-    o_all += ol;
-    if (l < sub) {
-      a_before += al;
-      o_before += ol;
-    }
+    a_all += quad_lane(na, l);
+    o_all += quad_lane(no, l);
   }
-  int32_t pa = a_before, po = a_all + o_before;
-  for (int m = m0; m < m1; ++m) {
+  // pass 2: the same trip count for the four lanes of an atom, so the quad is
+  // whole at every prefix sum; lane s rereads only the entries it wrote
+  int32_t pa = 0, po = a_all;  // next angular / outer position
+  const int steps = (nv + G - 1) / G;
+  for (int t = 0; t < steps; ++t) {
+    const int m = t * G + sub;
     const int64_t e = (int64_t)m * N + i;
-    const int32_t c = V.fmap[e];
-    if (c >= -1) continue;
-    const int32_t p = c == kAngular ? pa++ : po++;
-    V.fmap[e] = p;
-    if (p < L.MR) {
-      L.nlR[(int64_t)p * N + i] = V.nlR[e];
-      if (images) L.cdR[(int64_t)p * N + i] = V.cdR[e];
+    const int32_t c = m < nv ? V.fmap[e] : -1;
+    const int32_t fa = c == kAngular, fo = c == kOuter;
+    int32_t ba = 0, bo = 0, ta = 0, to = 0;
+#pragma unroll
+    for (int l = 0; l < G; ++l) {
+      const int32_t al = quad_lane(fa, l), ol = quad_lane(fo, l);
+      ta += al;
+      to += ol;
+      if (l < sub) {
+        ba += al;
+        bo += ol;
+      }
     }
+    if (fa | fo) {
+      const int32_t p = fa ? pa + ba : po + bo;
+      V.fmap[e] = p;
+      if (p < L.MR) {
+        L.nlR[(int64_t)p * N + i] = V.nlR[e];
+        L.revR[(int64_t)p * N + i] = V.revR[e];  // candidate position, resolved by the next kernel
+        if (images) L.cdR[(int64_t)p * N + i] = V.cdR[e];
+      }
+    }
+    pa += ta;
+    po += to;
   }
   if (sub == 0) {
     const int32_t total = a_all + o_all;
@@ -560,10 +574,12 @@ __global__ void __launch_bounds__(kBlock) k_filter_rows(const double* __restrict
   }
 }
 
-// rev of the exact rows: the entry of i in the row of j sits at candidate
-// position V.revR[m][i] there, whose exact position is V.fmap of that entry.
-// kRevLanes lanes per atom take candidates m = s, s + 4, ...; the words of a
-// lane's next candidate are loaded while the current one is resolved.
+// rev of the exact rows: the filter left in L.revR[p][i] the candidate
+// position of i in the row of j = L.nlR[p][i]; the exact position there is
+// V.fmap of that candidate entry, written in place.  kRevLanes lanes per atom
+// take exact entries p = s, s + 4, ..., so a wave writes whole 64-byte runs of
+// a row; the words of a lane's next entry are loaded while the current one
+// is resolved.
 constexpr int kRevLanes = 4;
 
 __global__ void __launch_bounds__(kBlock) k_reverse_from_candidates(int64_t N, Lists V, Lists L,
@@ -572,30 +588,27 @@ __global__ void __launch_bounds__(kBlock) k_reverse_from_candidates(int64_t N, L
   const int sub = threadIdx.x & (G - 1);
   const int64_t i = (xcd_block() * blockDim.x + threadIdx.x) / G;
   if (i >= N) return;
-  const int nv = min(V.nnR[i], V.MR);
-  int32_t fn = -1, jn = 0, rn = 0;
-  if (sub < nv) {
+  const int nn = min(L.nnR[i], L.MR);
+  int32_t jn = 0, rn = 0;
+  if (sub < nn) {
     const int64_t e0 = (int64_t)sub * N + i;
-    fn = V.fmap[e0];
-    jn = V.nlR[e0];
-    rn = V.revR[e0];
+    jn = L.nlR[e0];
+    rn = L.revR[e0];
   }
   bool broken = false;
-  for (int m = sub; m < nv; m += G) {
-    const int32_t f = fn, j = jn, r = rn;
-    if (m + G < nv) {
-      const int64_t e1 = (int64_t)(m + G) * N + i;
-      fn = V.fmap[e1];
-      jn = V.nlR[e1];
-      rn = V.revR[e1];
+  for (int p = sub; p < nn; p += G) {
+    const int32_t j = jn, r = rn;
+    if (p + G < nn) {
+      const int64_t e1 = (int64_t)(p + G) * N + i;
+      jn = L.nlR[e1];
+      rn = L.revR[e1];
     }
-    if (f < 0) continue;
     int32_t g = V.fmap[(int64_t)r * N + j];
     if (g < 0) {
       broken = true;
       g = 0;
     }
-    if (f < L.MR) L.revR[(int64_t)f * N + i] = min(g, L.MR - 1);
+    L.revR[(int64_t)p * N + i] = min(g, L.MR - 1);
   }
   if (broken) atomicExch(err, 1);
 }

@@ -385,6 +385,58 @@ def test_batch_invariance_bitwise():
         assert np.array_equal(w1[0], w[0, :, a:b])
 
 
+def test_batch_full_size_sampled():
+    """The training-style batch as benchmarked: 2,000 periodic triclinic cells
+    (8-256 atoms, 3 species) x 50 parameter vectors in one call; sampled
+    (structure, vector) pairs vs the oracle, the smallest and largest cells
+    included, and every structure total against its per-atom outputs."""
+    import torch
+    dev = torch.device("cuda:0")
+    h = synth.WORKLOADS["train3"]
+    structs = synth.random_structures(2000)
+    pos, types, boxes, offs = synth.concat_structures(structs)
+    n, S = pos.shape[1], boxes.shape[0]
+    mean = synth.random_params(O.num_params(h))
+    pop = synth.population(mean, 50)
+    log(f"[batch-full] {S} structures, {n} atoms x {pop.shape[0]} sets")
+    handle = nep.Handle(h, mean)
+    e = torch.empty(50, n, dtype=torch.float64, device=dev)
+    f = torch.empty(50, 3, n, dtype=torch.float64, device=dev)
+    w = torch.empty(50, 9, n, dtype=torch.float64, device=dev)
+    t = torch.empty(50, S, 10, dtype=torch.float64, device=dev)
+    handle.compute_batch(offs, torch.tensor(pos, device=dev), torch.tensor(types, device=dev),
+                         boxes, pop, e, f, w, t)
+    torch.cuda.synchronize()
+    sizes = np.diff(offs)
+    rng = np.random.default_rng(31)
+    picks = [int(np.argmin(sizes)), int(np.argmax(sizes))] + list(rng.choice(S, 4, replace=False))
+    sets = [0, 17, 49]
+    worst = 0.0
+    for p in sets:
+        for s in picks:
+            a, b = int(offs[s]), int(offs[s + 1])
+            ps, ts, bs = structs[s]
+            ref = O.evaluate(h, pop[p], ps, ts, bs)
+            ee = e[p, a:b].cpu().numpy()
+            ff = f[p, :, a:b].cpu().numpy()
+            ww = w[p, :, a:b].cpu().numpy()
+            dU = np.abs(ee - ref["U"]).max()
+            dE = abs(ee.sum() - ref["U"].sum()) / (b - a)
+            dF = np.abs(ff - ref["F"]).max()
+            dW = np.abs(ww - ref["W"]).max()
+            worst = max(worst, dF)
+            assert dE <= TOL_E and dU <= TOL_SITE and dF <= TOL_F and dW <= TOL_W, \
+                (p, s, b - a, dE, dU, dF, dW)
+    # structure totals: energy and virial sums of every structure and vector
+    seg = torch.tensor(np.repeat(np.arange(S), sizes), device=dev)
+    e_sum = torch.zeros(50, S, dtype=torch.float64, device=dev).index_add_(1, seg, e)
+    w_sum = torch.zeros(50, 9, S, dtype=torch.float64, device=dev).index_add_(2, seg, w)
+    tol = torch.tensor(sizes, dtype=torch.float64, device=dev)
+    assert bool(((t[:, :, 0] - e_sum).abs() <= 1e-9 * tol).all())
+    assert bool(((t[:, :, 1:] - w_sum.transpose(1, 2)).abs() <= 1e-9 * tol[None, :, None]).all())
+    log(f"[batch-full] sampled {len(sets)} x {len(picks)} pairs: worst |dF| {worst:.2e}")
+
+
 def test_md_with_skin_matches_rebuild_every_step():
     """Candidate rows at r_c + skin filtered each step give the same dynamics
     (up to float32 summation order) as exact rows rebuilt every step."""
