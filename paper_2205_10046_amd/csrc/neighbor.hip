@@ -452,9 +452,9 @@ void launch_build_verlet(const BuildArgs& b, const Lists& V, hipStream_t s) {
 // candidates m = s, s + 4, ..., so the 16 atoms of a wave read and write
 // whole 64-byte runs of a row.  Pass 1 classifies (neighbour index and
 // position of the lane's next candidate in flight while the current one is
-// tested) and counts the members; pass 2 walks the row four candidates at a
-// time in candidate order, and quad DPP prefix sums of the class flags give
-// each member its exact position.  The rows are the same as those of a
+// tested), counts the members and keeps the classes in register bit masks;
+// pass 2 walks the row four candidates at a time in candidate order, and quad
+// DPP prefix sums of the class flags give each member its exact position.  The rows are the same as those of a
 // single sequential pass.
 constexpr int kFilterLanes = 4;
 
@@ -488,7 +488,10 @@ __global__ void __launch_bounds__(kBlock) k_filter_rows(const double* __restrict
   uint16_t cn = (images && sub < nv) ? V.cdR[(int64_t)sub * N + i] : kCodeCenter;
   double px = pos[jn], py = pos[N + jn], pz = pos[2 * N + jn];
   int32_t na = 0, no = 0;
-  for (int m = sub; m < nv; m += G) {
+  // classes of the lane's first 64 candidates (t = local index) as bit masks;
+  // later ones (rows over 256 candidates) go through V.fmap
+  uint64_t mask_a = 0, mask_o = 0;
+  for (int m = sub, t = 0; m < nv; m += G, ++t) {
     const int64_t e = (int64_t)m * N + i;
     const uint16_t code = cn;
     double Dx, Dy, Dz;
@@ -525,7 +528,12 @@ __global__ void __launch_bounds__(kBlock) k_filter_rows(const double* __restrict
       f = kOuter;
       ++no;
     }
-    V.fmap[e] = f;
+    if (t < 64) {
+      if (f == kAngular) mask_a |= 1ull << t;
+      if (f == kOuter) mask_o |= 1ull << t;
+    } else {
+      V.fmap[e] = f;
+    }
   }
   int32_t a_all = 0, o_all = 0;
 #pragma unroll
@@ -534,13 +542,17 @@ __global__ void __launch_bounds__(kBlock) k_filter_rows(const double* __restrict
     o_all += quad_lane(no, l);
   }
   // pass 2: the same trip count for the four lanes of an atom, so the quad is
-  // whole at every prefix sum; lane s rereads only the entries it wrote
+  // whole at every prefix sum; candidate m = 4 t + s is lane s's t-th
   int32_t pa = 0, po = a_all;  // next angular / outer position
   const int steps = (nv + G - 1) / G;
   for (int t = 0; t < steps; ++t) {
     const int m = t * G + sub;
     const int64_t e = (int64_t)m * N + i;
-    const int32_t c = m < nv ? V.fmap[e] : -1;
+    int32_t c = -1;
+    if (m < nv) {
+      if (t < 64) c = ((mask_a >> t) & 1) ? kAngular : (((mask_o >> t) & 1) ? kOuter : -1);
+      else c = V.fmap[e];
+    }
     const int32_t fa = c == kAngular, fo = c == kOuter;
     int32_t ba = 0, bo = 0, ta = 0, to = 0;
 #pragma unroll
@@ -553,6 +565,7 @@ __global__ void __launch_bounds__(kBlock) k_filter_rows(const double* __restrict
         bo += ol;
       }
     }
+    if (m < nv && !(fa | fo)) V.fmap[e] = -1;
     if (fa | fo) {
       const int32_t p = fa ? pa + ba : po + bo;
       V.fmap[e] = p;
