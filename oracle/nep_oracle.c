@@ -722,9 +722,10 @@ static int geometry(const double *box, double *Hi, double *w) {
  * Phase 1 computes every atom's descriptor, network and partial forces
  * (parallel over atoms); phase 2 adds the partial forces into F and W in a
  * fixed serial order. */
-int ora_evaluate(const ora_hparams *h, const double *params, int64_t N, const double *pos,
-                 const int32_t *types, const double *box, const int32_t *pbc, double *U,
-                 double *F, double *W, double *q_out) {
+static int evaluate_core(const ora_hparams *h, const double *params, int64_t N,
+                         const double *pos, const int32_t *types, const double *box,
+                         const int32_t *pbc, double *U, double *F, double *W, double *q_out,
+                         const double *vel, double *J2) {
   if (check_hp(h) || N < 1) return ORA_EARG;
   for (int64_t i = 0; i < N; ++i)
     if (types[i] < 0 || types[i] >= h->n_types) return ORA_EARG;
@@ -766,6 +767,7 @@ int ora_evaluate(const ora_hparams *h, const double *params, int64_t N, const do
   if (err == ORA_OK) {
     if (F) memset(F, 0, sizeof(double) * 3 * N);
     if (W) memset(W, 0, sizeof(double) * 9 * N);
+    if (J2) J2[0] = J2[1] = J2[2] = 0.0;
     for (int64_t i = 0; i < N; ++i) {
       ora_site *st = &sites[i];
       if (U) U[i] = st->U;
@@ -784,6 +786,12 @@ int ora_evaluate(const ora_hparams *h, const double *params, int64_t N, const do
           if (W)
             for (int a = 0; a < 3; ++a)
               for (int b = 0; b < 3; ++b) W[(a * 3 + b) * N + j] += (-d[a]) * P[3 * m + b];
+          if (J2) {
+            /* eq. J-2: J = -sum_i sum_j r_ij (dU_i/dr_ij . v_j) */
+            double pv = 0.0;
+            for (int b = 0; b < 3; ++b) pv += P[3 * m + b] * vel[b * N + j];
+            for (int a = 0; a < 3; ++a) J2[a] -= d[a] * pv;
+          }
         }
       }
     }
@@ -795,6 +803,38 @@ int ora_evaluate(const ora_hparams *h, const double *params, int64_t N, const do
     free(sites[i].PA);
   }
   free(sites);
+  return err;
+}
+
+int ora_evaluate(const ora_hparams *h, const double *params, int64_t N, const double *pos,
+                 const int32_t *types, const double *box, const int32_t *pbc, double *U,
+                 double *F, double *W, double *q_out) {
+  return evaluate_core(h, params, N, pos, types, box, pbc, U, F, W, q_out, NULL, NULL);
+}
+
+/* Heat current (Sec. II.E).  Per-atom J_i = W_i . v_i (eq. Ji), i.e.
+ * J_i,a = sum_b W_i,ab v_i,b with the per-atom virial of eq. virial, written
+ * to Jatom[3][N]; J1[3] = sum_i J_i (eq. J-1).  J2[3] is the same total taken
+ * the other way, from each atom's own partial forces and its neighbours'
+ * velocities (eq. J-2).  vel is [3][N]; any output may be NULL. */
+int ora_heat_current(const ora_hparams *h, const double *params, int64_t N, const double *pos,
+                     const double *vel, const int32_t *types, const double *box,
+                     const int32_t *pbc, double *Jatom, double *J1, double *J2) {
+  if (N < 1 || !vel) return ORA_EARG;
+  double *W = (double *)malloc(sizeof(double) * 9 * N);
+  if (!W) return ORA_EMEM;
+  int err = evaluate_core(h, params, N, pos, types, box, pbc, NULL, NULL, W, NULL, vel, J2);
+  if (err == ORA_OK) {
+    if (J1) J1[0] = J1[1] = J1[2] = 0.0;
+    for (int64_t i = 0; i < N; ++i)
+      for (int a = 0; a < 3; ++a) {
+        double s = 0.0;
+        for (int b = 0; b < 3; ++b) s += W[(a * 3 + b) * N + i] * vel[b * N + i];
+        if (Jatom) Jatom[a * N + i] = s;
+        if (J1) J1[a] += s;
+      }
+  }
+  free(W);
   return err;
 }
 

@@ -72,6 +72,8 @@ def lib():
         L.ora_ann.restype = d
         L.ora_evaluate.argtypes = [hp, pd, i64, pd, pi32, pd, pi32, pd, pd,
                                    pd, pd]
+        L.ora_heat_current.argtypes = [hp, pd, i64, pd, pd, pi32, pd, pi32,
+                                       pd, pd, pd]
         L.ora_descriptors.argtypes = [hp, pd, i64, pd, pi32, pd, pi32, pd]
         L.ora_evaluate_atoms.argtypes = [hp, pd, i64, pd, pi32, pd, pi32,
                                          i64, pi64, pd, pd, pd]
@@ -206,6 +208,29 @@ def evaluate(h, params, pos, types, box, pbc=None, want_q=False):
     if want_q:
         out["q"] = q
     return out
+
+
+def heat_current(h, params, pos, vel, types, box, pbc=None):
+    """Heat current (Sec. II.E): J_i = W_i . v_i per atom (eq. Ji, (3,N)),
+    its sum (eq. J-1) and the total by eq. J-2 (partial forces of each atom
+    contracted with its neighbours' velocities).  Returns (J_atom, J1, J2)."""
+    params = _f64(params)
+    pos = _f64(pos)
+    vel = _f64(vel)
+    types = _i32(types)
+    box = _f64(box)
+    n = pos.shape[1]
+    Ja = np.zeros((3, n))
+    J1 = np.zeros(3)
+    J2 = np.zeros(3)
+    err = lib().ora_heat_current(C.byref(_hp(h)), _p(params, C.c_double), n,
+                                 _p(pos, C.c_double), _p(vel, C.c_double),
+                                 _p(types, C.c_int32), _p(box, C.c_double),
+                                 _p(_pbc(pbc), C.c_int32), _p(Ja, C.c_double),
+                                 _p(J1, C.c_double), _p(J2, C.c_double))
+    if err:
+        raise RuntimeError(f"ora_heat_current failed ({err})")
+    return Ja, J1, J2
 
 
 def descriptors(h, params, pos, types, box, pbc=None):

@@ -569,6 +569,55 @@ def test_cluster_virial_equals_r_outer_f():
 
 
 # ---------------------------------------------------------------------------
+# heat current (Sec. II.E, eqs. Ji, J-1, J-2)
+# ---------------------------------------------------------------------------
+
+def test_heat_current_j1_equals_j2():
+    """Eq. J-1 (per-atom virial times own velocity) and eq. J-2 (own partial
+    forces times the neighbours' velocities) give the same total current in a
+    periodic triclinic cell; a transposed virial or a wrong velocity index
+    breaks the equality."""
+    h = hp(n_types=2, l_max_3b=4, l_max_4b=2, l_max_5b=1)
+    p = synth.random_params(O.num_params(h), seed=61)
+    pos, types, box = small_cell(14, 2, seed=62, tilt=0.2)
+    vel = np.random.default_rng(63).normal(0.0, 0.01, size=(3, 14))
+    Ja, J1, J2 = O.heat_current(h, p, pos, vel, types, box)
+    scale = np.abs(Ja).sum()
+    assert scale > 1e-6
+    np.testing.assert_allclose(Ja.sum(axis=1), J1, atol=1e-14 * scale)
+    np.testing.assert_allclose(J1, J2, atol=1e-12 * scale)
+    zero = O.heat_current(h, p, pos, np.zeros_like(vel), types, box)
+    assert not np.any(zero[0]) and not np.any(zero[1]) and not np.any(zero[2])
+
+
+def test_heat_current_per_atom_finite_difference():
+    """Per-atom J_i = sum_j r_ij (dU_j/dr_ji . v_i) (eq. Ji) with dU_j/dr_ji
+    taken as the central difference of site energy U_j in the position of
+    atom i (U_j depends on r_i only through r_ji) in an isolated cluster."""
+    h = hp(n_types=2, l_max_3b=4, l_max_4b=2, l_max_5b=1)
+    p = synth.random_params(O.num_params(h), seed=64)
+    n = 7
+    pos, types, _ = small_cell(n, 2, seed=65, tilt=0.0)
+    box = np.diag([50.0, 50.0, 50.0]).reshape(9)
+    pbc = np.zeros(3, np.int32)
+    vel = np.random.default_rng(66).normal(0.0, 0.02, size=(3, n))
+    Ja, _, _ = O.heat_current(h, p, pos, vel, types, box, pbc)
+    e = 1e-5
+    for i in range(n):
+        dU = np.zeros((3, n))  # dU[c, j] = dU_j / dr_i,c
+        for c in range(3):
+            pp = pos.copy(); pp[c, i] += e
+            pm = pos.copy(); pm[c, i] -= e
+            dU[c] = (O.evaluate(h, p, pp, types, box, pbc)["U"] -
+                     O.evaluate(h, p, pm, types, box, pbc)["U"]) / (2 * e)
+        J = np.zeros(3)
+        for j in range(n):
+            if j != i:
+                J += (pos[:, j] - pos[:, i]) * (dU[:, j] @ vel[:, i])
+        np.testing.assert_allclose(Ja[:, i], J, atol=1e-8, rtol=1e-6)
+
+
+# ---------------------------------------------------------------------------
 # sampled evaluation (used at full sizes) == full evaluation
 # ---------------------------------------------------------------------------
 
