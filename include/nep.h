@@ -121,6 +121,24 @@ int nep_compute_dev(nep_handle *h, int64_t n_atoms, const double *pos,
                     double *energy, double *force, double *virial, double *totals,
                     void *stream);
 
+/* Heat current of one structure (Sec. II.E).  Per-atom J_i = W_i . v_i
+ * (eq. Ji), J_i,a = sum_b W_i,ab v_i,b with the per-atom virial W_i of
+ * eq. virial (units eV * A/fs for v in A/fs), and the total J = sum_i J_i
+ * (eq. J-1).  Host pointers: vel [3][N] (required, finite), heat [3][N]
+ * (may be NULL), total [3] (may be NULL).  The total is summed in float64 in
+ * a fixed order: the same inputs give the same bits.  Synchronous.  Errors as
+ * nep_compute, plus NEP_E_NONFINITE for non-finite velocities. */
+int nep_heat_current(nep_handle *h, int64_t n_atoms, const double *pos, const double *vel,
+                     const int32_t *types, const double box[9], const int32_t pbc[3],
+                     double *heat, double total[3]);
+
+/* Same as nep_heat_current with pos, vel, types, heat and total in device
+ * memory on `stream` (hipStream_t, NULL = default); box and pbc are host
+ * arrays.  Returns after the work is enqueued. */
+int nep_heat_current_dev(nep_handle *h, int64_t n_atoms, const double *pos, const double *vel,
+                         const int32_t *types, const double box[9], const int32_t pbc[3],
+                         double *heat, double *total, void *stream);
+
 /* Neighbour rows at the radial (which = 0) or angular (which = 1) cutoff,
  * as defined above, for diagnostics and parity.  Host pointers: count[N];
  * nbr[N][cap] neighbour indices and shift[N][cap][3] integer images n, each

@@ -1395,6 +1395,65 @@ int nep_compute_dev(nep_handle* h, int64_t N, const double* pos, const int32_t* 
   return NEP_OK;
 }
 
+namespace {
+// Heat current of eq. Ji from the per-atom virial left by compute_impl.
+void heat_current_impl(nep_handle* h, int64_t N, const double* d_pos, const double* d_vel,
+                       const int32_t* d_types, const double* box, const int32_t* pbc,
+                       double* d_heat, double* d_total, hipStream_t s) {
+  if (!d_vel) throw Failure{NEP_E_INVALID_ARG, "velocities are required"};
+  compute_impl(h, N, d_pos, d_types, box, pbc, nullptr, nullptr, nullptr, nullptr, s);
+  Stage st(h, "heat_current", s);
+  launch_heat_current(h->W, N, h->perm, d_vel, d_heat, d_total, h->partial, num_partials(N), s);
+}
+}  // namespace
+
+int nep_heat_current(nep_handle* h, int64_t N, const double* pos, const double* vel,
+                     const int32_t* types, const double box[9], const int32_t pbc[3], double* heat,
+                     double total[3]) {
+  if (!h) return fail(nullptr, {NEP_E_INVALID_ARG, "handle is NULL"});
+  if (!pos || !vel || !types || !box)
+    return fail(h, {NEP_E_INVALID_ARG, "pos, vel, types and box are required"});
+  try {
+    set_device(h);
+    if (N < 1) throw Failure{NEP_E_INVALID_ARG, "n_atoms must be >= 1"};
+    check_host_types(h, N, types);
+    check_host_finite(3 * N, pos, "positions");
+    check_host_finite(3 * N, vel, "velocities");
+    hipStream_t s = nullptr;
+    Prepared pp = prepare(h, N, box, pbc, h->hp.rc_radial, false, s);
+    (void)pp;
+    HIPCHK(hipMemcpyAsync(h->pos_ext, pos, 3 * N * sizeof(double), hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(h->types_ext, types, N * sizeof(int32_t), hipMemcpyHostToDevice, s));
+    // the velocities travel in the force buffer (3N doubles), unused by this call
+    HIPCHK(hipMemcpyAsync(h->out_f, vel, 3 * N * sizeof(double), hipMemcpyHostToDevice, s));
+    heat_current_impl(h, N, h->pos_ext, h->out_f, h->types_ext, box, pbc, heat ? h->out_w : nullptr,
+                      total ? h->totals : nullptr, s);
+    if (heat) HIPCHK(hipMemcpyAsync(heat, h->out_w, 3 * N * sizeof(double), hipMemcpyDeviceToHost, s));
+    if (total) HIPCHK(hipMemcpyAsync(total, h->totals, 3 * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    h->resolve_timing();
+  } catch (const Failure& f) {
+    return fail(h, f);
+  }
+  return NEP_OK;
+}
+
+int nep_heat_current_dev(nep_handle* h, int64_t N, const double* pos, const double* vel,
+                         const int32_t* types, const double box[9], const int32_t pbc[3],
+                         double* heat, double* total, void* stream) {
+  if (!h) return fail(nullptr, {NEP_E_INVALID_ARG, "handle is NULL"});
+  if (!pos || !vel || !types || !box)
+    return fail(h, {NEP_E_INVALID_ARG, "pos, vel, types and box are required"});
+  try {
+    set_device(h);
+    heat_current_impl(h, N, pos, vel, types, box, pbc, heat, total, (hipStream_t)stream);
+    h->resolve_timing();
+  } catch (const Failure& f) {
+    return fail(h, f);
+  }
+  return NEP_OK;
+}
+
 int nep_neighbors(nep_handle* h, int64_t N, const double* pos, const double box[9], const int32_t pbc[3],
                   int32_t which, int32_t cap, int32_t* count, int32_t* nbr, int32_t* shift) {
   if (!h) return fail(nullptr, {NEP_E_INVALID_ARG, "handle is NULL"});

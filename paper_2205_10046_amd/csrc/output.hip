@@ -162,3 +162,58 @@ void launch_neighbors_out(const Lists& L, int which, int64_t N, const int32_t* p
 }
 
 }  // namespace nep
+
+namespace nep {
+
+// Heat current of Sec. II.E: J_i = W_i . v_i (eq. Ji), J_i,a = sum_b W_i,ab v_i,b,
+// in float64 from the float32 per-atom virial (sorted order) and the caller's
+// float64 velocities [3][N] (caller order).  J_i goes to heat[3][N] in caller
+// order when heat is not NULL; block b sums the J_i of its chunk in a fixed
+// tree into partial[b][3] for the total of eq. J-1.
+__global__ void __launch_bounds__(kRedBlock) k_heat_current_partial(
+    const float* __restrict__ W, int64_t N, const int32_t* __restrict__ perm,
+    const double* __restrict__ vel, int64_t chunk, double* __restrict__ heat,
+    double* __restrict__ partial) {
+  __shared__ double sh[3][kRedBlock];
+  const int t = threadIdx.x;
+  const int64_t lo = (int64_t)blockIdx.x * chunk, hi = min(N, lo + chunk);
+  double acc[3] = {0.0, 0.0, 0.0};
+  for (int64_t k = lo + t; k < hi; k += kRedBlock) {
+    const int64_t e = perm[k];
+    const double v[3] = {vel[e], vel[N + e], vel[2 * N + e]};
+    for (int a = 0; a < 3; ++a) {
+      double j = 0.0;
+      for (int b = 0; b < 3; ++b) j = fma((double)W[(int64_t)(3 * a + b) * N + k], v[b], j);
+      if (heat) heat[(int64_t)a * N + e] = j;
+      acc[a] += j;
+    }
+  }
+  for (int a = 0; a < 3; ++a) sh[a][t] = acc[a];
+  __syncthreads();
+  for (int off = kRedBlock / 2; off > 0; off >>= 1) {
+    if (t < off)
+      for (int a = 0; a < 3; ++a) sh[a][t] += sh[a][t + off];
+    __syncthreads();
+  }
+  if (t < 3) partial[blockIdx.x * 3 + t] = sh[t][0];
+}
+
+__global__ void k_heat_current_final(const double* __restrict__ partial, int64_t n_part,
+                                     double* __restrict__ total) {
+  const int a = threadIdx.x;
+  if (a >= 3) return;
+  double s = 0.0;
+  for (int64_t b = 0; b < n_part; ++b) s += partial[b * 3 + a];
+  total[a] = s;
+}
+
+void launch_heat_current(const float* W, int64_t N, const int32_t* perm, const double* vel,
+                         double* heat, double* total, double* partial, int64_t n_part,
+                         hipStream_t s) {
+  const int64_t chunk = (N + n_part - 1) / n_part;
+  hipLaunchKernelGGL(k_heat_current_partial, dim3((unsigned)n_part), dim3(kRedBlock), 0, s, W, N,
+                     perm, vel, chunk, heat, partial);
+  if (total) hipLaunchKernelGGL(k_heat_current_final, dim3(1), dim3(64), 0, s, partial, n_part, total);
+}
+
+}  // namespace nep

@@ -31,7 +31,7 @@ NEP_MLP_BF16 = 1
 # every entry point declared in include/nep.h
 EXPORTS = ["nep_num_descriptors", "nep_num_params", "nep_create", "nep_set_params",
            "nep_destroy", "nep_last_error", "nep_compute", "nep_compute_dev",
-           "nep_neighbors", "nep_descriptors", "nep_md_run", "nep_md_run_dev",
+           "nep_heat_current", "nep_heat_current_dev", "nep_neighbors", "nep_descriptors", "nep_md_run", "nep_md_run_dev",
            "nep_compute_batch", "nep_set_timing", "nep_get_timing", "nep_get_tuning",
            "nep_server_create",
            "nep_server_submit", "nep_server_poll", "nep_server_stats", "nep_server_reset_stats",
@@ -130,6 +130,8 @@ def load():
     L.nep_last_error.restype = C.c_char_p
     L.nep_compute.argtypes = [vp, i64, pd, pi32, pd, pi32, pd, pd, pd, pd]
     L.nep_compute_dev.argtypes = [vp, i64, vp, vp, pd, pi32, vp, vp, vp, vp, vp]
+    L.nep_heat_current.argtypes = [vp, i64, pd, pd, pi32, pd, pi32, pd, pd]
+    L.nep_heat_current_dev.argtypes = [vp, i64, vp, vp, vp, pd, pi32, vp, vp, vp]
     L.nep_neighbors.argtypes = [vp, i64, pd, pd, pi32, i32, i32, pi32, pi32, pi32]
     L.nep_descriptors.argtypes = [vp, i64, pd, pi32, pd, pi32, pd]
     L.nep_md_run.argtypes = [vp, i64, pd, pd, pi32, pd, pd, pi32, d, i64, i64, pd]
@@ -240,6 +242,27 @@ class Handle:
         self._check(load().nep_compute_dev(
             self._h, n, p(pos), p(types), _ptr(box, C.c_double), _ptr(pbc, C.c_int32),
             p(energy), p(force), p(virial), p(totals), _torch_stream()))
+
+    def heat_current(self, pos, vel, types, box, pbc=None):
+        """nep_heat_current on host arrays: (J_i (3,N), total J (3,))."""
+        pos, vel, types, box = _f64(pos), _f64(vel), _i32(types), _f64(box)
+        pbc = _i32(np.ones(3) if pbc is None else pbc)
+        n = pos.shape[1]
+        J, T = np.zeros((3, n)), np.zeros(3)
+        self._check(load().nep_heat_current(
+            self._h, n, _ptr(pos, C.c_double), _ptr(vel, C.c_double), _ptr(types, C.c_int32),
+            _ptr(box, C.c_double), _ptr(pbc, C.c_int32), _ptr(J, C.c_double),
+            _ptr(T, C.c_double)))
+        return J, T
+
+    def heat_current_dev(self, pos, vel, types, box, pbc=None, heat=None, total=None):
+        """nep_heat_current_dev on torch CUDA tensors (float64 pos/vel (3,N))."""
+        box, pbc = _f64(box), _i32(np.ones(3) if pbc is None else pbc)
+        n = int(pos.shape[1])
+        p = lambda t: None if t is None else C.c_void_p(t.data_ptr())  # noqa: E731
+        self._check(load().nep_heat_current_dev(
+            self._h, n, p(pos), p(vel), p(types), _ptr(box, C.c_double), _ptr(pbc, C.c_int32),
+            p(heat), p(total), _torch_stream()))
 
     def neighbors(self, pos, box, which=0, pbc=None, cap=256):
         """Rows at the radial (0) or angular (1) cutoff: list of (j, shift (m,3))."""
