@@ -1283,6 +1283,25 @@ void server_loop(nep_server* sv) {
 // C ABI
 // ===========================================================================
 
+namespace nep {
+// output.hip (declared here so that the force kernel's headers stay as profiled)
+void launch_heat_current(const float* W, int64_t N, const int32_t* perm, const double* vel,
+                         double* heat, double* total, double* partial, int64_t n_part,
+                         hipStream_t s);
+}  // namespace nep
+
+namespace {
+// Heat current of eq. Ji from the per-atom virial left by compute_impl.
+void heat_current_impl(nep_handle* h, int64_t N, const double* d_pos, const double* d_vel,
+                       const int32_t* d_types, const double* box, const int32_t* pbc,
+                       double* d_heat, double* d_total, hipStream_t s) {
+  if (!d_vel) throw Failure{NEP_E_INVALID_ARG, "velocities are required"};
+  compute_impl(h, N, d_pos, d_types, box, pbc, nullptr, nullptr, nullptr, nullptr, s);
+  Stage st(h, "heat_current", s);
+  launch_heat_current(h->W, N, h->perm, d_vel, d_heat, d_total, h->partial, num_partials(N), s);
+}
+}  // namespace
+
 extern "C" {
 
 int nep_num_descriptors(const nep_hparams* hp) {
@@ -1394,18 +1413,6 @@ int nep_compute_dev(nep_handle* h, int64_t N, const double* pos, const int32_t* 
   }
   return NEP_OK;
 }
-
-namespace {
-// Heat current of eq. Ji from the per-atom virial left by compute_impl.
-void heat_current_impl(nep_handle* h, int64_t N, const double* d_pos, const double* d_vel,
-                       const int32_t* d_types, const double* box, const int32_t* pbc,
-                       double* d_heat, double* d_total, hipStream_t s) {
-  if (!d_vel) throw Failure{NEP_E_INVALID_ARG, "velocities are required"};
-  compute_impl(h, N, d_pos, d_types, box, pbc, nullptr, nullptr, nullptr, nullptr, s);
-  Stage st(h, "heat_current", s);
-  launch_heat_current(h->W, N, h->perm, d_vel, d_heat, d_total, h->partial, num_partials(N), s);
-}
-}  // namespace
 
 int nep_heat_current(nep_handle* h, int64_t N, const double* pos, const double* vel,
                      const int32_t* types, const double box[9], const int32_t pbc[3], double* heat,

@@ -106,9 +106,6 @@ void launch_totals(const float* U, const float* W, int64_t N, double* partial, i
                    double* totals, hipStream_t s);
 void launch_struct_totals(const float* U, const float* W, int64_t N, const StructInfo* structs,
                           int32_t n_struct, double* totals, hipStream_t s);
-void launch_heat_current(const float* W, int64_t N, const int32_t* perm, const double* vel,
-                         double* heat, double* total, double* partial, int64_t n_part,
-                         hipStream_t s);
 void launch_descriptors_out(const float* q, int64_t N, int NDp, int ND, const int32_t* perm,
                             double* out, hipStream_t s);
 void launch_neighbors_out(const Lists& L, int which, int64_t N, const int32_t* perm,

@@ -27,6 +27,19 @@ def test_every_declared_symbol_is_exported():
         assert hasattr(L, name), name
 
 
+def test_library_leaves_no_symbol_unresolved():
+    """Every undefined symbol of the library comes from a versioned system
+    library (HIP runtime, libc, libstdc++): a declaration given the wrong
+    linkage would leave an unversioned one that fails only when called."""
+    import subprocess
+    out = subprocess.run(["nm", "-D", "--undefined-only", nep.LIB_PATH],
+                         capture_output=True, text=True, check=True).stdout
+    loose = [ln.split()[-1] for ln in out.splitlines()
+             if ln.strip() and "@" not in ln and not ln.split()[-1].startswith("__")
+             and ln.split()[0] == "U"]
+    assert not loose, loose
+
+
 @pytest.mark.parametrize("name", sorted(synth.WORKLOADS))
 def test_sizes_match_oracle(name):
     for per in (0, 1):
