@@ -11,6 +11,7 @@ rows, per-atom virials (9, N) row-major per atom (W_ab at row 3a + b).
 from __future__ import annotations
 
 import ctypes as C
+import math
 import os
 import subprocess
 
@@ -291,3 +292,46 @@ def md_nve(h, params, pos, vel, types, mass_per_type, box, dt, n_steps,
     if err:
         raise RuntimeError(f"ora_md_nve failed ({err})")
     return pos, vel, th[:rows]
+
+
+# ---------------------------------------------------------------------------
+# training loss (Sec. II.E, eq. loss)
+# ---------------------------------------------------------------------------
+
+# the six independent virial components: xx, yy, zz, xy, yz, zx (row 3a + b)
+VIRIAL6 = (0, 4, 8, 1, 5, 6)
+
+
+def loss_terms(e_pred, f_pred, w_pred, e_tar, f_tar, w_tar, z, lam):
+    """Eq. loss written out.  e_* (S,) energy per atom of each structure,
+    f_* (3, N) forces, w_* (S, 6) virial per atom in VIRIAL6 order (w_tar None:
+    no virial term), z (N_par,) parameters, lam (lambda_e, lambda_f, lambda_v,
+    lambda_1, lambda_2).  Returns [L, L_e, L_f, L_v, L_1, L_2] where L is the
+    weighted sum and the others are the unweighted terms (RMSEs and norms)."""
+    e_pred, e_tar = np.asarray(e_pred, float), np.asarray(e_tar, float)
+    f_pred, f_tar = np.asarray(f_pred, float), np.asarray(f_tar, float)
+    z = np.asarray(z, float)
+    S, N, npar = e_pred.shape[0], f_pred.shape[1], z.shape[0]
+    le = math.sqrt(sum((e_pred[n] - e_tar[n]) ** 2 for n in range(S)) / S)
+    lf = math.sqrt(float(((f_pred - f_tar) ** 2).sum()) / (3 * N))
+    lv = 0.0
+    if w_tar is not None:
+        d = np.asarray(w_pred, float) - np.asarray(w_tar, float)
+        lv = math.sqrt(float((d ** 2).sum()) / (6 * S))
+    l1 = float(np.abs(z).sum()) / npar
+    l2 = math.sqrt(float((z ** 2).sum()) / npar)
+    total = lam[0] * le + lam[1] * lf + lam[2] * lv + lam[3] * l1 + lam[4] * l2
+    return np.array([total, le, lf, lv, l1, l2])
+
+
+def predictions(h, params, structs):
+    """Per-structure energy per atom (S,), forces (3, N) and virial per atom
+    (S, 6) of a list of (pos, types, box) structures."""
+    e, f, w = [], [], []
+    for pos, types, box in structs:
+        r = evaluate(h, params, pos, types, box)
+        n = pos.shape[1]
+        e.append(r["U"].sum() / n)
+        f.append(r["F"])
+        w.append(r["W"].sum(axis=1)[list(VIRIAL6)] / n)
+    return np.array(e), np.concatenate(f, axis=1), np.array(w)

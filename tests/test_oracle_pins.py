@@ -668,3 +668,49 @@ def test_nve_time_reversibility(nve_setup):
     p2, v2, _ = O.md_nve(h, p, p1, -v1, types, m, box, 1.0, 40, 0)
     np.testing.assert_allclose(p2, pos, atol=1e-9)
     np.testing.assert_allclose(-v2, vel, atol=1e-11)
+
+
+# ---------------------------------------------------------------------------
+# training loss (Sec. II.E, eq. loss)
+# ---------------------------------------------------------------------------
+
+def _loss_case():
+    h = hp(n_types=2, l_max_3b=4, l_max_4b=2, l_max_5b=0)
+    z = synth.random_params(O.num_params(h), seed=71)
+    rng = np.random.default_rng(72)
+    structs = [synth.random_cell(n, 0.07, 0.1, 1.6, 2, rng) for n in (6, 9, 13)]
+    return h, z, structs
+
+
+def test_loss_offsets_give_exact_rmse():
+    """Targets equal to the predictions leave only the regularisers; a common
+    offset d of every energy, every force component or every virial component
+    gives exactly |d| in that term, whatever the sizes -- which fixes the
+    1/N_str, 1/(3N) and 1/(6 N_str) normalisations and the square roots."""
+    h, z, structs = _loss_case()
+    e, f, w = O.predictions(h, z, structs)
+    lam = (1.0, 2.0, 3.0, 0.0, 0.0)
+    base = O.loss_terms(e, f, w, e, f, w, z, lam)
+    assert base[0] == 0.0 and base[1] == base[2] == base[3] == 0.0
+    d = 0.037
+    r = O.loss_terms(e, f, w, e + d, f, w, z, lam)
+    assert r[1] == pytest.approx(d, rel=1e-12) and r[0] == pytest.approx(d, rel=1e-12)
+    r = O.loss_terms(e, f, w, e, f - d, w, z, lam)
+    assert r[2] == pytest.approx(d, rel=1e-12) and r[0] == pytest.approx(2 * d, rel=1e-12)
+    r = O.loss_terms(e, f, w, e, f, w + d, z, lam)
+    assert r[3] == pytest.approx(d, rel=1e-12) and r[0] == pytest.approx(3 * d, rel=1e-12)
+    # one structure off by d among S: RMSE d / sqrt(S)
+    e2 = e.copy(); e2[1] += d
+    assert O.loss_terms(e, f, w, e2, f, w, z, lam)[1] == pytest.approx(d / math.sqrt(3), rel=1e-12)
+
+
+def test_loss_regularisers_and_virial_symmetry():
+    h, z, structs = _loss_case()
+    e, f, w = O.predictions(h, z, structs)
+    r = O.loss_terms(e, f, w, e, f, None, np.full(8, -0.5), (0, 0, 0, 1.0, 1.0))
+    assert r[4] == 0.5 and r[5] == 0.5 and r[0] == 1.0
+    # the total virial of a periodic structure is symmetric, so the six
+    # components are the whole tensor
+    for pos, types, box in structs:
+        W = O.evaluate(h, z, pos, types, box)["W"].sum(axis=1).reshape(3, 3)
+        np.testing.assert_allclose(W, W.T, atol=1e-10 * max(1.0, np.abs(W).max()))
