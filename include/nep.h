@@ -155,6 +155,28 @@ int nep_descriptors(nep_handle *h, int64_t n_atoms, const double *pos,
                     const int32_t *types, const double box[9], const int32_t pbc[3],
                     double *q);
 
+/* Training loss of eq. loss (Sec. II.E) for each of n_param_sets parameter
+ * vectors, from the outputs of nep_compute_batch on the same structures:
+ *   L = l_e RMSE(energy per atom over structures)
+ *     + l_f RMSE(force components over the 3N components)
+ *     + l_v RMSE(virial per atom over structures and the six components
+ *                xx, yy, zz, xy, yz, zx)
+ *     + l_1 mean|z| + l_2 sqrt(mean z^2),  lambda = {l_e, l_f, l_v, l_1, l_2}.
+ * offsets (host, int64[n_struct+1], offsets[0] = 0, every structure >= 1
+ * atom) and lambda (host, [5]) are host arrays; all others are device
+ * pointers: force [P][3][N] and totals [P][n_struct][10] as written by
+ * nep_compute_batch; energy_target [n_struct] (eV/atom); force_target
+ * [3][N] (eV/A); virial_target [n_struct][6] (eV/atom) or NULL (no virial
+ * term); params [P][n_par] or NULL (no regularisers; otherwise n_par must be
+ * nep_num_params).  loss [P][6] receives [L, RMSE_e, RMSE_f, RMSE_v,
+ * mean|z|, sqrt(mean z^2)]; absent terms read 0.  Sums are float64 in a fixed
+ * order (same inputs, same bits).  Synchronous on `stream`. */
+int nep_batch_loss(nep_handle *h, int32_t n_struct, const int64_t *offsets, int32_t n_param_sets,
+                   const double *params, int64_t n_par, const double *force, const double *totals,
+                   const double *energy_target, const double *force_target,
+                   const double *virial_target, const double lambda[5], double *loss,
+                   void *stream);
+
 /* Velocity-Verlet NVE for n_steps of dt_fs (the 'nve' ensemble of the paper,
  * Sec. IV): v += dt/2 F/m; r += dt v; F(r); v += dt/2 F/m.  pos and vel
  * (host, [3][N]) are updated in place.  mass_per_type: amu, [n_types].

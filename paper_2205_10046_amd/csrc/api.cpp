@@ -286,6 +286,10 @@ struct nep_handle {
   std::vector<ModelTables> pop;     // parameter sets of the last batch call
   int64_t* offs = nullptr;          // structure offsets of a batch (device)
   int32_t cap_struct = 0;
+  // training-loss workspace (grown on demand, kept until the handle ends)
+  double* loss_part = nullptr;
+  int64_t* loss_offs = nullptr;
+  int64_t loss_part_cap = 0, loss_offs_cap = 0;
   DevModel& M = main.M;
   // workspace
   int64_t capN = 0, cap_part = 0, rows_cap = 0;
@@ -322,6 +326,8 @@ struct nep_handle {
   void release() {
     if (pinned) (void)hipHostFree(pinned);
     pinned = nullptr;
+    dev_free(loss_part); dev_free(loss_offs);
+    loss_part_cap = loss_offs_cap = 0;
     main.release();
     for (auto& t : pop) t.release();
     pop.clear();
@@ -1288,6 +1294,11 @@ namespace nep {
 void launch_heat_current(const float* W, int64_t N, const int32_t* perm, const double* vel,
                          double* heat, double* total, double* partial, int64_t n_part,
                          hipStream_t s);
+int64_t loss_chunks(int64_t N);
+void launch_loss(const double* force, const double* totals, const int64_t* offs, int32_t S, int64_t N,
+                 int32_t P, const double* e_tar, const double* f_tar, const double* w_tar,
+                 const double* params, int64_t npar, const double lam[5], double* partial, double* loss,
+                 hipStream_t s);
 }  // namespace nep
 
 namespace {
@@ -1454,6 +1465,55 @@ int nep_heat_current_dev(nep_handle* h, int64_t N, const double* pos, const doub
   try {
     set_device(h);
     heat_current_impl(h, N, pos, vel, types, box, pbc, heat, total, (hipStream_t)stream);
+    h->resolve_timing();
+  } catch (const Failure& f) {
+    return fail(h, f);
+  }
+  return NEP_OK;
+}
+
+int nep_batch_loss(nep_handle* h, int32_t n_struct, const int64_t* offsets, int32_t n_param_sets,
+                   const double* params, int64_t n_par, const double* force, const double* totals,
+                   const double* energy_target, const double* force_target, const double* virial_target,
+                   const double lambda[5], double* loss, void* stream) {
+  if (!h) return fail(nullptr, {NEP_E_INVALID_ARG, "handle is NULL"});
+  try {
+    if (n_struct < 1 || n_param_sets < 1)
+      throw Failure{NEP_E_INVALID_ARG, "n_struct and n_param_sets must be >= 1"};
+    if (!offsets || !force || !totals || !energy_target || !force_target || !lambda || !loss)
+      throw Failure{NEP_E_INVALID_ARG,
+                    "offsets, force, totals, energy_target, force_target, lambda and loss are required"};
+    if (offsets[0] != 0) throw Failure{NEP_E_INVALID_ARG, "offsets[0] must be 0"};
+    for (int32_t s = 0; s < n_struct; ++s)
+      if (offsets[s + 1] <= offsets[s])
+        throw Failure{NEP_E_INVALID_ARG, "structure " + std::to_string(s) + " has no atoms"};
+    if (params && n_par != (int64_t)n_params(h->hp))
+      throw Failure{NEP_E_INVALID_ARG, "n_params does not match the model"};
+    for (int v = 0; v < 5; ++v)
+      if (!std::isfinite(lambda[v])) throw Failure{NEP_E_NONFINITE, "lambda contains NaN or Inf"};
+    set_device(h);
+    hipStream_t s = (hipStream_t)stream;
+    const int64_t N = offsets[n_struct];
+    const int64_t need_part = (int64_t)n_param_sets * loss_chunks(N) * 5;
+    if (need_part > h->loss_part_cap) {
+      HIPCHK(hipStreamSynchronize(s));
+      dev_alloc(h->loss_part, (size_t)need_part);
+      h->loss_part_cap = need_part;
+    }
+    if (n_struct + 1 > h->loss_offs_cap) {
+      HIPCHK(hipStreamSynchronize(s));
+      dev_alloc(h->loss_offs, (size_t)n_struct + 1);
+      h->loss_offs_cap = n_struct + 1;
+    }
+    HIPCHK(hipMemcpyAsync(h->loss_offs, offsets, ((size_t)n_struct + 1) * sizeof(int64_t),
+                          hipMemcpyHostToDevice, s));
+    {
+      Stage st(h, "batch_loss", s);
+      launch_loss(force, totals, h->loss_offs, n_struct, N, n_param_sets, energy_target, force_target,
+                  virial_target, params, params ? n_par : 0, lambda, h->loss_part, loss, s);
+    }
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(s));
     h->resolve_timing();
   } catch (const Failure& f) {
     return fail(h, f);

@@ -1,6 +1,8 @@
 // output.hip -- results back in the caller's atom order, and the float64
 // totals E = sum_i U_i, W = sum_i W_i (a fixed two-level tree: the same
 // inputs always give the same bits).
+#include <algorithm>
+
 #include "nep_kernels.h"
 
 namespace nep {
@@ -214,6 +216,108 @@ void launch_heat_current(const float* W, int64_t N, const int32_t* perm, const d
   hipLaunchKernelGGL(k_heat_current_partial, dim3((unsigned)n_part), dim3(kRedBlock), 0, s, W, N,
                      perm, vel, chunk, heat, partial);
   if (total) hipLaunchKernelGGL(k_heat_current_final, dim3(1), dim3(64), 0, s, partial, n_part, total);
+}
+
+}  // namespace nep
+
+namespace nep {
+
+// Training loss of Sec. II.E (eq. loss) for P parameter sets from the batch
+// outputs.  Block (c, p) takes chunk c of the structures (energy per atom and
+// the six virial components per atom), of the 3N force components and of the
+// parameters of set p, and writes its five fixed-tree sums
+// [sum de^2, sum df^2, sum dw^2, sum |z|, sum z^2] to partial[p][c][5].
+struct LossArgs {
+  const double* force;    // [P][3][N]
+  const double* totals;   // [P][S][10]
+  const int64_t* offs;    // [S + 1]
+  const double* e_tar;    // [S] eV/atom
+  const double* f_tar;    // [3][N]
+  const double* w_tar;    // [S][6] eV/atom (xx, yy, zz, xy, yz, zx) or NULL
+  const double* params;   // [P][npar] or NULL
+  int64_t N, npar;
+  int32_t S;
+  double lam[5];
+};
+
+__global__ void __launch_bounds__(kRedBlock) k_loss_partial(LossArgs a, double* __restrict__ partial) {
+  __shared__ double sh[5][kRedBlock];
+  const int t = threadIdx.x;
+  const int64_t p = blockIdx.y, c = blockIdx.x, C = gridDim.x;
+  double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+  {
+    const int64_t chunk = (a.S + C - 1) / C, lo = c * chunk, hi = min((int64_t)a.S, lo + chunk);
+    const int comp[6] = {0, 4, 8, 1, 5, 6};
+    for (int64_t n = lo + t; n < hi; n += kRedBlock) {
+      const double cnt = (double)(a.offs[n + 1] - a.offs[n]);
+      const double* T = a.totals + ((int64_t)p * a.S + n) * 10;
+      const double de = T[0] / cnt - a.e_tar[n];
+      acc[0] += de * de;
+      if (a.w_tar)
+        for (int v = 0; v < 6; ++v) {
+          const double dw = T[1 + comp[v]] / cnt - a.w_tar[n * 6 + v];
+          acc[2] += dw * dw;
+        }
+    }
+  }
+  {
+    const int64_t n3 = 3 * a.N, chunk = (n3 + C - 1) / C, lo = c * chunk, hi = min(n3, lo + chunk);
+    const double* f = a.force + p * n3;
+    for (int64_t k = lo + t; k < hi; k += kRedBlock) {
+      const double df = f[k] - a.f_tar[k];
+      acc[1] += df * df;
+    }
+  }
+  if (a.params) {
+    const int64_t chunk = (a.npar + C - 1) / C, lo = c * chunk, hi = min(a.npar, lo + chunk);
+    const double* z = a.params + p * a.npar;
+    for (int64_t k = lo + t; k < hi; k += kRedBlock) {
+      acc[3] += fabs(z[k]);
+      acc[4] += z[k] * z[k];
+    }
+  }
+  for (int v = 0; v < 5; ++v) sh[v][t] = acc[v];
+  __syncthreads();
+  for (int off = kRedBlock / 2; off > 0; off >>= 1) {
+    if (t < off)
+      for (int v = 0; v < 5; ++v) sh[v][t] += sh[v][t + off];
+    __syncthreads();
+  }
+  if (t < 5) partial[(p * C + c) * 5 + t] = sh[t][0];
+}
+
+// loss[p][6] = [L, L_e, L_f, L_v, L_1, L_2]: the chunk sums added in chunk
+// order, the RMSEs and norms formed, and L their lambda-weighted sum.
+__global__ void k_loss_final(LossArgs a, const double* __restrict__ partial, int64_t C, int32_t P,
+                             double* __restrict__ loss) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= P) return;
+  double s[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+  for (int64_t c = 0; c < C; ++c)
+    for (int v = 0; v < 5; ++v) s[v] += partial[(p * C + c) * 5 + v];
+  const double le = sqrt(s[0] / a.S), lf = sqrt(s[1] / (3.0 * a.N));
+  const double lv = a.w_tar ? sqrt(s[2] / (6.0 * a.S)) : 0.0;
+  const double l1 = a.params ? s[3] / a.npar : 0.0, l2 = a.params ? sqrt(s[4] / a.npar) : 0.0;
+  double* o = loss + p * 6;
+  o[0] = a.lam[0] * le + a.lam[1] * lf + a.lam[2] * lv + a.lam[3] * l1 + a.lam[4] * l2;
+  o[1] = le;
+  o[2] = lf;
+  o[3] = lv;
+  o[4] = l1;
+  o[5] = l2;
+}
+
+int64_t loss_chunks(int64_t N) { return std::min<int64_t>(256, std::max<int64_t>(1, (3 * N + 16383) / 16384)); }
+
+void launch_loss(const double* force, const double* totals, const int64_t* offs, int32_t S, int64_t N,
+                 int32_t P, const double* e_tar, const double* f_tar, const double* w_tar,
+                 const double* params, int64_t npar, const double lam[5], double* partial, double* loss,
+                 hipStream_t s) {
+  LossArgs a{force, totals, offs, e_tar, f_tar, w_tar, params, N, npar, S, {0, 0, 0, 0, 0}};
+  for (int v = 0; v < 5; ++v) a.lam[v] = lam[v];
+  const int64_t C = loss_chunks(N);
+  hipLaunchKernelGGL(k_loss_partial, dim3((unsigned)C, (unsigned)P), dim3(kRedBlock), 0, s, a, partial);
+  hipLaunchKernelGGL(k_loss_final, dim3((unsigned)((P + 63) / 64)), dim3(64), 0, s, a, partial, C, P, loss);
 }
 
 }  // namespace nep

@@ -32,7 +32,7 @@ NEP_MLP_BF16 = 1
 EXPORTS = ["nep_num_descriptors", "nep_num_params", "nep_create", "nep_set_params",
            "nep_destroy", "nep_last_error", "nep_compute", "nep_compute_dev",
            "nep_heat_current", "nep_heat_current_dev", "nep_neighbors", "nep_descriptors", "nep_md_run", "nep_md_run_dev",
-           "nep_compute_batch", "nep_set_timing", "nep_get_timing", "nep_get_tuning",
+           "nep_compute_batch", "nep_batch_loss", "nep_set_timing", "nep_get_timing", "nep_get_tuning",
            "nep_server_create",
            "nep_server_submit", "nep_server_poll", "nep_server_stats", "nep_server_reset_stats",
            "nep_server_destroy"]
@@ -138,6 +138,7 @@ def load():
     L.nep_md_run_dev.argtypes = [vp, i64, vp, vp, vp, pd, pd, pi32, d, i64, i64, vp, vp]
     L.nep_compute_batch.argtypes = [vp, i32, P(i64), vp, vp, pd, pi32, i32, pd, vp, vp, vp,
                                     vp, vp]
+    L.nep_batch_loss.argtypes = [vp, i32, P(i64), i32, vp, i64, vp, vp, vp, vp, vp, pd, vp, vp]
     L.nep_server_create.argtypes = [vp, C.c_size_t, i32, P(vp)]
     L.nep_server_submit.argtypes = [vp, P(nep_request), P(C.c_uint64)]
     L.nep_server_poll.argtypes = [vp, C.c_uint64, i32, P(nep_result)]
@@ -329,6 +330,22 @@ class Handle:
             self._h, S, _ptr(offsets, C.c_int64), p(pos), p(types), _ptr(boxes, C.c_double),
             _ptr(pbc, C.c_int32), P, _ptr(params, C.c_double), p(energy), p(force), p(virial),
             p(totals), _torch_stream()))
+
+    def batch_loss(self, offsets, force, totals, energy_target, force_target, lam,
+                   loss, virial_target=None, params=None):
+        """nep_batch_loss: force (P,3,N), totals (P,S,10), targets, params (P,N_par)
+        and loss (P,6) are torch CUDA float64 tensors; offsets (S+1) and lam (5)
+        are host arrays."""
+        offsets = np.ascontiguousarray(offsets, dtype=np.int64)
+        lam = _f64(lam)
+        S = offsets.shape[0] - 1
+        P = int(force.shape[0])
+        npar = 0 if params is None else int(params.shape[1])
+        p = lambda t: None if t is None else C.c_void_p(t.data_ptr())  # noqa: E731
+        self._check(load().nep_batch_loss(
+            self._h, S, _ptr(offsets, C.c_int64), P, p(params), npar, p(force), p(totals),
+            p(energy_target), p(force_target), p(virial_target), _ptr(lam, C.c_double), p(loss),
+            _torch_stream()))
 
     def set_timing(self, enable=True):
         self._check(load().nep_set_timing(self._h, 1 if enable else 0))
