@@ -335,3 +335,50 @@ def predictions(h, params, structs):
         f.append(r["F"])
         w.append(r["W"].sum(axis=1)[list(VIRIAL6)] / n)
     return np.array(e), np.concatenate(f, axis=1), np.array(w)
+
+
+# ---------------------------------------------------------------------------
+# separable natural evolution strategy (SNES), the trainer of Sec. II.E
+# ---------------------------------------------------------------------------
+# The paper cites SNES (Schaul et al. 2011) without restating it; this follows
+# that published algorithm: a Gaussian search distribution with mean mu and
+# per-parameter scale sigma, population z_k = mu + sigma * s_k with standard
+# normal s_k (passed in, never drawn here), fitness-shaped utilities by rank,
+# and natural-gradient steps on mu and log(sigma).
+
+def snes_rates(n_par):
+    """Default learning rates of SNES: eta_mu = 1, eta_sigma = (3 + ln d)/(5 sqrt d)."""
+    return 1.0, (3.0 + math.log(n_par)) / (5.0 * math.sqrt(n_par))
+
+
+def snes_utilities(n_pop):
+    """Utility of rank k (0 = best): max(0, ln(lambda/2 + 1) - ln(k + 1)),
+    normalised to sum 1, minus 1/lambda."""
+    raw = [max(0.0, math.log(n_pop / 2.0 + 1.0) - math.log(k + 1.0)) for k in range(n_pop)]
+    tot = sum(raw)
+    return np.array([r / tot - 1.0 / n_pop for r in raw])
+
+
+def snes_ranks(losses):
+    """Rank of each member, 0 for the smallest loss; ties go to the lower index."""
+    L = list(losses)
+    return np.array([sum(1 for j in range(len(L)) if L[j] < L[k] or (L[j] == L[k] and j < k))
+                     for k in range(len(L))])
+
+
+def snes_step(mean, sigma, noise, losses, eta_mu, eta_sigma):
+    """One SNES update from the population's standard-normal draws noise
+    (P, d) and losses (P,).  Returns the new (mean, sigma)."""
+    mean, sigma, noise = (np.asarray(a, dtype=np.float64) for a in (mean, sigma, noise))
+    u = snes_utilities(noise.shape[0])[snes_ranks(losses)]
+    g_mu = np.zeros_like(mean)
+    g_sigma = np.zeros_like(mean)
+    for k in range(noise.shape[0]):
+        g_mu += u[k] * noise[k]
+        g_sigma += u[k] * (noise[k] ** 2 - 1.0)
+    return mean + eta_mu * sigma * g_mu, sigma * np.exp(0.5 * eta_sigma * g_sigma)
+
+
+def snes_sample(mean, sigma, noise):
+    """Population z_k = mean + sigma * s_k, (P, d)."""
+    return np.asarray(mean)[None, :] + np.asarray(sigma)[None, :] * np.asarray(noise)

@@ -714,3 +714,43 @@ def test_loss_regularisers_and_virial_symmetry():
     for pos, types, box in structs:
         W = O.evaluate(h, z, pos, types, box)["W"].sum(axis=1).reshape(3, 3)
         np.testing.assert_allclose(W, W.T, atol=1e-10 * max(1.0, np.abs(W).max()))
+
+
+# ---------------------------------------------------------------------------
+# SNES (the trainer of Sec. II.E; Schaul et al. 2011)
+# ---------------------------------------------------------------------------
+
+def test_snes_utilities_shape():
+    for P in (2, 5, 50, 51):
+        u = O.snes_utilities(P)
+        assert abs(u.sum()) < 1e-15
+        assert np.all(np.diff(u) <= 0) and u[0] > 0 and u[-1] == pytest.approx(-1.0 / P)
+    assert list(O.snes_ranks([3.0, 1.0, 2.0, 1.0])) == [3, 0, 2, 1]
+
+
+def test_snes_rank_invariance():
+    """Only the order of the losses matters: a strictly increasing map of
+    them leaves the update unchanged, bit for bit."""
+    rng = np.random.default_rng(81)
+    d, P = 12, 10
+    mean, sigma = rng.normal(size=d), rng.uniform(0.5, 2.0, size=d)
+    s = rng.normal(size=(P, d))
+    L = rng.uniform(0, 1, size=P)
+    a = O.snes_step(mean, sigma, s, L, *O.snes_rates(d))
+    b = O.snes_step(mean, sigma, s, 3.0 * np.exp(L) + 7.0, *O.snes_rates(d))
+    assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+
+
+def test_snes_minimises_sphere_and_shrinks_sigma():
+    """On f(z) = |z - c|^2 the mean reaches c and the scales shrink; a sign
+    error in either natural-gradient step makes it diverge."""
+    rng = np.random.default_rng(82)
+    d, P = 8, 16
+    c = rng.normal(size=d)
+    mean, sigma = np.zeros(d), np.ones(d)
+    eta = O.snes_rates(d)
+    for _ in range(400):
+        s = rng.normal(size=(P, d))
+        z = O.snes_sample(mean, sigma, s)
+        mean, sigma = O.snes_step(mean, sigma, s, ((z - c) ** 2).sum(axis=1), *eta)
+    assert np.abs(mean - c).max() < 1e-3 and sigma.max() < 1e-3
