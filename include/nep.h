@@ -177,6 +177,31 @@ int nep_batch_loss(nep_handle *h, int32_t n_struct, const int64_t *offsets, int3
                    const double *virial_target, const double lambda[5], double *loss,
                    void *stream);
 
+/* One step of the separable natural evolution strategy (SNES, Schaul et al.
+ * 2011) that trains NEP (Sec. II.E).  The search distribution has mean
+ * mean[n_par] and scales sigma[n_par]; the population that produced loss was
+ * z_k = mean + sigma * noise[k] (see nep_snes_sample) with standard-normal
+ * noise [n_pop][n_par] supplied by the caller.  Member k's loss is
+ * loss[k * loss_stride] (so the [P][6] output of nep_batch_loss can be passed
+ * with stride 6); members are ranked by loss, ties to the lower index, and
+ * rank r gets the utility max(0, ln(P/2+1) - ln(r+1)) / sum - 1/P.  Then
+ *   mean  += eta_mu * sigma * sum_k u_k noise[k]
+ *   sigma *= exp(eta_sigma / 2 * sum_k u_k (noise[k]^2 - 1))
+ * in place.  The usual rates are eta_mu = 1 and
+ * eta_sigma = (3 + ln n_par) / (5 sqrt n_par).  All arrays are device
+ * pointers; losses must be finite (the rank of a NaN is unspecified).
+ * 2 <= n_pop <= 1024.  Asynchronous on `stream`; calls on one handle share a
+ * small utility buffer and must not overlap. */
+int nep_snes_step(nep_handle *h, int64_t n_par, int32_t n_pop, double *mean, double *sigma,
+                  const double *noise, const double *loss, int64_t loss_stride, double eta_mu,
+                  double eta_sigma, void *stream);
+
+/* SNES population population[k][i] = mean[i] + sigma[i] * noise[k][i]
+ * (device pointers, [n_pop][n_par]; 1 <= n_pop <= 65535), the parameter
+ * vectors to pass to nep_compute_batch.  Asynchronous on `stream`. */
+int nep_snes_sample(nep_handle *h, int64_t n_par, int32_t n_pop, const double *mean,
+                    const double *sigma, const double *noise, double *population, void *stream);
+
 /* Velocity-Verlet NVE for n_steps of dt_fs (the 'nve' ensemble of the paper,
  * Sec. IV): v += dt/2 F/m; r += dt v; F(r); v += dt/2 F/m.  pos and vel
  * (host, [3][N]) are updated in place.  mass_per_type: amu, [n_types].

@@ -290,6 +290,7 @@ struct nep_handle {
   double* loss_part = nullptr;
   int64_t* loss_offs = nullptr;
   int64_t loss_part_cap = 0, loss_offs_cap = 0;
+  double* snes_util = nullptr;     // [1024] SNES utilities of the last step
   DevModel& M = main.M;
   // workspace
   int64_t capN = 0, cap_part = 0, rows_cap = 0;
@@ -326,7 +327,7 @@ struct nep_handle {
   void release() {
     if (pinned) (void)hipHostFree(pinned);
     pinned = nullptr;
-    dev_free(loss_part); dev_free(loss_offs);
+    dev_free(loss_part); dev_free(loss_offs); dev_free(snes_util);
     loss_part_cap = loss_offs_cap = 0;
     main.release();
     for (auto& t : pop) t.release();
@@ -1299,6 +1300,11 @@ void launch_loss(const double* force, const double* totals, const int64_t* offs,
                  int32_t P, const double* e_tar, const double* f_tar, const double* w_tar,
                  const double* params, int64_t npar, const double lam[5], double* partial, double* loss,
                  hipStream_t s);
+void launch_snes_step(const double* loss, int64_t stride, int32_t P, const double* noise, int64_t n_par,
+                      double eta_mu, double eta_sigma, double* util, double* mean, double* sigma,
+                      hipStream_t s);
+void launch_snes_sample(const double* mean, const double* sigma, const double* noise, int64_t n_par,
+                        int32_t P, double* pop, hipStream_t s);
 }  // namespace nep
 
 namespace {
@@ -1515,6 +1521,45 @@ int nep_batch_loss(nep_handle* h, int32_t n_struct, const int64_t* offsets, int3
     HIPCHK(hipGetLastError());
     HIPCHK(hipStreamSynchronize(s));
     h->resolve_timing();
+  } catch (const Failure& f) {
+    return fail(h, f);
+  }
+  return NEP_OK;
+}
+
+int nep_snes_step(nep_handle* h, int64_t n_par, int32_t n_pop, double* mean, double* sigma,
+                  const double* noise, const double* loss, int64_t loss_stride, double eta_mu,
+                  double eta_sigma, void* stream) {
+  if (!h) return fail(nullptr, {NEP_E_INVALID_ARG, "handle is NULL"});
+  try {
+    if (n_par < 1 || n_pop < 2 || n_pop > 1024)
+      throw Failure{NEP_E_INVALID_ARG, "need n_par >= 1 and 2 <= n_pop <= 1024"};
+    if (!mean || !sigma || !noise || !loss || loss_stride < 1)
+      throw Failure{NEP_E_INVALID_ARG, "mean, sigma, noise and loss are required, loss_stride >= 1"};
+    if (!std::isfinite(eta_mu) || !std::isfinite(eta_sigma))
+      throw Failure{NEP_E_NONFINITE, "learning rates must be finite"};
+    set_device(h);
+    hipStream_t s = (hipStream_t)stream;
+    if (!h->snes_util) dev_alloc(h->snes_util, 1024);
+    launch_snes_step(loss, loss_stride, n_pop, noise, n_par, eta_mu, eta_sigma, h->snes_util, mean, sigma, s);
+    HIPCHK(hipGetLastError());
+  } catch (const Failure& f) {
+    return fail(h, f);
+  }
+  return NEP_OK;
+}
+
+int nep_snes_sample(nep_handle* h, int64_t n_par, int32_t n_pop, const double* mean, const double* sigma,
+                    const double* noise, double* population, void* stream) {
+  if (!h) return fail(nullptr, {NEP_E_INVALID_ARG, "handle is NULL"});
+  try {
+    if (n_par < 1 || n_pop < 1 || n_pop > 65535)
+      throw Failure{NEP_E_INVALID_ARG, "need n_par >= 1 and 1 <= n_pop <= 65535"};
+    if (!mean || !sigma || !noise || !population)
+      throw Failure{NEP_E_INVALID_ARG, "mean, sigma, noise and population are required"};
+    set_device(h);
+    launch_snes_sample(mean, sigma, noise, n_par, n_pop, population, (hipStream_t)stream);
+    HIPCHK(hipGetLastError());
   } catch (const Failure& f) {
     return fail(h, f);
   }

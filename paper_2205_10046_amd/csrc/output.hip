@@ -321,3 +321,73 @@ void launch_loss(const double* force, const double* totals, const int64_t* offs,
 }
 
 }  // namespace nep
+
+namespace nep {
+
+// SNES (the trainer of Sec. II.E; Schaul et al. 2011).  One block ranks the
+// population by loss (ties to the lower index) and gives member k the
+// utility of its rank r: max(0, ln(P/2 + 1) - ln(r + 1)) / sum - 1/P.  Every
+// thread forms the normaliser in the same order, so all agree bitwise.
+constexpr int kSnesMaxPop = 1024;
+
+__global__ void __launch_bounds__(kSnesMaxPop) k_snes_utilities(const double* __restrict__ loss,
+                                                                int64_t stride, int32_t P,
+                                                                double* __restrict__ util) {
+  const int k = threadIdx.x;
+  if (k >= P) return;
+  const double top = log(0.5 * P + 1.0);
+  double tot = 0.0;
+  for (int r = 0; r < P; ++r) tot += fmax(0.0, top - log(r + 1.0));
+  const double lk = loss[(int64_t)k * stride];
+  int rank = 0;
+  for (int j = 0; j < P; ++j) {
+    const double lj = loss[(int64_t)j * stride];
+    rank += (lj < lk || (lj == lk && j < k)) ? 1 : 0;
+  }
+  util[k] = fmax(0.0, top - log(rank + 1.0)) / tot - 1.0 / P;
+}
+
+// Natural-gradient steps per parameter i: g_mu = sum_k u_k s_ki,
+// g_sigma = sum_k u_k (s_ki^2 - 1) in member order; mu += eta_mu sigma g_mu,
+// sigma *= exp(eta_sigma g_sigma / 2).  noise is [P][n_par] (coalesced in i).
+__global__ void k_snes_update(const double* __restrict__ util, const double* __restrict__ noise,
+                              int64_t n_par, int32_t P, double eta_mu, double eta_sigma,
+                              double* __restrict__ mean, double* __restrict__ sigma) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n_par) return;
+  double gm = 0.0, gs = 0.0;
+  for (int k = 0; k < P; ++k) {
+    const double s = noise[(int64_t)k * n_par + i], u = util[k];
+    gm += u * s;
+    gs += u * (s * s - 1.0);
+  }
+  const double sg = sigma[i];
+  mean[i] += eta_mu * sg * gm;
+  sigma[i] = sg * exp(0.5 * eta_sigma * gs);
+}
+
+// population[k][i] = mean[i] + sigma[i] * noise[k][i]
+__global__ void k_snes_sample(const double* __restrict__ mean, const double* __restrict__ sigma,
+                              const double* __restrict__ noise, int64_t n_par,
+                              double* __restrict__ pop) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n_par) return;
+  const int64_t o = (int64_t)blockIdx.y * n_par + i;
+  pop[o] = mean[i] + sigma[i] * noise[o];
+}
+
+void launch_snes_step(const double* loss, int64_t stride, int32_t P, const double* noise, int64_t n_par,
+                      double eta_mu, double eta_sigma, double* util, double* mean, double* sigma,
+                      hipStream_t s) {
+  hipLaunchKernelGGL(k_snes_utilities, dim3(1), dim3(kSnesMaxPop), 0, s, loss, stride, P, util);
+  hipLaunchKernelGGL(k_snes_update, dim3((unsigned)div_up(n_par, kBlock)), dim3(kBlock), 0, s, util,
+                     noise, n_par, P, eta_mu, eta_sigma, mean, sigma);
+}
+
+void launch_snes_sample(const double* mean, const double* sigma, const double* noise, int64_t n_par,
+                        int32_t P, double* pop, hipStream_t s) {
+  hipLaunchKernelGGL(k_snes_sample, dim3((unsigned)div_up(n_par, kBlock), (unsigned)P), dim3(kBlock), 0,
+                     s, mean, sigma, noise, n_par, pop);
+}
+
+}  // namespace nep

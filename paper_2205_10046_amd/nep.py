@@ -32,7 +32,8 @@ NEP_MLP_BF16 = 1
 EXPORTS = ["nep_num_descriptors", "nep_num_params", "nep_create", "nep_set_params",
            "nep_destroy", "nep_last_error", "nep_compute", "nep_compute_dev",
            "nep_heat_current", "nep_heat_current_dev", "nep_neighbors", "nep_descriptors", "nep_md_run", "nep_md_run_dev",
-           "nep_compute_batch", "nep_batch_loss", "nep_set_timing", "nep_get_timing", "nep_get_tuning",
+           "nep_compute_batch", "nep_batch_loss", "nep_snes_step",
+           "nep_snes_sample", "nep_set_timing", "nep_get_timing", "nep_get_tuning",
            "nep_server_create",
            "nep_server_submit", "nep_server_poll", "nep_server_stats", "nep_server_reset_stats",
            "nep_server_destroy"]
@@ -139,6 +140,8 @@ def load():
     L.nep_compute_batch.argtypes = [vp, i32, P(i64), vp, vp, pd, pi32, i32, pd, vp, vp, vp,
                                     vp, vp]
     L.nep_batch_loss.argtypes = [vp, i32, P(i64), i32, vp, i64, vp, vp, vp, vp, vp, pd, vp, vp]
+    L.nep_snes_step.argtypes = [vp, i64, i32, vp, vp, vp, vp, i64, d, d, vp]
+    L.nep_snes_sample.argtypes = [vp, i64, i32, vp, vp, vp, vp, vp]
     L.nep_server_create.argtypes = [vp, C.c_size_t, i32, P(vp)]
     L.nep_server_submit.argtypes = [vp, P(nep_request), P(C.c_uint64)]
     L.nep_server_poll.argtypes = [vp, C.c_uint64, i32, P(nep_result)]
@@ -346,6 +349,21 @@ class Handle:
             self._h, S, _ptr(offsets, C.c_int64), P, p(params), npar, p(force), p(totals),
             p(energy_target), p(force_target), p(virial_target), _ptr(lam, C.c_double), p(loss),
             _torch_stream()))
+
+    def snes_step(self, mean, sigma, noise, loss, eta_mu, eta_sigma, loss_stride=1):
+        """nep_snes_step on torch CUDA float64 tensors: mean, sigma (n_par,) in
+        place; noise (P, n_par); loss with member k at loss[k * loss_stride]."""
+        p = lambda t: C.c_void_p(t.data_ptr())  # noqa: E731
+        self._check(load().nep_snes_step(
+            self._h, int(mean.shape[0]), int(noise.shape[0]), p(mean), p(sigma), p(noise), p(loss),
+            int(loss_stride), float(eta_mu), float(eta_sigma), _torch_stream()))
+
+    def snes_sample(self, mean, sigma, noise, population):
+        """nep_snes_sample: population (P, n_par) = mean + sigma * noise."""
+        p = lambda t: C.c_void_p(t.data_ptr())  # noqa: E731
+        self._check(load().nep_snes_sample(
+            self._h, int(mean.shape[0]), int(noise.shape[0]), p(mean), p(sigma), p(noise),
+            p(population), _torch_stream()))
 
     def set_timing(self, enable=True):
         self._check(load().nep_set_timing(self._h, 1 if enable else 0))
