@@ -213,7 +213,36 @@ def batch_leg(nep, synth, torch, n_struct, n_sets, reps=3):
     torch.cuda.synchronize()
     stages = handle.timing()
     handle.set_timing(False)
+    # the rest of one SNES generation: loss of every set (eq. loss) against
+    # synthetic targets, then the SNES update and the next population
+    npar = pop.shape[1]
+    zeros_e = torch.zeros(S, dtype=torch.float64, device=dev)
+    zeros_f = torch.zeros(3, n, dtype=torch.float64, device=dev)
+    zeros_w = torch.zeros(S, 6, dtype=torch.float64, device=dev)
+    pop_d = torch.tensor(pop, device=dev)
+    loss = torch.empty(n_sets, 6, dtype=torch.float64, device=dev)
+    mean_d = torch.tensor(mean, device=dev)
+    sigma_d = torch.full((npar,), 0.1, dtype=torch.float64, device=dev)
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(synth.SEED_WEIGHTS)
+    noise = torch.randn(n_sets, npar, dtype=torch.float64, device=dev, generator=gen)
+    lam = (1.0, 1.0, 0.1, 1e-4, 1e-4)
+    handle.batch_loss(offs, f, t, zeros_e, zeros_f, lam, loss, virial_target=zeros_w, params=pop_d)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        handle.batch_loss(offs, f, t, zeros_e, zeros_f, lam, loss, virial_target=zeros_w,
+                          params=pop_d)
+    torch.cuda.synchronize()
+    loss_ms = (time.perf_counter() - t0) / reps * 1e3
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        handle.snes_step(mean_d, sigma_d, noise, loss, 1.0, 0.01, loss_stride=6)
+        handle.snes_sample(mean_d, sigma_d, noise, pop_d)
+    torch.cuda.synchronize()
+    snes_ms = (time.perf_counter() - t0) / reps * 1e3
     handle.close()
+    del zeros_e, zeros_f, zeros_w, pop_d, loss, mean_d, sigma_d, noise
     g = stages.get("batch_graph", (float("nan"), 1))
     graph_ms = g[0] / max(g[1], 1)
     del pos_d, types_d, e, f, w, t
@@ -222,6 +251,8 @@ def batch_leg(nep, synth, torch, n_struct, n_sets, reps=3):
             "atom_evals_per_s": n * n_sets / dt, "evals_per_s": S * n_sets / dt,
             "ms_per_call": dt * 1e3, "graph_ms": graph_ms,
             "graph_atom_evals_per_s": n * n_sets / (graph_ms * 1e-3),
+            "loss_ms": loss_ms, "snes_step_and_sample_ms": snes_ms,
+            "generation_ms": dt * 1e3 + loss_ms + snes_ms,
             "workload": ("train3: random triclinic cells, 8-256 atoms, density 0.05-0.09 "
                          "atoms/A^3, 3 species; NEP r_c 6/3.5 A, n_max 12/8, N_bas 12/8, "
                          "l_max 4, 100 neurons per species; E, F, W per vector")}
