@@ -169,8 +169,9 @@ int nep_descriptors(nep_handle *h, int64_t n_atoms, const double *pos,
  * [3][N] (eV/A); virial_target [n_struct][6] (eV/atom) or NULL (no virial
  * term); params [P][n_par] or NULL (no regularisers; otherwise n_par must be
  * nep_num_params).  loss [P][6] receives [L, RMSE_e, RMSE_f, RMSE_v,
- * mean|z|, sqrt(mean z^2)]; absent terms read 0.  Sums are float64 in a fixed
- * order (same inputs, same bits).  Synchronous on `stream`. */
+ * mean|z|, sqrt(mean z^2)]; absent terms read 0.  1 <= n_param_sets <= 65535.
+ * Sums are float64 in a fixed order (same inputs, same bits).  Synchronous on
+ * `stream`. */
 int nep_batch_loss(nep_handle *h, int32_t n_struct, const int64_t *offsets, int32_t n_param_sets,
                    const double *params, int64_t n_par, const double *force, const double *totals,
                    const double *energy_target, const double *force_target,

@@ -1484,8 +1484,8 @@ int nep_batch_loss(nep_handle* h, int32_t n_struct, const int64_t* offsets, int3
                    const double lambda[5], double* loss, void* stream) {
   if (!h) return fail(nullptr, {NEP_E_INVALID_ARG, "handle is NULL"});
   try {
-    if (n_struct < 1 || n_param_sets < 1)
-      throw Failure{NEP_E_INVALID_ARG, "n_struct and n_param_sets must be >= 1"};
+    if (n_struct < 1 || n_param_sets < 1 || n_param_sets > 65535)
+      throw Failure{NEP_E_INVALID_ARG, "need n_struct >= 1 and 1 <= n_param_sets <= 65535"};
     if (!offsets || !force || !totals || !energy_target || !force_target || !lambda || !loss)
       throw Failure{NEP_E_INVALID_ARG,
                     "offsets, force, totals, energy_target, force_target, lambda and loss are required"};
