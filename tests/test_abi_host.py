@@ -86,3 +86,17 @@ def test_null_arguments():
     assert L.nep_compute(None, 1, None, None, None, None, None, None, None, None) == \
         nep.NEP_E_INVALID_ARG
     assert "NULL" in nep.last_error(None)
+
+
+def test_null_handle_on_new_entries():
+    L = nep.load()
+    assert L.nep_heat_current(None, 1, None, None, None, None, None, None, None) == \
+        nep.NEP_E_INVALID_ARG
+    assert L.nep_heat_current_dev(None, 1, None, None, None, None, None, None, None, None) == \
+        nep.NEP_E_INVALID_ARG
+    assert L.nep_batch_loss(None, 1, None, 1, None, 0, None, None, None, None, None, None, None,
+                            None) == nep.NEP_E_INVALID_ARG
+    assert L.nep_snes_step(None, 1, 2, None, None, None, None, 1, 1.0, 0.1, None) == \
+        nep.NEP_E_INVALID_ARG
+    assert L.nep_snes_sample(None, 1, 2, None, None, None, None, None) == nep.NEP_E_INVALID_ARG
+    assert "NULL" in nep.last_error(None)
