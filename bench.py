@@ -282,6 +282,42 @@ def cpu_baseline(h, params, seconds):
                         f"({dt:.1f} s); O(N^2) image pair search as written"))
 
 
+def heat_leg(nep, torch, h, params, pos, vel, types, box, reps=20):
+    """Per-atom heat current J_i = W_i . v_i (eq. Ji) of the 131k alloy at
+    300 K through nep_heat_current_dev: the whole call (a full evaluation and
+    the contraction) and the contraction kernel alone (HIP events), with its
+    algorithmic bytes (float32 virial 36 B, float64 velocity 24 B, index 4 B
+    read and J_i 24 B written per atom)."""
+    dev = torch.device("cuda:0")
+    n = pos.shape[1]
+    hd = nep.Handle(h, params)
+    pos_d, vel_d = torch.tensor(pos, device=dev), torch.tensor(vel, device=dev)
+    types_d = torch.tensor(types, device=dev)
+    heat = torch.empty(3, n, dtype=torch.float64, device=dev)
+    tot = torch.empty(3, dtype=torch.float64, device=dev)
+    hd.heat_current_dev(pos_d, vel_d, types_d, box, heat=heat, total=tot)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        hd.heat_current_dev(pos_d, vel_d, types_d, box, heat=heat, total=tot)
+    torch.cuda.synchronize()
+    call_ms = (time.perf_counter() - t0) / reps * 1e3
+    hd.set_timing(True)
+    for _ in range(reps):
+        hd.heat_current_dev(pos_d, vel_d, types_d, box, heat=heat, total=tot)
+    torch.cuda.synchronize()
+    st = hd.timing()
+    hd.set_timing(False)
+    hd.close()
+    del pos_d, vel_d, types_d, heat, tot
+    torch.cuda.empty_cache()
+    k = st.get("heat_current", (float("nan"), 1))
+    kernel_ms = k[0] / max(k[1], 1)
+    nbytes = 88 * n
+    return {"ms_per_call": call_ms, "kernel_ms": kernel_ms, "algorithmic_bytes": nbytes,
+            "kernel_GBps": nbytes / (kernel_ms * 1e-3) / 1e9, "atoms": n}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -317,6 +353,7 @@ def main():
         del pos_d, vel_d, types_d
         torch.cuda.empty_cache()
 
+    heat = heat_leg(nep, torch, h, params, pos, vel, types, box)
     dt, stages, th = results[nep.NEP_MLP_FP32]
     value = n * args.steps / dt
     fl = algorithmic_flops(h, p_r, p_a)
@@ -358,6 +395,7 @@ def main():
                          "avg_launch_ms": avg["mlp"]},
         "stages_ms_per_step": {k: v[0] / args.steps for k, v in stages.items()},
         "nve_drift_eV_per_atom": float(np.abs(e - e[0]).max() / n) if len(e) else None,
+        "heat_current": heat,
     }
     if nep.NEP_MLP_BF16 in results:
         dtb, stb, _ = results[nep.NEP_MLP_BF16]
