@@ -353,7 +353,10 @@ def main():
         del pos_d, vel_d, types_d
         torch.cuda.empty_cache()
 
-    heat = heat_leg(nep, torch, h, params, pos, vel, types, box)
+    try:
+        heat = heat_leg(nep, torch, h, params, pos, vel, types, box)
+    except nep.NepError as err:  # an auxiliary leg: report it, keep the MD line
+        heat = {"error": str(err)}
     dt, stages, th = results[nep.NEP_MLP_FP32]
     value = n * args.steps / dt
     fl = algorithmic_flops(h, p_r, p_a)
