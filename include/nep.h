@@ -134,7 +134,8 @@ int nep_heat_current(nep_handle *h, int64_t n_atoms, const double *pos, const do
 
 /* Same as nep_heat_current with pos, vel, types, heat and total in device
  * memory on `stream` (hipStream_t, NULL = default); box and pbc are host
- * arrays.  Returns after the work is enqueued. */
+ * arrays.  The velocity values are not inspected (non-finite velocities give
+ * non-finite currents).  Returns after the work is enqueued. */
 int nep_heat_current_dev(nep_handle *h, int64_t n_atoms, const double *pos, const double *vel,
                          const int32_t *types, const double box[9], const int32_t pbc[3],
                          double *heat, double *total, void *stream);
