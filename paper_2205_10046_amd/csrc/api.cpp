@@ -291,6 +291,8 @@ struct nep_handle {
   int64_t* loss_offs = nullptr;
   int64_t loss_part_cap = 0, loss_offs_cap = 0;
   double* snes_util = nullptr;     // [1024] SNES utilities of the last step
+  double* heat_part = nullptr;     // per-block heat-current sums
+  int64_t heat_part_cap = 0;
   DevModel& M = main.M;
   // workspace
   int64_t capN = 0, cap_part = 0, rows_cap = 0;
@@ -327,7 +329,8 @@ struct nep_handle {
   void release() {
     if (pinned) (void)hipHostFree(pinned);
     pinned = nullptr;
-    dev_free(loss_part); dev_free(loss_offs); dev_free(snes_util);
+    dev_free(loss_part); dev_free(loss_offs); dev_free(snes_util); dev_free(heat_part);
+    heat_part_cap = 0;
     loss_part_cap = loss_offs_cap = 0;
     main.release();
     for (auto& t : pop) t.release();
@@ -1314,8 +1317,15 @@ void heat_current_impl(nep_handle* h, int64_t N, const double* d_pos, const doub
                        double* d_heat, double* d_total, hipStream_t s) {
   if (!d_vel) throw Failure{NEP_E_INVALID_ARG, "velocities are required"};
   compute_impl(h, N, d_pos, d_types, box, pbc, nullptr, nullptr, nullptr, nullptr, s);
+  // one block of 256 threads per 256 atoms, each with its own partial row
+  const int64_t n_part = (N + 255) / 256;
+  if (3 * n_part > h->heat_part_cap) {
+    HIPCHK(hipStreamSynchronize(s));
+    dev_alloc(h->heat_part, (size_t)(3 * n_part));
+    h->heat_part_cap = 3 * n_part;
+  }
   Stage st(h, "heat_current", s);
-  launch_heat_current(h->W, N, h->perm, d_vel, d_heat, d_total, h->partial, num_partials(N), s);
+  launch_heat_current(h->W, N, h->perm, d_vel, d_heat, d_total, h->heat_part, n_part, s);
 }
 }  // namespace
 

@@ -200,13 +200,24 @@ __global__ void __launch_bounds__(kRedBlock) k_heat_current_partial(
   if (t < 3) partial[blockIdx.x * 3 + t] = sh[t][0];
 }
 
-__global__ void k_heat_current_final(const double* __restrict__ partial, int64_t n_part,
-                                     double* __restrict__ total) {
-  const int a = threadIdx.x;
-  if (a >= 3) return;
-  double s = 0.0;
-  for (int64_t b = 0; b < n_part; ++b) s += partial[b * 3 + a];
-  total[a] = s;
+// total[a] = sum_b partial[b][a]: thread t adds blocks t, t + kRedBlock, ...
+// in order, then a fixed tree over the threads (the same bits every call).
+__global__ void __launch_bounds__(kRedBlock) k_heat_current_final(const double* __restrict__ partial,
+                                                                  int64_t n_part,
+                                                                  double* __restrict__ total) {
+  __shared__ double sh[3][kRedBlock];
+  const int t = threadIdx.x;
+  double acc[3] = {0.0, 0.0, 0.0};
+  for (int64_t b = t; b < n_part; b += kRedBlock)
+    for (int a = 0; a < 3; ++a) acc[a] += partial[b * 3 + a];
+  for (int a = 0; a < 3; ++a) sh[a][t] = acc[a];
+  __syncthreads();
+  for (int off = kRedBlock / 2; off > 0; off >>= 1) {
+    if (t < off)
+      for (int a = 0; a < 3; ++a) sh[a][t] += sh[a][t + off];
+    __syncthreads();
+  }
+  if (t < 3) total[t] = sh[t][0];
 }
 
 void launch_heat_current(const float* W, int64_t N, const int32_t* perm, const double* vel,
@@ -215,7 +226,7 @@ void launch_heat_current(const float* W, int64_t N, const int32_t* perm, const d
   const int64_t chunk = (N + n_part - 1) / n_part;
   hipLaunchKernelGGL(k_heat_current_partial, dim3((unsigned)n_part), dim3(kRedBlock), 0, s, W, N,
                      perm, vel, chunk, heat, partial);
-  if (total) hipLaunchKernelGGL(k_heat_current_final, dim3(1), dim3(64), 0, s, partial, n_part, total);
+  if (total) hipLaunchKernelGGL(k_heat_current_final, dim3(1), dim3(kRedBlock), 0, s, partial, n_part, total);
 }
 
 }  // namespace nep
