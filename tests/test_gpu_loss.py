@@ -108,3 +108,32 @@ def test_loss_rejects_bad_offsets(setup):
     out = torch.zeros(st["pop"].shape[0], 6, dtype=torch.float64, device="cuda:0")
     with pytest.raises(nep.NepError):
         st["handle"].batch_loss(bad, st["f"], st["t"], st["tg"]["e"], st["tg"]["f"], LAM, out)
+
+
+def test_loss_single_structure():
+    """A batch of one structure and one parameter set: RMSEs over one energy."""
+    import torch
+    h = synth.WORKLOADS["train3"]
+    structs = synth.random_structures(1, 20, 20, seed=44)
+    pos, types, boxes, offs = synth.concat_structures(structs)
+    z = synth.random_params(O.num_params(h), seed=45)
+    teacher = synth.random_params(O.num_params(h), seed=46)
+    e_t, f_t, w_t = O.predictions(h, teacher, structs)
+    handle = nep.Handle(h, z)
+    dev = torch.device("cuda:0")
+    n = pos.shape[1]
+    f = torch.zeros(1, 3, n, dtype=torch.float64, device=dev)
+    t = torch.zeros(1, 1, 10, dtype=torch.float64, device=dev)
+    handle.compute_batch(offs, torch.tensor(pos, device=dev), torch.tensor(types, device=dev),
+                         boxes, z[None, :], None, f, None, t)
+    out = torch.zeros(1, 6, dtype=torch.float64, device=dev)
+    handle.batch_loss(offs, f, t, torch.tensor(e_t, device=dev), torch.tensor(f_t, device=dev),
+                      LAM, out, virial_target=torch.tensor(w_t, device=dev),
+                      params=torch.tensor(z[None, :], device=dev))
+    torch.cuda.synchronize()
+    got = out.cpu().numpy()[0]
+    ref = O.loss_terms(*O.predictions(h, z, structs), e_t, f_t, w_t, z, LAM)
+    d = np.abs(got - ref)
+    log(f"[loss] single structure: L={got[0]:.6f} oracle {ref[0]:.6f}")
+    assert d[1] <= TOL_E and d[2] <= TOL_F and d[3] <= TOL_E
+    handle.close()

@@ -31,7 +31,7 @@ def _t(a):
     return torch.tensor(np.ascontiguousarray(a), dtype=torch.float64, device="cuda:0")
 
 
-@pytest.mark.parametrize("P,stride", [(50, 1), (7, 6), (2, 1)])
+@pytest.mark.parametrize("P,stride", [(50, 1), (7, 6), (2, 1), (1024, 1)])
 def test_snes_step_matches_oracle(handle, P, stride):
     import torch
     h, _, hd = handle
