@@ -670,6 +670,109 @@ def test_nve_time_reversibility(nve_setup):
     np.testing.assert_allclose(-v2, vel, atol=1e-11)
 
 
+# Units of the integrator, pinned by numbers typed here rather than by the
+# CODATA expression the oracle, the library and the input generator evaluate:
+# 1 amu (A/fs)^2 = 103.642697 eV, and k_B = 8.617333e-5 eV/K.  Energy
+# conservation, dt^2 scaling and reversibility hold for any value of the
+# conversion factor, so these tests are what fixes it.
+AMU_A2FS2_EV_LITERAL = 103.642697
+KB_LITERAL = 8.617333e-5
+
+
+def test_nve_one_step_kinematics_literal_units():
+    """From rest, one velocity-Verlet step moves atom i by dt^2/2 F_i / m_i and
+    leaves v_i = dt/2 (F_i(0) + F_i(1)) / m_i, with m in eV fs^2/A^2 by the
+    literal factor.  A factor off by 1e-4 relative fails by two orders."""
+    h = hp(n_types=2)
+    p = synth.random_params(O.num_params(h), seed=5)
+    pos, types, box = small_cell(n=10, ntypes=2, seed=4)
+    m = np.array([12.011, 28.085])
+    dt = 5.0
+    f0 = O.evaluate(h, p, pos, types, box)["F"]
+    p1, v1, _ = O.md_nve(h, p, pos, np.zeros_like(pos), types, m, box, dt, 1, 0)
+    f1 = O.evaluate(h, p, p1, types, box)["F"]
+    meff = m[types][None, :] * AMU_A2FS2_EV_LITERAL
+    dpos = 0.5 * dt * dt * f0 / meff
+    np.testing.assert_allclose(p1 - pos, dpos, rtol=1e-6, atol=1e-6 * np.abs(dpos).max())
+    np.testing.assert_allclose(v1, 0.5 * dt * (f0 + f1) / meff, rtol=1e-6,
+                               atol=1e-6 * np.abs(v1).max())
+    assert np.abs(dpos).max() > 1e-5   # the check is not vacuous
+
+
+def _dimer_energy(h, p, r, mtype=0):
+    box = np.array([40.0, 0, 0, 0, 40.0, 0, 0, 0, 40.0])
+    pos = np.array([[20.0, 20.0 + r], [20.0, 20.0], [20.0, 20.0]])
+    res = O.evaluate(h, p, pos, np.full(2, mtype, np.int32), box, pbc=[0, 0, 0])
+    return res["U"].sum(), res["F"][0, 1]
+
+
+def test_nve_dimer_period_literal_units():
+    """A dimer released near a minimum r0 of its energy oscillates with the
+    harmonic period 2 pi sqrt(mu / k): mu the reduced mass in amu times the
+    literal factor, k = -dF/dr by central differences of the oracle's pinned
+    force.  The period is read from the zero crossings of r(t) - r0."""
+    h = hp(n_types=1, l_max_4b=0, l_max_5b=0)
+    found = None
+    for seed in range(40):
+        p = synth.random_params(O.num_params(h), seed=seed)
+        rs = np.linspace(1.0, 3.2, 89)
+        F = np.array([_dimer_energy(h, p, r)[1] for r in rs])
+        # force on the second atom along +x: a minimum is where F goes + -> -
+        for k in range(len(rs) - 1):
+            if F[k] > 0 >= F[k + 1]:
+                lo, hi = rs[k], rs[k + 1]
+                for _ in range(60):
+                    mid = 0.5 * (lo + hi)
+                    if _dimer_energy(h, p, mid)[1] > 0:
+                        lo = mid
+                    else:
+                        hi = mid
+                r0 = 0.5 * (lo + hi)
+                dr = 1e-4
+                kk = -(_dimer_energy(h, p, r0 + dr)[1] - _dimer_energy(h, p, r0 - dr)[1]) / (2 * dr)
+                if kk > 0.03:
+                    found = (p, r0, kk)
+                    break
+        if found:
+            break
+    assert found, "no dimer minimum with a usable curvature"
+    p, r0, kk = found
+    mass = 12.011
+    mu = 0.5 * mass * AMU_A2FS2_EV_LITERAL
+    period = 2 * math.pi * math.sqrt(mu / kk)
+    dt = period / 400.0
+    amp = 0.004
+    box = np.array([40.0, 0, 0, 0, 40.0, 0, 0, 0, 40.0])
+    pos = np.array([[20.0, 20.0 + r0 + amp], [20.0, 20.0], [20.0, 20.0]])
+    vel = np.zeros_like(pos)
+    xs = []
+    for _ in range(1000):
+        pos, vel, _ = O.md_nve(h, p, pos, vel, np.zeros(2, np.int32), [mass], box, dt, 1, 0,
+                               pbc=[0, 0, 0])
+        xs.append(pos[0, 1] - pos[0, 0] - r0)
+    xs = np.array(xs)
+    t = dt * np.arange(1, len(xs) + 1)
+    cross = [t[k] - xs[k] * dt / (xs[k + 1] - xs[k])
+             for k in range(len(xs) - 1) if xs[k] > 0 >= xs[k + 1]]
+    assert len(cross) >= 2
+    measured = (cross[-1] - cross[0]) / (len(cross) - 1)
+    assert measured == pytest.approx(period, rel=2e-3), (measured, period)
+
+
+def test_thermo_row_units_literal(nve_setup):
+    """The thermo row's kinetic energy and temperature from the returned
+    velocities with the literal factor and k_B, 3N - 3 degrees of freedom."""
+    h, p, pos, vel, types, m, box = nve_setup
+    n = pos.shape[1]
+    _, v1, th = O.md_nve(h, p, pos, vel, types, m, box, 1.0, 4, 4)
+    ek = 0.5 * (m[types][None, :] * v1 ** 2).sum() * AMU_A2FS2_EV_LITERAL
+    assert th[0, 2] == pytest.approx(ek, rel=1e-6)
+    assert th[0, 3] == pytest.approx(2 * ek / ((3 * n - 3) * KB_LITERAL), rel=1e-6)
+    # the input velocities themselves are at 300 K by the same literal units
+    ek0 = 0.5 * (m[types][None, :] * vel ** 2).sum() * AMU_A2FS2_EV_LITERAL
+    assert 2 * ek0 / ((3 * n - 3) * KB_LITERAL) == pytest.approx(300.0, rel=1e-6)
+
+
 # ---------------------------------------------------------------------------
 # training loss (Sec. II.E, eq. loss)
 # ---------------------------------------------------------------------------
