@@ -156,19 +156,32 @@ int nep_descriptors(nep_handle *h, int64_t n_atoms, const double *pos,
                     const int32_t *types, const double box[9], const int32_t pbc[3],
                     double *q);
 
+/* Latent-space vectors (Sec. IV, the active-learning scheme): for every atom
+ * the N_neu products w1_mu h_mu of the hidden-layer states
+ * h_mu = tanh(sum_nu w0_{mu nu} q_nu - b0_mu) and their weights to the
+ * output (eq. Ui), so that sum_mu latent[i][mu] - b1 = U_i.  Host pointers:
+ * latent [N][N_neu] float64, in the caller's atom order, computed with the
+ * float32 or bf16 network the handle was created with.  A structure's vector
+ * is the mean (or sum) of its atoms' rows.  Synchronous. */
+int nep_latent(nep_handle *h, int64_t n_atoms, const double *pos, const int32_t *types,
+               const double box[9], const int32_t pbc[3], double *latent);
+
 /* Training loss of eq. loss (Sec. II.E) for each of n_param_sets parameter
  * vectors, from the outputs of nep_compute_batch on the same structures:
  *   L = l_e RMSE(energy per atom over structures)
  *     + l_f RMSE(force components over the 3N components)
- *     + l_v RMSE(virial per atom over structures and the six components
- *                xx, yy, zz, xy, yz, zx)
+ *     + l_v RMSE(virial per atom over the structures that have virial
+ *                targets and the six components xx, yy, zz, xy, yz, zx)
  *     + l_1 mean|z| + l_2 sqrt(mean z^2),  lambda = {l_e, l_f, l_v, l_1, l_2}.
  * offsets (host, int64[n_struct+1], offsets[0] = 0, every structure >= 1
  * atom) and lambda (host, [5]) are host arrays; all others are device
  * pointers: force [P][3][N] and totals [P][n_struct][10] as written by
  * nep_compute_batch; energy_target [n_struct] (eV/atom); force_target
  * [3][N] (eV/A); virial_target [n_struct][6] (eV/atom) or NULL (no virial
- * term); params [P][n_par] or NULL (no regularisers; otherwise n_par must be
+ * term); a structure whose row holds a NaN has no virial target (training
+ * sets give virials for some structures only), and the virial RMSE is
+ * normalised by 6 times the number of structures that have one (0 if none);
+ * params [P][n_par] or NULL (no regularisers; otherwise n_par must be
  * nep_num_params).  loss [P][6] receives [L, RMSE_e, RMSE_f, RMSE_v,
  * mean|z|, sqrt(mean z^2)]; absent terms read 0.  1 <= n_param_sets <= 65535.
  * Sums are float64 in a fixed order (same inputs, same bits).  Synchronous on
@@ -185,13 +198,15 @@ int nep_batch_loss(nep_handle *h, int32_t n_struct, const int64_t *offsets, int3
  * z_k = mean + sigma * noise[k] (see nep_snes_sample) with standard-normal
  * noise [n_pop][n_par] supplied by the caller.  Member k's loss is
  * loss[k * loss_stride] (so the [P][6] output of nep_batch_loss can be passed
- * with stride 6); members are ranked by loss, ties to the lower index, and
- * rank r gets the utility max(0, ln(P/2+1) - ln(r+1)) / sum - 1/P.  Then
+ * with stride 6); members are ranked by loss, ties to the lower index, with
+ * every non-finite loss (NaN or Inf: a diverged member) ranked after all
+ * finite ones, and rank r gets the utility max(0, ln(P/2+1) - ln(r+1)) / sum
+ * - 1/P.  Then
  *   mean  += eta_mu * sigma * sum_k u_k noise[k]
  *   sigma *= exp(eta_sigma / 2 * sum_k u_k (noise[k]^2 - 1))
  * in place.  The usual rates are eta_mu = 1 and
  * eta_sigma = (3 + ln n_par) / (5 sqrt n_par).  All arrays are device
- * pointers; losses must be finite (the rank of a NaN is unspecified).
+ * pointers.
  * 2 <= n_pop <= 1024.  Asynchronous on `stream`; calls on one handle share a
  * small utility buffer and must not overlap. */
 int nep_snes_step(nep_handle *h, int64_t n_par, int32_t n_pop, double *mean, double *sigma,

@@ -636,6 +636,24 @@ double ora_ann(const ora_hparams *h, const double *params, int type, const doubl
   return U - params[M.b1];
 }
 
+/* Latent-space vector of one site (Sec. IV): the N_neu products of the
+ * hidden-layer states h_mu of eq. (Ui) and their output weights w1_mu, so
+ * that sum_mu lat_mu - b1 = U. */
+void ora_latent(const ora_hparams *h, const double *params, int type, const double *q,
+                double *lat) {
+  ora_model M;
+  model_init(&M, h, params);
+  int net = h->nn_per_type ? type : 0;
+  const double *w0 = params + (int64_t)net * (M.nd + 2) * M.nneu;
+  const double *b0 = w0 + (int64_t)M.nneu * M.nd;
+  const double *w1 = b0 + M.nneu;
+  for (int mu = 0; mu < M.nneu; ++mu) {
+    double a = 0.0;
+    for (int v = 0; v < M.nd; ++v) a += w0[mu * M.nd + v] * q[v];
+    lat[mu] = w1[mu] * tanh(a - b0[mu]);
+  }
+}
+
 /* D_{n,k} = dU/dS_{n,k} through q_{nl}, q_{n222} and q_{n1111}. */
 static void site_dUdS(const ora_hparams *h, const ora_model *M, const double *S,
                       const double *Fp, double *D) {

@@ -71,6 +71,8 @@ def lib():
         L.ora_coefficients.restype = None
         L.ora_ann.argtypes = [hp, pd, C.c_int, pd, pd]
         L.ora_ann.restype = d
+        L.ora_latent.argtypes = [hp, pd, C.c_int, pd, pd]
+        L.ora_latent.restype = None
         L.ora_evaluate.argtypes = [hp, pd, i64, pd, pi32, pd, pi32, pd, pd,
                                    pd, pd]
         L.ora_heat_current.argtypes = [hp, pd, i64, pd, pd, pi32, pd, pi32,
@@ -184,6 +186,22 @@ def ann(h, params, type_, q):
     u = lib().ora_ann(C.byref(_hp(h)), _p(params, C.c_double), int(type_),
                       _p(q, C.c_double), _p(fp, C.c_double))
     return u, fp
+
+
+def latent(h, params, pos, types, box, pbc=None):
+    """Per-atom latent-space vectors (Sec. IV), (N, N_neu): the descriptors
+    of each site through the hidden layer, times the output weights."""
+    q = descriptors(h, params, pos, types, box, pbc)
+    params = _f64(params)
+    types = _i32(types)
+    out = np.zeros((q.shape[0], h["n_neurons"]))
+    for i in range(q.shape[0]):
+        qi = np.ascontiguousarray(q[i])
+        li = np.zeros(h["n_neurons"])
+        lib().ora_latent(C.byref(_hp(h)), _p(params, C.c_double), int(types[i]),
+                         _p(qi, C.c_double), _p(li, C.c_double))
+        out[i] = li
+    return out
 
 
 def evaluate(h, params, pos, types, box, pbc=None, want_q=False):
@@ -305,7 +323,9 @@ VIRIAL6 = (0, 4, 8, 1, 5, 6)
 def loss_terms(e_pred, f_pred, w_pred, e_tar, f_tar, w_tar, z, lam):
     """Eq. loss written out.  e_* (S,) energy per atom of each structure,
     f_* (3, N) forces, w_* (S, 6) virial per atom in VIRIAL6 order (w_tar None:
-    no virial term), z (N_par,) parameters, lam (lambda_e, lambda_f, lambda_v,
+    no virial term; a target row with a NaN: that structure has no virial, and
+    the virial RMSE runs over the others), z (N_par,) parameters, lam
+    (lambda_e, lambda_f, lambda_v,
     lambda_1, lambda_2).  Returns [L, L_e, L_f, L_v, L_1, L_2] where L is the
     weighted sum and the others are the unweighted terms (RMSEs and norms)."""
     e_pred, e_tar = np.asarray(e_pred, float), np.asarray(e_tar, float)
@@ -316,8 +336,12 @@ def loss_terms(e_pred, f_pred, w_pred, e_tar, f_tar, w_tar, z, lam):
     lf = math.sqrt(float(((f_pred - f_tar) ** 2).sum()) / (3 * N))
     lv = 0.0
     if w_tar is not None:
-        d = np.asarray(w_pred, float) - np.asarray(w_tar, float)
-        lv = math.sqrt(float((d ** 2).sum()) / (6 * S))
+        # a structure whose virial target row holds a NaN has no virial target
+        w_tar = np.asarray(w_tar, float)
+        have = [n for n in range(S) if not np.isnan(w_tar[n]).any()]
+        if have:
+            d = np.asarray(w_pred, float)[have] - w_tar[have]
+            lv = math.sqrt(float((d ** 2).sum()) / (6 * len(have)))
     l1 = float(np.abs(z).sum()) / npar
     l2 = math.sqrt(float((z ** 2).sum()) / npar)
     total = lam[0] * le + lam[1] * lf + lam[2] * lv + lam[3] * l1 + lam[4] * l2
@@ -360,10 +384,18 @@ def snes_utilities(n_pop):
 
 
 def snes_ranks(losses):
-    """Rank of each member, 0 for the smallest loss; ties go to the lower index."""
-    L = list(losses)
-    return np.array([sum(1 for j in range(len(L)) if L[j] < L[k] or (L[j] == L[k] and j < k))
-                     for k in range(len(L))])
+    """Rank of each member, 0 for the smallest loss; ties go to the lower
+    index; a non-finite loss (NaN, Inf: a diverged member) ranks after every
+    finite one, non-finite ones among themselves by index."""
+    L = [float(x) for x in losses]
+
+    def key(k):
+        return (0, L[k], k) if math.isfinite(L[k]) else (1, 0.0, k)
+    order = sorted(range(len(L)), key=key)
+    ranks = np.zeros(len(L), dtype=int)
+    for r, k in enumerate(order):
+        ranks[k] = r
+    return ranks
 
 
 def snes_step(mean, sigma, noise, losses, eta_mu, eta_sigma):

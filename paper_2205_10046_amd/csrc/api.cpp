@@ -709,6 +709,15 @@ Prepared prepare(nep_handle* h, int64_t N, const double* box, const int32_t* pbc
   return prepare_batch(h, 1, offs, box, pbc, r_list, md, false, s);
 }
 
+// The evaluation kernels index their buffers through the rows; a row that
+// breaks one of the invariants k_check_rows tests would send them out of
+// bounds, so it stops the call before any of them runs.
+void check_row_flag(int32_t bits) {
+  if (bits)
+    throw Failure{NEP_E_HIP, "internal error: neighbour rows break an indexing invariant (bits " +
+                                 std::to_string(bits) + ")"};
+}
+
 // Rows for the current internal positions; grows the capacities (auto mode)
 // or fails (fixed capacities) when a row overflows.  Synchronises once.
 void build_rows_checked(nep_handle* h, const Prepared& pp, const BuildArgs& b, hipStream_t s,
@@ -724,6 +733,7 @@ void build_rows_checked(nep_handle* h, const Prepared& pp, const BuildArgs& b, h
       Stage st(h, "neighbor_rows", s);
       launch_build_rows(b, pp.geo.st, pp.batch, h->V, h->L, s);
     }
+    launch_check_rows(pp.N, h->sid, h->structs, pp.geo.st, pp.batch, h->L, h->flags + 6, s);
     int32_t* fl = (int32_t*)(h->pinned + 384);
     HIPCHK(hipMemcpyAsync(fl, h->flags, 8 * sizeof(int32_t), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
@@ -734,6 +744,7 @@ void build_rows_checked(nep_handle* h, const Prepared& pp, const BuildArgs& b, h
     if (fl[0] == 0 && fl[1] == 0) {
       // without truncated rows every entry has its reverse entry
       if (fl[2]) throw Failure{NEP_E_HIP, "internal error: neighbour rows are not symmetric"};
+      check_row_flag(fl[6]);
       return;
     }
     const bool fixed = h->hp.max_nb_radial || h->hp.max_nb_angular;
@@ -1510,7 +1521,7 @@ int nep_batch_loss(nep_handle* h, int32_t n_struct, const int64_t* offsets, int3
     set_device(h);
     hipStream_t s = (hipStream_t)stream;
     const int64_t N = offsets[n_struct];
-    const int64_t need_part = (int64_t)n_param_sets * loss_chunks(N) * 5;
+    const int64_t need_part = (int64_t)n_param_sets * loss_chunks(N) * 6;  // six sums per chunk
     if (need_part > h->loss_part_cap) {
       HIPCHK(hipStreamSynchronize(s));
       dev_alloc(h->loss_part, (size_t)need_part);
@@ -1656,6 +1667,44 @@ int nep_descriptors(nep_handle* h, int64_t N, const double* pos, const int32_t* 
   return NEP_OK;
 }
 
+int nep_latent(nep_handle* h, int64_t N, const double* pos, const int32_t* types, const double box[9],
+               const int32_t pbc[3], double* latent) {
+  if (!h) return fail(nullptr, {NEP_E_INVALID_ARG, "handle is NULL"});
+  if (!pos || !types || !box || !latent) return fail(h, {NEP_E_INVALID_ARG, "bad arguments"});
+  float* d_lat = nullptr;
+  double* d_out = nullptr;
+  try {
+    set_device(h);
+    if (N < 1) throw Failure{NEP_E_INVALID_ARG, "n_atoms must be >= 1"};
+    check_host_types(h, N, types);
+    check_host_finite(3 * N, pos, "positions");
+    hipStream_t s = nullptr;
+    Prepared pp = prepare(h, N, box, pbc, h->hp.rc_radial, false, s);
+    HIPCHK(hipMemcpyAsync(h->pos_ext, pos, 3 * N * sizeof(double), hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(h->types_ext, types, N * sizeof(int32_t), hipMemcpyHostToDevice, s));
+    order_and_build(h, pp, h->pos_ext, h->types_ext, s, true);
+    autotune(h, pp, s);
+    const int NN = h->hp.n_neurons;
+    dev_alloc(d_lat, (size_t)N * NN);
+    dev_alloc(d_out, (size_t)N * NN);
+    EvalArgs a = eval_args(h, pp, h->M);
+    set_groups(a, h->tune[0].NG_desc, h->tune[0].block_desc, h->M.nA, h->tune[0].lanes_desc);
+    if (!launch_descriptor(a, s)) throw Failure{NEP_E_UNSUPPORTED, "no descriptor kernel for this shape"};
+    a.latent = d_lat;
+    launch_mlp(a, s);
+    launch_descriptors_out(d_lat, N, NN, NN, h->perm, d_out, s);
+    HIPCHK(hipMemcpyAsync(latent, d_out, (size_t)N * NN * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    dev_free(d_lat);
+    dev_free(d_out);
+  } catch (const Failure& f) {
+    dev_free(d_lat);
+    dev_free(d_out);
+    return fail(h, f);
+  }
+  return NEP_OK;
+}
+
 namespace {
 
 // Rebuild now from the current internal state: re-sort into cell order
@@ -1732,11 +1781,14 @@ int md_skin(nep_handle* h, const Prepared& pp, double* d_pos, double* d_vel, con
     launch_fill_i32(h->flags + 5, 1, 0, s);
     skin_rebuild(h, pp, rl, nullptr, s);
     skin_filter(h, pp, s);
+    launch_fill_i32(h->flags + 6, 1, 0, s);
+    launch_check_rows(N, h->sid, h->structs, pp.geo.st, pp.batch, h->L, h->flags + 6, s);
     const int32_t* fl = read_flags(h, s);
     if (fl[3]) throw Failure{NEP_E_INVALID_ARG, "an atom type is out of range"};
     if (fl[4]) throw Failure{NEP_E_NONFINITE, "positions contain NaN or Inf"};
     if (!grow_rows(h, N, fl)) {
       if (fl[2]) throw Failure{NEP_E_HIP, "internal error: neighbour rows are not symmetric"};
+      check_row_flag(fl[6]);
       break;
     }
     if (attempt == 3) throw Failure{NEP_E_NEIGHBOR_OVERFLOW, "neighbour rows kept overflowing"};
@@ -1862,6 +1914,7 @@ int md_skin(nep_handle* h, const Prepared& pp, double* d_pos, double* d_vel, con
       }
     }
     launch_check_finite(h->pos, 3 * N, h->flags + 4, s);
+    launch_check_rows(N, h->sid, h->structs, pp.geo.st, pp.batch, h->L, h->flags + 6, s);
     const int32_t* fl = read_flags(h, s);
     if (fl[4]) throw Failure{NEP_E_NONFINITE, "positions became non-finite during the run"};
     if (grow_rows(h, N, fl)) {
@@ -1877,6 +1930,7 @@ int md_skin(nep_handle* h, const Prepared& pp, double* d_pos, double* d_vel, con
       continue;
     }
     if (fl[2]) throw Failure{NEP_E_HIP, "internal error: neighbour rows are not symmetric"};
+    check_row_flag(fl[6]);
     c0 = c1;
   }
   launch_unpermute_md(h->ext_id, N, h->pos, h->vel, d_pos, d_vel, s);
@@ -1990,6 +2044,7 @@ static int md_impl(nep_handle* h, int64_t N, double* d_pos, double* d_vel, const
       }
     }
     launch_check_finite(h->pos, 3 * N, h->flags + 4, s);
+    launch_check_rows(N, h->sid, h->structs, pp.geo.st, pp.batch, h->L, h->flags + 6, s);
     int32_t* fl = (int32_t*)(h->pinned + 384);
     HIPCHK(hipMemcpyAsync(fl, h->flags, 8 * sizeof(int32_t), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
@@ -1997,6 +2052,7 @@ static int md_impl(nep_handle* h, int64_t N, double* d_pos, double* d_vel, const
     fl[0] = std::max(fl[0], fl[5]);  // candidate rows at r_c^R: the same count
     if (fl[2] && !(fl[0] || fl[1]))
       throw Failure{NEP_E_HIP, "internal error: neighbour rows are not symmetric"};
+    if (!(fl[0] || fl[1])) check_row_flag(fl[6]);
     if (fl[0] || fl[1]) {
       if (h->hp.max_nb_radial || h->hp.max_nb_angular)
         throw Failure{NEP_E_NEIGHBOR_OVERFLOW, "neighbour row overflow during the run"};

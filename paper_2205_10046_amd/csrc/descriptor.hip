@@ -665,31 +665,36 @@ int angular_group_size(int nA, int L) {
 }
 
 template <int NG, int L, bool BATCH, int G>
-static void launch_pair_g(const EvalArgs& a, const StructInfo& st0, bool force, hipStream_t s) {
+static bool launch_pair_g(const EvalArgs& a, const StructInfo& st0, bool force, hipStream_t s) {
   const int block = a.block > 0 ? a.block : kBlock;
   const size_t lds = eval_lds_bytes(a.M, block);
+  // the kernels' LDS layout: radial table, the angular table of this group
+  // size, then T K_R per-lane slots; refuse a shape it does not fit
+  const DevModel& M = a.M;
+  if (M.cA_off[NG] < 0 || block % 64 != 0 || block > kBlock) return false;
+  const size_t need = ((size_t)round4(M.T * M.T * M.nR * M.KR) + (size_t)round4(M.T * M.T * M.cA_pair[NG]) +
+                       (size_t)M.T * M.KR * block) * sizeof(float);
+  if (need > lds || lds > 64 * 1024) return false;
   dim3 grid((unsigned)div_up(a.N * G, block));
   if (force)
     hipLaunchKernelGGL((k_partial_forces<NG, L, BATCH, G>), grid, dim3(block), lds, s, a, st0);
   else
     hipLaunchKernelGGL((k_descriptor<NG, L, BATCH, G>), grid, dim3(block), lds, s, a, st0);
+  return true;
 }
 
 template <int NG, int L, bool BATCH>
-static void launch_pair(const EvalArgs& a, const StructInfo& st0, bool force, hipStream_t s) {
-  if (a.lanes == 4) launch_pair_g<NG, L, BATCH, 4>(a, st0, force, s);
-  else launch_pair_g<NG, L, BATCH, 1>(a, st0, force, s);
+static bool launch_pair(const EvalArgs& a, const StructInfo& st0, bool force, hipStream_t s) {
+  if (a.lanes == 4) return launch_pair_g<NG, L, BATCH, 4>(a, st0, force, s);
+  return launch_pair_g<NG, L, BATCH, 1>(a, st0, force, s);
 }
 
 template <bool BATCH>
 static bool dispatch(const EvalArgs& a, const StructInfo& st0, bool force, hipStream_t s) {
   const int L = a.M.L, NG = a.NG;
   if (a.lanes != 1 && a.lanes != 4) return false;
-#define NEP_CASE(ng, l)                                  \
-  if (NG == ng && L == l) {                              \
-    launch_pair<ng, l, BATCH>(a, st0, force, s);         \
-    return true;                                         \
-  }
+#define NEP_CASE(ng, l) \
+  if (NG == ng && L == l) return launch_pair<ng, l, BATCH>(a, st0, force, s);
   NEP_CASE(2, 1) NEP_CASE(4, 1) NEP_CASE(5, 1) NEP_CASE(7, 1)
   NEP_CASE(2, 2) NEP_CASE(4, 2) NEP_CASE(5, 2) NEP_CASE(7, 2)
   NEP_CASE(2, 3) NEP_CASE(4, 3) NEP_CASE(5, 3) NEP_CASE(7, 3)

@@ -125,17 +125,24 @@ __global__ void __launch_bounds__(256) k_mlp(EvalArgs a) {
       b0v[nb][r] = b0[mu];
       w1v[nb][r] = w1[mu];
     }
+  // the latent-space vector of Sec. IV is the products w1_mu h_mu, one per
+  // neuron, written when asked for
+  float* __restrict__ lat = (a.latent && atom >= 0) ? a.latent + (int64_t)atom * M.NN : nullptr;
 #pragma unroll
   for (int nb = 0; nb < NNB; ++nb)
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       const float h = tanhf(acc[nb][r] - b0v[nb][r]);
-      u += w1v[nb][r] * h;
+      const float wh = w1v[nb][r] * h;
+      u += wh;
       g[nb][r] = w1v[nb][r] * (1.f - h * h);
+      const int mu = 16 * nb + 4 * grp + r;
+      if (lat && mu < M.NN) lat[mu] = wh;
     }
   u += __shfl_xor(u, 16);
   u += __shfl_xor(u, 32);
   if (grp == 0 && atom >= 0) a.U[atom] = u - M.b1;
+
 
   // ---- GEMM 2: dU/dq[atom][d] = sum_mu G[atom][mu] w0[mu][d] ----
   int out_atom[4];

@@ -626,6 +626,59 @@ __global__ void __launch_bounds__(kBlock) k_reverse_from_candidates(int64_t N, L
   if (broken) atomicExch(err, 1);
 }
 
+// Checks, for every atom i of the exact rows, the invariants under which the
+// evaluation kernels only touch memory inside their buffers: nnA <= nnR <= MR;
+// every neighbour j lies in i's structure; its reverse position r lies in
+// j's row (r < nnR[j]) and that entry points back to i with the opposite
+// image code; image codes stay within the structure's image reach.  Any
+// violation sets a bit of *bad (1: counts, 2: neighbour index, 4: reverse
+// position, 8: reverse entry, 16: image code); rows that overflowed their
+// capacity are reported by the overflow flags instead.
+__global__ void __launch_bounds__(kBlock) k_check_rows(int64_t N, const int32_t* __restrict__ sid,
+                                                       const StructInfo* __restrict__ structs,
+                                                       StructInfo st0, int32_t batch, Lists L,
+                                                       int32_t* __restrict__ bad) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= N) return;
+  const StructInfo& st = batch ? structs[sid[i]] : st0;
+  const int nn = L.nnR[i], na = L.nnA[i];
+  if (nn > L.MR) return;  // overflow: reported and handled by the caller
+  int32_t b = 0;
+  if (na < 0 || nn < 0 || na > nn) b |= 1;
+  const bool images = st.mode == kModeImages;
+  const int64_t lo = st.start, hi = st.start + st.count;
+  for (int m = 0; m < max(nn, 0) && !(b & 6); ++m) {
+    const int64_t e = (int64_t)m * N + i;
+    const int32_t j = L.nlR[e];
+    if (j < lo || j >= hi) {
+      b |= 2;
+      break;
+    }
+    const int32_t r = L.revR[e];
+    const int nj = L.nnR[j];
+    if (r < 0 || r >= min(nj, L.MR)) {
+      b |= 4;
+      break;
+    }
+    const int64_t er = (int64_t)r * N + j;
+    if (L.nlR[er] != (int32_t)i) b |= 8;
+    if (images) {
+      int oa, ob, oc, ra, rb, rc;
+      split_code(L.cdR[e], oa, ob, oc);
+      split_code(L.cdR[er], ra, rb, rc);
+      if (oa != -ra || ob != -rb || oc != -rc) b |= 8;
+      if (abs(oa) > st.reach[0] || abs(ob) > st.reach[1] || abs(oc) > st.reach[2]) b |= 16;
+    }
+  }
+  if (b) atomicOr(bad, b);
+}
+
+void launch_check_rows(int64_t N, const int32_t* sid, const StructInfo* structs, const StructInfo& st0,
+                       bool batch, const Lists& L, int32_t* bad, hipStream_t s) {
+  hipLaunchKernelGGL(k_check_rows, grid_for(N), dim3(kBlock), 0, s, N, sid, structs, st0,
+                     (int32_t)(batch ? 1 : 0), L, bad);
+}
+
 void launch_filter_rows(const BuildArgs& b, const StructInfo& st0, bool batch, const Lists& V,
                         const Lists& L, hipStream_t s) {
   const dim3 grid = grid_for(b.N * kFilterLanes);

@@ -236,15 +236,19 @@ namespace nep {
 // Training loss of Sec. II.E (eq. loss) for P parameter sets from the batch
 // outputs.  Block (c, p) takes chunk c of the structures (energy per atom and
 // the six virial components per atom), of the 3N force components and of the
-// parameters of set p, and writes its five fixed-tree sums
-// [sum de^2, sum df^2, sum dw^2, sum |z|, sum z^2] to partial[p][c][5].
+// parameters of set p, and writes its six fixed-tree sums
+// [sum de^2, sum df^2, sum dw^2, sum |z|, sum z^2, structures with a virial]
+// to partial[p][c][6].  A structure whose six virial targets include a NaN
+// has no virial target: it adds nothing to sum dw^2 and is not counted.
+constexpr int kLossSums = 6;
+
 struct LossArgs {
   const double* force;    // [P][3][N]
   const double* totals;   // [P][S][10]
   const int64_t* offs;    // [S + 1]
   const double* e_tar;    // [S] eV/atom
   const double* f_tar;    // [3][N]
-  const double* w_tar;    // [S][6] eV/atom (xx, yy, zz, xy, yz, zx) or NULL
+  const double* w_tar;    // [S][6] eV/atom (xx, yy, zz, xy, yz, zx) or NULL; NaN rows absent
   const double* params;   // [P][npar] or NULL
   int64_t N, npar;
   int32_t S;
@@ -252,10 +256,10 @@ struct LossArgs {
 };
 
 __global__ void __launch_bounds__(kRedBlock) k_loss_partial(LossArgs a, double* __restrict__ partial) {
-  __shared__ double sh[5][kRedBlock];
+  __shared__ double sh[kLossSums][kRedBlock];
   const int t = threadIdx.x;
   const int64_t p = blockIdx.y, c = blockIdx.x, C = gridDim.x;
-  double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+  double acc[kLossSums] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
   {
     const int64_t chunk = (a.S + C - 1) / C, lo = c * chunk, hi = min((int64_t)a.S, lo + chunk);
     const int comp[6] = {0, 4, 8, 1, 5, 6};
@@ -264,11 +268,20 @@ __global__ void __launch_bounds__(kRedBlock) k_loss_partial(LossArgs a, double* 
       const double* T = a.totals + ((int64_t)p * a.S + n) * 10;
       const double de = T[0] / cnt - a.e_tar[n];
       acc[0] += de * de;
-      if (a.w_tar)
+      if (a.w_tar) {
+        double sw = 0.0;
+        bool has = true;
         for (int v = 0; v < 6; ++v) {
-          const double dw = T[1 + comp[v]] / cnt - a.w_tar[n * 6 + v];
-          acc[2] += dw * dw;
+          const double target = a.w_tar[n * 6 + v];
+          has = has && !isnan(target);
+          const double dw = T[1 + comp[v]] / cnt - target;
+          sw += dw * dw;
         }
+        if (has) {
+          acc[2] += sw;
+          acc[5] += 1.0;
+        }
+      }
     }
   }
   {
@@ -287,14 +300,14 @@ __global__ void __launch_bounds__(kRedBlock) k_loss_partial(LossArgs a, double* 
       acc[4] += z[k] * z[k];
     }
   }
-  for (int v = 0; v < 5; ++v) sh[v][t] = acc[v];
+  for (int v = 0; v < kLossSums; ++v) sh[v][t] = acc[v];
   __syncthreads();
   for (int off = kRedBlock / 2; off > 0; off >>= 1) {
     if (t < off)
-      for (int v = 0; v < 5; ++v) sh[v][t] += sh[v][t + off];
+      for (int v = 0; v < kLossSums; ++v) sh[v][t] += sh[v][t + off];
     __syncthreads();
   }
-  if (t < 5) partial[(p * C + c) * 5 + t] = sh[t][0];
+  if (t < kLossSums) partial[(p * C + c) * kLossSums + t] = sh[t][0];
 }
 
 // loss[p][6] = [L, L_e, L_f, L_v, L_1, L_2]: the chunk sums added in chunk
@@ -303,11 +316,12 @@ __global__ void k_loss_final(LossArgs a, const double* __restrict__ partial, int
                              double* __restrict__ loss) {
   const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= P) return;
-  double s[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+  double s[kLossSums] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
   for (int64_t c = 0; c < C; ++c)
-    for (int v = 0; v < 5; ++v) s[v] += partial[(p * C + c) * 5 + v];
+    for (int v = 0; v < kLossSums; ++v) s[v] += partial[(p * C + c) * kLossSums + v];
   const double le = sqrt(s[0] / a.S), lf = sqrt(s[1] / (3.0 * a.N));
-  const double lv = a.w_tar ? sqrt(s[2] / (6.0 * a.S)) : 0.0;
+  // the virial RMSE runs over the structures that have virial targets
+  const double lv = (a.w_tar && s[5] > 0) ? sqrt(s[2] / (6.0 * s[5])) : 0.0;
   const double l1 = a.params ? s[3] / a.npar : 0.0, l2 = a.params ? sqrt(s[4] / a.npar) : 0.0;
   double* o = loss + p * 6;
   o[0] = a.lam[0] * le + a.lam[1] * lf + a.lam[2] * lv + a.lam[3] * l1 + a.lam[4] * l2;
@@ -336,7 +350,7 @@ void launch_loss(const double* force, const double* totals, const int64_t* offs,
 namespace nep {
 
 // SNES (the trainer of Sec. II.E; Schaul et al. 2011).  One block ranks the
-// population by loss (ties to the lower index) and gives member k the
+// population by loss (ties to the lower index, non-finite losses last) and gives member k the
 // utility of its rank r: max(0, ln(P/2 + 1) - ln(r + 1)) / sum - 1/P.  Every
 // thread forms the normaliser in the same order, so all agree bitwise.
 constexpr int kSnesMaxPop = 1024;
@@ -350,10 +364,15 @@ __global__ void __launch_bounds__(kSnesMaxPop) k_snes_utilities(const double* __
   double tot = 0.0;
   for (int r = 0; r < P; ++r) tot += fmax(0.0, top - log(r + 1.0));
   const double lk = loss[(int64_t)k * stride];
+  const bool fk = isfinite(lk);
   int rank = 0;
   for (int j = 0; j < P; ++j) {
     const double lj = loss[(int64_t)j * stride];
-    rank += (lj < lk || (lj == lk && j < k)) ? 1 : 0;
+    const bool fj = isfinite(lj);
+    // finite losses first, in increasing order; non-finite ones (a diverged
+    // member) after them; ties by index, so the ranks are a permutation
+    const bool before = (fj && !fk) || (fj == fk && (fj ? (lj < lk || (lj == lk && j < k)) : j < k));
+    rank += before ? 1 : 0;
   }
   util[k] = fmax(0.0, top - log(rank + 1.0)) / tot - 1.0 / P;
 }

@@ -31,7 +31,8 @@ NEP_MLP_BF16 = 1
 # every entry point declared in include/nep.h
 EXPORTS = ["nep_num_descriptors", "nep_num_params", "nep_create", "nep_set_params",
            "nep_destroy", "nep_last_error", "nep_compute", "nep_compute_dev",
-           "nep_heat_current", "nep_heat_current_dev", "nep_neighbors", "nep_descriptors", "nep_md_run", "nep_md_run_dev",
+           "nep_heat_current", "nep_heat_current_dev", "nep_neighbors", "nep_descriptors",
+           "nep_latent", "nep_md_run", "nep_md_run_dev",
            "nep_compute_batch", "nep_batch_loss", "nep_snes_step",
            "nep_snes_sample", "nep_set_timing", "nep_get_timing", "nep_get_tuning",
            "nep_server_create",
@@ -135,6 +136,7 @@ def load():
     L.nep_heat_current_dev.argtypes = [vp, i64, vp, vp, vp, pd, pi32, vp, vp, vp]
     L.nep_neighbors.argtypes = [vp, i64, pd, pd, pi32, i32, i32, pi32, pi32, pi32]
     L.nep_descriptors.argtypes = [vp, i64, pd, pi32, pd, pi32, pd]
+    L.nep_latent.argtypes = [vp, i64, pd, pi32, pd, pi32, pd]
     L.nep_md_run.argtypes = [vp, i64, pd, pd, pi32, pd, pd, pi32, d, i64, i64, pd]
     L.nep_md_run_dev.argtypes = [vp, i64, vp, vp, vp, pd, pd, pi32, d, i64, i64, vp, vp]
     L.nep_compute_batch.argtypes = [vp, i32, P(i64), vp, vp, pd, pi32, i32, pd, vp, vp, vp,
@@ -186,6 +188,41 @@ def last_error(handle=None) -> str:
 def _torch_stream():
     import torch
     return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _dev(t, dtype, shape, name, optional=False):
+    """A tensor argument for _devs: (tensor, dtype "f64"/"i32", expected
+    shape with None entries free, name, may it be None)."""
+    return (t, dtype, shape, name, optional)
+
+
+def _devs(*args):
+    """Device pointers of torch tensors after checking what the kernels
+    assume of them: dtype, C-contiguous layout and shape for every argument
+    first, then GPU residence.  A mismatch raises NepError before anything
+    reaches the library."""
+    import torch
+    kinds = {"f64": torch.float64, "i32": torch.int32}
+    for t, dtype, shape, name, optional in args:
+        if t is None:
+            if optional:
+                continue
+            raise NepError(NEP_E_INVALID_ARG, f"{name} is required")
+        if not isinstance(t, torch.Tensor):
+            raise NepError(NEP_E_INVALID_ARG, f"{name} must be a torch tensor")
+        if t.dtype != kinds[dtype]:
+            raise NepError(NEP_E_INVALID_ARG, f"{name} must be {kinds[dtype]}, got {t.dtype}")
+        if not t.is_contiguous():
+            raise NepError(NEP_E_INVALID_ARG, f"{name} must be contiguous")
+        if shape is not None and not (t.dim() == len(shape) and all(
+                w is None or int(g) == int(w) for g, w in zip(t.shape, shape))):
+            raise NepError(NEP_E_INVALID_ARG,
+                           f"{name} has shape {tuple(t.shape)}, expected "
+                           f"{tuple('*' if w is None else w for w in shape)}")
+    for t, _, _, name, _ in args:
+        if t is not None and not t.is_cuda:
+            raise NepError(NEP_E_INVALID_ARG, f"{name} must be a CUDA tensor")
+    return [None if a[0] is None else C.c_void_p(a[0].data_ptr()) for a in args]
 
 
 class Handle:
@@ -241,11 +278,14 @@ class Handle:
                     totals=None):
         """nep_compute_dev on torch CUDA tensors (float64 pos (3,N), int32 types)."""
         box, pbc = _f64(box), _i32(np.ones(3) if pbc is None else pbc)
-        n = int(pos.shape[1])
-        p = lambda t: None if t is None else C.c_void_p(t.data_ptr())  # noqa: E731
+        n = int(pos.shape[-1])
+        args = _devs(_dev(pos, "f64", (3, n), "pos"), _dev(types, "i32", (n,), "types"),
+                     _dev(energy, "f64", (n,), "energy", True), _dev(force, "f64", (3, n), "force", True),
+                     _dev(virial, "f64", (9, n), "virial", True),
+                     _dev(totals, "f64", (10,), "totals", True))
         self._check(load().nep_compute_dev(
-            self._h, n, p(pos), p(types), _ptr(box, C.c_double), _ptr(pbc, C.c_int32),
-            p(energy), p(force), p(virial), p(totals), _torch_stream()))
+            self._h, n, args[0], args[1], _ptr(box, C.c_double), _ptr(pbc, C.c_int32),
+            *args[2:], _torch_stream()))
 
     def heat_current(self, pos, vel, types, box, pbc=None):
         """nep_heat_current on host arrays: (J_i (3,N), total J (3,))."""
@@ -262,11 +302,13 @@ class Handle:
     def heat_current_dev(self, pos, vel, types, box, pbc=None, heat=None, total=None):
         """nep_heat_current_dev on torch CUDA tensors (float64 pos/vel (3,N))."""
         box, pbc = _f64(box), _i32(np.ones(3) if pbc is None else pbc)
-        n = int(pos.shape[1])
-        p = lambda t: None if t is None else C.c_void_p(t.data_ptr())  # noqa: E731
+        n = int(pos.shape[-1])
+        a = _devs(_dev(pos, "f64", (3, n), "pos"), _dev(vel, "f64", (3, n), "vel"),
+                  _dev(types, "i32", (n,), "types"), _dev(heat, "f64", (3, n), "heat", True),
+                  _dev(total, "f64", (3,), "total", True))
         self._check(load().nep_heat_current_dev(
-            self._h, n, p(pos), p(vel), p(types), _ptr(box, C.c_double), _ptr(pbc, C.c_int32),
-            p(heat), p(total), _torch_stream()))
+            self._h, n, *a[:3], _ptr(box, C.c_double), _ptr(pbc, C.c_int32), *a[3:],
+            _torch_stream()))
 
     def neighbors(self, pos, box, which=0, pbc=None, cap=256):
         """Rows at the radial (0) or angular (1) cutoff: list of (j, shift (m,3))."""
@@ -293,6 +335,17 @@ class Handle:
             _ptr(pbc, C.c_int32), _ptr(q, C.c_double)))
         return q
 
+    def latent(self, pos, types, box, pbc=None):
+        """Per-atom latent-space vectors w1_mu h_mu, (N, N_neu)."""
+        pos, types, box = _f64(pos), _i32(types), _f64(box)
+        pbc = _i32(np.ones(3) if pbc is None else pbc)
+        n = pos.shape[1]
+        lat = np.zeros((n, self.h["n_neurons"]))
+        self._check(load().nep_latent(
+            self._h, n, _ptr(pos, C.c_double), _ptr(types, C.c_int32), _ptr(box, C.c_double),
+            _ptr(pbc, C.c_int32), _ptr(lat, C.c_double)))
+        return lat
+
     def md_run(self, pos, vel, types, masses, box, dt, n_steps, thermo_every, pbc=None):
         """nep_md_run on host arrays; returns (pos, vel, thermo (rows, 13))."""
         pos, vel = _f64(pos).copy(), _f64(vel).copy()
@@ -312,11 +365,17 @@ class Handle:
         """nep_md_run_dev on torch CUDA tensors; thermo is a (rows, 13) float64 tensor."""
         box, m = _f64(box), _f64(masses)
         pbc = _i32(np.ones(3) if pbc is None else pbc)
-        p = lambda t: None if t is None else C.c_void_p(t.data_ptr())  # noqa: E731
+        n = int(pos.shape[-1])
+        rows = n_steps // thermo_every if thermo_every > 0 else 0
+        if rows and thermo is not None and thermo.shape[0] < rows:
+            raise NepError(NEP_E_INVALID_ARG, f"thermo needs {rows} rows of 13")
+        a = _devs(_dev(pos, "f64", (3, n), "pos"), _dev(vel, "f64", (3, n), "vel"),
+                  _dev(types, "i32", (n,), "types"),
+                  _dev(thermo if rows else None, "f64", (None, 13), "thermo", rows == 0))
         self._check(load().nep_md_run_dev(
-            self._h, int(pos.shape[1]), p(pos), p(vel), p(types), _ptr(m, C.c_double),
+            self._h, n, *a[:3], _ptr(m, C.c_double),
             _ptr(box, C.c_double), _ptr(pbc, C.c_int32), float(dt), int(n_steps),
-            int(thermo_every), p(thermo), _torch_stream()))
+            int(thermo_every), a[3], _torch_stream()))
 
     def compute_batch(self, offsets, pos, types, boxes, params=None, energy=None, force=None,
                       virial=None, totals=None, pbc=None):
@@ -328,11 +387,17 @@ class Handle:
         P = 1 if params is None else int(np.asarray(params).shape[0])
         params = None if params is None else _f64(params)
         pbc = None if pbc is None else _i32(pbc)
-        p = lambda t: None if t is None else C.c_void_p(t.data_ptr())  # noqa: E731
+        n = int(offsets[-1])
+        if boxes.shape != (S, 9) or (pbc is not None and pbc.shape != (S, 3)):
+            raise NepError(NEP_E_INVALID_ARG, "boxes must be (S, 9) and pbc (S, 3)")
+        a = _devs(_dev(pos, "f64", (3, n), "pos"), _dev(types, "i32", (n,), "types"),
+                  _dev(energy, "f64", (P, n), "energy", True),
+                  _dev(force, "f64", (P, 3, n), "force", True),
+                  _dev(virial, "f64", (P, 9, n), "virial", True),
+                  _dev(totals, "f64", (P, S, 10), "totals", True))
         self._check(load().nep_compute_batch(
-            self._h, S, _ptr(offsets, C.c_int64), p(pos), p(types), _ptr(boxes, C.c_double),
-            _ptr(pbc, C.c_int32), P, _ptr(params, C.c_double), p(energy), p(force), p(virial),
-            p(totals), _torch_stream()))
+            self._h, S, _ptr(offsets, C.c_int64), *a[:2], _ptr(boxes, C.c_double),
+            _ptr(pbc, C.c_int32), P, _ptr(params, C.c_double), *a[2:], _torch_stream()))
 
     def batch_loss(self, offsets, force, totals, energy_target, force_target, lam,
                    loss, virial_target=None, params=None):
@@ -341,29 +406,39 @@ class Handle:
         are host arrays."""
         offsets = np.ascontiguousarray(offsets, dtype=np.int64)
         lam = _f64(lam)
+        if lam.shape != (5,):
+            raise NepError(NEP_E_INVALID_ARG, "lam must hold 5 weights")
         S = offsets.shape[0] - 1
+        n = int(offsets[-1])
         P = int(force.shape[0])
-        npar = 0 if params is None else int(params.shape[1])
-        p = lambda t: None if t is None else C.c_void_p(t.data_ptr())  # noqa: E731
+        npar = 0 if params is None else int(params.shape[-1])
+        a = _devs(_dev(params, "f64", (P, npar), "params", True),
+                  _dev(force, "f64", (P, 3, n), "force"), _dev(totals, "f64", (P, S, 10), "totals"),
+                  _dev(energy_target, "f64", (S,), "energy_target"),
+                  _dev(force_target, "f64", (3, n), "force_target"),
+                  _dev(virial_target, "f64", (S, 6), "virial_target", True),
+                  _dev(loss, "f64", (P, 6), "loss"))
         self._check(load().nep_batch_loss(
-            self._h, S, _ptr(offsets, C.c_int64), P, p(params), npar, p(force), p(totals),
-            p(energy_target), p(force_target), p(virial_target), _ptr(lam, C.c_double), p(loss),
-            _torch_stream()))
+            self._h, S, _ptr(offsets, C.c_int64), P, a[0], npar, *a[1:6], _ptr(lam, C.c_double),
+            a[6], _torch_stream()))
 
     def snes_step(self, mean, sigma, noise, loss, eta_mu, eta_sigma, loss_stride=1):
         """nep_snes_step on torch CUDA float64 tensors: mean, sigma (n_par,) in
         place; noise (P, n_par); loss with member k at loss[k * loss_stride]."""
-        p = lambda t: C.c_void_p(t.data_ptr())  # noqa: E731
+        d, P = int(mean.shape[0]), int(noise.shape[0])
+        if loss is not None and loss.numel() < (P - 1) * int(loss_stride) + 1:
+            raise NepError(NEP_E_INVALID_ARG, "loss is shorter than n_pop * loss_stride")
+        a = _devs(_dev(mean, "f64", (d,), "mean"), _dev(sigma, "f64", (d,), "sigma"),
+                  _dev(noise, "f64", (P, d), "noise"), _dev(loss, "f64", None, "loss"))
         self._check(load().nep_snes_step(
-            self._h, int(mean.shape[0]), int(noise.shape[0]), p(mean), p(sigma), p(noise), p(loss),
-            int(loss_stride), float(eta_mu), float(eta_sigma), _torch_stream()))
+            self._h, d, P, *a, int(loss_stride), float(eta_mu), float(eta_sigma), _torch_stream()))
 
     def snes_sample(self, mean, sigma, noise, population):
         """nep_snes_sample: population (P, n_par) = mean + sigma * noise."""
-        p = lambda t: C.c_void_p(t.data_ptr())  # noqa: E731
-        self._check(load().nep_snes_sample(
-            self._h, int(mean.shape[0]), int(noise.shape[0]), p(mean), p(sigma), p(noise),
-            p(population), _torch_stream()))
+        d, P = int(mean.shape[0]), int(noise.shape[0])
+        a = _devs(_dev(mean, "f64", (d,), "mean"), _dev(sigma, "f64", (d,), "sigma"),
+                  _dev(noise, "f64", (P, d), "noise"), _dev(population, "f64", (P, d), "population"))
+        self._check(load().nep_snes_sample(self._h, d, P, *a, _torch_stream()))
 
     def set_timing(self, enable=True):
         self._check(load().nep_set_timing(self._h, 1 if enable else 0))

@@ -100,3 +100,42 @@ def test_null_handle_on_new_entries():
         nep.NEP_E_INVALID_ARG
     assert L.nep_snes_sample(None, 1, 2, None, None, None, None, None) == nep.NEP_E_INVALID_ARG
     assert "NULL" in nep.last_error(None)
+
+
+def test_binding_rejects_bad_tensors_before_the_library():
+    """The device-pointer wrappers check dtype, layout and shape of every
+    tensor (and that it lives on the GPU) before calling the C ABI, so a
+    float32, transposed or short tensor never reaches a kernel."""
+    import torch
+    hd = nep.Handle.__new__(nep.Handle)   # no device handle: checks run first
+    hd._h = None
+    n = 5
+    good_pos = torch.zeros(3, n, dtype=torch.float64)
+    types = torch.zeros(n, dtype=torch.int32)
+    box = np.eye(3).ravel() * 10
+    cases = [
+        (lambda: hd.compute_dev(good_pos.float(), types, box), "torch.float64"),
+        (lambda: hd.compute_dev(good_pos, types.long(), box), "torch.int32"),
+        (lambda: hd.compute_dev(torch.zeros(n, 3, dtype=torch.float64).t(), types, box), "contiguous"),
+        (lambda: hd.compute_dev(good_pos, types[:4], box), "shape"),
+        (lambda: hd.compute_dev(good_pos, types, box, force=torch.zeros(3, n - 1, dtype=torch.float64)),
+         "shape"),
+        (lambda: hd.compute_dev(good_pos, types, box), "CUDA"),
+        (lambda: hd.snes_step(torch.zeros(4, dtype=torch.float64), torch.zeros(4, dtype=torch.float64),
+                              torch.zeros(3, 4, dtype=torch.float64), torch.zeros(2, dtype=torch.float64),
+                              1.0, 0.1), "shorter"),
+        (lambda: hd.snes_sample(torch.zeros(4, dtype=torch.float64), torch.zeros(4, dtype=torch.float64),
+                                torch.zeros(3, 4, dtype=torch.float64),
+                                torch.zeros(3, 5, dtype=torch.float64)), "shape"),
+        (lambda: hd.batch_loss(np.array([0, 2, 5]), torch.zeros(2, 3, 5, dtype=torch.float64),
+                               torch.zeros(2, 2, 10, dtype=torch.float64), torch.zeros(2, dtype=torch.float64),
+                               torch.zeros(3, 5, dtype=torch.float64), (1, 1, 1, 0, 0),
+                               torch.zeros(1, 6, dtype=torch.float64)), "shape"),
+        (lambda: hd.md_run_dev(good_pos, good_pos, types, [1.0], box, 1.0, 20, 10,
+                               torch.zeros(1, 13, dtype=torch.float64)), "rows"),
+    ]
+    for call, word in cases:
+        with pytest.raises(nep.NepError) as e:
+            call()
+        assert e.value.code == nep.NEP_E_INVALID_ARG
+        assert word in str(e.value), (word, str(e.value))

@@ -1,0 +1,298 @@
+"""Host replay of the evaluation kernels' address arithmetic (no GPU).
+
+For the 40-atom triclinic 3-species structure of the training-batch model
+(several periodic images per pair, so image codes are read), this replays on
+the CPU, thread by thread, the index expressions of the descriptor, network,
+partial-force and gather kernels for every (angular group size, block size,
+lanes per atom) shape the autotuner launches, on rows in the library's layout
+(the angular entries first, then the outer ones) built from the oracle's pair
+search, and checks that every global and LDS access lies inside the buffer the
+library allocates for it.  The GPU checks the row invariants this relies on
+(k_check_rows) before any evaluation kernel runs.
+
+The replay mirrors the kernels' loops: the software-pipelined neighbour loads
+(entries up to two steps ahead; past the row they read atom 0), the clamped
+prefetches of the gather, the per-lane LDS slots, and the network tile loads.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2205_10046_amd import synth
+
+XCDS = 8
+
+
+def xcd_block(b, nb):
+    x, k, q, r = b % XCDS, b // XCDS, nb // XCDS, nb % XCDS
+    return x * q + min(x, r) + k
+
+
+def ng_pad(ng):
+    return ng if ng <= 2 else (ng + 3) // 4 * 4
+
+
+def round4(n):
+    return (n + 3) // 4 * 4
+
+
+def pair_stride(n):
+    return n + ((4 - n % 64) + 64) % 64
+
+
+def group_options(nA, L):
+    cap = 7 if L <= 4 else (5 if L == 5 else 4)
+    out = [ng for ng in (2, 4, 5, 7) if ng <= cap and (ng <= nA or ng == 2)]
+    return out or [2]
+
+
+def estimate_capacity(rc, density):
+    m = math.ceil(1.3 * 4.0 / 3.0 * math.pi * rc ** 3 * density + 24)
+    return (m + 3) // 4 * 4
+
+
+class Bounds:
+    def __init__(self, sizes):
+        self.sizes = sizes
+        self.hi = {k: -1 for k in sizes}
+        self.lo = {k: 0 for k in sizes}
+
+    def touch(self, buf, idx):
+        idx = int(idx)
+        self.hi[buf] = max(self.hi[buf], idx)
+        self.lo[buf] = min(self.lo[buf], idx)
+
+    def check(self, what):
+        for k, n in self.sizes.items():
+            assert self.lo[k] >= 0, (what, k, self.lo[k])
+            assert self.hi[k] < n, (what, k, self.hi[k], n)
+
+
+def library_rows(pos, box, rcR, rcA):
+    """Exact rows in the library's layout: angular-range entries first, then
+    the outer ones, each part in (j, image) order; rev[i][m] = position of i
+    in the row of its m-th neighbour."""
+    R = O.pairs(pos, box, rcR)
+    H = box.reshape(3, 3)
+    rows = []
+    for i, (j, sh) in enumerate(R):
+        d = (pos[:, j] - pos[:, [i]]).T + sh @ H
+        r2 = (d ** 2).sum(1)
+        inner = [k for k in range(len(j)) if r2[k] < rcA * rcA]
+        outer = [k for k in range(len(j)) if r2[k] >= rcA * rcA]
+        order = inner + outer
+        rows.append((j[order], sh[order], len(inner)))
+    rev = []
+    for i, (j, sh, _) in enumerate(rows):
+        rv = []
+        for jj, s in zip(j, sh):
+            jr, sr, _ = rows[jj]
+            hit = [k for k in range(len(jr)) if jr[k] == i and np.array_equal(sr[k], -s)]
+            assert len(hit) == 1
+            rv.append(hit[0])
+        rev.append(rv)
+    return rows, rev
+
+
+def for_entries(b, N, i, first, nn, step, nl_row):
+    """The entries a lane visits and the global reads of its pipelined loop."""
+    def index_of(m):
+        if m >= nn:
+            return 0
+        b.touch("nl", m * N + i)
+        b.touch("cd", m * N + i)
+        return nl_row[m]
+    j0 = index_of(first)
+    index_of(first + step)
+    for c in range(3):
+        b.touch("pos", c * N + j0)
+    b.touch("types", j0)
+    out = []
+    m = first
+    while m < nn:
+        out.append(m)
+        nxt = index_of(m + step) if m + step < nn else 0
+        for c in range(3):
+            b.touch("pos", c * N + nxt)
+        b.touch("types", nxt)
+        index_of(m + 2 * step)
+        m += step
+    return out
+
+
+def replay_pair(N, capN, rows, rev, types, M, NG, block, G, force):
+    T, nR, KR, nA, KA, L, NB, NDp = (M[k] for k in ("T", "nR", "KR", "nA", "KA", "L", "NB", "NDp"))
+    MR = M["MR"]
+    W = ng_pad(NG)
+    groups = -(-nA // NG)
+    cA_pair = pair_stride(groups * KA * W)
+    lds_floats = (round4(T * T * nR * KR) + round4(M["cA_max"]) + T * KR * block)
+    sR0, sA0 = 0, round4(T * T * nR * KR)
+    acc0 = sA0 + round4(T * T * cA_pair)
+    b = Bounds(dict(nl=MR * capN, cd=MR * capN, rev=MR * capN, P=MR * capN, pos=3 * capN,
+                    types=capN, sums=nA * NB * capN, q=capN * NDp, fp=capN * NDp,
+                    lds=lds_floats, sR=T * T * nR * KR, sA=T * T * cA_pair))
+    nb = -(-N * G // block)
+    for blk in range(nb):
+        xb = xcd_block(blk, nb)
+        for tid in range(block):
+            i = (xb * block + tid) // G
+            if i >= N:
+                continue
+            sub = tid % G
+            j, _, nnA = rows[i]
+            nnR = len(j)
+            ti = types[i]
+            for t in range(T):
+                for k in range(KR):
+                    b.touch("lds", acc0 + (t * KR + k) * block + tid)
+            if not force:
+                for m in for_entries(b, N, i, sub, nnR, G, j):
+                    b.touch("lds", acc0 + (types[j[m]] * KR + KR - 1) * block + tid)
+                for t in range(T):
+                    for k in range(KR):
+                        for n in range(nR):
+                            b.touch("sR", (ti * T + t) * nR * KR + k + n * KR)
+                for n in range(nR):
+                    b.touch("q", i * NDp + n)
+                for g in range(groups):
+                    for m in for_entries(b, N, i, sub, nnA, G, j):
+                        base = (ti * T + types[j[m]]) * cA_pair + g * KA * W
+                        for k in range(KA):
+                            b.touch("sA", base + k * W)
+                            b.touch("sA", base + k * W + W - 1)
+                    for q in range(NG):
+                        n = g * NG + q
+                        if n >= nA:
+                            break
+                        for k in range(NB):
+                            b.touch("sums", (n * NB + k) * N + i)
+                b.touch("q", i * NDp + NDp - 1)
+            else:
+                for n in range(nR):
+                    b.touch("fp", i * NDp + n)
+                m_outer = sub + ((nnA - sub + G - 1) // G * G if nnA > sub else 0)
+                for m in for_entries(b, N, i, m_outer, nnR, G, j):
+                    b.touch("P", m * N + i)
+                for g in range(groups):
+                    for q in range(NG):
+                        n = min(g * NG + q, nA - 1)
+                        for k in range(NB):
+                            b.touch("sums", (n * NB + k) * N + i)
+                        if g * NG + q < nA:
+                            b.touch("fp", i * NDp + nR + (L - 1) * nA + n)
+                            b.touch("fp", i * NDp + nR + (L + M["has4b"] + M["has5b"] - 1) * nA + n)
+                    for m in for_entries(b, N, i, sub, nnA, G, j):
+                        base = (ti * T + types[j[m]]) * cA_pair + g * KA * W
+                        b.touch("sA", base + (KA - 1) * W + W - 1)
+                        b.touch("P", m * N + i)
+    # the gather: dU_j/dr_ji at rev[m][i] of row j, prefetched one entry ahead
+    if force:
+        nbg = -(-N * G // 256)
+        for blk in range(nbg):
+            xb = xcd_block(blk, nbg)
+            for tid in range(256):
+                i = (xb * 256 + tid) // G
+                if i >= N:
+                    continue
+                sub = tid % G
+                j, _, _ = rows[i]
+                nn = len(j)
+                for m in list(range(sub, nn, G)) + [sub, sub + G]:
+                    mm = min(m, max(nn - 1, 0))
+                    b.touch("P", mm * N + i)
+                    if m < nn:
+                        b.touch("rev", m * N + i)
+                        b.touch("P", rev[i][m] * N + j[m])
+                        for c in range(3):
+                            b.touch("pos", c * N + j[m])
+    assert b.sizes["lds"] * 4 <= 64 * 1024
+    b.check((NG, block, G, "force" if force else "descriptor"))
+    return b
+
+
+def test_train3_triclinic40_every_autotuned_shape_in_bounds():
+    h = synth.WORKLOADS["train3"]
+    rng = np.random.default_rng(77)
+    # the same structure as the GPU parity case triclinic40_train3
+    synth.random_cell(8, 0.07, 0.2, 1.5, 3, rng)
+    pos, types, box = synth.random_cell(40, 0.07, 0.2, 1.5, 3, rng)
+    N = pos.shape[1]
+    rows, rev = library_rows(pos, box, h["rc_radial"], h["rc_angular"])
+    vol = abs(np.linalg.det(box.reshape(3, 3)))
+    MR = estimate_capacity(h["rc_radial"], N / vol)
+    assert max(len(r[0]) for r in rows) <= MR
+    assert all(len(set(r[0].tolist())) < len(r[0]) for r in rows)  # several images per pair
+    T, L = h["n_types"], h["l_max_3b"]
+    nA, KA = h["n_max_angular"] + 1, h["basis_angular"] + 1
+    nd = O.num_descriptors(h)
+    M = dict(T=T, nR=h["n_max_radial"] + 1, KR=h["basis_radial"] + 1, nA=nA, KA=KA, L=L,
+             NB=(L + 1) ** 2 - 1, NDp=(nd + 7) // 8 * 8, MR=MR, has4b=int(h["l_max_4b"] >= 2),
+             has5b=int(h["l_max_5b"] >= 1))
+    M["cA_max"] = max(T * T * pair_stride(-(-nA // ng) * KA * ng_pad(ng))
+                      for ng in group_options(nA, L))
+    shapes = 0
+    for ng in group_options(nA, L):
+        for block in (128, 256):
+            for G in (1, 4):
+                for force in (False, True):
+                    replay_pair(N, N, rows, rev, types, M, ng, block, G, force)
+                    shapes += 1
+    assert shapes == 4 * 2 * 2 * 2
+
+
+def test_network_tiles_in_bounds():
+    """k_mlp: 16-row tiles of the species-grouped row order (padding -1),
+    clamped q loads, w0/w0t/bf16 weight rows, for the same model."""
+    h = synth.WORKLOADS["train3"]
+    nd = O.num_descriptors(h)
+    NN = h["n_neurons"]
+    NNp, NDp, NDp32 = (NN + 31) // 32 * 32, (nd + 7) // 8 * 8, (nd + 31) // 32 * 32
+    rng = np.random.default_rng(5)
+    for N, T in ((40, 3), (1, 3), (17, 1), (300, 3)):
+        types = rng.integers(0, T, N)
+        rows_len = (N + 15) // 16 * 16 + 16 * T
+        rows = []
+        for t in range(T):
+            idx = [i for i in range(N) if types[i] == t]
+            rows += idx + [-1] * ((-len(idx)) % 16)
+        assert len(rows) <= rows_len
+        rows += [-1] * (rows_len - len(rows))
+        nets = T
+        sizes = dict(q=N * NDp, w0t=nets * nd * NNp, w0=nets * NNp * nd, w0b=nets * NNp * NDp32,
+                     w0tb=nets * NDp32 * NNp, rows=rows_len)
+        hi = {k: -1 for k in sizes}
+        for base in range(0, rows_len, 16):
+            first = rows[base]
+            if first < 0:
+                continue
+            net = types[first]
+            for lane in range(64):
+                col, grp = lane & 15, lane >> 4
+                atom = rows[base + col]
+                qrow = (atom if atom >= 0 else 0) * NDp
+                for s in range(-(-nd // 4)):
+                    d = 4 * s + grp
+                    dn = min(d + 4, nd - 1)
+                    hi["q"] = max(hi["q"], qrow + min(d, nd - 1), qrow + dn)
+                    for nb in range(NNp // 16):
+                        hi["w0t"] = max(hi["w0t"], net * nd * NNp + dn * NNp + 16 * nb + col)
+                for s in range(NDp32 // 32):
+                    d0 = 32 * s + 8 * grp
+                    hi["q"] = max(hi["q"], qrow + min(d0, NDp - 8) + 7)
+                    for nb in range(NNp // 16):
+                        hi["w0b"] = max(hi["w0b"], net * NNp * NDp32 + (16 * nb + col) * NDp32 + d0 + 7)
+                for db in range(-(-nd // 16)):
+                    d = 16 * db + col
+                    dc = min(d, nd - 1)
+                    for nb in range(NNp // 16):
+                        for r in range(4):
+                            hi["w0"] = max(hi["w0"], net * NNp * nd + (16 * nb + 4 * grp + r) * nd + dc)
+                    wrow = net * NDp32 * NNp + (d if d < NDp32 else 0) * NNp
+                    for p in range(NNp // 32):
+                        hi["w0tb"] = max(hi["w0tb"], wrow + 32 * p + 16 + 4 * grp + 3)
+                hi["rows"] = max(hi["rows"], base + 4 * 3 + 3, base + col)
+        for k, n in sizes.items():
+            assert hi[k] < n, (N, k, hi[k], n)

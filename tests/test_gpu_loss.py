@@ -137,3 +137,34 @@ def test_loss_single_structure():
     log(f"[loss] single structure: L={got[0]:.6f} oracle {ref[0]:.6f}")
     assert d[1] <= TOL_E and d[2] <= TOL_F and d[3] <= TOL_E
     handle.close()
+
+
+def test_loss_virial_nan_rows_are_absent(setup):
+    """Structures whose virial target row holds a NaN have no virial: the
+    virial RMSE runs over the others, as in the oracle, on the kernel's own
+    float64 inputs."""
+    import torch
+    st = setup
+    e_t, f_t, w_t = st["targets"]
+    wt = np.array(w_t, dtype=np.float64)
+    wt[[1, 4], 3] = np.nan
+    wt[6, :] = np.nan
+    P = st["pop"].shape[0]
+    out = torch.full((P, 6), -1.0, dtype=torch.float64, device="cuda:0")
+    st["handle"].batch_loss(st["offs"], st["f"], st["t"], st["tg"]["e"], st["tg"]["f"], LAM, out,
+                            virial_target=torch.tensor(wt, device="cuda:0"), params=st["tg"]["z"])
+    torch.cuda.synchronize()
+    got = out.cpu().numpy()
+    f, t = st["f"].cpu().numpy(), st["t"].cpu().numpy()
+    cnt = np.diff(st["offs"]).astype(np.float64)
+    for p in range(P):
+        e = t[p, :, 0] / cnt
+        w = t[p, :, 1:][:, list(O.VIRIAL6)] / cnt[:, None]
+        ref = O.loss_terms(e, f[p], w, e_t, f_t, wt, st["pop"][p], LAM)
+        assert np.isfinite(got[p]).all()
+        np.testing.assert_allclose(got[p], ref, rtol=1e-12, atol=1e-15)
+    out2 = torch.full((P, 6), -1.0, dtype=torch.float64, device="cuda:0")
+    st["handle"].batch_loss(st["offs"], st["f"], st["t"], st["tg"]["e"], st["tg"]["f"], LAM, out2,
+                            virial_target=torch.full_like(st["tg"]["w"], float("nan")))
+    torch.cuda.synchronize()
+    assert not np.any(out2.cpu().numpy()[:, 3])

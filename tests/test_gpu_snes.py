@@ -53,6 +53,28 @@ def test_snes_step_matches_oracle(handle, P, stride):
     np.testing.assert_allclose(ts.cpu().numpy(), rs, rtol=1e-12)
 
 
+def test_snes_step_ranks_non_finite_losses_last(handle):
+    """A diverged member (NaN or Inf loss) ranks after every finite one on
+    the device as in the oracle, so the update stays that of a permutation
+    of utilities."""
+    import torch
+    h, _, hd = handle
+    d, P = O.num_params(h), 9
+    rng = np.random.default_rng(150)
+    mean, sigma = rng.normal(0, 0.1, d), rng.uniform(0.05, 0.2, d)
+    noise = rng.normal(size=(P, d))
+    losses = rng.uniform(0.1, 1.0, P)
+    losses[2], losses[5], losses[7] = np.nan, np.inf, np.nan
+    eta = O.snes_rates(d)
+    tm, ts = _t(mean), _t(sigma)
+    hd.snes_step(tm, ts, _t(noise), _t(losses), *eta)
+    torch.cuda.synchronize()
+    rm, rs = O.snes_step(mean, sigma, noise, losses, *eta)
+    assert np.isfinite(tm.cpu().numpy()).all()
+    np.testing.assert_allclose(tm.cpu().numpy(), rm, rtol=1e-12, atol=1e-15)
+    np.testing.assert_allclose(ts.cpu().numpy(), rs, rtol=1e-12)
+
+
 def test_snes_sample_matches_oracle(handle):
     import torch
     h, _, hd = handle

@@ -857,3 +857,53 @@ def test_snes_minimises_sphere_and_shrinks_sigma():
         z = O.snes_sample(mean, sigma, s)
         mean, sigma = O.snes_step(mean, sigma, s, ((z - c) ** 2).sum(axis=1), *eta)
     assert np.abs(mean - c).max() < 1e-3 and sigma.max() < 1e-3
+
+
+def test_snes_ranks_put_non_finite_losses_last():
+    """A diverged member (NaN or Inf loss) ranks after every finite one, so
+    the ranks stay a permutation and the utilities still sum to zero."""
+    r = O.snes_ranks([3.0, float("nan"), 1.0, float("inf"), 1.0, -float("inf")])
+    assert list(r) == [2, 3, 0, 4, 1, 5]
+    u = O.snes_utilities(6)[r]
+    assert abs(u.sum()) < 1e-15
+
+
+def test_loss_virial_rows_with_nan_are_absent():
+    """Structures without a virial target (a NaN row) leave the virial term:
+    an offset d of the remaining rows still gives exactly |d|, normalised by
+    6 times the number of structures that have a target."""
+    h, z, structs = _loss_case()
+    e, f, w = O.predictions(h, z, structs)
+    lam = (0.0, 0.0, 1.0, 0.0, 0.0)
+    d = 0.021
+    wt = w + d
+    wt[1, 2] = float("nan")
+    r = O.loss_terms(e, f, w, e, f, wt, z, lam)
+    assert r[3] == pytest.approx(d, rel=1e-12) and r[0] == pytest.approx(d, rel=1e-12)
+    wt2 = w.copy()
+    wt2[0] += 3 * d
+    wt2[2] = float("nan")
+    assert O.loss_terms(e, f, w, e, f, wt2, z, lam)[3] == pytest.approx(3 * d / math.sqrt(2), rel=1e-12)
+    assert O.loss_terms(e, f, w, e, f, np.full_like(w, np.nan), z, lam)[3] == 0.0
+
+
+def test_latent_vectors():
+    """Latent-space vectors (Sec. IV): per atom, w1_mu h_mu from a numpy
+    matmul/tanh of the oracle's descriptors with the weights read straight from
+    the parameter blob, per-species networks included; their sum minus b1 is
+    the site energy of the full evaluation."""
+    h = hp(n_types=2)
+    p = synth.random_params(O.num_params(h), seed=61)
+    pos, types, box = small_cell(n=12, ntypes=2, seed=62)
+    lat = O.latent(h, p, pos, types, box)
+    q = O.descriptors(h, p, pos, types, box)
+    o = blob_offsets(h)
+    nd, nn = o["nd"], h["n_neurons"]
+    for i in range(pos.shape[1]):
+        base = types[i] * (nd + 2) * nn
+        w0 = p[base:base + nn * nd].reshape(nn, nd)
+        b0 = p[base + nn * nd:base + nn * nd + nn]
+        w1 = p[base + nn * nd + nn:base + nn * nd + 2 * nn]
+        np.testing.assert_allclose(lat[i], w1 * np.tanh(w0 @ q[i] - b0), rtol=1e-12, atol=1e-15)
+    U = O.evaluate(h, p, pos, types, box)["U"]
+    np.testing.assert_allclose(lat.sum(axis=1) - p[o["b1"]], U, rtol=1e-12, atol=1e-14)
