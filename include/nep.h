@@ -192,6 +192,24 @@ int nep_batch_loss(nep_handle *h, int32_t n_struct, const int64_t *offsets, int3
                    const double *virial_target, const double lambda[5], double *loss,
                    void *stream);
 
+/* nep_batch_loss for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving or training loops, harnesses that forbid
+ * hipMalloc): the same arguments, kernels and results (bitwise), with its
+ * workspace in a fixed 1 MiB array in each GPU's memory instead of the
+ * handle's growable buffers.  It allocates nothing.  The workspace holds
+ * 6 n_param_sets C doubles of partial sums, C = min(256, max(1,
+ * (3N + 16383) / 16384)), plus the n_struct + 1 offsets (rounded to 256
+ * bytes); a larger batch fails with NEP_E_INVALID_ARG.  Every call on one GPU
+ * uses the same array, and nothing in it needs to start at zero (each call
+ * writes all of its partial sums before reading them): calls that overlap on
+ * one GPU (different streams or threads) race.  Synchronous on `stream`. */
+int nep_batch_loss_noalloc(nep_handle *h, int32_t n_struct, const int64_t *offsets,
+                           int32_t n_param_sets, const double *params, int64_t n_par,
+                           const double *force, const double *totals,
+                           const double *energy_target, const double *force_target,
+                           const double *virial_target, const double lambda[5], double *loss,
+                           void *stream);
+
 /* One step of the separable natural evolution strategy (SNES, Schaul et al.
  * 2011) that trains NEP (Sec. II.E).  The search distribution has mean
  * mean[n_par] and scales sigma[n_par]; the population that produced loss was

@@ -293,6 +293,7 @@ struct nep_handle {
   double* snes_util = nullptr;     // [1024] SNES utilities of the last step
   double* heat_part = nullptr;     // per-block heat-current sums
   int64_t heat_part_cap = 0;
+  void* scratch = nullptr;         // this device's fixed workspace of nep_batch_loss_noalloc
   DevModel& M = main.M;
   // workspace
   int64_t capN = 0, cap_part = 0, rows_cap = 0;
@@ -1379,6 +1380,7 @@ int nep_create(const nep_hparams* hp, const double* params, size_t n, nep_handle
     h->nd = n_descriptors(*hp);
     h->nets = hp->nn_per_type ? hp->n_types : 1;
     upload_model(h, params, h->main);
+    HIPCHK(loss_scratch_address(h->device, &h->scratch));
     // LDS budget of the pair kernels: coefficient tables + per-thread slots
     if (eval_lds_bytes(h->M, kBlock) > 64 * 1024)
       throw Failure{NEP_E_UNSUPPORTED, "n_types x basis sizes too large for the LDS budget"};
@@ -1499,25 +1501,39 @@ int nep_heat_current_dev(nep_handle* h, int64_t N, const double* pos, const doub
   return NEP_OK;
 }
 
+}  // extern "C"
+
+namespace {
+void check_loss_args(const nep_handle* h, int32_t n_struct, const int64_t* offsets, int32_t n_param_sets,
+                     const double* params, int64_t n_par, const double* force, const double* totals,
+                     const double* energy_target, const double* force_target, const double* lambda,
+                     const double* loss) {
+  if (n_struct < 1 || n_param_sets < 1 || n_param_sets > 65535)
+    throw Failure{NEP_E_INVALID_ARG, "need n_struct >= 1 and 1 <= n_param_sets <= 65535"};
+  if (!offsets || !force || !totals || !energy_target || !force_target || !lambda || !loss)
+    throw Failure{NEP_E_INVALID_ARG,
+                  "offsets, force, totals, energy_target, force_target, lambda and loss are required"};
+  if (offsets[0] != 0) throw Failure{NEP_E_INVALID_ARG, "offsets[0] must be 0"};
+  for (int32_t s = 0; s < n_struct; ++s)
+    if (offsets[s + 1] <= offsets[s])
+      throw Failure{NEP_E_INVALID_ARG, "structure " + std::to_string(s) + " has no atoms"};
+  if (params && n_par != (int64_t)n_params(h->hp))
+    throw Failure{NEP_E_INVALID_ARG, "n_params does not match the model"};
+  for (int v = 0; v < 5; ++v)
+    if (!std::isfinite(lambda[v])) throw Failure{NEP_E_NONFINITE, "lambda contains NaN or Inf"};
+}
+}  // namespace
+
+extern "C" {
+
 int nep_batch_loss(nep_handle* h, int32_t n_struct, const int64_t* offsets, int32_t n_param_sets,
                    const double* params, int64_t n_par, const double* force, const double* totals,
                    const double* energy_target, const double* force_target, const double* virial_target,
                    const double lambda[5], double* loss, void* stream) {
   if (!h) return fail(nullptr, {NEP_E_INVALID_ARG, "handle is NULL"});
   try {
-    if (n_struct < 1 || n_param_sets < 1 || n_param_sets > 65535)
-      throw Failure{NEP_E_INVALID_ARG, "need n_struct >= 1 and 1 <= n_param_sets <= 65535"};
-    if (!offsets || !force || !totals || !energy_target || !force_target || !lambda || !loss)
-      throw Failure{NEP_E_INVALID_ARG,
-                    "offsets, force, totals, energy_target, force_target, lambda and loss are required"};
-    if (offsets[0] != 0) throw Failure{NEP_E_INVALID_ARG, "offsets[0] must be 0"};
-    for (int32_t s = 0; s < n_struct; ++s)
-      if (offsets[s + 1] <= offsets[s])
-        throw Failure{NEP_E_INVALID_ARG, "structure " + std::to_string(s) + " has no atoms"};
-    if (params && n_par != (int64_t)n_params(h->hp))
-      throw Failure{NEP_E_INVALID_ARG, "n_params does not match the model"};
-    for (int v = 0; v < 5; ++v)
-      if (!std::isfinite(lambda[v])) throw Failure{NEP_E_NONFINITE, "lambda contains NaN or Inf"};
+    check_loss_args(h, n_struct, offsets, n_param_sets, params, n_par, force, totals, energy_target,
+                    force_target, lambda, loss);
     set_device(h);
     hipStream_t s = (hipStream_t)stream;
     const int64_t N = offsets[n_struct];
@@ -1542,6 +1558,41 @@ int nep_batch_loss(nep_handle* h, int32_t n_struct, const int64_t* offsets, int3
     HIPCHK(hipGetLastError());
     HIPCHK(hipStreamSynchronize(s));
     h->resolve_timing();
+  } catch (const Failure& f) {
+    return fail(h, f);
+  }
+  return NEP_OK;
+}
+
+int nep_batch_loss_noalloc(nep_handle* h, int32_t n_struct, const int64_t* offsets, int32_t n_param_sets,
+                           const double* params, int64_t n_par, const double* force, const double* totals,
+                           const double* energy_target, const double* force_target,
+                           const double* virial_target, const double lambda[5], double* loss,
+                           void* stream) {
+  if (!h) return fail(nullptr, {NEP_E_INVALID_ARG, "handle is NULL"});
+  try {
+    check_loss_args(h, n_struct, offsets, n_param_sets, params, n_par, force, totals, energy_target,
+                    force_target, lambda, loss);
+    // the workspace: per-chunk partial sums, then the structure offsets
+    const int64_t N = offsets[n_struct];
+    const size_t part_bytes = (size_t)n_param_sets * loss_chunks(N) * 6 * sizeof(double);
+    const size_t offs_at = (part_bytes + 255) / 256 * 256;
+    const size_t need = offs_at + ((size_t)n_struct + 1) * sizeof(int64_t);
+    if (need > (size_t)kLossScratchBytes)
+      throw Failure{NEP_E_INVALID_ARG, "batch too large for the fixed loss workspace: needs " +
+                                           std::to_string(need) + " bytes, the limit is " +
+                                           std::to_string(kLossScratchBytes)};
+    if (!h->scratch) throw Failure{NEP_E_HIP, "the loss workspace has no device address"};
+    set_device(h);
+    hipStream_t s = (hipStream_t)stream;
+    unsigned char* base = (unsigned char*)h->scratch;
+    double* part = (double*)base;
+    int64_t* d_offs = (int64_t*)(base + offs_at);
+    HIPCHK(hipMemcpyAsync(d_offs, offsets, ((size_t)n_struct + 1) * sizeof(int64_t), hipMemcpyHostToDevice, s));
+    launch_loss(force, totals, d_offs, n_struct, N, n_param_sets, energy_target, force_target, virial_target,
+                params, params ? n_par : 0, lambda, part, loss, s);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(s));
   } catch (const Failure& f) {
     return fail(h, f);
   }

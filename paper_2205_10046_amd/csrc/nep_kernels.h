@@ -119,6 +119,13 @@ void launch_neighbors_out(const Lists& L, int which, int64_t N, const int32_t* p
                           int32_t* shift, hipStream_t s);
 void launch_inverse_perm(const int32_t* perm, int64_t N, int32_t* inv, hipStream_t s);
 
+// output.hip: the fixed workspace of nep_batch_loss_noalloc (one per GPU).
+constexpr int64_t kLossScratchBytes = 1 << 20;
+constexpr int kMaxDevices = 64;
+// Device address of the workspace on `device`, which must be current;
+// looked up on the first call per device, then cached.
+hipError_t loss_scratch_address(int device, void** out);
+
 // md.hip
 struct MDArgs {
   int64_t N;

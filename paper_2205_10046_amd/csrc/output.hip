@@ -2,6 +2,7 @@
 // totals E = sum_i U_i, W = sum_i W_i (a fixed two-level tree: the same
 // inputs always give the same bits).
 #include <algorithm>
+#include <mutex>
 
 #include "nep_kernels.h"
 
@@ -330,6 +331,32 @@ __global__ void k_loss_final(LossArgs a, const double* __restrict__ partial, int
   o[3] = lv;
   o[4] = l1;
   o[5] = l2;
+}
+
+// Workspace of the allocation-free loss entry point: a fixed 1 MiB array in
+// every GPU's memory, held until the process ends.  Host code never passes
+// the array's name to a kernel or a copy (on the host it is only a stand-in
+// symbol): it uses the device address hipGetSymbolAddress gives for the
+// current device, looked up once per device and kept here.
+static __device__ __align__(256) unsigned char scratch[kLossScratchBytes];
+
+namespace {
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+}  // namespace
+
+hipError_t loss_scratch_address(int device, void** out) {
+  *out = nullptr;
+  if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[device]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch_ptr[device] = p;
+  }
+  *out = g_scratch_ptr[device];
+  return hipSuccess;
 }
 
 int64_t loss_chunks(int64_t N) { return std::min<int64_t>(256, std::max<int64_t>(1, (3 * N + 16383) / 16384)); }

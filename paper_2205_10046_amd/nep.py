@@ -33,7 +33,7 @@ EXPORTS = ["nep_num_descriptors", "nep_num_params", "nep_create", "nep_set_param
            "nep_destroy", "nep_last_error", "nep_compute", "nep_compute_dev",
            "nep_heat_current", "nep_heat_current_dev", "nep_neighbors", "nep_descriptors",
            "nep_latent", "nep_md_run", "nep_md_run_dev",
-           "nep_compute_batch", "nep_batch_loss", "nep_snes_step",
+           "nep_compute_batch", "nep_batch_loss", "nep_batch_loss_noalloc", "nep_snes_step",
            "nep_snes_sample", "nep_set_timing", "nep_get_timing", "nep_get_tuning",
            "nep_server_create",
            "nep_server_submit", "nep_server_poll", "nep_server_stats", "nep_server_reset_stats",
@@ -142,6 +142,7 @@ def load():
     L.nep_compute_batch.argtypes = [vp, i32, P(i64), vp, vp, pd, pi32, i32, pd, vp, vp, vp,
                                     vp, vp]
     L.nep_batch_loss.argtypes = [vp, i32, P(i64), i32, vp, i64, vp, vp, vp, vp, vp, pd, vp, vp]
+    L.nep_batch_loss_noalloc.argtypes = L.nep_batch_loss.argtypes
     L.nep_snes_step.argtypes = [vp, i64, i32, vp, vp, vp, vp, i64, d, d, vp]
     L.nep_snes_sample.argtypes = [vp, i64, i32, vp, vp, vp, vp, vp]
     L.nep_server_create.argtypes = [vp, C.c_size_t, i32, P(vp)]
@@ -400,10 +401,10 @@ class Handle:
             _ptr(pbc, C.c_int32), P, _ptr(params, C.c_double), *a[2:], _torch_stream()))
 
     def batch_loss(self, offsets, force, totals, energy_target, force_target, lam,
-                   loss, virial_target=None, params=None):
-        """nep_batch_loss: force (P,3,N), totals (P,S,10), targets, params (P,N_par)
-        and loss (P,6) are torch CUDA float64 tensors; offsets (S+1) and lam (5)
-        are host arrays."""
+                   loss, virial_target=None, params=None, noalloc=False):
+        """nep_batch_loss (nep_batch_loss_noalloc with noalloc=True): force
+        (P,3,N), totals (P,S,10), targets, params (P,N_par) and loss (P,6) are
+        torch CUDA float64 tensors; offsets (S+1) and lam (5) are host arrays."""
         offsets = np.ascontiguousarray(offsets, dtype=np.int64)
         lam = _f64(lam)
         if lam.shape != (5,):
@@ -418,9 +419,9 @@ class Handle:
                   _dev(force_target, "f64", (3, n), "force_target"),
                   _dev(virial_target, "f64", (S, 6), "virial_target", True),
                   _dev(loss, "f64", (P, 6), "loss"))
-        self._check(load().nep_batch_loss(
-            self._h, S, _ptr(offsets, C.c_int64), P, a[0], npar, *a[1:6], _ptr(lam, C.c_double),
-            a[6], _torch_stream()))
+        fn = load().nep_batch_loss_noalloc if noalloc else load().nep_batch_loss
+        self._check(fn(self._h, S, _ptr(offsets, C.c_int64), P, a[0], npar, *a[1:6],
+                       _ptr(lam, C.c_double), a[6], _torch_stream()))
 
     def snes_step(self, mean, sigma, noise, loss, eta_mu, eta_sigma, loss_stride=1):
         """nep_snes_step on torch CUDA float64 tensors: mean, sigma (n_par,) in
