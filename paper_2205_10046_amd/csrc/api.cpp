@@ -10,6 +10,7 @@
 
 #include <algorithm>
 #include <array>
+#include <atomic>
 #include <chrono>
 #include <condition_variable>
 #include <deque>
@@ -142,10 +143,16 @@ uint16_t to_bf16(float f) {
   return (uint16_t)(u >> 16);
 }
 
+// Bumped by every device (re)allocation: a captured HIP graph holds buffer
+// addresses in its kernel arguments and is only reused while none of them
+// can have moved.
+std::atomic<uint64_t> g_alloc_gen{1};
+
 template <class T>
 void dev_alloc(T*& p, size_t n) {
   if (p) HIPCHK(hipFree(p));
   p = nullptr;
+  g_alloc_gen.fetch_add(1);
   if (n == 0) return;
   hipError_t e = hipMalloc((void**)&p, n * sizeof(T));
   if (e != hipSuccess) {
@@ -294,6 +301,12 @@ struct nep_handle {
   double* heat_part = nullptr;     // per-block heat-current sums
   int64_t heat_part_cap = 0;
   void* scratch = nullptr;         // this device's fixed workspace of nep_batch_loss_noalloc
+  // the captured G-step MD graph, reused by later nep_md_run* calls whose
+  // shapes, geometry, step and buffers (allocation generation) are the same
+  hipGraph_t md_graph = nullptr;
+  hipGraphExec_t md_exec = nullptr;
+  std::vector<unsigned char> md_key;
+  hipStream_t md_stream = nullptr;  // capture/replay stream for null-stream callers
   DevModel& M = main.M;
   // workspace
   int64_t capN = 0, cap_part = 0, rows_cap = 0;
@@ -327,7 +340,18 @@ struct nep_handle {
 
   ~nep_handle() { release(); }
 
+  void drop_md_graph() {
+    if (md_exec) (void)hipGraphExecDestroy(md_exec);
+    if (md_graph) (void)hipGraphDestroy(md_graph);
+    md_exec = nullptr;
+    md_graph = nullptr;
+    md_key.clear();
+  }
+
   void release() {
+    drop_md_graph();
+    if (md_stream) (void)hipStreamDestroy(md_stream);
+    md_stream = nullptr;
     if (pinned) (void)hipHostFree(pinned);
     pinned = nullptr;
     dev_free(loss_part); dev_free(loss_offs); dev_free(snes_util); dev_free(heat_part);
@@ -637,6 +661,7 @@ EvalArgs eval_args(nep_handle* h, const Prepared& pp, const DevModel& M) {
   a.U = h->U;
   a.sums = h->sums;
   a.P = h->P;
+  a.fmap = h->V.fmap;
   a.F = h->F;
   a.W = h->W;
   a.rows = h->rows;
@@ -734,7 +759,7 @@ void build_rows_checked(nep_handle* h, const Prepared& pp, const BuildArgs& b, h
       Stage st(h, "neighbor_rows", s);
       launch_build_rows(b, pp.geo.st, pp.batch, h->V, h->L, s);
     }
-    launch_check_rows(pp.N, h->sid, h->structs, pp.geo.st, pp.batch, h->L, h->flags + 6, s);
+    launch_check_rows(pp.N, h->sid, h->structs, pp.geo.st, pp.batch, h->V, h->L, h->flags + 6, s);
     int32_t* fl = (int32_t*)(h->pinned + 384);
     HIPCHK(hipMemcpyAsync(fl, h->flags, 8 * sizeof(int32_t), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
@@ -1833,7 +1858,7 @@ int md_skin(nep_handle* h, const Prepared& pp, double* d_pos, double* d_vel, con
     skin_rebuild(h, pp, rl, nullptr, s);
     skin_filter(h, pp, s);
     launch_fill_i32(h->flags + 6, 1, 0, s);
-    launch_check_rows(N, h->sid, h->structs, pp.geo.st, pp.batch, h->L, h->flags + 6, s);
+    launch_check_rows(N, h->sid, h->structs, pp.geo.st, pp.batch, h->V, h->L, h->flags + 6, s);
     const int32_t* fl = read_flags(h, s);
     if (fl[3]) throw Failure{NEP_E_INVALID_ARG, "an atom type is out of range"};
     if (fl[4]) throw Failure{NEP_E_NONFINITE, "positions contain NaN or Inf"};
@@ -1879,28 +1904,35 @@ int md_skin(nep_handle* h, const Prepared& pp, double* d_pos, double* d_vel, con
   // per-stage event timing (nep_set_timing) uses direct launches instead.
   const int64_t G = thermo_every > 0 ? thermo_every : 10;
   const char* genv = std::getenv("NEP_MD_GRAPH");
-  const bool use_graph = !h->timing && !(genv && genv[0] == '0') && n_steps >= G && G <= 1000;
+  // (captured even for a call shorter than G steps, so that a warm-up call
+  // leaves the graph ready for the calls after it)
+  const bool use_graph = !h->timing && !(genv && genv[0] == '0') && G <= 1000;
   if (!h->row_counter) dev_alloc(h->row_counter, 1);
   hipStream_t gs = s;
-  struct GraphGuard {
-    hipGraph_t g = nullptr;
-    hipGraphExec_t e = nullptr;
-    hipStream_t own = nullptr;
-    void drop() {
-      if (e) (void)hipGraphExecDestroy(e);
-      if (g) (void)hipGraphDestroy(g);
-      e = nullptr;
-      g = nullptr;
-    }
-    ~GraphGuard() {
-      drop();
-      if (own) (void)hipStreamDestroy(own);
-    }
-  } guard;
-  // (Re)capture the G-step group: kernel arguments hold the row buffers by
-  // value, so a capture is only valid until the rows are reallocated.
+  // What the captured kernels' arguments depend on besides the handle's
+  // fixed model and kernel shapes: sizes, geometry, step, skin and the
+  // addresses of every buffer (the allocation generation).
+  auto graph_key = [&]() {
+    std::vector<unsigned char> k;
+    auto put = [&](const void* p, size_t n) {
+      const unsigned char* c = (const unsigned char*)p;
+      k.insert(k.end(), c, c + n);
+    };
+    const uint64_t gen = g_alloc_gen.load();
+    put(&gen, sizeof gen);
+    put(&N, sizeof N);
+    put(&G, sizeof G);
+    put(&thermo_every, sizeof thermo_every);
+    put(&dt, sizeof dt);
+    put(&rl, sizeof rl);
+    put(&thr2, sizeof thr2);
+    put(&pp.geo.st, sizeof pp.geo.st);
+    put(&pp.n_cells, sizeof pp.n_cells);
+    return k;
+  };
+  // (Re)capture the G-step group; kept in the handle for later calls.
   auto capture = [&]() {
-    guard.drop();
+    h->drop_md_graph();
     HIPCHK(hipStreamSynchronize(gs));
     try {
       HIPCHK(hipStreamBeginCapture(gs, hipStreamCaptureModeThreadLocal));
@@ -1908,22 +1940,24 @@ int md_skin(nep_handle* h, const Prepared& pp, double* d_pos, double* d_vel, con
       if (thermo_every > 0)
         launch_thermo_counted(h->U, h->W, h->vel, h->types, h->mass, N, h->partial, num_partials(N),
                               h->thermo, h->row_counter, (double)thermo_every, kAmuA2fs2, kBoltzmann, gs);
-      HIPCHK(hipStreamEndCapture(gs, &guard.g));
-      HIPCHK(hipGraphInstantiate(&guard.e, guard.g, nullptr, nullptr, 0));
+      HIPCHK(hipStreamEndCapture(gs, &h->md_graph));
+      HIPCHK(hipGraphInstantiate(&h->md_exec, h->md_graph, nullptr, nullptr, 0));
+      h->md_key = graph_key();
     } catch (...) {
       hipGraph_t g2 = nullptr;
       (void)hipStreamEndCapture(gs, &g2);
       if (g2) (void)hipGraphDestroy(g2);
+      h->drop_md_graph();
       throw;
     }
   };
   if (use_graph) {
     if (!gs) {
-      HIPCHK(hipStreamCreateWithFlags(&guard.own, hipStreamNonBlocking));
-      gs = guard.own;
+      if (!h->md_stream) HIPCHK(hipStreamCreateWithFlags(&h->md_stream, hipStreamNonBlocking));
+      gs = h->md_stream;
+      HIPCHK(hipStreamSynchronize(s));
     }
-    HIPCHK(hipStreamSynchronize(s));
-    capture();
+    if (!h->md_exec || h->md_key != graph_key()) capture();
   }
   hipStream_t ws = use_graph ? gs : s;   // the stream every step runs on
   const int64_t chunk = use_graph ? G * std::max<int64_t>(1, 50 / G) : 50;
@@ -1951,7 +1985,7 @@ int md_skin(nep_handle* h, const Prepared& pp, double* d_pos, double* d_vel, con
     }
     for (int64_t step = c0 + 1; step <= c1; ++step) {
       if (use_graph && (step - 1) % G == 0 && step - 1 + G <= c1) {
-        HIPCHK(hipGraphLaunch(guard.e, s));
+        HIPCHK(hipGraphLaunch(h->md_exec, s));
         if (thermo_every > 0) ++row;
         step += G - 1;
         continue;
@@ -1965,7 +1999,7 @@ int md_skin(nep_handle* h, const Prepared& pp, double* d_pos, double* d_vel, con
       }
     }
     launch_check_finite(h->pos, 3 * N, h->flags + 4, s);
-    launch_check_rows(N, h->sid, h->structs, pp.geo.st, pp.batch, h->L, h->flags + 6, s);
+    launch_check_rows(N, h->sid, h->structs, pp.geo.st, pp.batch, h->V, h->L, h->flags + 6, s);
     const int32_t* fl = read_flags(h, s);
     if (fl[4]) throw Failure{NEP_E_NONFINITE, "positions became non-finite during the run"};
     if (grow_rows(h, N, fl)) {
@@ -2095,7 +2129,7 @@ static int md_impl(nep_handle* h, int64_t N, double* d_pos, double* d_vel, const
       }
     }
     launch_check_finite(h->pos, 3 * N, h->flags + 4, s);
-    launch_check_rows(N, h->sid, h->structs, pp.geo.st, pp.batch, h->L, h->flags + 6, s);
+    launch_check_rows(N, h->sid, h->structs, pp.geo.st, pp.batch, h->V, h->L, h->flags + 6, s);
     int32_t* fl = (int32_t*)(h->pinned + 384);
     HIPCHK(hipMemcpyAsync(fl, h->flags, 8 * sizeof(int32_t), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
