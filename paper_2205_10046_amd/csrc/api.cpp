@@ -661,7 +661,6 @@ EvalArgs eval_args(nep_handle* h, const Prepared& pp, const DevModel& M) {
   a.U = h->U;
   a.sums = h->sums;
   a.P = h->P;
-  a.fmap = h->V.fmap;
   a.F = h->F;
   a.W = h->W;
   a.rows = h->rows;
@@ -759,7 +758,7 @@ void build_rows_checked(nep_handle* h, const Prepared& pp, const BuildArgs& b, h
       Stage st(h, "neighbor_rows", s);
       launch_build_rows(b, pp.geo.st, pp.batch, h->V, h->L, s);
     }
-    launch_check_rows(pp.N, h->sid, h->structs, pp.geo.st, pp.batch, h->V, h->L, h->flags + 6, s);
+    launch_check_rows(pp.N, h->sid, h->structs, pp.geo.st, pp.batch, h->L, h->flags + 6, s);
     int32_t* fl = (int32_t*)(h->pinned + 384);
     HIPCHK(hipMemcpyAsync(fl, h->flags, 8 * sizeof(int32_t), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
@@ -1858,7 +1857,7 @@ int md_skin(nep_handle* h, const Prepared& pp, double* d_pos, double* d_vel, con
     skin_rebuild(h, pp, rl, nullptr, s);
     skin_filter(h, pp, s);
     launch_fill_i32(h->flags + 6, 1, 0, s);
-    launch_check_rows(N, h->sid, h->structs, pp.geo.st, pp.batch, h->V, h->L, h->flags + 6, s);
+    launch_check_rows(N, h->sid, h->structs, pp.geo.st, pp.batch, h->L, h->flags + 6, s);
     const int32_t* fl = read_flags(h, s);
     if (fl[3]) throw Failure{NEP_E_INVALID_ARG, "an atom type is out of range"};
     if (fl[4]) throw Failure{NEP_E_NONFINITE, "positions contain NaN or Inf"};
@@ -1999,7 +1998,7 @@ int md_skin(nep_handle* h, const Prepared& pp, double* d_pos, double* d_vel, con
       }
     }
     launch_check_finite(h->pos, 3 * N, h->flags + 4, s);
-    launch_check_rows(N, h->sid, h->structs, pp.geo.st, pp.batch, h->V, h->L, h->flags + 6, s);
+    launch_check_rows(N, h->sid, h->structs, pp.geo.st, pp.batch, h->L, h->flags + 6, s);
     const int32_t* fl = read_flags(h, s);
     if (fl[4]) throw Failure{NEP_E_NONFINITE, "positions became non-finite during the run"};
     if (grow_rows(h, N, fl)) {
@@ -2129,7 +2128,7 @@ static int md_impl(nep_handle* h, int64_t N, double* d_pos, double* d_vel, const
       }
     }
     launch_check_finite(h->pos, 3 * N, h->flags + 4, s);
-    launch_check_rows(N, h->sid, h->structs, pp.geo.st, pp.batch, h->V, h->L, h->flags + 6, s);
+    launch_check_rows(N, h->sid, h->structs, pp.geo.st, pp.batch, h->L, h->flags + 6, s);
     int32_t* fl = (int32_t*)(h->pinned + 384);
     HIPCHK(hipMemcpyAsync(fl, h->flags, 8 * sizeof(int32_t), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));

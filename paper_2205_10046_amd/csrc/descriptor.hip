@@ -537,14 +537,10 @@ __global__ void __launch_bounds__(kBlock, (NG * num_poly(L) > 120) ? 1 : 2)
 // ---------------------------------------------------------------------------
 
 // G lanes per atom (1 or 4) walk its radial row (lane s takes entries
-// s, s + G, ...).  dU_j/dr_ji sits in row j at the exact position of i:
-// the row entry holds c, the candidate position of i in the candidate row of
-// j (fixed between candidate rebuilds), and the filter's candidate -> exact
-// map of this step gives fmap[c][j].  The loads are pipelined in three
-// stages: the index words of the entry three ahead, the map of the entry two
-// ahead, and the partial forces (and neighbour position, for the virial) of
-// the next entry are in flight while the current one is accumulated; the lane
-// sums are combined with DPP quad sums.
+// s, s + G, ...); dU_j/dr_ji sits at position rev[m][i] of row j.  The index
+// words of a lane's entry after next and the partial forces (and neighbour
+// position, for the virial) of its next entry are loaded while the current
+// one is accumulated; the lane sums are combined with DPP quad sums.
 // VIRIAL = false leaves W untouched (MD steps without a thermo row).
 template <bool BATCH, bool VIRIAL, int G>
 __global__ void __launch_bounds__(kBlock) k_gather(EvalArgs a, StructInfo st0) {
@@ -557,7 +553,7 @@ __global__ void __launch_bounds__(kBlock) k_gather(EvalArgs a, StructInfo st0) {
   const double* __restrict__ pos = a.pos;
   const double xi = pos[i], yi = pos[N + i], zi = pos[2 * N + i];
   struct Words {
-    int32_t j, c;
+    int32_t j, r;
     uint16_t code;
   };
   auto words = [&](int m) -> Words {
@@ -565,22 +561,14 @@ __global__ void __launch_bounds__(kBlock) k_gather(EvalArgs a, StructInfo st0) {
     if (m < nn) {
       const int64_t e = (int64_t)m * N + i;
       w.j = a.L.nlR[e];
-      w.c = a.L.revR[e];
+      w.r = a.L.revR[e];
       if (VIRIAL && st.mode == kModeImages) w.code = a.L.cdR[e];
     }
     return w;
   };
-  // exact position of i in the row of w.j (clamped: a broken row is reported
-  // by the row check, and the reads stay in bounds meanwhile)
-  const int MR = a.L.MR;
-  auto slot = [&](const Words& w) -> int32_t {
-    const int32_t g = a.fmap[(int64_t)w.c * N + w.j];
-    return min(max(g, 0), MR - 1);
-  };
-  Words w0 = words(sub), w1 = words(sub + G), w2 = words(sub + 2 * G);
-  int32_t g0 = slot(w0), g1 = slot(w1);
+  Words w0 = words(sub), w1 = words(sub + G);
   float4 pij = a.P[(int64_t)min(sub, max(nn - 1, 0)) * N + i];
-  float4 pji = a.P[(int64_t)g0 * N + w0.j];
+  float4 pji = a.P[(int64_t)w0.r * N + w0.j];
   double px = 0.0, py = 0.0, pz = 0.0;
   if (VIRIAL) {
     px = pos[w0.j];
@@ -593,12 +581,9 @@ __global__ void __launch_bounds__(kBlock) k_gather(EvalArgs a, StructInfo st0) {
     const float4 cij = pij, cji = pji;
     const double cx = px, cy = py, cz = pz;
     w0 = w1;
-    g0 = g1;
-    w1 = w2;
-    g1 = slot(w1);
-    w2 = words(m + 3 * G);
+    w1 = words(m + 2 * G);
     pij = a.P[(int64_t)min(m + G, nn - 1) * N + i];
-    pji = a.P[(int64_t)g0 * N + w0.j];
+    pji = a.P[(int64_t)w0.r * N + w0.j];
     if (VIRIAL) {
       px = pos[w0.j];
       py = pos[N + w0.j];

@@ -16,11 +16,10 @@
 //      angular-range entries (|d|^2 < (r_c^A)^2) first and the rest after,
 //      each part in candidate order: the angular row of the sums is the
 //      first nnA entries of the radial row;
-//   6. every exact entry keeps the candidate position of i in the candidate
-//      row of its neighbour j (a binary search on the sorted candidate rows,
-//      once per candidate build); with the candidate -> exact position map
-//      the filter writes every step it locates i in the exact row of j, so
-//      the force gather can read dU_j/dr_ji without atomics.
+//   6. rev[m][i] locates i in the radial row of its m-th neighbour: a binary
+//      search on the sorted candidate rows (once per candidate build) and the
+//      candidate -> exact position map of every filter, so the force pass
+//      can gather dU_j/dr_ji without atomics.
 #include "nep_kernels.h"
 
 namespace nep {
@@ -572,7 +571,7 @@ __global__ void __launch_bounds__(kBlock) k_filter_rows(const double* __restrict
       V.fmap[e] = p;
       if (p < L.MR) {
         L.nlR[(int64_t)p * N + i] = V.nlR[e];
-        L.revR[(int64_t)p * N + i] = V.revR[e];  // candidate position of i in the row of j
+        L.revR[(int64_t)p * N + i] = V.revR[e];  // candidate position, resolved by the next kernel
         if (images) L.cdR[(int64_t)p * N + i] = V.cdR[e];
       }
     }
@@ -588,18 +587,56 @@ __global__ void __launch_bounds__(kBlock) k_filter_rows(const double* __restrict
   }
 }
 
+// rev of the exact rows: the filter left in L.revR[p][i] the candidate
+// position of i in the row of j = L.nlR[p][i]; the exact position there is
+// V.fmap of that candidate entry, written in place.  kRevLanes lanes per atom
+// take exact entries p = s, s + 4, ..., so a wave writes whole 64-byte runs of
+// a row; the words of a lane's next entry are loaded while the current one
+// is resolved.
+constexpr int kRevLanes = 4;
+
+__global__ void __launch_bounds__(kBlock) k_reverse_from_candidates(int64_t N, Lists V, Lists L,
+                                                                    int32_t* __restrict__ err) {
+  constexpr int G = kRevLanes;
+  const int sub = threadIdx.x & (G - 1);
+  const int64_t i = (xcd_block() * blockDim.x + threadIdx.x) / G;
+  if (i >= N) return;
+  const int nn = min(L.nnR[i], L.MR);
+  int32_t jn = 0, rn = 0;
+  if (sub < nn) {
+    const int64_t e0 = (int64_t)sub * N + i;
+    jn = L.nlR[e0];
+    rn = L.revR[e0];
+  }
+  bool broken = false;
+  for (int p = sub; p < nn; p += G) {
+    const int32_t j = jn, r = rn;
+    if (p + G < nn) {
+      const int64_t e1 = (int64_t)(p + G) * N + i;
+      jn = L.nlR[e1];
+      rn = L.revR[e1];
+    }
+    int32_t g = V.fmap[(int64_t)r * N + j];
+    if (g < 0) {
+      broken = true;
+      g = 0;
+    }
+    L.revR[(int64_t)p * N + i] = min(g, L.MR - 1);
+  }
+  if (broken) atomicExch(err, 1);
+}
+
 // Checks, for every atom i of the exact rows, the invariants under which the
 // evaluation kernels only touch memory inside their buffers: nnA <= nnR <= MR;
-// every neighbour j lies in i's structure; the candidate position c an entry
-// holds lies in j's candidate row, the exact position fmap[c][j] it maps to
-// lies in j's exact row, and that entry points back to i with the opposite
+// every neighbour j lies in i's structure; its reverse position r lies in
+// j's row (r < nnR[j]) and that entry points back to i with the opposite
 // image code; image codes stay within the structure's image reach.  Any
-// violation sets a bit of *bad (1: counts, 2: neighbour index, 4: candidate
-// or exact reverse position, 8: reverse entry, 16: image code); rows that
-// overflowed their capacity are reported by the overflow flags instead.
+// violation sets a bit of *bad (1: counts, 2: neighbour index, 4: reverse
+// position, 8: reverse entry, 16: image code); rows that overflowed their
+// capacity are reported by the overflow flags instead.
 __global__ void __launch_bounds__(kBlock) k_check_rows(int64_t N, const int32_t* __restrict__ sid,
                                                        const StructInfo* __restrict__ structs,
-                                                       StructInfo st0, int32_t batch, Lists V, Lists L,
+                                                       StructInfo st0, int32_t batch, Lists L,
                                                        int32_t* __restrict__ bad) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= N) return;
@@ -617,13 +654,9 @@ __global__ void __launch_bounds__(kBlock) k_check_rows(int64_t N, const int32_t*
       b |= 2;
       break;
     }
-    const int32_t c = L.revR[e];
-    if (c < 0 || c >= min(V.nnR[j], V.MR)) {
-      b |= 4;
-      break;
-    }
-    const int32_t r = V.fmap[(int64_t)c * N + j];
-    if (r < 0 || r >= min(L.nnR[j], L.MR)) {
+    const int32_t r = L.revR[e];
+    const int nj = L.nnR[j];
+    if (r < 0 || r >= min(nj, L.MR)) {
       b |= 4;
       break;
     }
@@ -641,9 +674,9 @@ __global__ void __launch_bounds__(kBlock) k_check_rows(int64_t N, const int32_t*
 }
 
 void launch_check_rows(int64_t N, const int32_t* sid, const StructInfo* structs, const StructInfo& st0,
-                       bool batch, const Lists& V, const Lists& L, int32_t* bad, hipStream_t s) {
+                       bool batch, const Lists& L, int32_t* bad, hipStream_t s) {
   hipLaunchKernelGGL(k_check_rows, grid_for(N), dim3(kBlock), 0, s, N, sid, structs, st0,
-                     (int32_t)(batch ? 1 : 0), V, L, bad);
+                     (int32_t)(batch ? 1 : 0), L, bad);
 }
 
 void launch_filter_rows(const BuildArgs& b, const StructInfo& st0, bool batch, const Lists& V,
@@ -655,6 +688,8 @@ void launch_filter_rows(const BuildArgs& b, const StructInfo& st0, bool batch, c
   else
     hipLaunchKernelGGL(k_filter_rows<false>, grid, dim3(kBlock), 0, s, b.pos, b.N, b.sid, b.structs,
                        st0, V, b.rcR2, b.rcA2, L, b.overflow);
+  hipLaunchKernelGGL(k_reverse_from_candidates, grid_for(b.N * kRevLanes), dim3(kBlock), 0, s,
+                     b.N, V, L, b.overflow + 2);
 }
 
 // gate = any |r_i - r_i(at last build)|^2 > thr2

@@ -7,8 +7,7 @@
 //   nl_*     int32   [M][N]           neighbour m of atom i at nl[m*N + i]
 //   cd_*     uint16  [M][N]           image offset code of that entry (exact rows:
 //                                     stored only for kModeImages structures)
-//   revR     int32   [MR][N]          position of i in the candidate row of that j
-//                                     (exact rows; candidate rows: in the candidate row)
+//   revR     int32   [MR][N]          position of i in the radial row of that j
 //   nnA                               the angular row is the first nnA[i] entries
 //                                     of the radial row
 //   V.*      int32/uint16 [MV][N]     candidate rows (radius r_c^R + skin), their

@@ -46,7 +46,6 @@ struct EvalArgs {
   float* U;                   // [N]
   float* sums;                // [nA_pad * NB][N]
   float4* P;                  // [MR][N] dU_i/dr_ij per radial entry
-  const int32_t* fmap;        // [MV][N] candidate -> exact row position of this step
   float* F;                   // [3][N] internal
   float* W;                   // [9][N] internal
   float* latent;              // [N][N_neu] w1_mu h_mu of every atom, or NULL
@@ -73,7 +72,7 @@ void launch_reverse(int64_t N, const Lists& L, int32_t* err, const int32_t* gate
 // Sets bits of *bad when the exact rows break an invariant the evaluation
 // kernels rely on for in-bounds access (see neighbor.hip).
 void launch_check_rows(int64_t N, const int32_t* sid, const StructInfo* structs, const StructInfo& st0,
-                       bool batch, const Lists& V, const Lists& L, int32_t* bad, hipStream_t s);
+                       bool batch, const Lists& L, int32_t* bad, hipStream_t s);
 void launch_build_verlet(const BuildArgs& b, const Lists& V, hipStream_t s);
 // After a gated re-sort: pos/vel/types/ext <- their permuted copies, pos_ref <- pos.
 void launch_commit_rebuild(int64_t N, const double* pos2, const double* vel2, const int32_t* types2,

@@ -72,35 +72,28 @@ class Bounds:
 
 def library_rows(pos, box, rcR, rcA):
     """Exact rows in the library's layout: angular-range entries first, then
-    the outer ones, each part in candidate ((j, image)) order.  rev[i][m] is
-    the candidate position of i in the row of its m-th neighbour (what the
-    exact entry holds) and fmap[i][c] the exact position of candidate c of
-    atom i (the filter's map)."""
+    the outer ones, each part in (j, image) order; rev[i][m] = position of i
+    in the row of its m-th neighbour."""
     R = O.pairs(pos, box, rcR)
     H = box.reshape(3, 3)
-    rows, fmap = [], []
+    rows = []
     for i, (j, sh) in enumerate(R):
         d = (pos[:, j] - pos[:, [i]]).T + sh @ H
         r2 = (d ** 2).sum(1)
         inner = [k for k in range(len(j)) if r2[k] < rcA * rcA]
         outer = [k for k in range(len(j)) if r2[k] >= rcA * rcA]
         order = inner + outer
-        rows.append((j[order], sh[order], len(inner), order))
-        fm = [0] * len(j)
-        for p, c in enumerate(order):
-            fm[c] = p
-        fmap.append(fm)
+        rows.append((j[order], sh[order], len(inner)))
     rev = []
-    for i, (j, sh, _, _) in enumerate(rows):
+    for i, (j, sh, _) in enumerate(rows):
         rv = []
         for jj, s in zip(j, sh):
-            cj, sj = R[jj]
-            hit = [k for k in range(len(cj)) if cj[k] == i and np.array_equal(sj[k], -s)]
+            jr, sr, _ = rows[jj]
+            hit = [k for k in range(len(jr)) if jr[k] == i and np.array_equal(sr[k], -s)]
             assert len(hit) == 1
-            assert rows[jj][0][fmap[jj][hit[0]]] == i   # the map leads back to i
             rv.append(hit[0])
         rev.append(rv)
-    return [r[:3] for r in rows], rev, fmap
+    return rows, rev
 
 
 def for_entries(b, N, i, first, nn, step, nl_row):
@@ -129,7 +122,7 @@ def for_entries(b, N, i, first, nn, step, nl_row):
     return out
 
 
-def replay_pair(N, capN, rows, rev, fmap, types, M, NG, block, G, force):
+def replay_pair(N, capN, rows, rev, types, M, NG, block, G, force):
     T, nR, KR, nA, KA, L, NB, NDp = (M[k] for k in ("T", "nR", "KR", "nA", "KA", "L", "NB", "NDp"))
     MR = M["MR"]
     W = ng_pad(NG)
@@ -139,7 +132,6 @@ def replay_pair(N, capN, rows, rev, fmap, types, M, NG, block, G, force):
     sR0, sA0 = 0, round4(T * T * nR * KR)
     acc0 = sA0 + round4(T * T * cA_pair)
     b = Bounds(dict(nl=MR * capN, cd=MR * capN, rev=MR * capN, P=MR * capN, pos=3 * capN,
-                    fmap=MR * capN,
                     types=capN, sums=nA * NB * capN, q=capN * NDp, fp=capN * NDp,
                     lds=lds_floats, sR=T * T * nR * KR, sA=T * T * cA_pair))
     nb = -(-N * G // block)
@@ -196,8 +188,7 @@ def replay_pair(N, capN, rows, rev, fmap, types, M, NG, block, G, force):
                         base = (ti * T + types[j[m]]) * cA_pair + g * KA * W
                         b.touch("sA", base + (KA - 1) * W + W - 1)
                         b.touch("P", m * N + i)
-    # the gather: dU_j/dr_ji at fmap[c][j] of row j, c = rev[m][i]; the map
-    # two entries ahead and the partial forces one entry ahead are prefetched
+    # the gather: dU_j/dr_ji at rev[m][i] of row j, prefetched one entry ahead
     if force:
         nbg = -(-N * G // 256)
         for blk in range(nbg):
@@ -209,18 +200,14 @@ def replay_pair(N, capN, rows, rev, fmap, types, M, NG, block, G, force):
                 sub = tid % G
                 j, _, _ = rows[i]
                 nn = len(j)
-                for m in list(range(sub, nn, G)) + [sub, sub + G, sub + 2 * G]:
+                for m in list(range(sub, nn, G)) + [sub, sub + G]:
                     mm = min(m, max(nn - 1, 0))
                     b.touch("P", mm * N + i)
-                    jm, cm = (j[m], rev[i][m]) if m < nn else (0, 0)
                     if m < nn:
-                        b.touch("nl", m * N + i)
                         b.touch("rev", m * N + i)
-                    b.touch("fmap", cm * N + jm)
-                    g = min(max(fmap[jm][cm] if m < nn else 0, 0), MR - 1)
-                    b.touch("P", g * N + jm)
-                    for c in range(3):
-                        b.touch("pos", c * N + jm)
+                        b.touch("P", rev[i][m] * N + j[m])
+                        for c in range(3):
+                            b.touch("pos", c * N + j[m])
     assert b.sizes["lds"] * 4 <= 64 * 1024
     b.check((NG, block, G, "force" if force else "descriptor"))
     return b
@@ -233,7 +220,7 @@ def test_train3_triclinic40_every_autotuned_shape_in_bounds():
     synth.random_cell(8, 0.07, 0.2, 1.5, 3, rng)
     pos, types, box = synth.random_cell(40, 0.07, 0.2, 1.5, 3, rng)
     N = pos.shape[1]
-    rows, rev, fmap = library_rows(pos, box, h["rc_radial"], h["rc_angular"])
+    rows, rev = library_rows(pos, box, h["rc_radial"], h["rc_angular"])
     vol = abs(np.linalg.det(box.reshape(3, 3)))
     MR = estimate_capacity(h["rc_radial"], N / vol)
     assert max(len(r[0]) for r in rows) <= MR
@@ -251,7 +238,7 @@ def test_train3_triclinic40_every_autotuned_shape_in_bounds():
         for block in (128, 256):
             for G in (1, 4):
                 for force in (False, True):
-                    replay_pair(N, N, rows, rev, fmap, types, M, ng, block, G, force)
+                    replay_pair(N, N, rows, rev, types, M, ng, block, G, force)
                     shapes += 1
     assert shapes == 4 * 2 * 2 * 2
 
