@@ -1091,6 +1091,306 @@ int ora_md_nve(const ora_hparams *h, const double *params, int64_t N, double *po
 }
 
 /* ===================================================================== */
+/* counter-based random numbers: Philox4x32-10                            */
+/* ===================================================================== */
+
+/* Philox4x32 with 10 rounds (Salmon, Moraes, Dror, Shaw, "Parallel random
+ * numbers: as easy as 1, 2, 3", SC'11): each round multiplies counter words
+ * 0 and 2 by the two round constants, takes high and low halves and mixes
+ * them with words 1 and 3 and the key; the key is bumped by the two Weyl
+ * constants between rounds. */
+void ora_philox4x32_10(const uint32_t ctr_in[4], const uint32_t key_in[2], uint32_t out[4]) {
+  uint32_t c0 = ctr_in[0], c1 = ctr_in[1], c2 = ctr_in[2], c3 = ctr_in[3];
+  uint32_t k0 = key_in[0], k1 = key_in[1];
+  for (int r = 0; r < 10; ++r) {
+    uint64_t p0 = (uint64_t)0xD2511F53u * c0;
+    uint64_t p1 = (uint64_t)0xCD9E8D57u * c2;
+    uint32_t hi0 = (uint32_t)(p0 >> 32), lo0 = (uint32_t)p0;
+    uint32_t hi1 = (uint32_t)(p1 >> 32), lo1 = (uint32_t)p1;
+    uint32_t n0 = hi1 ^ c1 ^ k0, n2 = hi0 ^ c3 ^ k1;
+    c0 = n0;
+    c1 = lo1;
+    c2 = n2;
+    c3 = lo0;
+    k0 += 0x9E3779B9u;
+    k1 += 0xBB67AE85u;
+  }
+  out[0] = c0;
+  out[1] = c1;
+  out[2] = c2;
+  out[3] = c3;
+}
+
+/* Four standard normal numbers from counter (index, step, stream, 0) under
+ * the 64-bit seed: the four Philox words as uniforms (x + 1/2) 2^-32 in
+ * (0, 1), turned into normals pairwise by the Box-Muller transform. */
+void ora_normal4(uint64_t seed, uint32_t index, uint32_t step, uint32_t stream, double z[4]) {
+  const uint32_t ctr[4] = {index, step, stream, 0u};
+  const uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+  uint32_t w[4];
+  ora_philox4x32_10(ctr, key, w);
+  for (int p = 0; p < 2; ++p) {
+    double u1 = ((double)w[2 * p] + 0.5) * (1.0 / 4294967296.0);
+    double u2 = ((double)w[2 * p + 1] + 0.5) * (1.0 / 4294967296.0);
+    double rad = sqrt(-2.0 * log(u1));
+    z[2 * p] = rad * cos(2.0 * M_PI * u2);
+    z[2 * p + 1] = rad * sin(2.0 * M_PI * u2);
+  }
+}
+
+/* ===================================================================== */
+/* thermostats and barostats (the NVT and NPT ensembles of Sec. II.F)     */
+/* ===================================================================== */
+
+/* The paper lists the ensembles GPUMD offers and cites their methods without
+ * restating them; each follows its publication:
+ *   1 Berendsen thermostat (Berendsen et al. 1984): after a velocity-Verlet
+ *     step, v *= sqrt(1 + dt/tau (T0/T - 1)).
+ *   2 Bussi-Donadio-Parrinello stochastic velocity rescaling (2007): the
+ *     kinetic energy K is replaced by
+ *     K + (1-c)(K0 (R1^2 + S)/Nf - K) + 2 R1 sqrt(c (1-c) K0 K / Nf),
+ *     c = exp(-dt/tau), K0 = Nf kB T0 / 2, R1 normal, S a sum of Nf - 1
+ *     squared normals; v *= sqrt(K'/K).
+ *   3 Langevin dynamics in the Bussi-Parrinello (2007) splitting: a half-step
+ *     Ornstein-Uhlenbeck update v = c1 v + sqrt((1 - c1^2) kB T0 / m) xi,
+ *     c1 = exp(-dt / (2 tau)), before and after the velocity-Verlet step.
+ *   4 Nose-Hoover chain (Martyna, Klein, Tuckerman 1992) of length M with
+ *     masses Q1 = Nf kB T0 tau^2, Qk = kB T0 tau^2, integrated by the Trotter
+ *     splitting chain(dt/2), velocity Verlet, chain(dt/2) (Martyna et al.
+ *     1996, one sub-step).
+ *   5 Berendsen barostat (isotropic) with the Berendsen thermostat: after
+ *     the thermostat, P = (2K + tr W)/(3V); box and positions scale by
+ *     mu = (1 - beta dt/tau_p (P0 - P))^(1/3).
+ *   6 Stochastic cell rescaling (Bernetti, Bussi 2020, isotropic) with the
+ *     BDP thermostat: d eps = -(beta/tau_p)(P0 - P - kB T0/V) dt
+ *     + sqrt(2 kB T0 beta dt / (V tau_p)) R, eps = ln V; positions and box
+ *     scale by exp(d eps / 3), velocities by exp(-d eps / 3).
+ * Nf = 3N - 3.  Random numbers come from ora_normal4 with counter
+ * (index, step, stream): Langevin streams 1 and 2 (the two half steps,
+ * index = atom), BDP stream 3 (R1 = the first normal of index 0) and 4 (the
+ * Nf - 1 normals of S, four per index in order), SCR stream 5 (index 0).
+ * The step in the counter is state[0] + the step number (1-based) of this
+ * call, so consecutive calls continue one stream.
+ *
+ * state (in/out, 20 doubles): [0] steps done before this call; [1] energy
+ * taken out of the system by thermostat and barostat so far (so that
+ * K + U (+ P0 V for NPT) + state[1] is the effective energy H~; for the
+ * Nose-Hoover chain H~ adds the chain's own energy instead); [2..9] chain
+ * positions xi_k; [10..17] chain velocities v_xi_k.
+ * Thermo rows of 16: step, E_pot, E_kin, T, W (9), V, P (GPa), H~. */
+
+#define ORA_GPA (160.21766208)  /* 1 eV/A^3 in GPa */
+
+typedef struct {
+  int32_t kind;
+  double temperature, tau_t;
+  int32_t nhc_length;
+  double pressure, tau_p, compressibility;
+  uint64_t seed;
+} ora_ensemble;
+
+static double kinetic(int64_t N, const double *vel, const int32_t *types, const double *mass,
+                      double conv) {
+  double k = 0.0;
+  for (int64_t i = 0; i < N; ++i) {
+    double m = mass[types[i]];
+    for (int c = 0; c < 3; ++c) k += 0.5 * m * vel[c * N + i] * vel[c * N + i];
+  }
+  return k * conv;
+}
+
+static void scale_vel(int64_t N, double *vel, double s) {
+  for (int64_t i = 0; i < 3 * N; ++i) vel[i] *= s;
+}
+
+/* Chain half step of length dt/2 (MKT 1992 / Martyna et al. 1996): returns
+ * the velocity scale and updates xi, v_xi; K is the current kinetic energy. */
+static double nhc_half(int M, double dt, double K, double Nf, double kT, double tau, double *xi,
+                       double *vx) {
+  double Q[8];
+  for (int k = 0; k < M; ++k) Q[k] = (k == 0 ? Nf : 1.0) * kT * tau * tau;
+  const double h = 0.5 * dt;
+  double G;
+#define ORA_G(k) ((k) == 0 ? (2.0 * K - Nf * kT) / Q[0] : (Q[(k)-1] * vx[(k)-1] * vx[(k)-1] - kT) / Q[k])
+  G = ORA_G(M - 1);
+  vx[M - 1] += 0.5 * h * G;
+  for (int k = M - 2; k >= 0; --k) {
+    double a = exp(-0.25 * h * vx[k + 1]);
+    vx[k] *= a;
+    G = ORA_G(k);
+    vx[k] += 0.5 * h * G;
+    vx[k] *= a;
+  }
+  double s = exp(-h * vx[0]);
+  K *= s * s;
+  for (int k = 0; k < M; ++k) xi[k] += h * vx[k];
+  for (int k = 0; k < M - 1; ++k) {
+    double a = exp(-0.25 * h * vx[k + 1]);
+    vx[k] *= a;
+    G = ORA_G(k);
+    vx[k] += 0.5 * h * G;
+    vx[k] *= a;
+  }
+  G = ORA_G(M - 1);
+  vx[M - 1] += 0.5 * h * G;
+#undef ORA_G
+  return s;
+}
+
+/* Box volume from the rows of H. */
+static double volume(const double *H) {
+  return H[0] * (H[4] * H[8] - H[5] * H[7]) - H[1] * (H[3] * H[8] - H[5] * H[6]) +
+         H[2] * (H[3] * H[7] - H[4] * H[6]);
+}
+
+/* BDP kinetic-energy resampling; returns the new kinetic energy. */
+static double bdp_target(double K, double K0, double Nf, double c, uint64_t seed, uint32_t step) {
+  double z[4];
+  ora_normal4(seed, 0u, step, 3u, z);
+  const double R1 = z[0];
+  double S = 0.0;
+  const int64_t nS = (int64_t)Nf - 1;
+  for (int64_t k = 0; k < nS; k += 4) {
+    ora_normal4(seed, (uint32_t)(k / 4), step, 4u, z);
+    for (int q = 0; q < 4 && k + q < nS; ++q) S += z[q] * z[q];
+  }
+  return K + (1.0 - c) * (K0 * (R1 * R1 + S) / Nf - K) + 2.0 * R1 * sqrt(c * (1.0 - c) * K0 * K / Nf);
+}
+
+int ora_md_ensemble(const ora_hparams *h, const double *params, int64_t N, double *pos,
+                    double *vel, const int32_t *types, const double *mass, double *box,
+                    const int32_t *pbc, double dt, int64_t n_steps, int64_t thermo_every,
+                    double *thermo, const ora_ensemble *ens, double *state) {
+  if (ens->kind < 0 || ens->kind > 6 || N < 2) return ORA_EARG;
+  const int M = ens->nhc_length;
+  if (ens->kind == 4 && (M < 1 || M > 8)) return ORA_EARG;
+  double conv = amu_a2_fs2_ev();
+  const double Nf = 3.0 * N - 3.0, kT = ORA_KB * ens->temperature;
+  const double K0 = 0.5 * Nf * kT;
+  double *F = (double *)malloc(sizeof(double) * 3 * N);
+  double *U = (double *)malloc(sizeof(double) * N);
+  double *W = (double *)malloc(sizeof(double) * 9 * N);
+  if (!F || !U || !W) return ORA_EMEM;
+  int err = ora_evaluate(h, params, N, pos, types, box, pbc, U, F, W, NULL);
+  int64_t row = 0;
+  double *xi = state + 2, *vx = state + 10;
+  for (int64_t step = 1; step <= n_steps && err == ORA_OK; ++step) {
+    const uint32_t rstep = (uint32_t)((int64_t)state[0] + step);
+    if (ens->kind == 4) {
+      double s = nhc_half(M, dt, kinetic(N, vel, types, mass, conv), Nf, kT, ens->tau_t, xi, vx);
+      scale_vel(N, vel, s);
+    }
+    if (ens->kind == 3) {  /* first Ornstein-Uhlenbeck half step */
+      double c1 = exp(-0.5 * dt / ens->tau_t), k_before = kinetic(N, vel, types, mass, conv);
+      for (int64_t i = 0; i < N; ++i) {
+        double z[4], m = mass[types[i]] * conv;
+        ora_normal4(ens->seed, (uint32_t)i, rstep, 1u, z);
+        for (int c = 0; c < 3; ++c)
+          vel[c * N + i] = c1 * vel[c * N + i] + sqrt((1.0 - c1 * c1) * kT / m) * z[c];
+      }
+      state[1] += k_before - kinetic(N, vel, types, mass, conv);
+    }
+    for (int64_t i = 0; i < N; ++i) {
+      double a = 1.0 / (mass[types[i]] * conv);
+      for (int c = 0; c < 3; ++c) {
+        vel[c * N + i] += 0.5 * dt * F[c * N + i] * a;
+        pos[c * N + i] += dt * vel[c * N + i];
+      }
+    }
+    err = ora_evaluate(h, params, N, pos, types, box, pbc, U, F, W, NULL);
+    if (err) break;
+    for (int64_t i = 0; i < N; ++i) {
+      double a = 1.0 / (mass[types[i]] * conv);
+      for (int c = 0; c < 3; ++c) vel[c * N + i] += 0.5 * dt * F[c * N + i] * a;
+    }
+    double K = kinetic(N, vel, types, mass, conv);
+    if (ens->kind == 3) {  /* second Ornstein-Uhlenbeck half step */
+      double c1 = exp(-0.5 * dt / ens->tau_t);
+      for (int64_t i = 0; i < N; ++i) {
+        double z[4], m = mass[types[i]] * conv;
+        ora_normal4(ens->seed, (uint32_t)i, rstep, 2u, z);
+        for (int c = 0; c < 3; ++c)
+          vel[c * N + i] = c1 * vel[c * N + i] + sqrt((1.0 - c1 * c1) * kT / m) * z[c];
+      }
+      double Kn = kinetic(N, vel, types, mass, conv);
+      state[1] += K - Kn;
+      K = Kn;
+    } else if (ens->kind == 1 || ens->kind == 5) {  /* Berendsen */
+      double T = 2.0 * K / (Nf * ORA_KB);
+      double l2 = 1.0 + dt / ens->tau_t * (ens->temperature / T - 1.0);
+      if (l2 < 0.0) l2 = 0.0;
+      scale_vel(N, vel, sqrt(l2));
+      state[1] += K * (1.0 - l2);
+      K *= l2;
+    } else if (ens->kind == 2 || ens->kind == 6) {  /* BDP */
+      double Kn = bdp_target(K, K0, Nf, exp(-dt / ens->tau_t), ens->seed, rstep);
+      if (Kn < 0.0) Kn = 0.0;
+      scale_vel(N, vel, sqrt(Kn / K));
+      state[1] += K - Kn;
+      K = Kn;
+    } else if (ens->kind == 4) {
+      double s = nhc_half(M, dt, K, Nf, kT, ens->tau_t, xi, vx);
+      scale_vel(N, vel, s);
+      K *= s * s;
+    }
+    /* pressure of the state at the end of the step (before any box change) */
+    double V = volume(box);
+    double wtr = 0.0;
+    for (int64_t i = 0; i < N; ++i) wtr += W[0 * N + i] + W[4 * N + i] + W[8 * N + i];
+    const double P = (2.0 * K + wtr) / (3.0 * V) * ORA_GPA;
+    if (thermo_every > 0 && step % thermo_every == 0) {
+      double ep = 0.0, wt[9] = {0};
+      for (int64_t i = 0; i < N; ++i) {
+        ep += U[i];
+        for (int v = 0; v < 9; ++v) wt[v] += W[v * N + i];
+      }
+      double *t = thermo + 16 * row++;
+      t[0] = (double)step;
+      t[1] = ep;
+      t[2] = K;
+      t[3] = 2.0 * K / (Nf * ORA_KB);
+      for (int v = 0; v < 9; ++v) t[4 + v] = wt[v];
+      t[13] = V;
+      t[14] = P;
+      double Hx = K + ep + state[1];
+      if (ens->kind == 4) {
+        Hx = K + ep;
+        for (int k = 0; k < M; ++k) {
+          double Q = (k == 0 ? Nf : 1.0) * kT * ens->tau_t * ens->tau_t;
+          Hx += 0.5 * Q * vx[k] * vx[k] + (k == 0 ? Nf : 1.0) * kT * xi[k];
+        }
+      }
+      if (ens->kind >= 5) Hx += ens->pressure / ORA_GPA * V;
+      t[15] = Hx;
+    }
+    /* barostat: scale the box and the positions (and for SCR the velocities);
+     * the next step starts from the forces of the unscaled positions */
+    if (ens->kind == 5 || ens->kind == 6) {
+      double mu;
+      if (ens->kind == 5) {
+        mu = cbrt(1.0 - ens->compressibility * dt / ens->tau_p * (ens->pressure - P));
+      } else {
+        double z[4];
+        ora_normal4(ens->seed, 0u, rstep, 5u, z);
+        double kTV = kT / V * ORA_GPA;
+        double deps = -ens->compressibility / ens->tau_p * (ens->pressure - P - kTV) * dt +
+                      sqrt(2.0 * kTV * ens->compressibility * dt / ens->tau_p) * z[0];
+        mu = exp(deps / 3.0);
+        scale_vel(N, vel, 1.0 / mu);
+        state[1] += K - K / (mu * mu);
+      }
+      for (int64_t i = 0; i < 3 * N; ++i) pos[i] *= mu;
+      for (int k = 0; k < 9; ++k) box[k] *= mu;
+    }
+  }
+  state[0] += (double)n_steps;
+  free(F);
+  free(U);
+  free(W);
+  return err;
+}
+
+/* ===================================================================== */
 /* threads                                                                */
 /* ===================================================================== */
 

@@ -82,11 +82,28 @@ def lib():
                                          i64, pi64, pd, pd, pd]
         L.ora_md_nve.argtypes = [hp, pd, i64, pd, pd, pi32, pd, pd, pi32, d,
                                  i64, i64, pd]
+        L.ora_philox4x32_10.argtypes = [C.POINTER(C.c_uint32), C.POINTER(C.c_uint32),
+                                        C.POINTER(C.c_uint32)]
+        L.ora_philox4x32_10.restype = None
+        L.ora_normal4.argtypes = [C.c_uint64, C.c_uint32, C.c_uint32, C.c_uint32, pd]
+        L.ora_normal4.restype = None
+        L.ora_md_ensemble.argtypes = [hp, pd, i64, pd, pd, pi32, pd, pd, pi32, d, i64, i64, pd,
+                                      C.POINTER(_Ensemble), pd]
         L.ora_set_threads.argtypes = [C.c_int]
         L.ora_set_threads.restype = None
         L.ora_get_threads.restype = C.c_int
         _lib = L
     return _lib
+
+
+class _Ensemble(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("temperature", C.c_double), ("tau_t", C.c_double),
+                ("nhc_length", C.c_int32), ("pressure", C.c_double), ("tau_p", C.c_double),
+                ("compressibility", C.c_double), ("seed", C.c_uint64)]
+
+
+ENSEMBLES = {"nve": 0, "nvt_berendsen": 1, "nvt_bdp": 2, "nvt_langevin": 3, "nvt_nhc": 4,
+             "npt_berendsen": 5, "npt_scr": 6}
 
 
 def _hp(h):
@@ -310,6 +327,86 @@ def md_nve(h, params, pos, vel, types, mass_per_type, box, dt, n_steps,
     if err:
         raise RuntimeError(f"ora_md_nve failed ({err})")
     return pos, vel, th[:rows]
+
+
+def philox4x32_10(ctr, key):
+    """Philox4x32-10 (Salmon et al. 2011) of a 4-word counter and 2-word key."""
+    c = (C.c_uint32 * 4)(*ctr)
+    k = (C.c_uint32 * 2)(*key)
+    o = (C.c_uint32 * 4)()
+    lib().ora_philox4x32_10(c, k, o)
+    return [int(x) for x in o]
+
+
+def normal4(seed, index, step, stream):
+    """Four standard normals of counter (index, step, stream) under seed."""
+    z = np.zeros(4)
+    lib().ora_normal4(int(seed), int(index), int(step), int(stream), _p(z, C.c_double))
+    return z
+
+
+def md_ensemble(h, params, pos, vel, types, mass_per_type, box, dt, n_steps, thermo_every,
+                ens, state=None, pbc=None):
+    """MD in one of the ensembles (see ora_md_ensemble): ens is a dict with
+    kind (a name of ENSEMBLES), temperature (K), tau_t (fs), nhc_length,
+    pressure (GPa), tau_p (fs), compressibility (1/GPa), seed.  Returns
+    (pos, vel, box, thermo rows (n_rows, 16), state (20,))."""
+    e = _Ensemble(kind=ENSEMBLES[ens["kind"]], temperature=ens.get("temperature", 300.0),
+                  tau_t=ens.get("tau_t", 100.0), nhc_length=ens.get("nhc_length", 4),
+                  pressure=ens.get("pressure", 0.0), tau_p=ens.get("tau_p", 1000.0),
+                  compressibility=ens.get("compressibility", 0.01), seed=ens.get("seed", 0))
+    params = _f64(params)
+    pos = _f64(pos).copy()
+    vel = _f64(vel).copy()
+    box = _f64(box).copy()
+    types = _i32(types)
+    m = _f64(mass_per_type)
+    st = np.zeros(20) if state is None else _f64(state).copy()
+    rows = n_steps // thermo_every if thermo_every > 0 else 0
+    th = np.zeros((max(rows, 1), 16))
+    err = lib().ora_md_ensemble(C.byref(_hp(h)), _p(params, C.c_double), pos.shape[1],
+                                _p(pos, C.c_double), _p(vel, C.c_double), _p(types, C.c_int32),
+                                _p(m, C.c_double), _p(box, C.c_double), _p(_pbc(pbc), C.c_int32),
+                                float(dt), int(n_steps), int(thermo_every),
+                                _p(th, C.c_double), C.byref(e), _p(st, C.c_double))
+    if err:
+        raise RuntimeError(f"ora_md_ensemble failed ({err})")
+    return pos, vel, box, th[:rows], st
+
+
+# ---------------------------------------------------------------------------
+# elastic constants of a cubic crystal by the energy-strain relation
+# (Sec. V "Elastic constants": +-1 % strains)
+# ---------------------------------------------------------------------------
+
+EV_A3_GPA = 160.21766208
+
+
+def strained(pos, box, eps):
+    """Positions and box under the homogeneous deformation r -> (I + eps) r."""
+    Fm = np.eye(3) + np.asarray(eps, float)
+    return (Fm @ np.asarray(pos, float)), (np.asarray(box, float).reshape(3, 3) @ Fm.T).ravel()
+
+
+def elastic_cubic(h, params, pos, types, box, delta=0.01):
+    """C11, C12, C44 (GPa) from energies at +-delta strains: uniaxial xx
+    (E'' = V C11), biaxial xx = yy (E'' = 2 V (C11 + C12)) and shear
+    xy = yx = delta/2 (E'' = V C44), each second derivative by the central
+    difference (E(+) + E(-) - 2 E(0)) / delta^2.  Atoms are not relaxed."""
+    V = abs(np.linalg.det(np.asarray(box, float).reshape(3, 3)))
+
+    def energy(eps):
+        p, b = strained(pos, box, eps)
+        return evaluate(h, params, p, types, b)["U"].sum()
+    e0 = energy(np.zeros((3, 3)))
+
+    def second(eps):
+        e = np.asarray(eps, float) * delta
+        return (energy(e) + energy(-e) - 2.0 * e0) / (delta * delta)
+    c11 = second([[1, 0, 0], [0, 0, 0], [0, 0, 0]]) / V
+    c11_12 = second([[1, 0, 0], [0, 1, 0], [0, 0, 0]]) / (2.0 * V)
+    c44 = second([[0, 0.5, 0], [0.5, 0, 0], [0, 0, 0]]) / V
+    return np.array([c11, c11_12 - c11, c44]) * EV_A3_GPA
 
 
 # ---------------------------------------------------------------------------
