@@ -258,6 +258,70 @@ int nep_md_run_dev(nep_handle *h, int64_t n_atoms, double *pos, double *vel,
                    int64_t n_steps, int64_t thermo_every, double *thermo,
                    void *stream);
 
+/* ---- NVT and NPT ensembles (Sec. II.F lists them; each follows its own
+ * publication) ----
+ *   NEP_ENS_BERENDSEN      after each velocity-Verlet step v *= sqrt(1 + dt/tau_t (T0/T - 1))
+ *                          (Berendsen et al. 1984)
+ *   NEP_ENS_BDP            stochastic velocity rescaling (Bussi, Donadio, Parrinello 2007):
+ *                          K' = K + (1-c)(K0 (R1^2 + S)/Nf - K) + 2 R1 sqrt(c (1-c) K0 K / Nf),
+ *                          c = exp(-dt/tau_t), K0 = Nf kB T0 / 2, S = a sum of Nf - 1 squared normals
+ *   NEP_ENS_LANGEVIN       Bussi-Parrinello (2007) splitting: v = c1 v + sqrt((1 - c1^2) kB T0/m) xi,
+ *                          c1 = exp(-dt/(2 tau_t)), before and after each velocity-Verlet step
+ *   NEP_ENS_NHC            Nose-Hoover chain of nhc_length (Martyna, Klein, Tuckerman 1992),
+ *                          Q1 = Nf kB T0 tau_t^2, Qk = kB T0 tau_t^2, Trotter-split around the step
+ *   NEP_ENS_NPT_BERENDSEN  Berendsen thermostat, then P = (2K + tr W)/(3V) and box and positions
+ *                          scaled by mu = (1 - beta dt/tau_p (P0 - P))^(1/3)
+ *   NEP_ENS_NPT_SCR        BDP thermostat, then stochastic cell rescaling (Bernetti, Bussi 2020):
+ *                          d eps = -(beta/tau_p)(P0 - P - kB T0/V) dt + sqrt(2 kB T0 beta dt/(V tau_p)) R,
+ *                          positions and box scaled by exp(d eps/3), velocities by exp(-d eps/3)
+ * Nf = 3N - 3.  Order of one step: chain half step (NHC) or Ornstein-Uhlenbeck
+ * half step (Langevin); v += dt/2 F/m; r += dt v; forces; v += dt/2 F/m;
+ * thermostat; P; thermo row; barostat (the next step starts from the forces
+ * of the unscaled positions).  Random numbers: Philox4x32-10 (Salmon et al.
+ * 2011) of the counter (index, step, stream, 0) under the key (seed low word,
+ * seed high word), each call giving four normals by the Box-Muller
+ * transform of the uniform pairs (w0, w1), (w2, w3), u = (w + 1/2) 2^-32;
+ * step = state[0] + the 1-based step of the call; Langevin: streams 1 and 2
+ * (the two half steps), index = the caller's atom index, normals x, y, z;
+ * BDP: R1 = the first normal of stream 3 index 0, S from stream 4 (the
+ * normals of indices 0, 1, ... in order); SCR: stream 5 index 0. */
+#define NEP_ENS_NVE 0
+#define NEP_ENS_BERENDSEN 1
+#define NEP_ENS_BDP 2
+#define NEP_ENS_LANGEVIN 3
+#define NEP_ENS_NHC 4
+#define NEP_ENS_NPT_BERENDSEN 5
+#define NEP_ENS_NPT_SCR 6
+
+typedef struct nep_ensemble {
+  int32_t kind;             /* NEP_ENS_* */
+  double temperature;       /* T0 (K) */
+  double tau_t;             /* thermostat time (fs): coupling time, 1/friction, chain period */
+  int32_t nhc_length;       /* chain length, 1..8 (NEP_ENS_NHC) */
+  double pressure;          /* P0 (GPa, NPT) */
+  double tau_p;             /* barostat time (fs, NPT) */
+  double compressibility;   /* beta (1/GPa, NPT) */
+  uint64_t seed;            /* key of the random streams */
+} nep_ensemble;
+
+/* Molecular dynamics in one of the ensembles above (NEP_ENS_NVE: the steps
+ * of nep_md_run with these rows).  Host arrays as in nep_md_run; box (host, inout) returns the
+ * final cell for NPT; thermo rows of 16 doubles [step, E_pot, E_kin, T,
+ * W_xx .. W_zz, V (A^3), P (GPa), H~] of the end-of-step state (before the
+ * barostat); H~ = E_kin + E_pot + state[1] (+ P0 V for NPT), and for NHC
+ * E_kin + E_pot + sum_k (Q_k v_xik^2 / 2 + (Nf if k = 0 else 1) kB T0 xi_k).
+ * state (host, inout, 20 doubles, zeros to start): [0] steps done (the step
+ * word of the random counters, a whole number below 2^32), [1] energy taken
+ * out by thermostat and barostat, [2..9] chain positions, [10..17] chain
+ * velocities (1/fs); passing it to the next call continues the run exactly.
+ * NPT fails with NEP_E_BOX if the cell shrinks more than 3 % (linear) within
+ * one call; a new call from the returned state continues.  Synchronous. */
+int nep_md_run_ensemble(nep_handle *h, int64_t n_atoms, double *pos, double *vel,
+                        const int32_t *types, const double *mass_per_type, double box[9],
+                        const int32_t pbc[3], double dt_fs, int64_t n_steps,
+                        int64_t thermo_every, double *thermo, const nep_ensemble *ens,
+                        double state[20]);
+
 /* Energies, forces and virials of n_struct structures for n_param_sets
  * parameter vectors in one call: the population evaluation of the SNES
  * trainer (Sec. II.E) on a training-style batch.  Structure s holds atoms

@@ -307,6 +307,9 @@ struct nep_handle {
   hipGraphExec_t md_exec = nullptr;
   std::vector<unsigned char> md_key;
   hipStream_t md_stream = nullptr;  // capture/replay stream for null-stream callers
+  double* ens_state = nullptr;      // ensemble state, its chunk save and the saved cell
+  double* ens_partial = nullptr;    // ensemble reduction partials
+  int64_t ens_partial_cap = 0;
   DevModel& M = main.M;
   // workspace
   int64_t capN = 0, cap_part = 0, rows_cap = 0;
@@ -355,6 +358,8 @@ struct nep_handle {
     if (pinned) (void)hipHostFree(pinned);
     pinned = nullptr;
     dev_free(loss_part); dev_free(loss_offs); dev_free(snes_util); dev_free(heat_part);
+    dev_free(ens_state); dev_free(ens_partial);
+    ens_partial_cap = 0;
     heat_part_cap = 0;
     loss_part_cap = loss_offs_cap = 0;
     main.release();
@@ -1785,7 +1790,8 @@ namespace {
 // Rebuild now from the current internal state: re-sort into cell order
 // (velocities and caller indices follow), remember the positions, and build
 // the candidate rows.  gate = NULL runs unconditionally.
-void skin_rebuild(nep_handle* h, const Prepared& pp, double rl, const int32_t* gate, hipStream_t s) {
+void skin_rebuild(nep_handle* h, const Prepared& pp, double rl, const int32_t* gate, hipStream_t s,
+                  double* mu_cum = nullptr) {
   const int64_t N = pp.N;
   BuildArgs br = build_args(h, pp, h->pos, h->types, h->pos2, h->types2);
   br.ext_src = h->ext_id;
@@ -1796,7 +1802,7 @@ void skin_rebuild(nep_handle* h, const Prepared& pp, double rl, const int32_t* g
   br.ext_out = h->ext_id2;
   launch_order_atoms(br, s);
   launch_commit_rebuild(N, h->pos2, h->vel2, h->types2, h->ext_id2, h->pos, h->vel, h->types,
-                        h->ext_id, h->pos_ref, gate, s);
+                        h->ext_id, h->pos_ref, gate, s, mu_cum);
   BuildArgs bv = build_args(h, pp, nullptr, nullptr, h->pos, h->types);
   bv.rcR2 = rl * rl;
   bv.gate = gate;
@@ -1830,17 +1836,67 @@ int32_t* read_flags(nep_handle* h, hipStream_t s) {
   return fl;
 }
 
+// NPT: the cell grid and the minimum-image rule were set up for the box at
+// the start of the call (with headroom); fail clearly once the box has
+// shrunk past them (a new call sets them up for the current box).
+void check_npt_cell(const StructInfo& now, const StructInfo& start, double rl) {
+  for (int k = 0; k < 3; ++k) {
+    if (!now.pbc[k]) continue;
+    const double* u = now.H + 3 * ((k + 1) % 3);
+    const double* v = now.H + 3 * ((k + 2) % 3);
+    const double cx = u[1] * v[2] - u[2] * v[1], cy = u[2] * v[0] - u[0] * v[2], cz = u[0] * v[1] - u[1] * v[0];
+    const double* a = now.H + 3 * k;
+    const double w = std::fabs(a[0] * cx + a[1] * cy + a[2] * cz) / std::sqrt(cx * cx + cy * cy + cz * cz);
+    const bool cells_ok = start.mode != kModeCells || w / start.ncell[k] >= rl;
+    const bool image_ok = start.mode == kModeImages || w > 2.0 * rl;
+    if (!cells_ok || !image_ok)
+      throw Failure{NEP_E_BOX, "the box shrank past the cell grid set up at the start of the call; "
+                               "continue with a new call from the returned state"};
+  }
+}
+
 // Velocity Verlet with candidate rows at r_c^R + skin, rebuilt on the device
 // when an atom has moved more than skin / 2 since the last build; the exact
 // rows are filtered from them every step.
 int md_skin(nep_handle* h, const Prepared& pp, double* d_pos, double* d_vel, const int32_t* d_types,
             double dt, int64_t n_steps, int64_t thermo_every, double* thermo_out, bool thermo_on_host,
-            int64_t n_rows, hipStream_t s) {
+            int64_t n_rows, hipStream_t s, const EnsParams* ep = nullptr, double* ens_state = nullptr,
+            double* box_out = nullptr) {
   const int64_t N = pp.N;
   const double skin = h->hp.skin, rl = h->hp.rc_radial + skin;
   const double thr2 = 0.25 * skin * skin;
   int32_t* gate = h->flags + 7;
   ensure_verlet(h, N, std::max(h->V.MR, estimate_capacity(rl, (double)N / pp.geo.volume)));
+  // ensemble state on the device (thermostats and barostats)
+  const bool ens = ep != nullptr;
+  const bool npt = ens && ep->kind >= kEnsNptBerendsen;
+  const int64_t step_base = ens ? (int64_t)ens_state[0] : 0;
+  const int row_len = ens ? 16 : 13;
+  EnsState* est = nullptr;
+  double* mu_cum = nullptr;
+  if (ens) {
+    // [state][saved state][saved structure 0], 256-byte aligned parts
+    if (!h->ens_state) dev_alloc(h->ens_state, 3 * 512 / sizeof(double));
+    static_assert(sizeof(StructInfo) <= 512, "staging slot");
+    const int64_t need = std::max<int64_t>(ens_partials(N), div_up(N, 256) + 1) + 1;
+    if (need > h->ens_partial_cap) {
+      dev_alloc(h->ens_partial, (size_t)need);
+      h->ens_partial_cap = need;
+    }
+    est = (EnsState*)h->ens_state;
+    EnsState init{};
+    init.heat = ens_state[1];
+    for (int k = 0; k < kMaxChain; ++k) {
+      init.xi[k] = ens_state[2 + k];
+      init.vxi[k] = ens_state[10 + k];
+    }
+    init.step = step_base;
+    init.mu = init.mu_cum = init.scale = 1.0;
+    static_assert(sizeof(EnsState) <= 512, "staging slot");
+    std::memcpy(h->pinned + 1024, &init, sizeof init);
+    HIPCHK(hipMemcpyAsync(est, h->pinned + 1024, sizeof init, hipMemcpyHostToDevice, s));
+    if (npt) mu_cum = &est->mu_cum;
+  }
   // initial order from the caller arrays
   {
     BuildArgs b0 = build_args(h, pp, d_pos, d_types, h->pos, h->types);
@@ -1854,7 +1910,7 @@ int md_skin(nep_handle* h, const Prepared& pp, double* d_pos, double* d_vel, con
   for (int attempt = 0;; ++attempt) {
     launch_fill_i32(h->flags, 3, 0, s);
     launch_fill_i32(h->flags + 5, 1, 0, s);
-    skin_rebuild(h, pp, rl, nullptr, s);
+    skin_rebuild(h, pp, rl, nullptr, s, mu_cum);
     skin_filter(h, pp, s);
     launch_fill_i32(h->flags + 6, 1, 0, s);
     launch_check_rows(N, h->sid, h->structs, pp.geo.st, pp.batch, h->L, h->flags + 6, s);
@@ -1877,8 +1933,21 @@ int md_skin(nep_handle* h, const Prepared& pp, double* d_pos, double* d_vel, con
   md.pos = h->pos;
   md.vel = h->vel;
   md.types = h->types;
-  // one MD step with a device-decided rebuild (a fixed kernel sequence)
-  auto step_body = [&](hipStream_t cs, bool virial) {
+  // one MD step with a device-decided rebuild (a fixed kernel sequence); in
+  // an ensemble run the thermostat and barostat kernels around it follow the
+  // order of the ensembles' publications (see nep.h), and `row` writes the
+  // step's thermo row before the barostat acts
+  auto step_body = [&](hipStream_t cs, bool virial, bool row) {
+    if (ens) {
+      Stage st(h, "ensemble", cs);
+      launch_ens_step_begin(est, cs);
+      if (ep->kind == kEnsNHC) {
+        launch_ens_kinetic(h->vel, h->types, h->mass, N, kAmuA2fs2, h->ens_partial, est, cs);
+        launch_ens_thermostat(h->vel, N, *ep, est, h->ens_partial, cs);
+      } else if (ep->kind == kEnsLangevin) {
+        launch_ens_langevin(h->vel, h->types, h->mass, h->ext_id, N, *ep, 1u, est, h->ens_partial, cs);
+      }
+    }
     {
       Stage st(h, "integrate", cs);
       launch_kick_drift(md, cs);
@@ -1886,17 +1955,31 @@ int md_skin(nep_handle* h, const Prepared& pp, double* d_pos, double* d_vel, con
     {
       Stage st(h, "order_atoms", cs);
       launch_fill_i32(gate, 1, 0, cs);
-      launch_check_displacement(h->pos, h->pos_ref, N, thr2, gate, cs);
-      skin_rebuild(h, pp, rl, gate, cs);
+      launch_check_displacement(h->pos, h->pos_ref, N, thr2, gate, cs, mu_cum, h->hp.rc_radial, rl);
+      skin_rebuild(h, pp, rl, gate, cs, mu_cum);
     }
     {
       Stage st(h, "neighbor_rows", cs);
       skin_filter(h, pp, cs);
     }
-    forces(h, pp, cs, nullptr, virial);
+    forces(h, pp, cs, nullptr, virial || npt);
     {
       Stage st(h, "integrate", cs);
       launch_kick(md, cs);
+    }
+    if (ens) {
+      Stage st(h, "ensemble", cs);
+      launch_ens_kinetic(h->vel, h->types, h->mass, N, kAmuA2fs2, h->ens_partial, est, cs);
+      if (ep->kind == kEnsLangevin)
+        launch_ens_langevin(h->vel, h->types, h->mass, h->ext_id, N, *ep, 2u, est, h->ens_partial, cs);
+      else
+        launch_ens_thermostat(h->vel, N, *ep, est, h->ens_partial, cs);
+      if (row || npt) {
+        launch_thermo(h->U, h->W, h->vel, h->types, h->mass, N, h->partial, num_partials(N), est->row, 0.0,
+                      kAmuA2fs2, kBoltzmann, cs);
+        launch_ens_pressure_row(*ep, est, h->structs, h->thermo, h->row_counter, row, step_base, cs);
+      }
+      if (npt) launch_ens_barostat(h->pos, h->vel, N, *ep, est, h->structs, cs);
     }
   };
   // Replay groups of G steps (+ their thermo row) from a captured HIP graph;
@@ -1927,6 +2010,10 @@ int md_skin(nep_handle* h, const Prepared& pp, double* d_pos, double* d_vel, con
     put(&thr2, sizeof thr2);
     put(&pp.geo.st, sizeof pp.geo.st);
     put(&pp.n_cells, sizeof pp.n_cells);
+    put(&pp.batch, sizeof pp.batch);
+    const int32_t kind = ens ? ep->kind : -1;
+    put(&kind, sizeof kind);
+    if (ens) put(ep, sizeof *ep);
     return k;
   };
   // (Re)capture the G-step group; kept in the handle for later calls.
@@ -1935,8 +2022,11 @@ int md_skin(nep_handle* h, const Prepared& pp, double* d_pos, double* d_vel, con
     HIPCHK(hipStreamSynchronize(gs));
     try {
       HIPCHK(hipStreamBeginCapture(gs, hipStreamCaptureModeThreadLocal));
-      for (int64_t k = 0; k < G; ++k) step_body(gs, thermo_every > 0 && k == G - 1);
-      if (thermo_every > 0)
+      for (int64_t k = 0; k < G; ++k) {
+        const bool last_row = thermo_every > 0 && k == G - 1;
+        step_body(gs, last_row, last_row);
+      }
+      if (thermo_every > 0 && !ens)
         launch_thermo_counted(h->U, h->W, h->vel, h->types, h->mass, N, h->partial, num_partials(N),
                               h->thermo, h->row_counter, (double)thermo_every, kAmuA2fs2, kBoltzmann, gs);
       HIPCHK(hipStreamEndCapture(gs, &h->md_graph));
@@ -1971,13 +2061,18 @@ int md_skin(nep_handle* h, const Prepared& pp, double* d_pos, double* d_vel, con
     HIPCHK(hipMemcpyAsync(h->types_save, h->types, N * sizeof(int32_t), hipMemcpyDeviceToDevice, s));
     HIPCHK(hipMemcpyAsync(h->ext_save, h->ext_id, N * sizeof(int32_t), hipMemcpyDeviceToDevice, s));
     HIPCHK(hipMemcpyAsync(h->F_save, h->F, 3 * N * sizeof(float), hipMemcpyDeviceToDevice, s));
+    unsigned char* ens_base = (unsigned char*)h->ens_state;
+    if (ens) {
+      HIPCHK(hipMemcpyAsync(ens_base + 512, est, sizeof(EnsState), hipMemcpyDeviceToDevice, s));
+      HIPCHK(hipMemcpyAsync(ens_base + 1024, h->structs, sizeof(StructInfo), hipMemcpyDeviceToDevice, s));
+    }
     const int64_t row0 = row;
     launch_fill_i32(h->flags, 8, 0, s);
     if (redo) {  // rows were grown: rebuild them for the restored state first
-      skin_rebuild(h, pp, rl, nullptr, s);
+      skin_rebuild(h, pp, rl, nullptr, s, mu_cum);
       redo = false;
     }
-    if (use_graph) {
+    if (use_graph || ens) {
       int32_t* rc = (int32_t*)(h->pinned + 416);
       *rc = (int32_t)row;
       HIPCHK(hipMemcpyAsync(h->row_counter, rc, sizeof(int32_t), hipMemcpyHostToDevice, s));
@@ -1989,8 +2084,11 @@ int md_skin(nep_handle* h, const Prepared& pp, double* d_pos, double* d_vel, con
         step += G - 1;
         continue;
       }
-      step_body(s, thermo_every > 0 && step % thermo_every == 0);
-      if (thermo_every > 0 && step % thermo_every == 0) {
+      const bool row_due = thermo_every > 0 && step % thermo_every == 0;
+      step_body(s, row_due, row_due);
+      if (ens && row_due) {
+        ++row;
+      } else if (row_due) {
         Stage st(h, "thermo", s);
         launch_thermo(h->U, h->W, h->vel, h->types, h->mass, N, h->partial, num_partials(N),
                       h->thermo + 13 * row, (double)step, kAmuA2fs2, kBoltzmann, s);
@@ -1999,9 +2097,16 @@ int md_skin(nep_handle* h, const Prepared& pp, double* d_pos, double* d_vel, con
     }
     launch_check_finite(h->pos, 3 * N, h->flags + 4, s);
     launch_check_rows(N, h->sid, h->structs, pp.geo.st, pp.batch, h->L, h->flags + 6, s);
+    if (npt)  // the current cell, read with the flags
+      HIPCHK(hipMemcpyAsync(h->pinned + 1536, h->structs, sizeof(StructInfo), hipMemcpyDeviceToHost, s));
     const int32_t* fl = read_flags(h, s);
     if (fl[4]) throw Failure{NEP_E_NONFINITE, "positions became non-finite during the run"};
+    if (npt) check_npt_cell(*(const StructInfo*)(h->pinned + 1536), pp.geo.st, rl);
     if (grow_rows(h, N, fl)) {
+      if (ens) {
+        HIPCHK(hipMemcpyAsync(est, ens_base + 512, sizeof(EnsState), hipMemcpyDeviceToDevice, s));
+        HIPCHK(hipMemcpyAsync(h->structs, ens_base + 1024, sizeof(StructInfo), hipMemcpyDeviceToDevice, s));
+      }
       HIPCHK(hipMemcpyAsync(h->pos, h->pos_save, 3 * N * sizeof(double), hipMemcpyDeviceToDevice, s));
       HIPCHK(hipMemcpyAsync(h->vel, h->vel_save, 3 * N * sizeof(double), hipMemcpyDeviceToDevice, s));
       HIPCHK(hipMemcpyAsync(h->pos_ref, h->ref_save, 3 * N * sizeof(double), hipMemcpyDeviceToDevice, s));
@@ -2019,9 +2124,23 @@ int md_skin(nep_handle* h, const Prepared& pp, double* d_pos, double* d_vel, con
   }
   launch_unpermute_md(h->ext_id, N, h->pos, h->vel, d_pos, d_vel, s);
   if (n_rows > 0)
-    HIPCHK(hipMemcpyAsync(thermo_out, h->thermo, 13 * n_rows * sizeof(double),
+    HIPCHK(hipMemcpyAsync(thermo_out, h->thermo, row_len * n_rows * sizeof(double),
                           thermo_on_host ? hipMemcpyDeviceToHost : hipMemcpyDeviceToDevice, s));
+  if (ens) {
+    HIPCHK(hipMemcpyAsync(h->pinned + 1024, est, sizeof(EnsState), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(h->pinned + 1536, h->structs, sizeof(StructInfo), hipMemcpyDeviceToHost, s));
+  }
   HIPCHK(hipStreamSynchronize(s));
+  if (ens) {
+    const EnsState& e = *(const EnsState*)(h->pinned + 1024);
+    ens_state[0] = (double)e.step;
+    ens_state[1] = e.heat;
+    for (int k = 0; k < kMaxChain; ++k) {
+      ens_state[2 + k] = e.xi[k];
+      ens_state[10 + k] = e.vxi[k];
+    }
+    if (box_out) std::memcpy(box_out, ((const StructInfo*)(h->pinned + 1536))->H, 9 * sizeof(double));
+  }
   return NEP_OK;
 }
 
@@ -2030,7 +2149,8 @@ int md_skin(nep_handle* h, const Prepared& pp, double* d_pos, double* d_vel, con
 static int md_impl(nep_handle* h, int64_t N, double* d_pos, double* d_vel, const int32_t* d_types,
                    const double* mass_per_type, const double* box, const int32_t* pbc, double dt,
                    int64_t n_steps, int64_t thermo_every, double* thermo_out, bool thermo_on_host,
-                   hipStream_t s) {
+                   hipStream_t s, const nep_ensemble* ens = nullptr, double* ens_state = nullptr,
+                   double* box_out = nullptr) {
   if (!mass_per_type) throw Failure{NEP_E_INVALID_ARG, "mass_per_type is required"};
   for (int t = 0; t < h->hp.n_types; ++t)
     if (!(mass_per_type[t] > 0) || !std::isfinite(mass_per_type[t]))
@@ -2039,10 +2159,49 @@ static int md_impl(nep_handle* h, int64_t N, double* d_pos, double* d_vel, const
   if (n_steps < 0 || thermo_every < 0) throw Failure{NEP_E_INVALID_ARG, "negative step counts"};
   const int64_t n_rows = thermo_every > 0 ? n_steps / thermo_every : 0;
   if (n_rows > 0 && !thermo_out) throw Failure{NEP_E_INVALID_ARG, "thermo buffer is required"};
-  const bool with_skin = h->hp.skin > 0;
-  Prepared pp = prepare(h, N, box, pbc, h->hp.rc_radial + h->hp.skin, true, s);
+  const bool use_ens = ens != nullptr;  // NEP_ENS_NVE here: plain steps with the 16-column rows
+  EnsParams ep{};
+  if (use_ens) {
+    if (ens->kind < 0 || ens->kind > NEP_ENS_NPT_SCR) throw Failure{NEP_E_INVALID_ARG, "unknown ensemble"};
+    if (N < 2) throw Failure{NEP_E_INVALID_ARG, "an ensemble run needs at least 2 atoms"};
+    if (ens->kind != NEP_ENS_NVE &&
+        (!(ens->temperature > 0) || !(ens->tau_t > 0) || !std::isfinite(ens->temperature) ||
+         !std::isfinite(ens->tau_t)))
+      throw Failure{NEP_E_INVALID_ARG, "temperature and tau_t must be positive"};
+    if (ens->kind == NEP_ENS_NHC && (ens->nhc_length < 1 || ens->nhc_length > kMaxChain))
+      throw Failure{NEP_E_INVALID_ARG, "nhc_length must be in [1, 8]"};
+    if (ens->kind >= NEP_ENS_NPT_BERENDSEN &&
+        (!(ens->tau_p > 0) || !(ens->compressibility > 0) || !std::isfinite(ens->pressure) ||
+         !std::isfinite(ens->tau_p) || !std::isfinite(ens->compressibility)))
+      throw Failure{NEP_E_INVALID_ARG, "NPT needs a finite pressure and positive tau_p and compressibility"};
+    if (!ens_state) throw Failure{NEP_E_INVALID_ARG, "state is required"};
+    ep.kind = ens->kind;
+    ep.nhc_length = ens->nhc_length;
+    ep.T0 = ens->temperature;
+    ep.tau_t = ens->tau_t;
+    ep.P0 = ens->pressure;
+    ep.tau_p = ens->tau_p;
+    ep.beta = ens->compressibility;
+    ep.dt = dt;
+    ep.kB = kBoltzmann;
+    ep.kT = kBoltzmann * ens->temperature;
+    ep.Nf = 3.0 * (double)N - 3.0;
+    ep.conv = kAmuA2fs2;
+    ep.seed = ens->seed;
+  }
+  const bool npt = use_ens && ens->kind >= NEP_ENS_NPT_BERENDSEN;
+  const bool with_skin = h->hp.skin > 0 || use_ens;
+  // NPT: the box lives on the device (batch-mode kernels read it there), and
+  // the cell grid gets 3 % headroom for a box that shrinks during the call
+  Prepared pp;
+  if (npt) {
+    const int64_t offs[2] = {0, N};
+    pp = prepare_batch(h, 1, offs, box, pbc, (h->hp.rc_radial + h->hp.skin) * 1.03, true, true, s);
+  } else {
+    pp = prepare(h, N, box, pbc, h->hp.rc_radial + h->hp.skin, true, s);
+  }
   if (n_rows > h->thermo_cap) {
-    dev_alloc(h->thermo, 13 * n_rows);
+    dev_alloc(h->thermo, 16 * n_rows);
     h->thermo_cap = n_rows;
   }
   double m[kMaxTypes] = {0}, im[kMaxTypes] = {0};
@@ -2056,7 +2215,7 @@ static int md_impl(nep_handle* h, int64_t N, double* d_pos, double* d_vel, const
   HIPCHK(hipMemcpyAsync(h->inv_mass, h->pinned + 320, sizeof im, hipMemcpyHostToDevice, s));
   if (with_skin)
     return md_skin(h, pp, d_pos, d_vel, d_types, dt, n_steps, thermo_every, thermo_out, thermo_on_host,
-                   n_rows, s);
+                   n_rows, s, use_ens ? &ep : nullptr, ens_state, box_out);
   // initial order: internal <- caller, velocities follow
   order_and_build(h, pp, d_pos, d_types, s, true);
   launch_permute_md(h->perm, N, d_pos, d_vel, h->pos2, h->vel, s);  // pos2 is scratch here
@@ -2198,6 +2357,39 @@ int nep_md_run_dev(nep_handle* h, int64_t N, double* pos, double* vel, const int
     set_device(h);
     md_impl(h, N, pos, vel, types, mass_per_type, box, pbc, dt_fs, n_steps, thermo_every, thermo, false,
             (hipStream_t)stream);
+    h->resolve_timing();
+  } catch (const Failure& f) {
+    return fail(h, f);
+  }
+  return NEP_OK;
+}
+
+int nep_md_run_ensemble(nep_handle* h, int64_t N, double* pos, double* vel, const int32_t* types,
+                        const double* mass_per_type, double box[9], const int32_t pbc[3], double dt_fs,
+                        int64_t n_steps, int64_t thermo_every, double* thermo, const nep_ensemble* ens,
+                        double state[20]) {
+  if (!h) return fail(nullptr, {NEP_E_INVALID_ARG, "handle is NULL"});
+  if (!pos || !vel || !types || !box || !ens || !state) return fail(h, {NEP_E_INVALID_ARG, "bad arguments"});
+  try {
+    set_device(h);
+    if (N < 1) throw Failure{NEP_E_INVALID_ARG, "n_atoms must be >= 1"};
+    check_host_types(h, N, types);
+    check_host_finite(3 * N, pos, "positions");
+    check_host_finite(3 * N, vel, "velocities");
+    if (!(state[0] >= 0) || state[0] > 4294967295.0 || state[0] != std::floor(state[0]))
+      throw Failure{NEP_E_INVALID_ARG, "state[0] (steps done) must be a whole number in [0, 2^32)"};
+    hipStream_t s = nullptr;
+    prepare(h, N, box, pbc, h->hp.rc_radial, true, s);
+    HIPCHK(hipMemcpyAsync(h->pos_ext, pos, 3 * N * sizeof(double), hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(h->vel_ext, vel, 3 * N * sizeof(double), hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(h->types_ext, types, N * sizeof(int32_t), hipMemcpyHostToDevice, s));
+    double box_new[9];
+    std::memcpy(box_new, box, sizeof box_new);
+    md_impl(h, N, h->pos_ext, h->vel_ext, h->types_ext, mass_per_type, box, pbc, dt_fs, n_steps, thermo_every,
+            thermo, true, s, ens, state, box_new);
+    HIPCHK(hipMemcpy(pos, h->pos_ext, 3 * N * sizeof(double), hipMemcpyDeviceToHost));
+    HIPCHK(hipMemcpy(vel, h->vel_ext, 3 * N * sizeof(double), hipMemcpyDeviceToHost));
+    std::memcpy(box, box_new, sizeof box_new);
     h->resolve_timing();
   } catch (const Failure& f) {
     return fail(h, f);

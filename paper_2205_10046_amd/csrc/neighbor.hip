@@ -179,9 +179,10 @@ __global__ void k_commit_rebuild(int64_t N, const double* __restrict__ pos2,
                                  const int32_t* __restrict__ ext2, double* __restrict__ pos,
                                  double* __restrict__ vel, int32_t* __restrict__ types,
                                  int32_t* __restrict__ ext, double* __restrict__ pos_ref,
-                                 const int32_t* gate) {
+                                 const int32_t* gate, double* mu_cum) {
   int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= N || gated_off(gate)) return;
+  if (k == 0 && mu_cum) *mu_cum = 1.0;  // the reference positions are the current ones
   for (int c = 0; c < 3; ++c) {
     const double x = pos2[c * N + k];
     pos[c * N + k] = x;
@@ -419,9 +420,9 @@ void launch_order_atoms(const BuildArgs& b, hipStream_t s) {
 
 void launch_commit_rebuild(int64_t N, const double* pos2, const double* vel2, const int32_t* types2,
                            const int32_t* ext2, double* pos, double* vel, int32_t* types, int32_t* ext,
-                           double* pos_ref, const int32_t* gate, hipStream_t s) {
+                           double* pos_ref, const int32_t* gate, hipStream_t s, double* mu_cum) {
   hipLaunchKernelGGL(k_commit_rebuild, grid_for(N), dim3(kBlock), 0, s, N, pos2, vel2, types2, ext2,
-                     pos, vel, types, ext, pos_ref, gate);
+                     pos, vel, types, ext, pos_ref, gate, mu_cum);
 }
 
 void launch_build_rows(const BuildArgs& b, const StructInfo& st0, bool batch, const Lists& V,
@@ -692,18 +693,29 @@ void launch_filter_rows(const BuildArgs& b, const StructInfo& st0, bool batch, c
                      b.N, V, L, b.overflow + 2);
 }
 
-// gate = any |r_i - r_i(at last build)|^2 > thr2
+// gate = any |r_i - r_i(at last build)|^2 > thr2.  With a box scaled by mu
+// since the build (NPT), a pair within r_c now was within r_c + skin then as
+// long as every |r_i - mu r_i(build)| <= (mu (r_c + skin) - r_c) / 2.
 __global__ void k_check_displacement(const double* __restrict__ pos, const double* __restrict__ ref,
-                                     int64_t N, double thr2, int32_t* __restrict__ gate) {
+                                     int64_t N, double thr2, int32_t* __restrict__ gate,
+                                     const double* __restrict__ mu_cum, double rc, double rl) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= N) return;
-  const double dx = pos[i] - ref[i], dy = pos[N + i] - ref[N + i], dz = pos[2 * N + i] - ref[2 * N + i];
-  if (dx * dx + dy * dy + dz * dz > thr2) atomicExch(gate, 1);
+  double m = 1.0, t2 = thr2;
+  if (mu_cum) {
+    m = *mu_cum;
+    const double a = fmax(0.0, 0.5 * (m * rl - rc));
+    t2 = a * a;
+  }
+  const double dx = pos[i] - m * ref[i], dy = pos[N + i] - m * ref[N + i],
+               dz = pos[2 * N + i] - m * ref[2 * N + i];
+  if (dx * dx + dy * dy + dz * dz > t2) atomicExch(gate, 1);
 }
 
 void launch_check_displacement(const double* pos, const double* ref, int64_t N, double thr2,
-                               int32_t* gate, hipStream_t s) {
-  hipLaunchKernelGGL(k_check_displacement, grid_for(N), dim3(kBlock), 0, s, pos, ref, N, thr2, gate);
+                               int32_t* gate, hipStream_t s, const double* mu_cum, double rc, double rl) {
+  hipLaunchKernelGGL(k_check_displacement, grid_for(N), dim3(kBlock), 0, s, pos, ref, N, thr2, gate,
+                     mu_cum, rc, rl);
 }
 
 template <class T>

@@ -77,11 +77,16 @@ void launch_build_verlet(const BuildArgs& b, const Lists& V, hipStream_t s);
 // After a gated re-sort: pos/vel/types/ext <- their permuted copies, pos_ref <- pos.
 void launch_commit_rebuild(int64_t N, const double* pos2, const double* vel2, const int32_t* types2,
                            const int32_t* ext2, double* pos, double* vel, int32_t* types, int32_t* ext,
-                           double* pos_ref, const int32_t* gate, hipStream_t s);
+                           double* pos_ref, const int32_t* gate, hipStream_t s,
+                           double* mu_cum = nullptr);
 void launch_filter_rows(const BuildArgs& b, const StructInfo& st0, bool batch, const Lists& V,
                         const Lists& L, hipStream_t s);
+// gate = 1 if an atom moved more than allowed since the last build; with
+// mu_cum (box scaling since the build, NPT) the allowance shrinks to
+// (mu (r_c + skin) - r_c) / 2 around the scaled reference positions.
 void launch_check_displacement(const double* pos, const double* ref, int64_t N, double thr2,
-                               int32_t* gate, hipStream_t s);
+                               int32_t* gate, hipStream_t s, const double* mu_cum = nullptr,
+                               double rc = 0.0, double rl = 0.0);
 void launch_copy_gated_f64(double* dst, const double* src, int64_t n, const int32_t* gate,
                            hipStream_t s);
 void launch_copy_gated_i32(int32_t* dst, const int32_t* src, int64_t n, const int32_t* gate,
@@ -164,5 +169,46 @@ void launch_gather3_gated(const int32_t* src, int64_t N, const double* in, doubl
 void launch_gather_i32_gated(const int32_t* src, int64_t N, const int32_t* in, int32_t* out,
                              const int32_t* gate, hipStream_t s);
 void launch_gather_i32(const int32_t* src, int64_t N, const int32_t* in, int32_t* out, hipStream_t s);
+
+// ensemble.hip: thermostats and barostats (kinds as NEP_ENS_* in nep.h)
+constexpr int kEnsNVE = 0, kEnsBerendsen = 1, kEnsBDP = 2, kEnsLangevin = 3, kEnsNHC = 4,
+              kEnsNptBerendsen = 5, kEnsNptSCR = 6;
+constexpr int kMaxChain = 8;
+
+// Scalar state of an ensemble run, in device memory.
+struct EnsState {
+  double K;              // kinetic energy of the current velocities (eV)
+  double heat;           // energy taken out by thermostat and barostat so far (eV)
+  double scale;          // velocity factor of the last thermostat or barostat kernel
+  double mu;             // box factor of the last barostat step
+  double mu_cum;         // box factor since the last neighbour build
+  double P;              // end-of-step pressure (GPa)
+  double xi[kMaxChain];  // chain positions
+  double vxi[kMaxChain]; // chain velocities (1/fs)
+  int64_t step;          // steps done (the step word of the random counters)
+  double row[13];        // end-of-step sums: [., E_pot, E_kin, T, W_xx .. W_zz]
+};
+
+struct EnsParams {
+  int32_t kind, nhc_length;
+  double T0, tau_t, P0, tau_p, beta;  // K, fs, GPa, fs, 1/GPa
+  double dt, kT, kB, Nf, conv;        // fs, eV, eV/K, 3N - 3, amu (A/fs)^2 in eV
+  uint64_t seed;
+};
+
+int64_t ens_partials(int64_t N);
+void launch_ens_kinetic(const double* vel, const int32_t* types, const double* mass, int64_t N, double conv,
+                        double* partial, EnsState* st, hipStream_t s);
+void launch_ens_step_begin(EnsState* st, hipStream_t s);
+void launch_ens_langevin(double* vel, const int32_t* types, const double* mass, const int32_t* ext,
+                         int64_t N, const EnsParams& p, uint32_t stream, EnsState* st, double* partial,
+                         hipStream_t s);
+// Thermostat after the second half kick (from st->K): scale the velocities.
+void launch_ens_thermostat(double* vel, int64_t N, const EnsParams& p, EnsState* st, double* partial,
+                           hipStream_t s);
+void launch_ens_pressure_row(const EnsParams& p, EnsState* st, const StructInfo* structs, double* rows,
+                             int32_t* counter, bool write_row, int64_t step_base, hipStream_t s);
+void launch_ens_barostat(double* pos, double* vel, int64_t N, const EnsParams& p, EnsState* st,
+                         StructInfo* structs, hipStream_t s);
 
 }  // namespace nep

@@ -32,7 +32,7 @@ NEP_MLP_BF16 = 1
 EXPORTS = ["nep_num_descriptors", "nep_num_params", "nep_create", "nep_set_params",
            "nep_destroy", "nep_last_error", "nep_compute", "nep_compute_dev",
            "nep_heat_current", "nep_heat_current_dev", "nep_neighbors", "nep_descriptors",
-           "nep_latent", "nep_md_run", "nep_md_run_dev",
+           "nep_latent", "nep_md_run", "nep_md_run_dev", "nep_md_run_ensemble",
            "nep_compute_batch", "nep_batch_loss", "nep_batch_loss_noalloc", "nep_snes_step",
            "nep_snes_sample", "nep_set_timing", "nep_get_timing", "nep_get_tuning",
            "nep_server_create",
@@ -72,6 +72,16 @@ def make_hparams(h: dict, mlp_precision=NEP_MLP_FP32, max_nb_radial=0,
         max_nb_radial=h.get("max_nb_radial", max_nb_radial),
         max_nb_angular=h.get("max_nb_angular", max_nb_angular),
         skin=h.get("skin", skin))
+
+
+ENSEMBLES = {"nve": 0, "nvt_berendsen": 1, "nvt_bdp": 2, "nvt_langevin": 3, "nvt_nhc": 4,
+             "npt_berendsen": 5, "npt_scr": 6}
+
+
+class nep_ensemble(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("temperature", C.c_double), ("tau_t", C.c_double),
+                ("nhc_length", C.c_int32), ("pressure", C.c_double), ("tau_p", C.c_double),
+                ("compressibility", C.c_double), ("seed", C.c_uint64)]
 
 
 class nep_request(C.Structure):
@@ -139,6 +149,8 @@ def load():
     L.nep_latent.argtypes = [vp, i64, pd, pi32, pd, pi32, pd]
     L.nep_md_run.argtypes = [vp, i64, pd, pd, pi32, pd, pd, pi32, d, i64, i64, pd]
     L.nep_md_run_dev.argtypes = [vp, i64, vp, vp, vp, pd, pd, pi32, d, i64, i64, vp, vp]
+    L.nep_md_run_ensemble.argtypes = [vp, i64, pd, pd, pi32, pd, pd, pi32, d, i64, i64, pd,
+                                      P(nep_ensemble), pd]
     L.nep_compute_batch.argtypes = [vp, i32, P(i64), vp, vp, pd, pi32, i32, pd, vp, vp, vp,
                                     vp, vp]
     L.nep_batch_loss.argtypes = [vp, i32, P(i64), i32, vp, i64, vp, vp, vp, vp, vp, pd, vp, vp]
@@ -360,6 +372,29 @@ class Handle:
             _ptr(pbc, C.c_int32), float(dt), int(n_steps), int(thermo_every),
             _ptr(th, C.c_double)))
         return pos, vel, th[:rows]
+
+    def md_run_ensemble(self, pos, vel, types, masses, box, dt, n_steps, thermo_every, ens,
+                        state=None, pbc=None):
+        """nep_md_run_ensemble on host arrays.  ens: dict with kind (a name of
+        ENSEMBLES), temperature (K), tau_t (fs), nhc_length, pressure (GPa),
+        tau_p (fs), compressibility (1/GPa), seed.  Returns (pos, vel, box,
+        thermo (rows, 16), state (20,))."""
+        e = nep_ensemble(kind=ENSEMBLES[ens["kind"]], temperature=ens.get("temperature", 300.0),
+                         tau_t=ens.get("tau_t", 100.0), nhc_length=ens.get("nhc_length", 4),
+                         pressure=ens.get("pressure", 0.0), tau_p=ens.get("tau_p", 1000.0),
+                         compressibility=ens.get("compressibility", 0.01), seed=ens.get("seed", 0))
+        pos, vel = _f64(pos).copy(), _f64(vel).copy()
+        types, box, m = _i32(types), _f64(box).copy(), _f64(masses)
+        pbc = _i32(np.ones(3) if pbc is None else pbc)
+        st = np.zeros(20) if state is None else _f64(state).copy()
+        rows = n_steps // thermo_every if thermo_every > 0 else 0
+        th = np.zeros((max(rows, 1), 16))
+        self._check(load().nep_md_run_ensemble(
+            self._h, pos.shape[1], _ptr(pos, C.c_double), _ptr(vel, C.c_double),
+            _ptr(types, C.c_int32), _ptr(m, C.c_double), _ptr(box, C.c_double),
+            _ptr(pbc, C.c_int32), float(dt), int(n_steps), int(thermo_every),
+            _ptr(th, C.c_double), C.byref(e), _ptr(st, C.c_double)))
+        return pos, vel, box, th[:rows], st
 
     def md_run_dev(self, pos, vel, types, masses, box, dt, n_steps, thermo_every, thermo,
                    pbc=None):

@@ -1,0 +1,132 @@
+"""NVT and NPT ensembles on the GPU (nep_md_run_ensemble) against the FP64
+oracle's ensembles: the same thermostat and barostat steps and the same
+Philox4x32-10 random streams, so short trajectories agree to the float32
+force tolerance (1e-7 A in positions after 10 steps, as the NVE parity test),
+and the thermostat state (heat, chain) and the NPT cell follow.  Longer GPU
+runs check the physics: the Nose-Hoover-chain extended energy is conserved,
+the stochastic thermostats hold the target temperature, the barostats move
+the volume toward the target pressure, and a run split into two calls
+continues the random streams."""
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2205_10046_amd import nep, synth
+
+pytestmark = pytest.mark.gpu
+
+
+def log(*a):
+    print(*a, flush=True)
+
+
+ENS = {
+    "nve": {"kind": "nve"},
+    "nvt_berendsen": {"kind": "nvt_berendsen", "temperature": 500.0, "tau_t": 20.0},
+    "nvt_bdp": {"kind": "nvt_bdp", "temperature": 500.0, "tau_t": 20.0, "seed": 77},
+    "nvt_langevin": {"kind": "nvt_langevin", "temperature": 500.0, "tau_t": 20.0, "seed": 78},
+    "nvt_nhc": {"kind": "nvt_nhc", "temperature": 500.0, "tau_t": 30.0, "nhc_length": 3},
+    # the benchmark's repulsive parameter vector holds this lattice at ~125 GPa
+    "npt_berendsen": {"kind": "npt_berendsen", "temperature": 500.0, "tau_t": 20.0,
+                      "pressure": 100.0, "tau_p": 200.0, "compressibility": 0.001},
+    "npt_scr": {"kind": "npt_scr", "temperature": 500.0, "tau_t": 20.0, "pressure": 100.0,
+                "tau_p": 200.0, "compressibility": 0.001, "seed": 79},
+}
+
+
+@pytest.fixture(scope="module")
+def alloy():
+    h = synth.WORKLOADS["fcc131k"]
+    p = synth.solid_params(h, O.num_descriptors(h), O.num_params(h))
+    pos, types, box = synth.lattice("fcc", 5, 4.05, 0.05, 4, seed=15)
+    m = np.array(synth.MASSES["fcc131k"])
+    vel = synth.maxwell_velocities(m[types], 300.0, seed=16)
+    return h, p, pos, vel, types, m, box
+
+
+@pytest.mark.parametrize("name", list(ENS))
+@pytest.mark.parametrize("skin", [0.0, 0.5], ids=["skin0", "skin0.5"])
+def test_short_run_matches_oracle(alloy, name, skin):
+    h, p, pos, vel, types, m, box = alloy
+    ens = ENS[name]
+    handle = nep.Handle(h, p, skin=skin)
+    log(f"[ens] {name} skin={skin} N={pos.shape[1]} 10 steps")
+    gp, gv, gb, gth, gst = handle.md_run_ensemble(pos, vel, types, m, box, 1.0, 10, 5, ens)
+    op, ov, ob, oth, ost = O.md_ensemble(h, p, pos, vel, types, m, box, 1.0, 10, 5, ens)
+    n = pos.shape[1]
+    dp, dv = np.abs(gp - op).max(), np.abs(gv - ov).max()
+    log(f"[ens] {name}: max|dr|={dp:.2e} max|dv|={dv:.2e} T {gth[-1, 3]:.3f}/{oth[-1, 3]:.3f} "
+        f"P {gth[-1, 14]:.5f}/{oth[-1, 14]:.5f} H {gth[-1, 15]:.6f}/{oth[-1, 15]:.6f}")
+    assert dp < 1e-7 and dv < 1e-8
+    np.testing.assert_allclose(gb, ob, rtol=1e-12)
+    np.testing.assert_array_equal(gth[:, 0], oth[:, 0])
+    np.testing.assert_allclose(gth[:, 1:3], oth[:, 1:3], atol=1e-6 * n)      # E_pot, E_kin
+    np.testing.assert_allclose(gth[:, 3], oth[:, 3], rtol=1e-6)               # T
+    np.testing.assert_allclose(gth[:, 4:13], oth[:, 4:13], atol=1e-4 * n)     # W
+    np.testing.assert_allclose(gth[:, 13], oth[:, 13], rtol=1e-12)            # V
+    np.testing.assert_allclose(gth[:, 14], oth[:, 14], atol=1e-3)             # P (GPa)
+    np.testing.assert_allclose(gth[:, 15], oth[:, 15], atol=1e-6 * n)         # H~
+    assert gst[0] == ost[0] == 10
+    np.testing.assert_allclose(gst[1:], ost[1:], atol=1e-6 * n, rtol=1e-6)
+    handle.close()
+
+
+def test_split_run_continues_random_streams(alloy):
+    """Two calls of 10 steps carrying the state follow one call of 20 steps
+    (to the float32 tolerance: the second call re-sorts the atoms), which
+    holds only if the second call continues the Langevin streams."""
+    h, p, pos, vel, types, m, box = alloy
+    ens = ENS["nvt_langevin"]
+    handle = nep.Handle(h, p, skin=0.5)
+    a = handle.md_run_ensemble(pos, vel, types, m, box, 1.0, 20, 0, ens)
+    b = handle.md_run_ensemble(pos, vel, types, m, box, 1.0, 10, 0, ens)
+    c = handle.md_run_ensemble(b[0], b[1], types, m, b[2], 1.0, 10, 0, ens, state=b[4])
+    assert a[4][0] == c[4][0] == 20
+    assert np.abs(a[0] - c[0]).max() < 1e-6 and np.abs(a[1] - c[1]).max() < 1e-7
+    handle.close()
+
+
+def test_nhc_conserves_extended_energy_gpu(alloy):
+    h, p, pos, vel, types, m, box = alloy
+    handle = nep.Handle(h, p, skin=0.5)
+    _, _, _, th, _ = handle.md_run_ensemble(pos, vel, types, m, box, 1.0, 2000, 10, ENS["nvt_nhc"])
+    n = pos.shape[1]
+    drift = np.abs(th[:, 15] - th[0, 15]).max() / n
+    log(f"[ens] NHC 2000 steps: max|H~(t) - H~(0)|/N = {drift:.2e} eV/atom, "
+        f"T range {th[:, 3].min():.0f}-{th[:, 3].max():.0f} K")
+    assert drift < 2e-4
+    assert th[len(th) // 2:, 3].mean() == pytest.approx(500.0, rel=0.1)
+    handle.close()
+
+
+@pytest.mark.parametrize("name", ["nvt_bdp", "nvt_langevin", "nvt_berendsen"])
+def test_thermostats_reach_target(alloy, name):
+    h, p, pos, vel, types, m, box = alloy
+    handle = nep.Handle(h, p, skin=0.5)
+    _, _, _, th, st = handle.md_run_ensemble(pos, vel, types, m, box, 1.0, 2000, 10, ENS[name])
+    n = pos.shape[1]
+    T = th[len(th) // 2:, 3]
+    if name == "nvt_langevin":
+        T = T * (3 * n - 3) / (3 * n)
+    log(f"[ens] {name} 2000 steps: <T> = {T.mean():.1f} K, heat {st[1]:.4f} eV")
+    assert T.mean() == pytest.approx(500.0, rel=0.05)
+    # the effective energy only drifts by the integrator's error
+    drift = np.abs(th[:, 15] - th[0, 15]).max() / n
+    assert drift < 2e-4, drift
+    handle.close()
+
+
+@pytest.mark.parametrize("name", ["npt_berendsen", "npt_scr"])
+def test_barostats_move_toward_target(alloy, name):
+    h, p, pos, vel, types, m, box = alloy
+    handle = nep.Handle(h, p, skin=0.5)
+    P0 = 60.0
+    ens = dict(ENS[name], pressure=P0, tau_p=100.0, compressibility=0.002)
+    _, _, box2, th, _ = handle.md_run_ensemble(pos, vel, types, m, box, 1.0, 1500, 10, ens)
+    V0 = abs(np.linalg.det(box.reshape(3, 3)))
+    V1 = abs(np.linalg.det(box2.reshape(3, 3)))
+    P = th[:, 14]
+    log(f"[ens] {name}: P {P[0]:.3f} -> {P[-1]:.3f} GPa (target {P0}), V {V0:.1f} -> {V1:.1f} A^3")
+    assert abs(P[-30:].mean() - P0) < 0.25 * abs(P[0] - P0)
+    assert V1 > V0   # the lattice above the target pressure expands
+    handle.close()

@@ -1,0 +1,123 @@
+"""Error of every result against the FP64 oracle, for the float32 network and
+the bf16 network on MFMA: the max and RMS error of the site energies U_i,
+the energy per atom E/N, the force components and the per-atom virial
+components (the library keeps float64 only for displacements, integration and
+totals; the float32 internals are the paper's GPU precision, Sec. II "GPU
+implementation").
+
+Workloads: the 1,024-atom BCC sub-cell of the 2,000,000-atom benchmark
+(l_max = 6, 4-body and 5-body, 80 neurons), and 20 single-evaluation requests
+of the seeded serving stream (log-uniform 64-100,000 atoms, FCC/BCC, 2
+species) served by a float32 and a bf16 server.  Requests above 3,000 atoms
+are compared on 24 sampled atoms (their E/N error is then not formed).
+
+Gates: float32 |dE|/N <= 1e-6 eV/atom, every force component <= 1e-4 eV/A,
+every per-atom virial component <= 1e-4 eV, largest site error <= 1e-5 eV;
+bf16 |dE|/N <= 1 meV/atom and every force component <= 10 meV/A.  With
+NEP_ERROR_TABLE set, the table is written there as JSON.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2205_10046_amd import nep, synth
+
+pytestmark = pytest.mark.gpu
+
+GATES = {nep.NEP_MLP_FP32: dict(e=1e-6, f=1e-4, w=1e-4, u=1e-5),
+         nep.NEP_MLP_BF16: dict(e=1e-3, f=1e-2, w=None, u=None)}
+NAME = {nep.NEP_MLP_FP32: "fp32", nep.NEP_MLP_BF16: "bf16"}
+
+
+def log(*a):
+    print(*a, flush=True)
+
+
+def _stats(d):
+    d = np.asarray(d, dtype=np.float64).ravel()
+    return float(np.abs(d).max()), float(np.sqrt(np.mean(d * d)))
+
+
+def _row(label, prec, n, dU, dF, dW, dE=None):
+    u, f, w = _stats(dU), _stats(dF), _stats(dW)
+    row = dict(workload=label, mlp=NAME[prec], atoms=int(n), compared=int(np.size(dU)),
+               U_max=u[0], U_rms=u[1], F_max=f[0], F_rms=f[1], W_max=w[0], W_rms=w[1],
+               E_per_atom=None if dE is None else float(dE))
+    g = GATES[prec]
+    assert f[0] <= g["f"], row
+    if dE is not None:
+        assert abs(dE) <= g["e"], row
+    if g["w"] is not None:
+        assert w[0] <= g["w"] and u[0] <= g["u"], row
+    log(f"[errors] {label} {NAME[prec]} N={n}: U max {u[0]:.2e} rms {u[1]:.2e} | "
+        f"E/N {('%.2e' % dE) if dE is not None else '-'} | F max {f[0]:.2e} rms {f[1]:.2e} | "
+        f"W max {w[0]:.2e} rms {w[1]:.2e}")
+    return row
+
+
+@pytest.fixture(scope="module")
+def table():
+    rows = []
+    yield rows
+    path = os.environ.get("NEP_ERROR_TABLE")
+    if path and rows:
+        with open(path, "w") as fh:
+            json.dump(rows, fh, indent=1)
+
+
+@pytest.mark.parametrize("prec", [nep.NEP_MLP_FP32, nep.NEP_MLP_BF16], ids=["fp32", "bf16"])
+def test_error_table_bcc_subcell(prec, table):
+    h = synth.WORKLOADS["bcc2m"]
+    p = synth.random_params(O.num_params(h))
+    pos, types, box = synth.bcc_subcell()
+    n = pos.shape[1]
+    handle = nep.Handle(h, p, mlp_precision=prec)
+    res = handle.compute(pos, types, box)
+    ref = O.evaluate(h, p, pos, types, box)
+    dE = (res["U"].sum() - ref["U"].sum()) / n
+    table.append(_row("bcc_subcell_1024 (l_max 6, 4b, 5b, 80 neurons)", prec, n,
+                      res["U"] - ref["U"], res["F"] - ref["F"], res["W"] - ref["W"], dE))
+    handle.close()
+
+
+def _eval_requests(count=20, seed=synth.SEED_STRUCT + 11):
+    reqs = [r for r in synth.serving_stream(n_requests=3 * count, rate_hz=1.0, seed=seed)
+            if r.kind == "eval"]
+    assert len(reqs) >= count
+    return reqs[:count]
+
+
+@pytest.mark.parametrize("prec", [nep.NEP_MLP_FP32, nep.NEP_MLP_BF16], ids=["fp32", "bf16"])
+def test_error_table_served_requests(prec, table):
+    h = synth.WORKLOADS["serve2"]
+    p = synth.random_params(O.num_params(h))
+    reqs = _eval_requests()
+    srv = nep.Server(nep.Handle(h, p, mlp_precision=prec), 8 << 30, max_slots=32)
+    tickets = [srv.submit(r.pos, r.types, r.box) for r in reqs]
+    rng = np.random.default_rng(17)
+    dU, dF, dW, dEs, sizes = [], [], [], [], []
+    for r, t in zip(reqs, tickets):
+        res = srv.poll(t, wait_ms=-1)
+        n = r.pos.shape[1]
+        sizes.append(n)
+        if n <= 3000:
+            ref = O.evaluate(h, p, r.pos, r.types, r.box)
+            dU.append(res["U"] - ref["U"])
+            dF.append((res["F"] - ref["F"]).ravel())
+            dW.append((res["W"] - ref["W"]).ravel())
+            dEs.append((res["U"].sum() - ref["U"].sum()) / n)
+        else:
+            idx = rng.choice(n, 24, replace=False)
+            ref = O.evaluate_atoms(h, p, r.pos, r.types, r.box, idx)
+            dU.append(res["U"][idx] - ref["U"])
+            dF.append((res["F"][:, idx].T - ref["F"]).ravel())
+            dW.append((res["W"][:, idx].T - ref["W"]).ravel())
+    srv.close()
+    dE = max(dEs, key=abs) if dEs else None
+    row = _row(f"served_requests_20 (sizes {min(sizes)}-{max(sizes)} atoms, "
+               f"{len(dEs)} compared whole)", prec, int(np.sum(sizes)),
+               np.concatenate(dU), np.concatenate(dF), np.concatenate(dW), dE)
+    table.append(row)
