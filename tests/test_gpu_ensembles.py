@@ -58,12 +58,15 @@ def test_short_run_matches_oracle(alloy, name, skin):
     log(f"[ens] {name}: max|dr|={dp:.2e} max|dv|={dv:.2e} T {gth[-1, 3]:.3f}/{oth[-1, 3]:.3f} "
         f"P {gth[-1, 14]:.5f}/{oth[-1, 14]:.5f} H {gth[-1, 15]:.6f}/{oth[-1, 15]:.6f}")
     assert dp < 1e-7 and dv < 1e-8
-    np.testing.assert_allclose(gb, ob, rtol=1e-12)
+    # the NPT cell follows the pressure, whose float32-virial error (<= 1e-3 GPa
+    # below) moves the cell by at most steps * beta dt / (3 tau_p) * 1e-3
+    # relative: 1.7e-8 for these settings
+    np.testing.assert_allclose(gb, ob, rtol=2e-8)
     np.testing.assert_array_equal(gth[:, 0], oth[:, 0])
     np.testing.assert_allclose(gth[:, 1:3], oth[:, 1:3], atol=1e-6 * n)      # E_pot, E_kin
     np.testing.assert_allclose(gth[:, 3], oth[:, 3], rtol=1e-6)               # T
     np.testing.assert_allclose(gth[:, 4:13], oth[:, 4:13], atol=1e-4 * n)     # W
-    np.testing.assert_allclose(gth[:, 13], oth[:, 13], rtol=1e-12)            # V
+    np.testing.assert_allclose(gth[:, 13], oth[:, 13], rtol=6e-8)             # V
     np.testing.assert_allclose(gth[:, 14], oth[:, 14], atol=1e-3)             # P (GPa)
     np.testing.assert_allclose(gth[:, 15], oth[:, 15], atol=1e-6 * n)         # H~
     assert gst[0] == ost[0] == 10
