@@ -156,6 +156,19 @@ int nep_descriptors(nep_handle *h, int64_t n_atoms, const double *pos,
                     const int32_t *types, const double box[9], const int32_t pbc[3],
                     double *q);
 
+/* Zero-temperature elastic constants C11, C12, C44 (GPa) of a cubic crystal
+ * by the energy-strain relation with +-strain (Sec. V "Elastic constants",
+ * where strain = 0.01): the total energy is evaluated for the cell and
+ * positions deformed by F = I + eps (r -> F r, cell vectors a -> F a) at
+ * eps = 0 and +-strain along three paths, and
+ *   C11 = E''(uniaxial xx) / V,  C11 + C12 = E''(biaxial xx = yy) / (2V),
+ *   C44 = E''(shear xy = yx = strain / 2, so the engineering shear is strain) / V,
+ * E'' = (E(+) + E(-) - 2 E(0)) / strain^2 and V the unstrained volume.  Atoms
+ * are not relaxed inside the cell (exact for one-atom Bravais lattices).
+ * Host arrays; 0 < strain < 0.2.  Seven evaluations; synchronous. */
+int nep_elastic_cubic(nep_handle *h, int64_t n_atoms, const double *pos, const int32_t *types,
+                      const double box[9], const int32_t pbc[3], double strain, double C[3]);
+
 /* Latent-space vectors (Sec. IV, the active-learning scheme): for every atom
  * the N_neu products w1_mu h_mu of the hidden-layer states
  * h_mu = tanh(sum_nu w0_{mu nu} q_nu - b0_mu) and their weights to the
@@ -184,8 +197,9 @@ int nep_latent(nep_handle *h, int64_t n_atoms, const double *pos, const int32_t 
  * params [P][n_par] or NULL (no regularisers; otherwise n_par must be
  * nep_num_params).  loss [P][6] receives [L, RMSE_e, RMSE_f, RMSE_v,
  * mean|z|, sqrt(mean z^2)]; absent terms read 0.  1 <= n_param_sets <= 65535.
- * Sums are float64 in a fixed order (same inputs, same bits).  Synchronous on
- * `stream`. */
+ * Sums are float64 in a fixed order (same inputs, same bits).  Asynchronous
+ * on `stream`, except that growing the workspace or new offsets (copied to the
+ * device, then free for the caller to change) synchronise once. */
 int nep_batch_loss(nep_handle *h, int32_t n_struct, const int64_t *offsets, int32_t n_param_sets,
                    const double *params, int64_t n_par, const double *force, const double *totals,
                    const double *energy_target, const double *force_target,
@@ -339,6 +353,26 @@ int nep_compute_batch(nep_handle *h, int32_t n_struct, const int64_t *offsets,
                       const int32_t *pbc, int32_t n_param_sets, const double *params,
                       double *energy, double *force, double *virial, double *totals,
                       void *stream);
+
+/* nep_compute_batch with the parameter vectors in device memory: params is
+ * a device array [n_param_sets][nep_num_params] (float64), converted to the
+ * float32 / bf16 tables by a kernel (bitwise the tables nep_compute_batch
+ * builds on the host, so the results are the same bits).  With flags =
+ * NEP_BATCH_REUSE_ROWS the caller declares that pos, types, offsets and boxes
+ * describe the same structures as in the previous batch call on this handle,
+ * whose neighbour rows are then reused (boxes may be NULL); the call fails
+ * with NEP_E_INVALID_ARG if that call had other sizes.  The per-set passes
+ * (with the table conversion) are captured once into a HIP graph kept in the
+ * handle and replayed while the sizes and the params / output pointers are
+ * unchanged.  Asynchronous on `stream` when the rows are reused (a training
+ * generation of nep_snes_sample, this call, nep_batch_loss and nep_snes_step
+ * then never waits on the host); building rows synchronises once. */
+#define NEP_BATCH_REUSE_ROWS 1
+int nep_compute_batch_dev(nep_handle *h, int32_t n_struct, const int64_t *offsets,
+                          const double *pos, const int32_t *types, const double *boxes,
+                          const int32_t *pbc, int32_t n_param_sets, const double *params,
+                          int32_t flags, double *energy, double *force, double *virial,
+                          double *totals, void *stream);
 
 /* ---- serving: continuous batching ----
  * A server owns a handle and a worker thread.  Requests (single energy/force/

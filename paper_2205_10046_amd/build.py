@@ -23,7 +23,7 @@ COMMON = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
           "-I" + os.path.join(ROOT, "include"), "-I" + CSRC]
 
 SOURCES = ["api.cpp", "neighbor.hip", "descriptor.hip", "mlp.hip", "output.hip",
-           "md.hip", "ensemble.hip"]
+           "md.hip", "ensemble.hip", "params.hip"]
 
 
 def _compile(src: str) -> str:

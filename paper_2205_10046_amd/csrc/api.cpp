@@ -291,11 +291,25 @@ struct nep_handle {
   Tuning tune[2];                   // [single structure, batch]
   ModelTables main;                 // the handle's own parameter vector
   std::vector<ModelTables> pop;     // parameter sets of the last batch call
+  unsigned char* pop_tables = nullptr;  // device-built tables of a device population
+  int64_t pop_tables_cap = 0;
+  // the captured per-set passes of the last batch call, reused while the
+  // shapes, buffers and output pointers stay the same
+  hipGraph_t batch_graph = nullptr;
+  hipGraphExec_t batch_exec = nullptr;
+  std::vector<unsigned char> batch_key;
+  // rows of the last batch call, for callers that pass the same structures
+  bool batch_rows_ready = false;
+  int32_t batch_S = 0;
+  int64_t batch_N = 0;
+  std::vector<StructInfo> batch_sts;
+  int32_t batch_cells = 0;
   int64_t* offs = nullptr;          // structure offsets of a batch (device)
   int32_t cap_struct = 0;
   // training-loss workspace (grown on demand, kept until the handle ends)
   double* loss_part = nullptr;
   int64_t* loss_offs = nullptr;
+  std::vector<int64_t> loss_offs_host;  // the offsets loss_offs holds
   int64_t loss_part_cap = 0, loss_offs_cap = 0;
   double* snes_util = nullptr;     // [1024] SNES utilities of the last step
   double* heat_part = nullptr;     // per-block heat-current sums
@@ -343,6 +357,14 @@ struct nep_handle {
 
   ~nep_handle() { release(); }
 
+  void drop_batch_graph() {
+    if (batch_exec) (void)hipGraphExecDestroy(batch_exec);
+    if (batch_graph) (void)hipGraphDestroy(batch_graph);
+    batch_exec = nullptr;
+    batch_graph = nullptr;
+    batch_key.clear();
+  }
+
   void drop_md_graph() {
     if (md_exec) (void)hipGraphExecDestroy(md_exec);
     if (md_graph) (void)hipGraphDestroy(md_graph);
@@ -353,6 +375,9 @@ struct nep_handle {
 
   void release() {
     drop_md_graph();
+    drop_batch_graph();
+    dev_free(pop_tables);
+    pop_tables_cap = 0;
     if (md_stream) (void)hipStreamDestroy(md_stream);
     md_stream = nullptr;
     if (pinned) (void)hipHostFree(pinned);
@@ -459,7 +484,7 @@ void upload_model(nep_handle* h, const double* p, ModelTables& mt) {
   for (size_t k = 0; k < n_params(hp); ++k)
     if (!std::isfinite(p[k])) throw Failure{NEP_E_INVALID_ARG, "parameter vector has a non-finite entry"};
   std::vector<float> w0((size_t)nets * NNp * nd, 0.f), w0t((size_t)nets * nd * NNp, 0.f);
-  std::vector<float> b0((size_t)nets * NNp, 0.f), w1((size_t)nets * NNp, 0.f);
+  std::vector<float> b0((size_t)nets * NNp + 1, 0.f), w1((size_t)nets * NNp, 0.f);
   std::vector<uint16_t> w0b((size_t)nets * NNp * NDp32, 0), w0tb((size_t)nets * NDp32 * NNp, 0);
   size_t off = 0;
   for (int t = 0; t < nets; ++t) {
@@ -478,6 +503,7 @@ void upload_model(nep_handle* h, const double* p, ModelTables& mt) {
     off += NN;
   }
   const float b1 = (float)p[off++];
+  b0[(size_t)nets * NNp] = b1;  // b1 rides at the end of the b0 table
   std::vector<float> cR((size_t)T * T * nR * KR);
   for (size_t k = 0; k < cR.size(); ++k) cR[k] = (float)p[off + k];
   off += cR.size();
@@ -521,7 +547,7 @@ void upload_model(nep_handle* h, const double* p, ModelTables& mt) {
     M.cA_off[ng] = cA_off[ng];
     M.cA_pair[ng] = cA_pair[ng];
   }
-  M.rcR = (float)hp.rc_radial; M.rcA = (float)hp.rc_angular; M.b1 = b1;
+  M.rcR = (float)hp.rc_radial; M.rcA = (float)hp.rc_angular; M.b1 = mt.b0 + (size_t)nets * NNp;
   M.cR = mt.cR; M.cA = mt.cA; M.NNp = NNp; M.NDp32 = NDp32;
   M.w0 = mt.w0; M.w0t = mt.w0t; M.b0 = mt.b0; M.w1 = mt.w1; M.w0b = mt.w0b; M.w0tb = mt.w0tb;
   double C3[kMaxNB] = {0}, C4[5], C5[3];
@@ -529,6 +555,78 @@ void upload_model(nep_handle* h, const double* p, ModelTables& mt) {
   for (int k = 0; k < kMaxNB; ++k) M.C3[k] = (float)C3[k];
   for (int k = 0; k < 5; ++k) M.C4[k] = (float)C4[k];
   for (int k = 0; k < 3; ++k) M.C5[k] = (float)C5[k];
+}
+
+// Layout of the device-built tables of one parameter set (the same tables
+// upload_model builds on the host).
+TableLayout table_layout(const nep_hparams& hp, int nd) {
+  TableLayout L{};
+  L.nets = hp.nn_per_type ? hp.n_types : 1;
+  L.NN = hp.n_neurons;
+  L.NNp = (L.NN + 31) / 32 * 32;
+  L.ND = nd;
+  L.NDp32 = (nd + 31) / 32 * 32;
+  L.T = hp.n_types;
+  L.nR = hp.n_max_radial + 1;
+  L.KR = hp.basis_radial + 1;
+  L.nA = hp.n_max_angular + 1;
+  L.KA = hp.basis_angular + 1;
+  L.off_b1 = (int64_t)L.nets * (nd + 2) * L.NN;
+  L.off_cR = L.off_b1 + 1;
+  L.off_cA = L.off_cR + (int64_t)L.T * L.T * L.nR * L.KR;
+  L.n_ng = 0;
+  int64_t cA = 0;
+  for (int ng : angular_group_options(L.nA, hp.l_max_3b)) {
+    const int ps = pair_stride((L.nA + ng - 1) / ng * L.KA * ng_pad(ng));
+    L.ng_of[L.n_ng] = ng;
+    L.cA_pair_of[L.n_ng] = ps;
+    L.cA_off_of[L.n_ng] = cA;
+    cA += (int64_t)L.T * L.T * ps;
+    ++L.n_ng;
+  }
+  L.n_cA = cA;
+  auto take = [](int64_t& at, int64_t bytes) {
+    const int64_t o = at;
+    at += (bytes + 255) / 256 * 256;
+    return o;
+  };
+  int64_t at = 0;
+  L.at_w0 = take(at, (int64_t)L.nets * L.NNp * L.ND * 4);
+  L.at_w0t = take(at, (int64_t)L.nets * L.ND * L.NNp * 4);
+  L.at_b0 = take(at, ((int64_t)L.nets * L.NNp + 1) * 4);
+  L.at_w1 = take(at, (int64_t)L.nets * L.NNp * 4);
+  L.at_w0b = take(at, (int64_t)L.nets * L.NNp * L.NDp32 * 2);
+  L.at_w0tb = take(at, (int64_t)L.nets * L.NDp32 * L.NNp * 2);
+  L.at_cR = take(at, (int64_t)L.T * L.T * L.nR * L.KR * 4);
+  L.at_cA = take(at, L.n_cA * 4);
+  L.set_bytes = at;
+  return L;
+}
+
+// The DevModel of tables at `base` laid out by L (scalars from the handle's).
+DevModel model_at(const DevModel& proto, const TableLayout& L, const unsigned char* base) {
+  DevModel M = proto;
+  M.w0 = (const float*)(base + L.at_w0);
+  M.w0t = (const float*)(base + L.at_w0t);
+  M.b0 = (const float*)(base + L.at_b0);
+  M.b1 = M.b0 + (size_t)L.nets * L.NNp;
+  M.w1 = (const float*)(base + L.at_w1);
+  M.w0b = (const uint16_t*)(base + L.at_w0b);
+  M.w0tb = (const uint16_t*)(base + L.at_w0tb);
+  M.cR = (const float*)(base + L.at_cR);
+  M.cA = (const float*)(base + L.at_cA);
+  for (int ng = 0; ng < 8; ++ng) {
+    M.cA_off[ng] = -1;
+    M.cA_pair[ng] = 0;
+  }
+  int32_t cA_max = 0;
+  for (int o = 0; o < L.n_ng; ++o) {
+    M.cA_off[L.ng_of[o]] = (int32_t)L.cA_off_of[o];
+    M.cA_pair[L.ng_of[o]] = L.cA_pair_of[o];
+    cA_max = std::max(cA_max, L.T * L.T * L.cA_pair_of[o]);
+  }
+  M.cA_max = cA_max;
+  return M;
 }
 
 // Length of the species-grouped row order: every species segment is padded
@@ -681,6 +779,7 @@ EvalArgs eval_args(nep_handle* h, const Prepared& pp, const DevModel& M) {
 Prepared prepare_batch(nep_handle* h, int32_t S, const int64_t* offs, const double* boxes,
                        const int32_t* pbcs, double r_list, bool md, bool force_batch, hipStream_t s) {
   if (S < 1) throw Failure{NEP_E_INVALID_ARG, "n_struct must be >= 1"};
+  h->batch_rows_ready = false;  // the rows are about to belong to other structures
   const int64_t N = offs ? offs[S] : 0;
   if (N < 1 || N > (int64_t)1 << 30) throw Failure{NEP_E_INVALID_ARG, "n_atoms must be in [1, 2^30]"};
   Prepared pp;
@@ -968,70 +1067,120 @@ int compute_impl(nep_handle* h, int64_t N, const double* d_pos, const int32_t* d
 }
 
 // Batch of structures x parameter sets (device pointers).  Rows are built once
-// and shared by every parameter set; the per-set passes are captured once
-// into a HIP graph and launched as one graph.
+// and shared by every parameter set (or reused from the previous batch call
+// when the caller says the structures are the same); the per-set passes are
+// captured into a HIP graph, kept in the handle and replayed by later calls
+// with the same shapes, buffers and output pointers.  Parameter vectors come
+// from the host (tables built there, one upload per set) or from device
+// memory (tables built by a kernel inside the graph, so a training
+// generation never goes through the host).
 int batch_impl(nep_handle* h, int32_t S, const int64_t* offs, const double* d_pos, const int32_t* d_types,
-               const double* boxes, const int32_t* pbcs, int32_t P, const double* params, double* d_energy,
-               double* d_force, double* d_virial, double* d_totals, hipStream_t s) {
-  if (!offs || !boxes) throw Failure{NEP_E_INVALID_ARG, "offsets and boxes are required"};
+               const double* boxes, const int32_t* pbcs, int32_t P, const double* params,
+               const double* d_params, int32_t flags, double* d_energy, double* d_force, double* d_virial,
+               double* d_totals, hipStream_t s) {
+  if (!offs) throw Failure{NEP_E_INVALID_ARG, "offsets are required"};
   if (P < 1) throw Failure{NEP_E_INVALID_ARG, "n_param_sets must be >= 1"};
-  Prepared pp = prepare_batch(h, S, offs, boxes, pbcs, h->hp.rc_radial, false, true, s);
+  if (params && d_params) throw Failure{NEP_E_INVALID_ARG, "pass host or device parameters, not both"};
+  const bool reuse = (flags & NEP_BATCH_REUSE_ROWS) != 0;
+  Prepared pp;
+  if (reuse) {
+    if (!h->batch_rows_ready || h->batch_S != S || S < 1 || h->batch_N != offs[S])
+      throw Failure{NEP_E_INVALID_ARG, "no rows of the same structures to reuse: call once without "
+                                       "NEP_BATCH_REUSE_ROWS first"};
+    pp.sts = h->batch_sts;
+    pp.geo.st = pp.sts[0];
+    pp.n_cells = h->batch_cells;
+    pp.N = h->batch_N;
+    pp.batch = true;
+  } else {
+    if (!boxes) throw Failure{NEP_E_INVALID_ARG, "boxes are required"};
+    h->batch_rows_ready = false;
+    pp = prepare_batch(h, S, offs, boxes, pbcs, h->hp.rc_radial, false, true, s);
+  }
   const int64_t N = pp.N;
-  std::vector<const DevModel*> models;
+  std::vector<DevModel> models;
+  TableLayout TL{};
   if (params) {
     if ((int32_t)h->pop.size() < P) h->pop.resize(P);
     for (int32_t p = 0; p < P; ++p) {
       upload_model(h, params + (size_t)p * n_params(h->hp), h->pop[p]);
-      models.push_back(&h->pop[p].M);
+      models.push_back(h->pop[p].M);
     }
+  } else if (d_params) {
+    TL = table_layout(h->hp, h->nd);
+    const int64_t need = (int64_t)P * TL.set_bytes;
+    if (need > h->pop_tables_cap) {
+      HIPCHK(hipStreamSynchronize(s));
+      dev_alloc(h->pop_tables, (size_t)need);
+      h->pop_tables_cap = need;
+    }
+    for (int32_t p = 0; p < P; ++p) models.push_back(model_at(h->M, TL, h->pop_tables + p * TL.set_bytes));
   } else {
-    if (P != 1) throw Failure{NEP_E_INVALID_ARG, "params is NULL: use n_param_sets = 1"};
-    models.push_back(&h->M);
+    if (P != 1) throw Failure{NEP_E_INVALID_ARG, "no parameters given: use n_param_sets = 1"};
+    models.push_back(h->M);
   }
-  order_and_build(h, pp, d_pos, d_types, s, true);
+  if (!reuse) {
+    order_and_build(h, pp, d_pos, d_types, s, true);
+    h->batch_rows_ready = true;
+    h->batch_S = S;
+    h->batch_N = N;
+    h->batch_sts = pp.sts;
+    h->batch_cells = pp.n_cells;
+  }
   autotune(h, pp, s);
-  // capture the per-set passes (descriptor, network, forces, gather, outputs)
+  // everything the captured kernels hold by value or by address
+  std::vector<unsigned char> key;
+  auto put = [&](const void* p, size_t n) {
+    const unsigned char* c = (const unsigned char*)p;
+    key.insert(key.end(), c, c + n);
+  };
+  const uint64_t gen = g_alloc_gen.load();
+  put(&gen, sizeof gen);
+  put(&S, sizeof S);
+  put(&N, sizeof N);
+  put(&P, sizeof P);
+  const void* ptrs[6] = {d_params, d_energy, d_force, d_virial, d_totals, params};
+  put(ptrs, sizeof ptrs);
   const bool timing = h->timing;
   hipStream_t cs = s;
-  hipStream_t own = nullptr;
-  if (!cs) {  // the legacy null stream cannot be captured: use a private stream
-    HIPCHK(hipStreamCreateWithFlags(&own, hipStreamNonBlocking));
+  if (!cs) {  // the legacy null stream cannot be captured: use the handle's own stream
+    if (!h->md_stream) HIPCHK(hipStreamCreateWithFlags(&h->md_stream, hipStreamNonBlocking));
     HIPCHK(hipStreamSynchronize(s));
-    cs = own;
+    cs = h->md_stream;
   }
-  h->timing = false;
-  hipGraph_t graph = nullptr;
-  hipGraphExec_t exec = nullptr;
-  try {
-    HIPCHK(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
-    for (int32_t p = 0; p < P; ++p) {
-      forces(h, pp, cs, models[p]);
-      EvalArgs a = eval_args(h, pp, *models[p]);
-      launch_scatter_outputs(a, h->perm, d_energy ? d_energy + (size_t)p * N : nullptr,
-                             d_force ? d_force + (size_t)p * 3 * N : nullptr,
-                             d_virial ? d_virial + (size_t)p * 9 * N : nullptr, cs);
-      if (d_totals) launch_struct_totals(h->U, h->W, N, h->structs, S, d_totals + (size_t)p * S * 10, cs);
+  if (!h->batch_exec || h->batch_key != key) {
+    h->drop_batch_graph();
+    h->timing = false;
+    try {
+      HIPCHK(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+      if (d_params) launch_model_tables(d_params, (int64_t)n_params(h->hp), P, TL, h->pop_tables, TL.set_bytes, cs);
+      for (int32_t p = 0; p < P; ++p) {
+        forces(h, pp, cs, &models[p]);
+        EvalArgs a = eval_args(h, pp, models[p]);
+        launch_scatter_outputs(a, h->perm, d_energy ? d_energy + (size_t)p * N : nullptr,
+                               d_force ? d_force + (size_t)p * 3 * N : nullptr,
+                               d_virial ? d_virial + (size_t)p * 9 * N : nullptr, cs);
+        if (d_totals) launch_struct_totals(h->U, h->W, N, h->structs, S, d_totals + (size_t)p * S * 10, cs);
+      }
+      HIPCHK(hipStreamEndCapture(cs, &h->batch_graph));
+      HIPCHK(hipGraphInstantiate(&h->batch_exec, h->batch_graph, nullptr, nullptr, 0));
+      h->batch_key = key;
+    } catch (...) {
+      hipGraph_t g2 = nullptr;
+      (void)hipStreamEndCapture(cs, &g2);
+      if (g2) (void)hipGraphDestroy(g2);
+      h->drop_batch_graph();
+      h->timing = timing;
+      throw;
     }
-    HIPCHK(hipStreamEndCapture(cs, &graph));
-    HIPCHK(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
-  } catch (...) {
-    hipGraph_t g2 = nullptr;
-    (void)hipStreamEndCapture(cs, &g2);
-    if (g2) (void)hipGraphDestroy(g2);
-    if (graph) (void)hipGraphDestroy(graph);
-    if (own) (void)hipStreamDestroy(own);
     h->timing = timing;
-    throw;
   }
-  h->timing = timing;
   {
     Stage st(h, "batch_graph", cs);
-    HIPCHK(hipGraphLaunch(exec, cs));
+    HIPCHK(hipGraphLaunch(h->batch_exec, cs));
   }
-  HIPCHK(hipStreamSynchronize(cs));
-  (void)hipGraphExecDestroy(exec);
-  (void)hipGraphDestroy(graph);
-  if (own) (void)hipStreamDestroy(own);
+  // host parameters (and the null stream) keep the call synchronous
+  if (params || cs != s) HIPCHK(hipStreamSynchronize(cs));
   return NEP_OK;
 }
 
@@ -1576,17 +1725,23 @@ int nep_batch_loss(nep_handle* h, int32_t n_struct, const int64_t* offsets, int3
       HIPCHK(hipStreamSynchronize(s));
       dev_alloc(h->loss_offs, (size_t)n_struct + 1);
       h->loss_offs_cap = n_struct + 1;
+      h->loss_offs_host.clear();
     }
-    HIPCHK(hipMemcpyAsync(h->loss_offs, offsets, ((size_t)n_struct + 1) * sizeof(int64_t),
-                          hipMemcpyHostToDevice, s));
+    // the offsets are uploaded only when they differ from the last call's
+    if (h->loss_offs_host.size() != (size_t)n_struct + 1 ||
+        !std::equal(offsets, offsets + n_struct + 1, h->loss_offs_host.begin())) {
+      HIPCHK(hipMemcpyAsync(h->loss_offs, offsets, ((size_t)n_struct + 1) * sizeof(int64_t),
+                            hipMemcpyHostToDevice, s));
+      HIPCHK(hipStreamSynchronize(s));  // the host array may change after the call
+      h->loss_offs_host.assign(offsets, offsets + n_struct + 1);
+    }
     {
       Stage st(h, "batch_loss", s);
       launch_loss(force, totals, h->loss_offs, n_struct, N, n_param_sets, energy_target, force_target,
                   virial_target, params, params ? n_par : 0, lambda, h->loss_part, loss, s);
     }
     HIPCHK(hipGetLastError());
-    HIPCHK(hipStreamSynchronize(s));
-    h->resolve_timing();
+    if (h->timing) h->resolve_timing();
   } catch (const Failure& f) {
     return fail(h, f);
   }
@@ -1711,6 +1866,68 @@ int nep_neighbors(nep_handle* h, int64_t N, const double* pos, const double box[
         for (int c = 0; c < 3; ++c) shift[(i * cap + m) * 3 + c] = row[m][1 + c];
       }
     }
+  } catch (const Failure& f) {
+    return fail(h, f);
+  }
+  return NEP_OK;
+}
+
+int nep_elastic_cubic(nep_handle* h, int64_t N, const double* pos, const int32_t* types, const double box[9],
+                      const int32_t pbc[3], double strain, double C[3]) {
+  if (!h) return fail(nullptr, {NEP_E_INVALID_ARG, "handle is NULL"});
+  if (!pos || !types || !box || !C) return fail(h, {NEP_E_INVALID_ARG, "bad arguments"});
+  try {
+    set_device(h);
+    if (N < 1) throw Failure{NEP_E_INVALID_ARG, "n_atoms must be >= 1"};
+    if (!(strain > 0) || !(strain < 0.2)) throw Failure{NEP_E_INVALID_ARG, "strain must be in (0, 0.2)"};
+    check_host_types(h, N, types);
+    check_host_finite(3 * N, pos, "positions");
+    const double V = std::fabs(box[0] * (box[4] * box[8] - box[5] * box[7]) -
+                               box[1] * (box[3] * box[8] - box[5] * box[6]) +
+                               box[2] * (box[3] * box[7] - box[4] * box[6]));
+    hipStream_t s = nullptr;
+    std::vector<double> p(3 * N);
+    // total energy of the cell deformed by F = I + eps (positions r -> F r,
+    // cell vectors a -> F a), from the device totals
+    auto energy = [&](const double eps[9]) {
+      double F[9], b[9];
+      for (int k = 0; k < 9; ++k) F[k] = eps[k] + ((k % 4) == 0 ? 1.0 : 0.0);
+      for (int64_t i = 0; i < N; ++i)
+        for (int r = 0; r < 3; ++r)
+          p[r * N + i] = F[3 * r] * pos[i] + F[3 * r + 1] * pos[N + i] + F[3 * r + 2] * pos[2 * N + i];
+      for (int v = 0; v < 3; ++v)
+        for (int r = 0; r < 3; ++r)
+          b[3 * v + r] = F[3 * r] * box[3 * v] + F[3 * r + 1] * box[3 * v + 1] + F[3 * r + 2] * box[3 * v + 2];
+      prepare(h, N, b, pbc, h->hp.rc_radial, false, s);
+      HIPCHK(hipMemcpyAsync(h->pos_ext, p.data(), 3 * N * sizeof(double), hipMemcpyHostToDevice, s));
+      HIPCHK(hipMemcpyAsync(h->types_ext, types, N * sizeof(int32_t), hipMemcpyHostToDevice, s));
+      compute_impl(h, N, h->pos_ext, h->types_ext, b, pbc, nullptr, nullptr, nullptr, h->totals, s);
+      double t = 0;
+      HIPCHK(hipMemcpyAsync(h->pinned + 2048, h->totals, sizeof(double), hipMemcpyDeviceToHost, s));
+      HIPCHK(hipStreamSynchronize(s));
+      std::memcpy(&t, h->pinned + 2048, sizeof t);
+      return t;
+    };
+    const double zero[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+    const double e0 = energy(zero);
+    // second difference (E(+d) + E(-d) - 2 E(0)) / d^2 along eps = d A
+    auto curvature = [&](const double A[9]) {
+      double ep[9], em[9];
+      for (int k = 0; k < 9; ++k) {
+        ep[k] = strain * A[k];
+        em[k] = -strain * A[k];
+      }
+      return (energy(ep) + energy(em) - 2.0 * e0) / (strain * strain);
+    };
+    const double uni[9] = {1, 0, 0, 0, 0, 0, 0, 0, 0};
+    const double bi[9] = {1, 0, 0, 0, 1, 0, 0, 0, 0};
+    const double shear[9] = {0, 0.5, 0, 0.5, 0, 0, 0, 0, 0};
+    const double c11 = curvature(uni) / V, c1112 = curvature(bi) / (2.0 * V), c44 = curvature(shear) / V;
+    const double gpa = 160.21766208;  // eV/A^3 in GPa
+    C[0] = c11 * gpa;
+    C[1] = (c1112 - c11) * gpa;
+    C[2] = c44 * gpa;
+    h->resolve_timing();
   } catch (const Failure& f) {
     return fail(h, f);
   }
@@ -2405,9 +2622,28 @@ int nep_compute_batch(nep_handle* h, int32_t n_struct, const int64_t* offsets, c
   if (!pos || !types) return fail(h, {NEP_E_INVALID_ARG, "pos and types are required"});
   try {
     set_device(h);
-    batch_impl(h, n_struct, offsets, pos, types, boxes, pbc, n_param_sets, params, energy, force, virial,
-               totals, (hipStream_t)stream);
+    batch_impl(h, n_struct, offsets, pos, types, boxes, pbc, n_param_sets, params, nullptr, 0, energy, force,
+               virial, totals, (hipStream_t)stream);
+    HIPCHK(hipStreamSynchronize((hipStream_t)stream));
     h->resolve_timing();
+  } catch (const Failure& f) {
+    return fail(h, f);
+  }
+  return NEP_OK;
+}
+
+int nep_compute_batch_dev(nep_handle* h, int32_t n_struct, const int64_t* offsets, const double* pos,
+                          const int32_t* types, const double* boxes, const int32_t* pbc, int32_t n_param_sets,
+                          const double* params, int32_t flags, double* energy, double* force, double* virial,
+                          double* totals, void* stream) {
+  if (!h) return fail(nullptr, {NEP_E_INVALID_ARG, "handle is NULL"});
+  if (!pos || !types || !params) return fail(h, {NEP_E_INVALID_ARG, "pos, types and params are required"});
+  if (flags & ~NEP_BATCH_REUSE_ROWS) return fail(h, {NEP_E_INVALID_ARG, "unknown flags"});
+  try {
+    set_device(h);
+    batch_impl(h, n_struct, offsets, pos, types, boxes, pbc, n_param_sets, nullptr, params, flags, energy, force,
+               virial, totals, (hipStream_t)stream);
+    if (h->timing) h->resolve_timing();
   } catch (const Failure& f) {
     return fail(h, f);
   }

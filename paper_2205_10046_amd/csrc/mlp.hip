@@ -141,7 +141,7 @@ __global__ void __launch_bounds__(256) k_mlp(EvalArgs a) {
     }
   u += __shfl_xor(u, 16);
   u += __shfl_xor(u, 32);
-  if (grp == 0 && atom >= 0) a.U[atom] = u - M.b1;
+  if (grp == 0 && atom >= 0) a.U[atom] = u - *M.b1;
 
 
   // ---- GEMM 2: dU/dq[atom][d] = sum_mu G[atom][mu] w0[mu][d] ----

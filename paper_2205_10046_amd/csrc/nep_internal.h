@@ -138,7 +138,7 @@ struct DevModel {
   int32_t T, nR, KR, nA, KA, L, NB, ND, NDp, NN, nets, has4b, has5b;
   int32_t cA_max;           // largest angular table (floats) over the group sizes
   float rcR, rcA;
-  float b1;
+  const float* b1;          // the output bias b1, one float in device memory
   const float* cR;          // [T][T][nR][KR]
   // angular coefficients for group size NG at cA + cA_off[NG] (-1: none):
   // [T x T species pairs, cA_pair[NG] floats apart][groups][KA][ng_pad(NG)],
@@ -152,7 +152,7 @@ struct DevModel {
   int32_t NDp32;            // N_des rounded up to 32
   const float* w0;          // [nets][NNp][ND]   network weights w0, row = neuron
   const float* w0t;         // [nets][ND][NNp]   the same, transposed
-  const float* b0;          // [nets][NNp]
+  const float* b0;          // [nets][NNp], then b1
   const float* w1;          // [nets][NNp]
   const uint16_t* w0b;      // [nets][NNp][NDp32] w0 as bf16 bits
   const uint16_t* w0tb;     // [nets][NDp32][NNp] transposed, bf16 bits

@@ -124,6 +124,21 @@ void launch_neighbors_out(const Lists& L, int which, int64_t N, const int32_t* p
                           int32_t* shift, hipStream_t s);
 void launch_inverse_perm(const int32_t* perm, int64_t N, int32_t* inv, hipStream_t s);
 
+// params.hip: model tables of many parameter vectors built on the device.
+// Layout of one set's tables (byte offsets) and where each part of the
+// parameter vector starts.
+struct TableLayout {
+  int32_t nets, NN, NNp, ND, NDp32, T, nR, KR, nA, KA;
+  int64_t off_b1, off_cR, off_cA;           // in the float64 parameter vector
+  int32_t n_ng;                             // admissible angular group sizes
+  int32_t ng_of[4], cA_pair_of[4];
+  int64_t cA_off_of[4], n_cA;               // floats, per group size and in all
+  int64_t at_w0, at_w0t, at_b0, at_w1, at_w0b, at_w0tb, at_cR, at_cA, set_bytes;
+};
+int64_t table_elements(const TableLayout& L);
+void launch_model_tables(const double* params, int64_t npar, int32_t P, const TableLayout& L,
+                         unsigned char* base, int64_t set_stride, hipStream_t s);
+
 // output.hip: the fixed workspace of nep_batch_loss_noalloc (one per GPU).
 constexpr int64_t kLossScratchBytes = 1 << 20;
 constexpr int kMaxDevices = 64;

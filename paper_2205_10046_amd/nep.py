@@ -32,8 +32,8 @@ NEP_MLP_BF16 = 1
 EXPORTS = ["nep_num_descriptors", "nep_num_params", "nep_create", "nep_set_params",
            "nep_destroy", "nep_last_error", "nep_compute", "nep_compute_dev",
            "nep_heat_current", "nep_heat_current_dev", "nep_neighbors", "nep_descriptors",
-           "nep_latent", "nep_md_run", "nep_md_run_dev", "nep_md_run_ensemble",
-           "nep_compute_batch", "nep_batch_loss", "nep_batch_loss_noalloc", "nep_snes_step",
+           "nep_latent", "nep_elastic_cubic", "nep_md_run", "nep_md_run_dev", "nep_md_run_ensemble",
+           "nep_compute_batch", "nep_compute_batch_dev", "nep_batch_loss", "nep_batch_loss_noalloc", "nep_snes_step",
            "nep_snes_sample", "nep_set_timing", "nep_get_timing", "nep_get_tuning",
            "nep_server_create",
            "nep_server_submit", "nep_server_poll", "nep_server_stats", "nep_server_reset_stats",
@@ -147,12 +147,15 @@ def load():
     L.nep_neighbors.argtypes = [vp, i64, pd, pd, pi32, i32, i32, pi32, pi32, pi32]
     L.nep_descriptors.argtypes = [vp, i64, pd, pi32, pd, pi32, pd]
     L.nep_latent.argtypes = [vp, i64, pd, pi32, pd, pi32, pd]
+    L.nep_elastic_cubic.argtypes = [vp, i64, pd, pi32, pd, pi32, d, pd]
     L.nep_md_run.argtypes = [vp, i64, pd, pd, pi32, pd, pd, pi32, d, i64, i64, pd]
     L.nep_md_run_dev.argtypes = [vp, i64, vp, vp, vp, pd, pd, pi32, d, i64, i64, vp, vp]
     L.nep_md_run_ensemble.argtypes = [vp, i64, pd, pd, pi32, pd, pd, pi32, d, i64, i64, pd,
                                       P(nep_ensemble), pd]
     L.nep_compute_batch.argtypes = [vp, i32, P(i64), vp, vp, pd, pi32, i32, pd, vp, vp, vp,
                                     vp, vp]
+    L.nep_compute_batch_dev.argtypes = [vp, i32, P(i64), vp, vp, pd, pi32, i32, vp, i32, vp, vp,
+                                        vp, vp, vp]
     L.nep_batch_loss.argtypes = [vp, i32, P(i64), i32, vp, i64, vp, vp, vp, vp, vp, pd, vp, vp]
     L.nep_batch_loss_noalloc.argtypes = L.nep_batch_loss.argtypes
     L.nep_snes_step.argtypes = [vp, i64, i32, vp, vp, vp, vp, i64, d, d, vp]
@@ -348,6 +351,16 @@ class Handle:
             _ptr(pbc, C.c_int32), _ptr(q, C.c_double)))
         return q
 
+    def elastic_cubic(self, pos, types, box, strain=0.01, pbc=None):
+        """nep_elastic_cubic: (C11, C12, C44) in GPa by the energy-strain relation."""
+        pos, types, box = _f64(pos), _i32(types), _f64(box)
+        pbc = _i32(np.ones(3) if pbc is None else pbc)
+        out = np.zeros(3)
+        self._check(load().nep_elastic_cubic(
+            self._h, pos.shape[1], _ptr(pos, C.c_double), _ptr(types, C.c_int32),
+            _ptr(box, C.c_double), _ptr(pbc, C.c_int32), float(strain), _ptr(out, C.c_double)))
+        return out
+
     def latent(self, pos, types, box, pbc=None):
         """Per-atom latent-space vectors w1_mu h_mu, (N, N_neu)."""
         pos, types, box = _f64(pos), _i32(types), _f64(box)
@@ -434,6 +447,29 @@ class Handle:
         self._check(load().nep_compute_batch(
             self._h, S, _ptr(offsets, C.c_int64), *a[:2], _ptr(boxes, C.c_double),
             _ptr(pbc, C.c_int32), P, _ptr(params, C.c_double), *a[2:], _torch_stream()))
+
+    def compute_batch_dev(self, offsets, pos, types, boxes, params, energy=None, force=None,
+                          virial=None, totals=None, pbc=None, reuse_rows=False):
+        """nep_compute_batch_dev: params (P, N_par) float64 on the GPU like pos,
+        types and the outputs; offsets, boxes and pbc are host arrays (boxes
+        may be None with reuse_rows)."""
+        offsets = np.ascontiguousarray(offsets, dtype=np.int64)
+        S = offsets.shape[0] - 1
+        n = int(offsets[-1])
+        P = int(params.shape[0])
+        boxes = None if boxes is None else _f64(boxes)
+        pbc = None if pbc is None else _i32(pbc)
+        if boxes is not None and boxes.shape != (S, 9):
+            raise NepError(NEP_E_INVALID_ARG, "boxes must be (S, 9)")
+        a = _devs(_dev(pos, "f64", (3, n), "pos"), _dev(types, "i32", (n,), "types"),
+                  _dev(params, "f64", (P, None), "params"),
+                  _dev(energy, "f64", (P, n), "energy", True),
+                  _dev(force, "f64", (P, 3, n), "force", True),
+                  _dev(virial, "f64", (P, 9, n), "virial", True),
+                  _dev(totals, "f64", (P, S, 10), "totals", True))
+        self._check(load().nep_compute_batch_dev(
+            self._h, S, _ptr(offsets, C.c_int64), a[0], a[1], _ptr(boxes, C.c_double),
+            _ptr(pbc, C.c_int32), P, a[2], 1 if reuse_rows else 0, *a[3:], _torch_stream()))
 
     def batch_loss(self, offsets, force, totals, energy_target, force_target, lam,
                    loss, virial_target=None, params=None, noalloc=False):

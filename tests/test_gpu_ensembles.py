@@ -133,3 +133,20 @@ def test_barostats_move_toward_target(alloy, name):
     assert abs(P[-30:].mean() - P0) < 0.25 * abs(P[0] - P0)
     assert V1 > V0   # the lattice above the target pressure expands
     handle.close()
+
+
+@pytest.mark.parametrize("kind,a,nc", [("fcc", 4.05, 3), ("bcc", 3.16, 4)])
+def test_elastic_constants_match_oracle(kind, a, nc):
+    """C11, C12, C44 by the energy-strain relation with +-1 % strains (the
+    paper's compute_elastic 0.01) against the oracle's: the second
+    differences magnify the float32 energy error by 1/strain^2, so the
+    comparison allows 2e-3 relative and 0.05 GPa."""
+    h = synth.hparams(1, 5.0, 4.0, 4, 4, 5, 5, 4, 2, 0, 16, 0)
+    p = synth.random_params(O.num_params(h), seed=3)
+    pos, types, box = synth.lattice(kind, nc, a, 0.0, 1)
+    handle = nep.Handle(h, p)
+    got = handle.elastic_cubic(pos, types, box, 0.01)
+    ref = O.elastic_cubic(h, p, pos, types, box, 0.01)
+    log(f"[elastic] {kind}: C11 C12 C44 = {got} GPa (oracle {ref})")
+    np.testing.assert_allclose(got, ref, rtol=2e-3, atol=0.05)
+    handle.close()
