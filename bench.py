@@ -83,6 +83,11 @@ def algorithmic_flops(h, p_r, p_a):
     return dict(descriptor=desc, mlp=mlp, partial_forces=force, gather=gather)
 
 
+def progress(msg):
+    """A progress line on stderr (stdout carries only the JSON result)."""
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -371,6 +376,7 @@ def main():
         dt, stages, th = run_md(handle, pos_d, vel_d, types_d, masses, box, args.steps,
                                 args.warmup, torch)
         results[prec] = (dt, stages, th)
+        progress(f"fcc131k md mlp={'bf16' if prec else 'fp32'}: {dt / args.steps * 1e3:.4f} ms/step")
         if prec == nep.NEP_MLP_FP32:
             tune = handle.tuning()
         handle.close()
@@ -458,17 +464,21 @@ def main():
             hd.close()
             del pd_, vd_, td_
             torch.cuda.empty_cache()
+            progress(f"bcc2m md {tag}: {t2 / args.steps_2m * 1e3:.3f} ms/step")
     if not args.no_batch:
         out["population_batch"] = batch_leg(nep, synth, torch, args.batch_structs,
                                             args.batch_sets)
+        progress(f"population batch: {out['population_batch']['ms_per_call']:.1f} ms per call")
     if not args.no_serve:
         pof = lambda hh: synth.random_params(nep.nep_num_params(hh))  # noqa: E731
         out["serving"] = {"fp32": serving_leg(nep, synth, pof, args.serve_requests,
                                               args.serve_budget_gb, nep.NEP_MLP_FP32)}
+        progress("serving fp32 done")
         if not args.no_bf16:
             out["serving"]["bf16"] = serving_leg(nep, synth, pof, args.serve_requests,
                                                  args.serve_budget_gb, nep.NEP_MLP_BF16)
     if not args.no_cpu:
+        progress("cpu baseline (oracle) ...")
         out["cpu_baseline"] = cpu_baseline(h, params, args.cpu_seconds)
     print(json.dumps(out), flush=True)
 

@@ -630,8 +630,10 @@ DevModel model_at(const DevModel& proto, const TableLayout& L, const unsigned ch
 }
 
 // Length of the species-grouped row order: every species segment is padded
-// to whole 16-row tiles, so it never exceeds round16(N) + 16 T.
-int64_t rows_length(int64_t N, int T) { return (N + 15) / 16 * 16 + 16 * (int64_t)T; }
+// to whole groups of kRowGroup rows, so it never exceeds round(N) + kRowGroup T.
+int64_t rows_length(int64_t N, int T) {
+  return (N + kRowGroup - 1) / kRowGroup * kRowGroup + kRowGroup * (int64_t)T;
+}
 
 int64_t num_partials(int64_t N) { return std::min<int64_t>(512, std::max<int64_t>(1, (N + 1023) / 1024)); }
 

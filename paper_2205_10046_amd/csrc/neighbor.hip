@@ -321,7 +321,7 @@ __global__ void k_reverse(int64_t N, const int32_t* __restrict__ nn, const int32
 }
 
 // ---- row order for the network pass: atoms grouped by species in
-// increasing internal index, each group padded to whole 16-row tiles
+// increasing internal index, each group padded to whole kRowGroup-row groups
 // (padding rows hold -1).  Counting sort by blocks of kBlock atoms:
 // per-block species counts, one exclusive scan over [species][block], then
 // every atom takes its rank inside the block from wave ballots. ----
@@ -360,7 +360,7 @@ __global__ void k_type_shift(const int32_t* __restrict__ tex, int64_t N, int32_t
     const int32_t first = tex[(int64_t)t * nb];
     const int32_t next = t + 1 < Tn ? tex[(int64_t)(t + 1) * nb] : (int32_t)N;
     shift[t] = o - first;
-    o += (next - first + 15) / 16 * 16;
+    o += (next - first + kRowGroup - 1) / kRowGroup * kRowGroup;
   }
 }
 

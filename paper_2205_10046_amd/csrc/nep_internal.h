@@ -23,6 +23,10 @@
 namespace nep {
 
 constexpr int kBlock = 256;
+// The network pass takes the species-grouped rows four 16-row tiles at a
+// time; every species segment is padded to this many rows, so such a group
+// never mixes species.
+constexpr int kRowGroup = 64;
 constexpr int kMaxL = 6;
 constexpr int kMaxNB = (kMaxL + 1) * (kMaxL + 1) - 1;
 constexpr int kMaxBasis = 16;    // N_bas + 1 and n_max + 1 limits

@@ -244,55 +244,74 @@ def test_train3_triclinic40_every_autotuned_shape_in_bounds():
 
 
 def test_network_tiles_in_bounds():
-    """k_mlp: 16-row tiles of the species-grouped row order (padding -1),
-    clamped q loads, w0/w0t/bf16 weight rows, for the same model."""
+    """k_mlp_lds (and the 16-row-tile k_mlp it falls back to): groups of 64
+    species-grouped rows (each species padded to whole groups, padding -1),
+    the staged w0 / q reads and their LDS slots, the network weight rows and
+    the dU/dq writes, for the same model, float32 and bf16."""
     h = synth.WORKLOADS["train3"]
     nd = O.num_descriptors(h)
     NN = h["n_neurons"]
     NNp, NDp, NDp32 = (NN + 31) // 32 * 32, (nd + 7) // 8 * 8, (nd + 31) // 32 * 32
+    G = 64
     rng = np.random.default_rng(5)
     for N, T in ((40, 3), (1, 3), (17, 1), (300, 3)):
         types = rng.integers(0, T, N)
-        rows_len = (N + 15) // 16 * 16 + 16 * T
+        rows_len = (N + G - 1) // G * G + G * T
         rows = []
         for t in range(T):
             idx = [i for i in range(N) if types[i] == t]
-            rows += idx + [-1] * ((-len(idx)) % 16)
+            rows += idx + [-1] * ((-len(idx)) % G)
         assert len(rows) <= rows_len
         rows += [-1] * (rows_len - len(rows))
         nets = T
-        sizes = dict(q=N * NDp, w0t=nets * nd * NNp, w0=nets * NNp * nd, w0b=nets * NNp * NDp32,
-                     w0tb=nets * NDp32 * NNp, rows=rows_len)
+        sizes = dict(q=N * NDp, fp=N * NDp, w0=nets * NNp * nd, w0b=nets * NNp * NDp32,
+                     w0tb=nets * NDp32 * NNp, rows=rows_len,
+                     lds32=NNp * (nd + 1) + G * (NDp + 1),
+                     lds16=NNp * (NDp32 + 8) + NDp32 * (NNp + 8) + G * (NDp32 + 8))
         hi = {k: -1 for k in sizes}
-        for base in range(0, rows_len, 16):
+
+        def touch(k, v):
+            hi[k] = max(hi[k], v)
+        for base in range(0, rows_len, G):
             first = rows[base]
             if first < 0:
+                assert all(r < 0 for r in rows[base:base + G])   # padding groups are whole
                 continue
             net = types[first]
-            for lane in range(64):
-                col, grp = lane & 15, lane >> 4
-                atom = rows[base + col]
-                qrow = (atom if atom >= 0 else 0) * NDp
-                for s in range(-(-nd // 4)):
-                    d = 4 * s + grp
-                    dn = min(d + 4, nd - 1)
-                    hi["q"] = max(hi["q"], qrow + min(d, nd - 1), qrow + dn)
-                    for nb in range(NNp // 16):
-                        hi["w0t"] = max(hi["w0t"], net * nd * NNp + dn * NNp + 16 * nb + col)
-                for s in range(NDp32 // 32):
-                    d0 = 32 * s + 8 * grp
-                    hi["q"] = max(hi["q"], qrow + min(d0, NDp - 8) + 7)
-                    for nb in range(NNp // 16):
-                        hi["w0b"] = max(hi["w0b"], net * NNp * NDp32 + (16 * nb + col) * NDp32 + d0 + 7)
-                for db in range(-(-nd // 16)):
-                    d = 16 * db + col
-                    dc = min(d, nd - 1)
-                    for nb in range(NNp // 16):
+            assert all(r < 0 or types[r] == net for r in rows[base:base + G])  # one species
+            touch("w0", net * NNp * nd + NNp * nd - 1)
+            touch("w0b", net * NNp * NDp32 + NNp * NDp32 - 1)
+            touch("w0tb", net * NDp32 * NNp + NDp32 * NNp - 1)
+            for r in range(G):
+                touch("rows", base + r)
+                if rows[base + r] >= 0:
+                    touch("q", rows[base + r] * NDp + NDp - 1)
+            SW, SQ = nd + 1, NDp + 1
+            SWB, STB, SQB = NDp32 + 8, NNp + 8, NDp32 + 8
+            touch("lds32", NNp * SW + (G - 1) * SQ + NDp - 1)
+            touch("lds16", NNp * SWB + NDp32 * STB + (G - 1) * SQB + NDp32 - 1)
+            for wave in range(4):
+                r0 = 16 * wave
+                for lane in range(64):
+                    col, grp = lane & 15, lane >> 4
+                    for st in range(-(-nd // 4)):
+                        d = 4 * st + grp
+                        if d < nd:
+                            touch("lds32", NNp * SW + (r0 + col) * SQ + d)
+                            touch("lds32", (16 * (NNp // 16 - 1) + col) * SW + d)
+                    for st in range(NDp32 // 32):
+                        d0 = 32 * st + 8 * grp
+                        touch("lds16", NNp * SWB + NDp32 * STB + (r0 + col) * SQB + d0 + 7)
+                        touch("lds16", (16 * (NNp // 16 - 1) + col) * SWB + d0 + 7)
+                    for db in range(-(-nd // 16)):
+                        d = 16 * db + col
+                        touch("lds32", (16 * (NNp // 16 - 1) + 4 * grp + 3) * SW + min(d, nd - 1))
+                        wrow = NNp * SWB + (d if d < NDp32 else 0) * STB
+                        touch("lds16", wrow + 32 * (NNp // 32 - 1) + 16 + 4 * grp + 3)
                         for r in range(4):
-                            hi["w0"] = max(hi["w0"], net * NNp * nd + (16 * nb + 4 * grp + r) * nd + dc)
-                    wrow = net * NDp32 * NNp + (d if d < NDp32 else 0) * NNp
-                    for p in range(NNp // 32):
-                        hi["w0tb"] = max(hi["w0tb"], wrow + 32 * p + 16 + 4 * grp + 3)
-                hi["rows"] = max(hi["rows"], base + 4 * 3 + 3, base + col)
+                            at = rows[base + r0 + 4 * grp + r]
+                            if at >= 0 and d < nd:
+                                touch("fp", at * NDp + d)
         for k, n in sizes.items():
             assert hi[k] < n, (N, k, hi[k], n)
+        assert 4 * sizes["lds32"] <= 64 * 1024 and 2 * sizes["lds16"] <= 64 * 1024
