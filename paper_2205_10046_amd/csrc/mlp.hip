@@ -36,6 +36,22 @@ __device__ __forceinline__ v8bf bf16x8_from_bits(uint4 u) {
   return r;
 }
 
+// tanh from its definition, branch-free: the odd Taylor series through x^9
+// for |x| < 1/4 (the first dropped term is below 1e-8 relative there) and
+// 1 - 2 / (1 + e^{2|x|}) with the sign of x elsewhere (e^{2|x|} = inf gives
+// 1).  Both forms are evaluated and one is selected, so the lanes of a wave
+// never diverge.  Absolute error <= ~2e-7.
+__device__ __forceinline__ float tanh_net(float x) {
+  const float ax = fabsf(x), x2 = x * x;
+  float p = fmaf(x2, 62.f / 2835.f, -17.f / 315.f);
+  p = fmaf(x2, p, 2.f / 15.f);
+  p = fmaf(x2, p, -1.f / 3.f);
+  const float small = fmaf(x * x2, p, x);
+  const float e = __builtin_amdgcn_exp2f(2.8853900817779268f * ax);  // 2^(2 |x| log2 e)
+  const float big = copysignf(fmaf(-2.f, __builtin_amdgcn_rcpf(1.f + e), 1.f), x);
+  return ax < 0.25f ? small : big;
+}
+
 __device__ __forceinline__ void bf16x4_from_bits(uint2 u, v8bf& r, int off) {
   r[off + 0] = __builtin_bit_cast(__bf16, (uint16_t)(u.x & 0xffffu));
   r[off + 1] = __builtin_bit_cast(__bf16, (uint16_t)(u.x >> 16));
@@ -132,7 +148,7 @@ __global__ void __launch_bounds__(256) k_mlp(EvalArgs a) {
   for (int nb = 0; nb < NNB; ++nb)
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-      const float h = tanhf(acc[nb][r] - b0v[nb][r]);
+      const float h = tanh_net(acc[nb][r] - b0v[nb][r]);
       const float wh = w1v[nb][r] * h;
       u += wh;
       g[nb][r] = w1v[nb][r] * (1.f - h * h);
@@ -193,157 +209,310 @@ __global__ void __launch_bounds__(256) k_mlp(EvalArgs a) {
   }
 }
 
-// The same two GEMMs with their operands staged in LDS: a block takes one
-// group of kRowGroup = 64 species-grouped rows (four 16-row tiles, one per
-// wave, never mixing species), stages that species' w0 and the 64 descriptor
-// rows once with coalesced loads, and feeds every MFMA from LDS, so a wave's
-// chain of dependent global loads is gone.  The MFMA operands and their order
-// are those of k_mlp, so the results are the same bits.
-//   FP32 LDS: w0 [NNp][ND + 1], q [64][NDp + 1] (odd strides: lanes reading
-//             16 rows at one column hit 16 banks)
-//   BF16 LDS: w0 [NNp][NDp32 + 8], w0^T [NDp32][NNp + 8], q [64][NDp32 + 8]
-//             (bf16; rows of 16-byte multiples for the 8-wide loads)
+// The same two GEMMs with the species' weights staged in LDS.  The rows are
+// cut into groups of kRowGroup = 64 species-grouped rows (each species padded
+// to whole groups, so a group never mixes species); a block takes a run of
+// consecutive groups, one 16-row tile per wave per group, and stages w0 and
+// w0^T of a species once for all of its groups of that species (L2-resident
+// weights, 16-byte loads, kStageBatch per lane at a time).  A lane holds its
+// share of its atom's descriptor row in registers, and loads the next
+// group's share while the current group is computed; the MFMA weight
+// operands are 16-byte LDS reads.
+//   FP32: the reduction index of GEMM 1 runs over N_des padded to a multiple
+//         of 16 (zero weights past N_des), split into four contiguous
+//         quarters of KS = NDp16 / 4: step s of the 16x16x4 MFMA takes k =
+//         KS g + s from lane group g, so a lane's q values and w0 values are
+//         contiguous.  LDS: w0 [NNp][NDp16 + 4], w0^T [NDp16][NNp + 4].
+//   BF16: k = 32 s + 8 g + 0..7 as in k_mlp.  LDS: w0 [NNp][NDp32 + 8],
+//         w0^T [NDp32][NNp + 8] (bf16 bits).
+// Each output is accumulated in a fixed order that does not depend on the
+// other rows of the tile (results do not depend on how atoms are grouped);
+// the float32 order of GEMM 1 differs from k_mlp's.
+constexpr int kStageBatch = 8;
+constexpr int kMlpMaxKS = 24;  // LDS kernel: N_des padded to 16 at most 96
+constexpr int kMlpQ = 24;      // q values per lane (float32: KS <= 24; bf16: NDp32 <= 96)
+constexpr int kMlpBlocks = 1024;  // LDS kernel: target grid size
+constexpr size_t kMlpMaxLds = 160 * 1024;  // LDS a gfx950 block may hold
+
+__host__ __device__ inline int nd_pad16(int nd) { return (nd + 15) / 16 * 16; }
+
 size_t mlp_lds_bytes(const DevModel& M, bool bf16) {
-  if (!bf16)
-    return ((size_t)M.NNp * (M.ND + 1) + (size_t)kRowGroup * (M.NDp + 1)) * sizeof(float);
-  return ((size_t)M.NNp * (M.NDp32 + 8) + (size_t)M.NDp32 * (M.NNp + 8) + (size_t)kRowGroup * (M.NDp32 + 8)) *
-         sizeof(uint16_t);
+  if (!bf16) {
+    const size_t K = (size_t)nd_pad16(M.ND);
+    return ((size_t)M.NNp * (K + 4) + K * (M.NNp + 4)) * sizeof(float);
+  }
+  return ((size_t)M.NNp * (M.NDp32 + 8) + (size_t)M.NDp32 * (M.NNp + 8)) * sizeof(uint16_t);
 }
 
+namespace {
+
+// This lane's q values of atom `atom` (zero for padding rows and past the row).
+template <bool BF16>
+__device__ __forceinline__ void load_q(const EvalArgs& a, int atom, int grp, int KS, float (&qv)[kMlpQ]) {
+  const int NDp = a.M.NDp;
+  const float* __restrict__ qrow = a.q + (int64_t)(atom < 0 ? 0 : atom) * NDp;
+  if constexpr (!BF16) {
+#pragma unroll
+    for (int v = 0; v < kMlpQ / 4; ++v) {
+      const int c = KS * grp + 4 * v;  // NDp is a multiple of 8: a word is all in or all out
+      float4 x = make_float4(0.f, 0.f, 0.f, 0.f);
+      if (4 * v < KS && atom >= 0 && c < NDp) x = *reinterpret_cast<const float4*>(qrow + c);
+      qv[4 * v] = x.x;
+      qv[4 * v + 1] = x.y;
+      qv[4 * v + 2] = x.z;
+      qv[4 * v + 3] = x.w;
+    }
+  } else {
+#pragma unroll
+    for (int st = 0; st < kMlpQ / 8; ++st) {
+      const int d0 = 32 * st + 8 * grp;
+      float4 x0 = make_float4(0.f, 0.f, 0.f, 0.f), x1 = x0;
+      if (32 * st < a.M.NDp32 && atom >= 0 && d0 < NDp) {
+        x0 = *reinterpret_cast<const float4*>(qrow + d0);
+        x1 = *reinterpret_cast<const float4*>(qrow + d0 + 4);
+      }
+      const float xs[8] = {x0.x, x0.y, x0.z, x0.w, x1.x, x1.y, x1.z, x1.w};
+#pragma unroll
+      for (int k = 0; k < 8; ++k) qv[8 * st + k] = xs[k];
+    }
+  }
+}
+
+// w0 and w0^T of species net into LDS (the caller synchronises the block).
+template <bool BF16>
+__device__ __forceinline__ void stage_weights(const DevModel& M, int net, int tid, float4* lds) {
+  const int ND = M.ND, NNp = M.NNp, NDp32 = M.NDp32, K16 = nd_pad16(ND);
+  if constexpr (!BF16) {
+    float* sw = reinterpret_cast<float*>(lds);
+    const int SW = K16 + 4, ST = NNp + 4;
+    float* st = sw + NNp * SW;
+    const float4* __restrict__ w04 = reinterpret_cast<const float4*>(M.w0 + (int64_t)net * NNp * ND);
+    const float4* __restrict__ wt4 = reinterpret_cast<const float4*>(M.w0t + (int64_t)net * ND * NNp);
+    const int nw = NNp * ND / 4, t4 = NNp / 4, total = 2 * nw;  // NNp is a multiple of 32
+    for (int k0 = tid; k0 < total; k0 += kStageBatch * 256) {
+      float4 v[kStageBatch];
+#pragma unroll
+      for (int u = 0; u < kStageBatch; ++u) {
+        const int k = k0 + u * 256;
+        v[u] = make_float4(0.f, 0.f, 0.f, 0.f);
+        if (k < nw) v[u] = w04[k];
+        else if (k < total) v[u] = wt4[k - nw];
+      }
+#pragma unroll
+      for (int u = 0; u < kStageBatch; ++u) {
+        const int k = k0 + u * 256;
+        if (k < nw) {
+          int row = 4 * k / ND, c = 4 * k - row * ND;
+          const float x[4] = {v[u].x, v[u].y, v[u].z, v[u].w};
+#pragma unroll
+          for (int j = 0; j < 4; ++j) {
+            sw[row * SW + c] = x[j];
+            if (++c == ND) {
+              c = 0;
+              ++row;
+            }
+          }
+        } else if (k < total) {
+          const int r = (k - nw) / t4, c = k - nw - r * t4;
+          *reinterpret_cast<float4*>(st + r * ST + 4 * c) = v[u];
+        }
+      }
+    }
+    // zero weights past N_des: columns ND..K16-1 of w0, rows ND..K16-1 of w0^T
+    const int pad = K16 - ND;
+    for (int k = tid; k < NNp * pad; k += 256) sw[(k / pad) * SW + ND + k % pad] = 0.f;
+    for (int k = tid; k < pad * NNp; k += 256) st[(ND + k / NNp) * ST + k % NNp] = 0.f;
+  } else {
+    uint16_t* swb = reinterpret_cast<uint16_t*>(lds);
+    const int SWB = NDp32 + 8, STB = NNp + 8;
+    uint16_t* swtb = swb + NNp * SWB;
+    const uint4* __restrict__ wb = reinterpret_cast<const uint4*>(M.w0b + (int64_t)net * NNp * NDp32);
+    const uint4* __restrict__ wtb = reinterpret_cast<const uint4*>(M.w0tb + (int64_t)net * NDp32 * NNp);
+    const int c8 = NDp32 / 8, t8 = NNp / 8;
+    const int n1 = NNp * c8, total = n1 + NDp32 * t8;
+    for (int k0 = tid; k0 < total; k0 += kStageBatch * 256) {
+      uint4 v[kStageBatch];
+#pragma unroll
+      for (int u = 0; u < kStageBatch; ++u) {
+        const int k = k0 + u * 256;
+        v[u] = make_uint4(0u, 0u, 0u, 0u);
+        if (k < n1) v[u] = wb[k];
+        else if (k < total) v[u] = wtb[k - n1];
+      }
+#pragma unroll
+      for (int u = 0; u < kStageBatch; ++u) {
+        const int k = k0 + u * 256;
+        if (k < n1) {
+          const int r = k / c8, c = k - r * c8;
+          *reinterpret_cast<uint4*>(swb + r * SWB + 8 * c) = v[u];
+        } else if (k < total) {
+          const int r = (k - n1) / t8, c = k - n1 - r * t8;
+          *reinterpret_cast<uint4*>(swtb + r * STB + 8 * c) = v[u];
+        }
+      }
+    }
+  }
+}
+
+}  // namespace
+
 template <int NNB, bool BF16>
-__global__ void __launch_bounds__(256) k_mlp_lds(EvalArgs a) {
+__global__ void __launch_bounds__(256) k_mlp_lds(EvalArgs a, int32_t groups_per_block) {
   extern __shared__ float4 mlp_lds[];
   const DevModel& M = a.M;
-  const int64_t base = (int64_t)blockIdx.x * kRowGroup;
-  if (base >= a.rows_len) return;
-  const int first = a.rows[base];
-  if (first < 0) return;  // a group starting with padding is all padding (the whole block leaves)
-  const int net = M.nets > 1 ? a.types[first] : 0;
+  const int64_t n_groups = a.rows_len / kRowGroup;
+  const int64_t g_begin = (int64_t)blockIdx.x * groups_per_block;
+  const int64_t g_end = min(g_begin + groups_per_block, n_groups);
   const int tid = threadIdx.x, lane = tid & 63, r0 = (tid >> 6) * 16;
   const int col = lane & 15, grp = lane >> 4;
   const int ND = M.ND, NNp = M.NNp, NDp = M.NDp, NDp32 = M.NDp32;
-  const int atom = a.rows[base + r0 + col];
-  const float* __restrict__ b0 = M.b0 + net * NNp;
-  const float* __restrict__ w1 = M.w1 + net * NNp;
-  int out_atom[4];
-#pragma unroll
-  for (int r = 0; r < 4; ++r) out_atom[r] = a.rows[base + r0 + 4 * grp + r];
-
-  v4f acc[NNB];
-#pragma unroll
-  for (int nb = 0; nb < NNB; ++nb) acc[nb] = v4f{0.f, 0.f, 0.f, 0.f};
-  float* sw = reinterpret_cast<float*>(mlp_lds);
-  uint16_t* hw = reinterpret_cast<uint16_t*>(mlp_lds);
-  const int SW = ND + 1, SQ = NDp + 1;
-  const int SWB = NDp32 + 8, STB = NNp + 8, SQB = NDp32 + 8;
-  uint16_t* swb = hw;
-  uint16_t* swtb = swb + NNp * SWB;
-  uint16_t* sqb = swtb + NDp32 * STB;
-  float* sq = sw + NNp * SW;
-  // ---- stage w0 of this species and the 64 descriptor rows ----
-  if constexpr (!BF16) {
-    const float* __restrict__ w0 = M.w0 + (int64_t)net * NNp * ND;
-    for (int k = tid; k < NNp * ND; k += 256) sw[(k / ND) * SW + k % ND] = w0[k];
-    for (int k = tid; k < kRowGroup * NDp; k += 256) {
-      const int r = k / NDp, d = k % NDp, at = a.rows[base + r];
-      sq[r * SQ + d] = at >= 0 ? a.q[(int64_t)at * NDp + d] : 0.f;
+  const int K16 = nd_pad16(ND), KS = K16 / 4;
+  const float* sw = reinterpret_cast<const float*>(mlp_lds);
+  const uint16_t* hw = reinterpret_cast<const uint16_t*>(mlp_lds);
+  const int SW = K16 + 4, ST = NNp + 4;
+  const int SWB = NDp32 + 8, STB = NNp + 8;
+  const float* st = sw + NNp * SW;
+  const uint16_t* swb = hw;
+  const uint16_t* swtb = swb + NNp * SWB;
+  float qn[kMlpQ];
+  if (g_begin < g_end) load_q<BF16>(a, a.rows[g_begin * kRowGroup + r0 + col], grp, KS, qn);
+  int cur_net = -1;
+  for (int64_t gi = g_begin; gi < g_end; ++gi) {
+    const int64_t base = gi * kRowGroup;
+    const int first = a.rows[base];
+    if (first < 0) break;  // padding groups come after every species' rows
+    const int net = M.nets > 1 ? a.types[first] : 0;
+    if (net != cur_net) {  // the same for the whole block
+      __syncthreads();     // every wave is done with the previous species
+      stage_weights<BF16>(M, net, tid, mlp_lds);
+      __syncthreads();
+      cur_net = net;
     }
-  } else {
-    const uint16_t* __restrict__ w0b = M.w0b + (int64_t)net * NNp * NDp32;
-    const uint16_t* __restrict__ w0tb = M.w0tb + (int64_t)net * NDp32 * NNp;
-    for (int k = tid; k < NNp * NDp32; k += 256) swb[(k / NDp32) * SWB + k % NDp32] = w0b[k];
-    for (int k = tid; k < NDp32 * NNp; k += 256) swtb[(k / NNp) * STB + k % NNp] = w0tb[k];
-    for (int k = tid; k < kRowGroup * NDp32; k += 256) {
-      const int r = k / NDp32, d = k % NDp32, at = a.rows[base + r];
-      const float x = (at >= 0 && d < NDp) ? a.q[(int64_t)at * NDp + d] : 0.f;
-      sqb[r * SQB + d] = __builtin_bit_cast(uint16_t, (__bf16)x);
-    }
-  }
-  __syncthreads();
-
-  // ---- GEMM 1: acc[nb][r] = sum_d w0[16 nb + 4 grp + r][d] q[atom col][d] ----
-  if constexpr (!BF16) {
-    const int steps = (ND + 3) / 4;
-    for (int st = 0; st < steps; ++st) {
-      const int d = 4 * st + grp;
-      const float bq = (atom >= 0 && d < ND) ? sq[(r0 + col) * SQ + d] : 0.f;
+    const int atom = a.rows[base + r0 + col];
+    float qv[kMlpQ];
 #pragma unroll
-      for (int nb = 0; nb < NNB; ++nb) {
-        const float aw = d < ND ? sw[(16 * nb + col) * SW + d] : 0.f;
-        acc[nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(aw, bq, acc[nb], 0, 0, 0);
-      }
-    }
-  } else {
-    const int steps = NDp32 / 32;
-    for (int st = 0; st < steps; ++st) {
-      const int d0 = 32 * st + 8 * grp;
-      v8bf bq = bf16x8_from_bits(*reinterpret_cast<const uint4*>(sqb + (r0 + col) * SQB + d0));
-      if (atom < 0) {
+    for (int k = 0; k < kMlpQ; ++k) qv[k] = qn[k];
+    if (gi + 1 < g_end) load_q<BF16>(a, a.rows[base + kRowGroup + r0 + col], grp, KS, qn);
+    int out_atom[4];
 #pragma unroll
-        for (int k = 0; k < 8; ++k) bq[k] = (__bf16)0.f;
-      }
-#pragma unroll
-      for (int nb = 0; nb < NNB; ++nb) {
-        const uint4 u = *reinterpret_cast<const uint4*>(swb + (16 * nb + col) * SWB + d0);
-        acc[nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bf16x8_from_bits(u), bq, acc[nb], 0, 0, 0);
-      }
-    }
-  }
-
-  // ---- activation, site energy, latent vector and G = w1 (1 - h^2) ----
-  float u = 0.f;
-  float g[NNB][4];
-  float* __restrict__ lat = (a.latent && atom >= 0) ? a.latent + (int64_t)atom * M.NN : nullptr;
-#pragma unroll
-  for (int nb = 0; nb < NNB; ++nb)
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int mu = 16 * nb + 4 * grp + r;
-      const float h = tanhf(acc[nb][r] - b0[mu]);
-      const float wh = w1[mu] * h;
-      u += wh;
-      g[nb][r] = w1[mu] * (1.f - h * h);
-      if (lat && mu < M.NN) lat[mu] = wh;
-    }
-  u += __shfl_xor(u, 16);
-  u += __shfl_xor(u, 32);
-  if (grp == 0 && atom >= 0) a.U[atom] = u - *M.b1;
-
-  // ---- GEMM 2: dU/dq[atom][d] = sum_mu G[atom][mu] w0[mu][d] ----
-  const int dblocks = (ND + 15) / 16;
-  for (int db = 0; db < dblocks; ++db) {
-    const int d = 16 * db + col;
-    v4f c = v4f{0.f, 0.f, 0.f, 0.f};
-    if constexpr (!BF16) {
-      const int dc = min(d, ND - 1);
+    for (int r = 0; r < 4; ++r) out_atom[r] = a.rows[base + r0 + 4 * grp + r];
+    float b0v[NNB][4], w1v[NNB][4];
+    {
+      const float* __restrict__ b0 = M.b0 + net * NNp;
+      const float* __restrict__ w1 = M.w1 + net * NNp;
 #pragma unroll
       for (int nb = 0; nb < NNB; ++nb)
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-          const float bw = d < ND ? sw[(16 * nb + 4 * grp + r) * SW + dc] : 0.f;
-          c = __builtin_amdgcn_mfma_f32_16x16x4f32(g[nb][r], bw, c, 0, 0, 0);
+          b0v[nb][r] = b0[16 * nb + 4 * grp + r];
+          w1v[nb][r] = w1[16 * nb + 4 * grp + r];
         }
+    }
+
+    // ---- GEMM 1: acc[nb][r] = sum_k w0[16 nb + 4 grp + r][k] q[atom col][k] ----
+    v4f acc[NNB];
+#pragma unroll
+    for (int nb = 0; nb < NNB; ++nb) acc[nb] = v4f{0.f, 0.f, 0.f, 0.f};
+    if constexpr (!BF16) {
+#pragma unroll
+      for (int v = 0; v < kMlpQ / 4; ++v) {
+        if (4 * v >= KS) break;
+        float4 w[NNB];
+#pragma unroll
+        for (int nb = 0; nb < NNB; ++nb)
+          w[nb] = *reinterpret_cast<const float4*>(sw + (16 * nb + col) * SW + KS * grp + 4 * v);
+#pragma unroll
+        for (int nb = 0; nb < NNB; ++nb) acc[nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(w[nb].x, qv[4 * v], acc[nb], 0, 0, 0);
+#pragma unroll
+        for (int nb = 0; nb < NNB; ++nb) acc[nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(w[nb].y, qv[4 * v + 1], acc[nb], 0, 0, 0);
+#pragma unroll
+        for (int nb = 0; nb < NNB; ++nb) acc[nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(w[nb].z, qv[4 * v + 2], acc[nb], 0, 0, 0);
+#pragma unroll
+        for (int nb = 0; nb < NNB; ++nb) acc[nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(w[nb].w, qv[4 * v + 3], acc[nb], 0, 0, 0);
+      }
     } else {
-      const uint16_t* wrow = swtb + (d < NDp32 ? d : 0) * STB;
 #pragma unroll
-      for (int p = 0; p < NNB / 2; ++p) {
-        v8bf av, bv;
+      for (int s = 0; s < kMlpQ / 8; ++s) {
+        if (32 * s >= NDp32) break;
+        v8bf bq;
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          av[r] = (__bf16)g[2 * p][r];
-          av[4 + r] = (__bf16)g[2 * p + 1][r];
+        for (int k = 0; k < 8; ++k) bq[k] = (__bf16)qv[8 * s + k];
+#pragma unroll
+        for (int nb = 0; nb < NNB; ++nb) {
+          const uint4 u = *reinterpret_cast<const uint4*>(swb + (16 * nb + col) * SWB + 32 * s + 8 * grp);
+          acc[nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bf16x8_from_bits(u), bq, acc[nb], 0, 0, 0);
         }
-        const uint2 lo = *reinterpret_cast<const uint2*>(wrow + 32 * p + 4 * grp);
-        const uint2 hi = *reinterpret_cast<const uint2*>(wrow + 32 * p + 16 + 4 * grp);
-        bf16x4_from_bits(lo, bv, 0);
-        bf16x4_from_bits(hi, bv, 4);
-        c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, c, 0, 0, 0);
       }
     }
+
+    // ---- activation, site energy, latent vector and G = w1 (1 - h^2) ----
+    float u = 0.f;
+    float g[NNB][4];
+    float* __restrict__ lat = (a.latent && atom >= 0) ? a.latent + (int64_t)atom * M.NN : nullptr;
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int at = out_atom[r];
-      if (at >= 0 && d < ND) a.fp[(int64_t)at * M.NDp + d] = c[r];
+    for (int nb = 0; nb < NNB; ++nb)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int mu = 16 * nb + 4 * grp + r;
+        const float h = tanh_net(acc[nb][r] - b0v[nb][r]);
+        const float wh = w1v[nb][r] * h;
+        u += wh;
+        g[nb][r] = w1v[nb][r] * (1.f - h * h);
+        if (lat && mu < M.NN) lat[mu] = wh;
+      }
+    u += __shfl_xor(u, 16);
+    u += __shfl_xor(u, 32);
+    if (grp == 0 && atom >= 0) a.U[atom] = u - *M.b1;
+
+    // ---- GEMM 2: dU/dq[atom][d] = sum_mu G[atom][mu] w0[mu][d], two 16-column blocks at a time ----
+    const int dblocks = (ND + 15) / 16;
+    for (int db = 0; db < dblocks; db += 2) {
+      const bool two = db + 1 < dblocks;
+      v4f c0 = v4f{0.f, 0.f, 0.f, 0.f}, c1 = c0;
+      const int d0 = 16 * db + col, d1 = d0 + 16;
+      if constexpr (!BF16) {
+        const float* row0 = st + d0 * ST;
+        const float* row1 = st + (two ? d1 : d0) * ST;
+#pragma unroll
+        for (int nb = 0; nb < NNB; ++nb) {
+          const float4 x = *reinterpret_cast<const float4*>(row0 + 16 * nb + 4 * grp);
+          const float4 y = *reinterpret_cast<const float4*>(row1 + 16 * nb + 4 * grp);
+          c0 = __builtin_amdgcn_mfma_f32_16x16x4f32(g[nb][0], x.x, c0, 0, 0, 0);
+          c1 = __builtin_amdgcn_mfma_f32_16x16x4f32(g[nb][0], y.x, c1, 0, 0, 0);
+          c0 = __builtin_amdgcn_mfma_f32_16x16x4f32(g[nb][1], x.y, c0, 0, 0, 0);
+          c1 = __builtin_amdgcn_mfma_f32_16x16x4f32(g[nb][1], y.y, c1, 0, 0, 0);
+          c0 = __builtin_amdgcn_mfma_f32_16x16x4f32(g[nb][2], x.z, c0, 0, 0, 0);
+          c1 = __builtin_amdgcn_mfma_f32_16x16x4f32(g[nb][2], y.z, c1, 0, 0, 0);
+          c0 = __builtin_amdgcn_mfma_f32_16x16x4f32(g[nb][3], x.w, c0, 0, 0, 0);
+          c1 = __builtin_amdgcn_mfma_f32_16x16x4f32(g[nb][3], y.w, c1, 0, 0, 0);
+        }
+      } else {
+        const uint16_t* row0 = swtb + (d0 < NDp32 ? d0 : 0) * STB;
+        const uint16_t* row1 = swtb + (two && d1 < NDp32 ? d1 : 0) * STB;
+#pragma unroll
+        for (int p = 0; p < NNB / 2; ++p) {
+          v8bf av, bv0, bv1;
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            av[r] = (__bf16)g[2 * p][r];
+            av[4 + r] = (__bf16)g[2 * p + 1][r];
+          }
+          bf16x4_from_bits(*reinterpret_cast<const uint2*>(row0 + 32 * p + 4 * grp), bv0, 0);
+          bf16x4_from_bits(*reinterpret_cast<const uint2*>(row0 + 32 * p + 16 + 4 * grp), bv0, 4);
+          bf16x4_from_bits(*reinterpret_cast<const uint2*>(row1 + 32 * p + 4 * grp), bv1, 0);
+          bf16x4_from_bits(*reinterpret_cast<const uint2*>(row1 + 32 * p + 16 + 4 * grp), bv1, 4);
+          c0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv0, c0, 0, 0, 0);
+          c1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv1, c1, 0, 0, 0);
+        }
+      }
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int at = out_atom[r];
+        if (at < 0) continue;
+        float* out = a.fp + (int64_t)at * NDp;
+        if (d0 < ND) out[d0] = c0[r];
+        if (two && d1 < ND) out[d1] = c1[r];
+      }
     }
   }
 }
@@ -351,13 +520,24 @@ __global__ void __launch_bounds__(256) k_mlp_lds(EvalArgs a) {
 void launch_mlp(const EvalArgs& a, hipStream_t s) {
   const int nnb = a.M.NNp / 16;
   const size_t lds = mlp_lds_bytes(a.M, a.mlp_bf16 != 0);
-  if (lds <= 64 * 1024) {
-    dim3 grid((unsigned)div_up(a.rows_len, kRowGroup)), block(256);
-#define NEP_MLP(n)                                                                        \
-  if (nnb == n) {                                                                         \
-    if (a.mlp_bf16) hipLaunchKernelGGL((k_mlp_lds<n, true>), grid, block, lds, s, a);     \
-    else hipLaunchKernelGGL((k_mlp_lds<n, false>), grid, block, lds, s, a);               \
-    return;                                                                               \
+  const bool fits = a.mlp_bf16 ? a.M.NDp32 <= kMlpQ / 8 * 32 : nd_pad16(a.M.ND) <= 4 * kMlpMaxKS;
+  if (lds <= kMlpMaxLds && fits) {
+    // runs of consecutive row groups, about kMlpBlocks blocks in all
+    const int64_t n_groups = a.rows_len / kRowGroup;
+    const int32_t per = (int32_t)std::max<int64_t>(1, (n_groups + kMlpBlocks - 1) / kMlpBlocks);
+    dim3 grid((unsigned)div_up(n_groups, per)), block(256);
+    // (a block may take more than 64 KB of LDS on this chip when it asks for
+    // it; if the request is refused, the global-memory kernel below runs)
+#define NEP_MLP(n)                                                                                       \
+  if (nnb == n) {                                                                                        \
+    const void* k = a.mlp_bf16 ? (const void*)k_mlp_lds<n, true> : (const void*)k_mlp_lds<n, false>;    \
+    if (lds <= 64 * 1024 ||                                                                              \
+        hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) == hipSuccess) {    \
+      if (a.mlp_bf16) hipLaunchKernelGGL((k_mlp_lds<n, true>), grid, block, lds, s, a, per);             \
+      else hipLaunchKernelGGL((k_mlp_lds<n, false>), grid, block, lds, s, a, per);                       \
+      return;                                                                                            \
+    }                                                                                                    \
+    (void)hipGetLastError();                                                                             \
   }
     NEP_MLP(2) NEP_MLP(4) NEP_MLP(6) NEP_MLP(8)
 #undef NEP_MLP

@@ -451,13 +451,16 @@ void launch_build_verlet(const BuildArgs& b, const Lists& V, hipStream_t s) {
 // in candidate order; nnA = size of the first part.  V.fmap[m][i] = exact
 // position of candidate m (or -1).  kFilterLanes lanes per atom take the
 // candidates m = s, s + 4, ..., so the 16 atoms of a wave read and write
-// whole 64-byte runs of a row.  Pass 1 classifies (neighbour index and
-// position of the lane's next candidate in flight while the current one is
-// tested), counts the members and keeps the classes in register bit masks;
-// pass 2 walks the row four candidates at a time in candidate order, and quad
-// DPP prefix sums of the class flags give each member its exact position.  The rows are the same as those of a
-// single sequential pass.
+// whole 64-byte runs of a row.  Both passes walk a lane's candidates in
+// chunks of kFilterChunk: the index words of a chunk are loaded together,
+// then the positions (pass 1) or the row words (pass 2), so a lane has a
+// chunk's loads in flight at once instead of one dependent chain per
+// candidate.  Pass 1 classifies, counts the members and keeps the classes in
+// register bit masks; pass 2 goes through the candidates in order, and quad
+// DPP prefix sums of the class flags give each member its exact position.
+// The rows are the same as those of a single sequential pass.
 constexpr int kFilterLanes = 4;
+constexpr int kFilterChunk = 4;
 
 // Value of v held by lane l of this lane's quad.
 __device__ __forceinline__ int32_t quad_lane(int32_t v, int l) {
@@ -476,64 +479,84 @@ __global__ void __launch_bounds__(kBlock) k_filter_rows(const double* __restrict
                                                         StructInfo st0, Lists V, double rcR2,
                                                         double rcA2, Lists L,
                                                         int32_t* __restrict__ overflow) {
-  constexpr int G = kFilterLanes;
+  constexpr int G = kFilterLanes, U = kFilterChunk;
   constexpr int32_t kOuter = -2, kAngular = -3;
   const int sub = threadIdx.x & (G - 1);
   const int64_t i = (xcd_block() * blockDim.x + threadIdx.x) / G;
   if (i >= N) return;  // the lanes of an atom leave together
   const StructInfo& st = BATCH ? structs[sid[i]] : st0;
+  const int32_t* __restrict__ vnl = V.nlR;
+  const uint16_t* __restrict__ vcd = V.cdR;
+  const int32_t* __restrict__ vrev = V.revR;
+  int32_t* __restrict__ fmap = V.fmap;
+  int32_t* __restrict__ lnl = L.nlR;
+  int32_t* __restrict__ lrev = L.revR;
+  uint16_t* __restrict__ lcd = L.cdR;
   const int nv = min(V.nnR[i], V.MR);
+  const int steps = (nv + G - 1) / G;  // the same for the four lanes of an atom
   const bool images = st.mode == kModeImages;
   const double xi = pos[i], yi = pos[N + i], zi = pos[2 * N + i];
-  int32_t jn = sub < nv ? V.nlR[(int64_t)sub * N + i] : 0;
-  uint16_t cn = (images && sub < nv) ? V.cdR[(int64_t)sub * N + i] : kCodeCenter;
-  double px = pos[jn], py = pos[N + jn], pz = pos[2 * N + jn];
   int32_t na = 0, no = 0;
   // classes of the lane's first 64 candidates (t = local index) as bit masks;
   // later ones (rows over 256 candidates) go through V.fmap
   uint64_t mask_a = 0, mask_o = 0;
-  for (int m = sub, t = 0; m < nv; m += G, ++t) {
-    const int64_t e = (int64_t)m * N + i;
-    const uint16_t code = cn;
-    double Dx, Dy, Dz;
-    {
+  for (int t0 = 0; t0 < steps; t0 += U) {
+    int32_t j[U];
+    uint16_t code[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int m = (t0 + u) * G + sub;
+      j[u] = (int32_t)i;  // past the row: the atom itself, in bounds and never classified
+      code[u] = kCodeCenter;
+      if (m < nv) {
+        j[u] = vnl[(int64_t)m * N + i];
+        if (images) code[u] = vcd[(int64_t)m * N + i];
+      }
+    }
+    double px[U], py[U], pz[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      px[u] = pos[j[u]];
+      py[u] = pos[N + j[u]];
+      pz[u] = pos[2 * N + j[u]];
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int t = t0 + u, m = t * G + sub;
+      if (m >= nv) continue;
+      double Dx, Dy, Dz;
+      {
 #pragma clang fp contract(off)
-      Dx = px - xi;
-      Dy = py - yi;
-      Dz = pz - zi;
-    }
-    if (m + G < nv) {
-      jn = V.nlR[e + G * N];
-      if (images) cn = V.cdR[e + G * N];
-    }
-    px = pos[jn];
-    py = pos[N + jn];
-    pz = pos[2 * N + jn];
-    int n0, n1, n2;
-    min_image(st, Dx, Dy, Dz, n0, n1, n2);
-    if (code != kCodeCenter) {
-      int oa, ob, oc;
-      split_code(code, oa, ob, oc);
-      n0 += oa;
-      n1 += ob;
-      n2 += oc;
-    }
-    double dx, dy, dz;
-    image_disp(st, Dx, Dy, Dz, n0, n1, n2, dx, dy, dz);
-    const double r2 = norm2_exact(dx, dy, dz);
-    int32_t f = -1;
-    if (r2 < rcA2) {
-      f = kAngular;
-      ++na;
-    } else if (r2 < rcR2) {
-      f = kOuter;
-      ++no;
-    }
-    if (t < 64) {
-      if (f == kAngular) mask_a |= 1ull << t;
-      if (f == kOuter) mask_o |= 1ull << t;
-    } else {
-      V.fmap[e] = f;
+        Dx = px[u] - xi;
+        Dy = py[u] - yi;
+        Dz = pz[u] - zi;
+      }
+      int n0, n1, n2;
+      min_image(st, Dx, Dy, Dz, n0, n1, n2);
+      if (code[u] != kCodeCenter) {
+        int oa, ob, oc;
+        split_code(code[u], oa, ob, oc);
+        n0 += oa;
+        n1 += ob;
+        n2 += oc;
+      }
+      double dx, dy, dz;
+      image_disp(st, Dx, Dy, Dz, n0, n1, n2, dx, dy, dz);
+      const double r2 = norm2_exact(dx, dy, dz);
+      int32_t f = -1;
+      if (r2 < rcA2) {
+        f = kAngular;
+        ++na;
+      } else if (r2 < rcR2) {
+        f = kOuter;
+        ++no;
+      }
+      if (t < 64) {
+        if (f == kAngular) mask_a |= 1ull << t;
+        if (f == kOuter) mask_o |= 1ull << t;
+      } else {
+        fmap[(int64_t)m * N + i] = f;
+      }
     }
   }
   int32_t a_all = 0, o_all = 0;
@@ -542,42 +565,59 @@ __global__ void __launch_bounds__(kBlock) k_filter_rows(const double* __restrict
     a_all += quad_lane(na, l);
     o_all += quad_lane(no, l);
   }
-  // pass 2: the same trip count for the four lanes of an atom, so the quad is
-  // whole at every prefix sum; candidate m = 4 t + s is lane s's t-th
+  // pass 2: candidate m = 4 t + s is lane s's t-th; every lane of the quad
+  // runs every step, so the quad is whole at each prefix sum
   int32_t pa = 0, po = a_all;  // next angular / outer position
-  const int steps = (nv + G - 1) / G;
-  for (int t = 0; t < steps; ++t) {
-    const int m = t * G + sub;
-    const int64_t e = (int64_t)m * N + i;
-    int32_t c = -1;
-    if (m < nv) {
-      if (t < 64) c = ((mask_a >> t) & 1) ? kAngular : (((mask_o >> t) & 1) ? kOuter : -1);
-      else c = V.fmap[e];
-    }
-    const int32_t fa = c == kAngular, fo = c == kOuter;
-    int32_t ba = 0, bo = 0, ta = 0, to = 0;
+  for (int t0 = 0; t0 < steps; t0 += U) {
+    int32_t c[U], jn[U], rn[U];
+    uint16_t cn[U];
 #pragma unroll
-    for (int l = 0; l < G; ++l) {
-      const int32_t al = quad_lane(fa, l), ol = quad_lane(fo, l);
-      ta += al;
-      to += ol;
-      if (l < sub) {
-        ba += al;
-        bo += ol;
+    for (int u = 0; u < U; ++u) {
+      const int t = t0 + u, m = t * G + sub;
+      const int64_t e = (int64_t)m * N + i;
+      c[u] = -1;
+      if (m < nv) {
+        if (t < 64) c[u] = ((mask_a >> t) & 1) ? kAngular : (((mask_o >> t) & 1) ? kOuter : -1);
+        else c[u] = fmap[e];
+      }
+      jn[u] = 0;
+      rn[u] = 0;
+      cn[u] = kCodeCenter;
+      if (c[u] != -1) {
+        jn[u] = vnl[e];
+        rn[u] = vrev[e];
+        if (images) cn[u] = vcd[e];
       }
     }
-    if (m < nv && !(fa | fo)) V.fmap[e] = -1;
-    if (fa | fo) {
-      const int32_t p = fa ? pa + ba : po + bo;
-      V.fmap[e] = p;
-      if (p < L.MR) {
-        L.nlR[(int64_t)p * N + i] = V.nlR[e];
-        L.revR[(int64_t)p * N + i] = V.revR[e];  // candidate position, resolved by the next kernel
-        if (images) L.cdR[(int64_t)p * N + i] = V.cdR[e];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int m = (t0 + u) * G + sub;
+      const int64_t e = (int64_t)m * N + i;
+      const int32_t fa = c[u] == kAngular, fo = c[u] == kOuter;
+      int32_t ba = 0, bo = 0, ta = 0, to = 0;
+#pragma unroll
+      for (int l = 0; l < G; ++l) {
+        const int32_t al = quad_lane(fa, l), ol = quad_lane(fo, l);
+        ta += al;
+        to += ol;
+        if (l < sub) {
+          ba += al;
+          bo += ol;
+        }
       }
+      if (m < nv && !(fa | fo)) fmap[e] = -1;
+      if (fa | fo) {
+        const int32_t p = fa ? pa + ba : po + bo;
+        fmap[e] = p;
+        if (p < L.MR) {
+          lnl[(int64_t)p * N + i] = jn[u];
+          lrev[(int64_t)p * N + i] = rn[u];  // candidate position, resolved by the next kernel
+          if (images) lcd[(int64_t)p * N + i] = cn[u];
+        }
+      }
+      pa += ta;
+      po += to;
     }
-    pa += ta;
-    po += to;
   }
   if (sub == 0) {
     const int32_t total = a_all + o_all;
@@ -592,37 +632,45 @@ __global__ void __launch_bounds__(kBlock) k_filter_rows(const double* __restrict
 // position of i in the row of j = L.nlR[p][i]; the exact position there is
 // V.fmap of that candidate entry, written in place.  kRevLanes lanes per atom
 // take exact entries p = s, s + 4, ..., so a wave writes whole 64-byte runs of
-// a row; the words of a lane's next entry are loaded while the current one
-// is resolved.
+// a row; a lane loads the words of kFilterChunk entries, then their map
+// entries, then writes them.
 constexpr int kRevLanes = 4;
 
 __global__ void __launch_bounds__(kBlock) k_reverse_from_candidates(int64_t N, Lists V, Lists L,
                                                                     int32_t* __restrict__ err) {
-  constexpr int G = kRevLanes;
+  constexpr int G = kRevLanes, U = kFilterChunk;
   const int sub = threadIdx.x & (G - 1);
   const int64_t i = (xcd_block() * blockDim.x + threadIdx.x) / G;
   if (i >= N) return;
+  const int32_t* __restrict__ fmap = V.fmap;
+  const int32_t* __restrict__ lnl = L.nlR;
+  int32_t* __restrict__ lrev = L.revR;
   const int nn = min(L.nnR[i], L.MR);
-  int32_t jn = 0, rn = 0;
-  if (sub < nn) {
-    const int64_t e0 = (int64_t)sub * N + i;
-    jn = L.nlR[e0];
-    rn = L.revR[e0];
-  }
   bool broken = false;
-  for (int p = sub; p < nn; p += G) {
-    const int32_t j = jn, r = rn;
-    if (p + G < nn) {
-      const int64_t e1 = (int64_t)(p + G) * N + i;
-      jn = L.nlR[e1];
-      rn = L.revR[e1];
+  for (int p0 = sub; p0 < nn; p0 += U * G) {
+    int32_t j[U], r[U], g[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int p = p0 + u * G;
+      j[u] = 0;
+      r[u] = 0;
+      if (p < nn) {
+        j[u] = lnl[(int64_t)p * N + i];
+        r[u] = lrev[(int64_t)p * N + i];
+      }
     }
-    int32_t g = V.fmap[(int64_t)r * N + j];
-    if (g < 0) {
-      broken = true;
-      g = 0;
+#pragma unroll
+    for (int u = 0; u < U; ++u) g[u] = p0 + u * G < nn ? fmap[(int64_t)r[u] * N + j[u]] : 0;
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int p = p0 + u * G;
+      if (p >= nn) continue;
+      if (g[u] < 0) {
+        broken = true;
+        g[u] = 0;
+      }
+      lrev[(int64_t)p * N + i] = min(g[u], L.MR - 1);
     }
-    L.revR[(int64_t)p * N + i] = min(g, L.MR - 1);
   }
   if (broken) atomicExch(err, 1);
 }

@@ -243,16 +243,31 @@ def test_train3_triclinic40_every_autotuned_shape_in_bounds():
     assert shapes == 4 * 2 * 2 * 2
 
 
-def test_network_tiles_in_bounds():
-    """k_mlp_lds (and the 16-row-tile k_mlp it falls back to): groups of 64
-    species-grouped rows (each species padded to whole groups, padding -1),
-    the staged w0 / q reads and their LDS slots, the network weight rows and
-    the dU/dq writes, for the same model, float32 and bf16."""
-    h = synth.WORKLOADS["train3"]
+@pytest.mark.parametrize("workload", ["train3", "fcc131k", "bcc2m"])
+def test_network_tiles_in_bounds(workload):
+    """k_mlp_lds: groups of 64 species-grouped rows (each species padded to
+    whole groups, padding -1) taken in runs by a block; every lane's q words
+    (the next group's too), the staged w0 / w0^T words and their LDS slots,
+    the 16-byte LDS operand reads of both GEMMs and the dU/dq writes, for
+    float32 and bf16 whenever the launcher picks this kernel (the LDS image
+    within the 160 KB of a gfx950 block and the register arrays large
+    enough)."""
+    h = synth.WORKLOADS[workload]
     nd = O.num_descriptors(h)
     NN = h["n_neurons"]
     NNp, NDp, NDp32 = (NN + 31) // 32 * 32, (nd + 7) // 8 * 8, (nd + 31) // 32 * 32
+    K16 = (nd + 15) // 16 * 16
+    KS = K16 // 4
+    assert NNp * nd % 4 == 0 and NDp % 8 == 0 and KS % 4 == 0
     G = 64
+    SW, ST = K16 + 4, NNp + 4
+    SWB, STB = NDp32 + 8, NNp + 8
+    assert SW % 4 == 0 and ST % 4 == 0 and SWB % 8 == 0 and STB % 8 == 0   # 16-byte LDS words
+    use32 = 4 * (NNp * SW + K16 * ST) <= 160 * 1024 and KS <= 24      # LDS of a gfx950 block
+    use16 = 2 * (NNp * SWB + NDp32 * STB) <= 160 * 1024 and NDp32 <= 96
+    assert use32 and use16               # every benchmark model runs the LDS kernel
+    if not (use32 or use16):
+        pytest.skip("the launcher takes the global-memory kernel for this model")
     rng = np.random.default_rng(5)
     for N, T in ((40, 3), (1, 3), (17, 1), (300, 3)):
         types = rng.integers(0, T, N)
@@ -264,10 +279,9 @@ def test_network_tiles_in_bounds():
         assert len(rows) <= rows_len
         rows += [-1] * (rows_len - len(rows))
         nets = T
-        sizes = dict(q=N * NDp, fp=N * NDp, w0=nets * NNp * nd, w0b=nets * NNp * NDp32,
-                     w0tb=nets * NDp32 * NNp, rows=rows_len,
-                     lds32=NNp * (nd + 1) + G * (NDp + 1),
-                     lds16=NNp * (NDp32 + 8) + NDp32 * (NNp + 8) + G * (NDp32 + 8))
+        sizes = dict(q=N * NDp, fp=N * NDp, w0=nets * NNp * nd, w0t=nets * nd * NNp,
+                     w0b=nets * NNp * NDp32, w0tb=nets * NDp32 * NNp, rows=rows_len,
+                     lds32=NNp * SW + K16 * ST, lds16=NNp * SWB + NDp32 * STB)
         hi = {k: -1 for k in sizes}
 
         def touch(k, v):
@@ -279,39 +293,74 @@ def test_network_tiles_in_bounds():
                 continue
             net = types[first]
             assert all(r < 0 or types[r] == net for r in rows[base:base + G])  # one species
-            touch("w0", net * NNp * nd + NNp * nd - 1)
-            touch("w0b", net * NNp * NDp32 + NNp * NDp32 - 1)
-            touch("w0tb", net * NDp32 * NNp + NDp32 * NNp - 1)
-            for r in range(G):
-                touch("rows", base + r)
-                if rows[base + r] >= 0:
-                    touch("q", rows[base + r] * NDp + NDp - 1)
-            SW, SQ = nd + 1, NDp + 1
-            SWB, STB, SQB = NDp32 + 8, NNp + 8, NDp32 + 8
-            touch("lds32", NNp * SW + (G - 1) * SQ + NDp - 1)
-            touch("lds16", NNp * SWB + NDp32 * STB + (G - 1) * SQB + NDp32 - 1)
+            # staging, one index space of 16-byte words per precision
+            nw = NNp * nd // 4
+            for k in range(2 * nw):
+                if k < nw:
+                    touch("w0", net * NNp * nd + 4 * k + 3)
+                    for j in range(4):
+                        e = 4 * k + j
+                        touch("lds32", (e // nd) * SW + e % nd)
+                else:
+                    touch("w0t", net * nd * NNp + 4 * (k - nw) + 3)
+                    r, c = divmod(k - nw, NNp // 4)
+                    touch("lds32", NNp * SW + r * ST + 4 * c + 3)
+            pad = K16 - nd
+            for k in range(NNp * pad):
+                touch("lds32", (k // pad) * SW + nd + k % pad)
+            for k in range(pad * NNp):
+                touch("lds32", NNp * SW + (nd + k // NNp) * ST + k % NNp)
+            c8, t8 = NDp32 // 8, NNp // 8
+            n1 = NNp * c8
+            for k in range(n1 + NDp32 * t8):
+                if k < n1:
+                    touch("w0b", net * NNp * NDp32 + 8 * k + 7)
+                    r, c = divmod(k, c8)
+                    touch("lds16", r * SWB + 8 * c + 7)
+                else:
+                    touch("w0tb", net * NDp32 * NNp + 8 * (k - n1) + 7)
+                    r, c = divmod(k - n1, t8)
+                    touch("lds16", NNp * SWB + r * STB + 8 * c + 7)
             for wave in range(4):
                 r0 = 16 * wave
                 for lane in range(64):
                     col, grp = lane & 15, lane >> 4
-                    for st in range(-(-nd // 4)):
-                        d = 4 * st + grp
-                        if d < nd:
-                            touch("lds32", NNp * SW + (r0 + col) * SQ + d)
-                            touch("lds32", (16 * (NNp // 16 - 1) + col) * SW + d)
-                    for st in range(NDp32 // 32):
-                        d0 = 32 * st + 8 * grp
-                        touch("lds16", NNp * SWB + NDp32 * STB + (r0 + col) * SQB + d0 + 7)
-                        touch("lds16", (16 * (NNp // 16 - 1) + col) * SWB + d0 + 7)
-                    for db in range(-(-nd // 16)):
-                        d = 16 * db + col
-                        touch("lds32", (16 * (NNp // 16 - 1) + 4 * grp + 3) * SW + min(d, nd - 1))
-                        wrow = NNp * SWB + (d if d < NDp32 else 0) * STB
-                        touch("lds16", wrow + 32 * (NNp // 32 - 1) + 16 + 4 * grp + 3)
+                    touch("rows", base + r0 + col)
+                    if base + G < rows_len:        # the next group's q words, loaded ahead
+                        touch("rows", base + G + r0 + col)
+                    atom = rows[base + r0 + col]
+                    for v in range(24 // 4):       # float32 q words
+                        c = KS * grp + 4 * v
+                        if 4 * v < KS and atom >= 0 and c < NDp:
+                            touch("q", atom * NDp + c + 3)
+                    for s_ in range(24 // 8):      # bf16 q words
+                        d0 = 32 * s_ + 8 * grp
+                        if 32 * s_ < NDp32 and atom >= 0 and d0 < NDp:
+                            touch("q", atom * NDp + d0 + 7)
+                    for nb in range(NNp // 16):
+                        for v in range(KS // 4):
+                            touch("lds32", (16 * nb + col) * SW + KS * grp + 4 * v + 3)
+                        for s_ in range(NDp32 // 32):
+                            touch("lds16", (16 * nb + col) * SWB + 32 * s_ + 8 * grp + 7)
+                    dblocks = -(-nd // 16)
+                    for db in range(0, dblocks, 2):
+                        two = db + 1 < dblocks
+                        d0 = 16 * db + col
+                        d1 = d0 + 16
+                        for nb in range(NNp // 16):
+                            for d in ((d0, d1) if two else (d0,)):
+                                touch("lds32", NNp * SW + d * ST + 16 * nb + 4 * grp + 3)
+                        for p_ in range(NNp // 32):
+                            for d in (d0 if d0 < NDp32 else 0, d1 if two and d1 < NDp32 else 0):
+                                touch("lds16", NNp * SWB + d * STB + 32 * p_ + 16 + 4 * grp + 3)
                         for r in range(4):
+                            touch("rows", base + r0 + 4 * grp + r)
                             at = rows[base + r0 + 4 * grp + r]
-                            if at >= 0 and d < nd:
-                                touch("fp", at * NDp + d)
+                            if at >= 0:
+                                for d in ((d0, d1) if two else (d0,)):
+                                    if d < nd:
+                                        touch("fp", at * NDp + d)
         for k, n in sizes.items():
+            if (k == "lds32" and not use32) or (k == "lds16" and not use16):
+                continue
             assert hi[k] < n, (N, k, hi[k], n)
-        assert 4 * sizes["lds32"] <= 64 * 1024 and 2 * sizes["lds16"] <= 64 * 1024
