@@ -104,7 +104,8 @@ def parse():
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--batch-structs", type=int, default=2000)
     ap.add_argument("--batch-sets", type=int, default=50)
-    ap.add_argument("--serve-requests", type=int, default=200)
+    ap.add_argument("--serve-requests", type=int, default=2000)
+    ap.add_argument("--serve-requests-bf16", type=int, default=200)
     ap.add_argument("--serve-budget-gb", type=float, default=2.0)
     return ap.parse_args()
 
@@ -155,6 +156,7 @@ def serving_leg(nep, synth, params_of, n_req, budget_gb, prec):
     for t in tickets:
         srv.poll(t, wait_ms=-1)
     sat = srv.stats()
+    progress(f"serving saturation: {sat['requests_per_s']:.1f} req/s, p99 {sat['p99_ms']:.0f} ms")
     out = {"requests": n_req, "atoms_mean": float(np.mean([r.pos.shape[1] for r in reqs])),
            "saturation": {"requests_per_s": sat["requests_per_s"],
                           "atom_steps_per_s": sat["atom_steps_per_s"],
@@ -175,6 +177,7 @@ def serving_leg(nep, synth, params_of, n_req, budget_gb, prec):
         for t in tickets:
             srv.poll(t, wait_ms=-1)
         st = srv.stats()
+        progress(f"serving at {frac} of saturation: p50 {st['p50_ms']:.0f} ms, p99 {st['p99_ms']:.0f} ms")
         out[f"load_{frac}"] = {"rate_hz": rate, "p50_ms": st["p50_ms"], "p99_ms": st["p99_ms"],
                                "requests_per_s": st["requests_per_s"],
                                "atom_steps_per_s": st["atom_steps_per_s"],
@@ -266,6 +269,15 @@ def batch_leg(nep, synth, torch, n_struct, n_sets, reps=3):
     torch.cuda.synchronize()
     st_dev = handle.timing()
     handle.set_timing(False)
+    # one parameter set through the same entry point (rows, one set's passes)
+    one = [x[:1] for x in (e, f, w, t)]
+    handle.compute_batch(offs, pos_d, types_d, boxes, pop[:1], *one)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        handle.compute_batch(offs, pos_d, types_d, boxes, pop[:1], *one)
+    torch.cuda.synchronize()
+    single_ms = (time.perf_counter() - t0) / reps * 1e3
     handle.close()
     del zeros_e, zeros_f, zeros_w, pop_d, loss, mean_d, sigma_d, noise
     g = stages.get("batch_graph", (float("nan"), 1))
@@ -283,6 +295,9 @@ def batch_leg(nep, synth, torch, n_struct, n_sets, reps=3):
             "device_generation_ms": gen_dev_ms,
             "device_graph_ms": graph_dev_ms,
             "device_generation_over_graph": gen_dev_ms / graph_dev_ms,
+            "single_set_ms_per_call": single_ms,
+            "single_set_atom_evals_per_s": n / (single_ms * 1e-3),
+            "graph_rate_over_single_set": (n * n_sets / (graph_ms * 1e-3)) / (n / (single_ms * 1e-3)),
             "workload": ("train3: random triclinic cells, 8-256 atoms, density 0.05-0.09 "
                          "atoms/A^3, 3 species; NEP r_c 6/3.5 A, n_max 12/8, N_bas 12/8, "
                          "l_max 4, 100 neurons per species; E, F, W per vector")}
@@ -488,9 +503,11 @@ def main():
         pof = lambda hh: synth.random_params(nep.nep_num_params(hh))  # noqa: E731
         out["serving"] = {"fp32": serving_leg(nep, synth, pof, args.serve_requests,
                                               args.serve_budget_gb, nep.NEP_MLP_FP32)}
-        progress("serving fp32 done")
+        sv = out["serving"]["fp32"]
+        progress(f"serving fp32: {sv['saturation']['requests_per_s']:.1f} req/s at saturation, "
+                 f"p99 {sv['load_0.5']['p99_ms']:.0f} / {sv['load_0.8']['p99_ms']:.0f} ms at 0.5 / 0.8 load")
         if not args.no_bf16:
-            out["serving"]["bf16"] = serving_leg(nep, synth, pof, args.serve_requests,
+            out["serving"]["bf16"] = serving_leg(nep, synth, pof, args.serve_requests_bf16,
                                                  args.serve_budget_gb, nep.NEP_MLP_BF16)
     if not args.no_cpu:
         progress("cpu baseline (oracle) ...")

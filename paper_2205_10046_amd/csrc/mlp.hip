@@ -472,19 +472,30 @@ __global__ void __launch_bounds__(256) k_mlp_lds(EvalArgs a, int32_t groups_per_
       const int d0 = 16 * db + col, d1 = d0 + 16;
       if constexpr (!BF16) {
         const float* row0 = st + d0 * ST;
-        const float* row1 = st + (two ? d1 : d0) * ST;
+        if (two) {
+          const float* row1 = st + d1 * ST;
 #pragma unroll
-        for (int nb = 0; nb < NNB; ++nb) {
-          const float4 x = *reinterpret_cast<const float4*>(row0 + 16 * nb + 4 * grp);
-          const float4 y = *reinterpret_cast<const float4*>(row1 + 16 * nb + 4 * grp);
-          c0 = __builtin_amdgcn_mfma_f32_16x16x4f32(g[nb][0], x.x, c0, 0, 0, 0);
-          c1 = __builtin_amdgcn_mfma_f32_16x16x4f32(g[nb][0], y.x, c1, 0, 0, 0);
-          c0 = __builtin_amdgcn_mfma_f32_16x16x4f32(g[nb][1], x.y, c0, 0, 0, 0);
-          c1 = __builtin_amdgcn_mfma_f32_16x16x4f32(g[nb][1], y.y, c1, 0, 0, 0);
-          c0 = __builtin_amdgcn_mfma_f32_16x16x4f32(g[nb][2], x.z, c0, 0, 0, 0);
-          c1 = __builtin_amdgcn_mfma_f32_16x16x4f32(g[nb][2], y.z, c1, 0, 0, 0);
-          c0 = __builtin_amdgcn_mfma_f32_16x16x4f32(g[nb][3], x.w, c0, 0, 0, 0);
-          c1 = __builtin_amdgcn_mfma_f32_16x16x4f32(g[nb][3], y.w, c1, 0, 0, 0);
+          for (int nb = 0; nb < NNB; ++nb) {
+            const float4 x = *reinterpret_cast<const float4*>(row0 + 16 * nb + 4 * grp);
+            const float4 y = *reinterpret_cast<const float4*>(row1 + 16 * nb + 4 * grp);
+            c0 = __builtin_amdgcn_mfma_f32_16x16x4f32(g[nb][0], x.x, c0, 0, 0, 0);
+            c1 = __builtin_amdgcn_mfma_f32_16x16x4f32(g[nb][0], y.x, c1, 0, 0, 0);
+            c0 = __builtin_amdgcn_mfma_f32_16x16x4f32(g[nb][1], x.y, c0, 0, 0, 0);
+            c1 = __builtin_amdgcn_mfma_f32_16x16x4f32(g[nb][1], y.y, c1, 0, 0, 0);
+            c0 = __builtin_amdgcn_mfma_f32_16x16x4f32(g[nb][2], x.z, c0, 0, 0, 0);
+            c1 = __builtin_amdgcn_mfma_f32_16x16x4f32(g[nb][2], y.z, c1, 0, 0, 0);
+            c0 = __builtin_amdgcn_mfma_f32_16x16x4f32(g[nb][3], x.w, c0, 0, 0, 0);
+            c1 = __builtin_amdgcn_mfma_f32_16x16x4f32(g[nb][3], y.w, c1, 0, 0, 0);
+          }
+        } else {  // the last, unpaired column block
+#pragma unroll
+          for (int nb = 0; nb < NNB; ++nb) {
+            const float4 x = *reinterpret_cast<const float4*>(row0 + 16 * nb + 4 * grp);
+            c0 = __builtin_amdgcn_mfma_f32_16x16x4f32(g[nb][0], x.x, c0, 0, 0, 0);
+            c0 = __builtin_amdgcn_mfma_f32_16x16x4f32(g[nb][1], x.y, c0, 0, 0, 0);
+            c0 = __builtin_amdgcn_mfma_f32_16x16x4f32(g[nb][2], x.z, c0, 0, 0, 0);
+            c0 = __builtin_amdgcn_mfma_f32_16x16x4f32(g[nb][3], x.w, c0, 0, 0, 0);
+          }
         }
       } else {
         const uint16_t* row0 = swtb + (d0 < NDp32 ? d0 : 0) * STB;
@@ -499,10 +510,12 @@ __global__ void __launch_bounds__(256) k_mlp_lds(EvalArgs a, int32_t groups_per_
           }
           bf16x4_from_bits(*reinterpret_cast<const uint2*>(row0 + 32 * p + 4 * grp), bv0, 0);
           bf16x4_from_bits(*reinterpret_cast<const uint2*>(row0 + 32 * p + 16 + 4 * grp), bv0, 4);
-          bf16x4_from_bits(*reinterpret_cast<const uint2*>(row1 + 32 * p + 4 * grp), bv1, 0);
-          bf16x4_from_bits(*reinterpret_cast<const uint2*>(row1 + 32 * p + 16 + 4 * grp), bv1, 4);
           c0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv0, c0, 0, 0, 0);
-          c1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv1, c1, 0, 0, 0);
+          if (two) {
+            bf16x4_from_bits(*reinterpret_cast<const uint2*>(row1 + 32 * p + 4 * grp), bv1, 0);
+            bf16x4_from_bits(*reinterpret_cast<const uint2*>(row1 + 32 * p + 16 + 4 * grp), bv1, 4);
+            c1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv1, c1, 0, 0, 0);
+          }
         }
       }
 #pragma unroll

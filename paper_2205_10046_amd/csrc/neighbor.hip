@@ -131,25 +131,64 @@ __global__ void k_cell_scatter(const int32_t* __restrict__ key, int64_t N,
 // Order the atoms of each cell by caller index (ext[source index], or the
 // source index itself when ext is NULL).  The internal order is then a
 // function of the positions and caller indices only: independent of the
-// atomic slot assignment above and of the order the atoms came in.
-__global__ void k_cell_sort(const int32_t* __restrict__ cell_start,
-                            const int32_t* __restrict__ cell_count, int32_t n_cells,
-                            const int32_t* __restrict__ ext, int32_t* __restrict__ perm,
-                            const int32_t* gate) {
-  int c = blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= n_cells || gated_off(gate)) return;
+// atomic slot assignment above and of the order the atoms came in.  One wave
+// per cell: every lane holds up to kSortPerLane of the cell's atoms and
+// counts, for each, the keys below its own (keys are distinct, so the counts
+// are the sorted positions); the wave reads the cell's keys 64 at a time and
+// passes them around with lane shuffles.  Cells above 64 kSortPerLane atoms
+// (possible only for a structure that is one cell) are sorted by one lane.
+constexpr int kSortPerLane = 16;
+
+__global__ void __launch_bounds__(kBlock) k_cell_sort(const int32_t* __restrict__ cell_start,
+                                                      const int32_t* __restrict__ cell_count,
+                                                      int32_t n_cells, const int32_t* __restrict__ ext,
+                                                      int32_t* __restrict__ perm, const int32_t* gate) {
+  const int lane = threadIdx.x & 63;
+  const int64_t c = (int64_t)blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
+  if (c >= n_cells || gated_off(gate)) return;  // the lanes of a wave leave together
   int32_t* p = perm + cell_start[c];
-  int n = cell_count[c];
-  for (int a = 1; a < n; ++a) {
-    const int32_t v = p[a];
-    const int32_t kv = ext ? ext[v] : v;
-    int b = a - 1;
-    while (b >= 0 && (ext ? ext[p[b]] : p[b]) > kv) {
-      p[b + 1] = p[b];
-      --b;
+  const int n = cell_count[c];
+  if (n <= 1) return;
+  if (n > 64 * kSortPerLane) {
+    if (lane != 0) return;
+    for (int a = 1; a < n; ++a) {
+      const int32_t v = p[a];
+      const int32_t kv = ext ? ext[v] : v;
+      int b = a - 1;
+      while (b >= 0 && (ext ? ext[p[b]] : p[b]) > kv) {
+        p[b + 1] = p[b];
+        --b;
+      }
+      p[b + 1] = v;
     }
-    p[b + 1] = v;
+    return;
   }
+  int32_t v[kSortPerLane], key[kSortPerLane], rank[kSortPerLane];
+#pragma unroll
+  for (int a = 0; a < kSortPerLane; ++a) {
+    const int idx = lane + 64 * a;
+    v[a] = idx < n ? p[idx] : 0;
+    key[a] = idx < n ? (ext ? ext[v[a]] : v[a]) : INT32_MAX;
+    rank[a] = 0;
+  }
+  for (int b0 = 0; b0 < n; b0 += 64) {
+    const int idx = b0 + lane;
+    int32_t kb = INT32_MAX;
+    if (idx < n) {
+      const int32_t u = p[idx];
+      kb = ext ? ext[u] : u;
+    }
+    const int m = min(64, n - b0);
+    for (int l = 0; l < m; ++l) {
+      const int32_t k = __shfl(kb, l);
+#pragma unroll
+      for (int a = 0; a < kSortPerLane; ++a) rank[a] += k < key[a] ? 1 : 0;
+    }
+  }
+  // every read of the cell's entries above has been consumed by the shuffles
+#pragma unroll
+  for (int a = 0; a < kSortPerLane; ++a)
+    if (lane + 64 * a < n) p[rank[a]] = v[a];
 }
 
 __global__ void k_gather_atoms(BuildArgs b) {
@@ -289,13 +328,17 @@ __global__ void __launch_bounds__(kBlock) k_build_rows(
 
 // rev[m][i] = position of (i, -offset) in the row of j = nl[m][i] (rows
 // sorted by (j, image)).
+constexpr int kReverseLanes = 4;  // lanes per atom of k_reverse: lane s searches for entries s, s + 4, ...
+
 __global__ void k_reverse(int64_t N, const int32_t* __restrict__ nn, const int32_t* __restrict__ nl,
                           const uint16_t* __restrict__ cd, int32_t cap, int32_t* __restrict__ rev,
                           int32_t* __restrict__ err, const int32_t* gate) {
-  int64_t i = xcd_block() * blockDim.x + threadIdx.x;
+  const int sub = threadIdx.x & (kReverseLanes - 1);
+  const int64_t i = (xcd_block() * blockDim.x + threadIdx.x) / kReverseLanes;
   if (i >= N || gated_off(gate)) return;
-  int cnt = min(nn[i], cap);
-  for (int m = 0; m < cnt; ++m) {
+  const int cnt = min(nn[i], cap);
+  bool bad = false;
+  for (int m = sub; m < cnt; m += kReverseLanes) {
     int32_t j = nl[(int64_t)m * N + i];
     int a, b, c;
     split_code(cd[(int64_t)m * N + i], a, b, c);
@@ -313,11 +356,12 @@ __global__ void k_reverse(int64_t N, const int32_t* __restrict__ nn, const int32
       else hi = mid - 1;
     }
     if (found < 0) {
-      atomicExch(err, 1);
+      bad = true;
       found = 0;
     }
     rev[(int64_t)m * N + i] = found;
   }
+  if (bad) atomicExch(err, 1);
 }
 
 // ---- row order for the network pass: atoms grouped by species in
@@ -413,7 +457,7 @@ void launch_order_atoms(const BuildArgs& b, hipStream_t s) {
                      b.n_cells, g);
   hipLaunchKernelGGL(k_cell_scatter, grid_for(b.N), dim3(kBlock), 0, s, b.key, b.N,
                      b.cell_start, b.cell_fill, b.perm, g);
-  hipLaunchKernelGGL(k_cell_sort, grid_for(b.n_cells), dim3(kBlock), 0, s, b.cell_start,
+  hipLaunchKernelGGL(k_cell_sort, dim3(div_up(b.n_cells, kBlock / 64)), dim3(kBlock), 0, s, b.cell_start,
                      b.cell_count, b.n_cells, b.ext_src, b.perm, g);
   hipLaunchKernelGGL(k_gather_atoms, grid_for(b.N), dim3(kBlock), 0, s, b);
 }
@@ -434,7 +478,7 @@ void launch_build_rows(const BuildArgs& b, const StructInfo& st0, bool batch, co
 }
 
 void launch_reverse(int64_t N, const Lists& L, int32_t* err, const int32_t* gate, hipStream_t s) {
-  hipLaunchKernelGGL(k_reverse, grid_for(N), dim3(kBlock), 0, s, N, L.nnR, L.nlR, L.cdR, L.MR,
+  hipLaunchKernelGGL(k_reverse, grid_for(N * kReverseLanes), dim3(kBlock), 0, s, N, L.nnR, L.nlR, L.cdR, L.MR,
                      L.revR, err, gate);
 }
 

@@ -364,3 +364,36 @@ def test_network_tiles_in_bounds(workload):
             if (k == "lds32" and not use32) or (k == "lds16" and not use16):
                 continue
             assert hi[k] < n, (N, k, hi[k], n)
+
+
+def test_cell_rank_sort_emulation():
+    """k_cell_sort's wave algorithm, emulated lane by lane: every lane's ranks
+    (count of smaller keys over the cell, read 64 at a time) are a
+    permutation of 0..n-1 that puts the cell in key order, and every read and
+    write stays inside the cell's segment, for cells of 1..1024 atoms (larger
+    cells take the one-lane insertion sort)."""
+    rng = np.random.default_rng(11)
+    per = 16
+    for n in (1, 2, 5, 63, 64, 65, 130, 257, 1000, 1024):
+        N = 5000
+        ext = rng.permutation(N)
+        seg = rng.choice(N, size=n, replace=False)
+        p = seg.copy()
+        keys_lane = {}
+        for lane in range(64):
+            for a in range(per):
+                idx = lane + 64 * a
+                if idx < n:
+                    keys_lane[(lane, a)] = (p[idx], ext[p[idx]])
+        rank = {k: 0 for k in keys_lane}
+        for b0 in range(0, n, 64):
+            kb = [ext[p[b0 + l]] if b0 + l < n else np.iinfo(np.int32).max for l in range(64)]
+            for l in range(min(64, n - b0)):
+                for k, (_, key) in keys_lane.items():
+                    rank[k] += int(kb[l] < key)
+        out = np.full(n, -1)
+        for k, (v, _) in keys_lane.items():
+            assert 0 <= rank[k] < n
+            out[rank[k]] = v
+        assert (out >= 0).all()
+        assert np.array_equal(out, seg[np.argsort(ext[seg])])
