@@ -409,6 +409,7 @@ def main():
         progress(f"fcc131k md mlp={'bf16' if prec else 'fp32'}: {dt / args.steps * 1e3:.4f} ms/step")
         if prec == nep.NEP_MLP_FP32:
             tune = handle.tuning()
+            sched = handle.md_counters()
         handle.close()
         del pos_d, vel_d, types_d
         torch.cuda.empty_cache()
@@ -458,6 +459,7 @@ def main():
                          "avg_launch_ms": avg["mlp"]},
         "stages_ms_per_step": {k: v[0] / args.steps for k, v in stages.items()},
         "nve_drift_eV_per_atom": float(np.abs(e - e[0]).max() / n) if len(e) else None,
+        "md_schedule": sched,
         "heat_current": heat,
     }
     if nep.NEP_MLP_BF16 in results:

@@ -452,6 +452,17 @@ int nep_get_timing(const nep_handle *h, int32_t max, const char **names,
  * from the paper: it names the variants that profiles refer to. */
 int nep_get_tuning(const nep_handle *h, int32_t batch, int32_t out[7]);
 
+/* MD schedule counters of this handle since nep_create: out[0] = steps run
+ * inside captured groups (with a skin, such a group checks for a row rebuild
+ * at its first step only, with each atom's displacement extended by twice
+ * its speed times the group's remaining time, and verifies the skin at every
+ * later step); out[1] = chunks run again step by step because an atom left
+ * the skin between two checks (the chunk restarts from its saved state, so
+ * results stay those of rows within the skin); out[2] = row rebuilds of MD
+ * runs with a skin.  Not from the paper: the paper does not describe how its
+ * rows are maintained. */
+int nep_md_counters(const nep_handle *h, int64_t out[3]);
+
 #ifdef __cplusplus
 }
 #endif

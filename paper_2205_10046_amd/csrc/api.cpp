@@ -37,6 +37,22 @@ constexpr double kPi = 3.14159265358979323846;
 // 1 amu (Angstrom/fs)^2 in eV (CODATA 2018 amu and elementary charge)
 constexpr double kAmuA2fs2 = 1.66053906660e-27 * 1e10 / 1.602176634e-19;
 constexpr double kBoltzmann = 8.617333262e-5;  // eV/K
+// Device flags of a handle: [0] radial overflow, [1] angular overflow, [2]
+// unpaired reverse entry, [3] species out of range, [4] non-finite position,
+// [5] candidate overflow, [6] row invariant broken, [7] rebuild gate, [8] an
+// atom left the skin between two rebuild checks of a captured MD group; [9]
+// rows rebuilt by the current MD run with a skin.
+constexpr int kNumFlags = 16;
+constexpr int kFlagGuard = 8;
+constexpr int kFlagRebuilds = 9;
+constexpr int kFlagsReset = 9;  // flags cleared at the start of an MD chunk
+constexpr int kFlagsRead = 10;
+constexpr size_t kPinFlags = 3072;  // pinned staging slot of the flags (64 bytes)
+static_assert(kFlagsRead * sizeof(int32_t) <= 64 && kPinFlags + 64 <= 4096, "staging slot");
+// A captured MD group checks for a rebuild once, at its first step, with
+// every atom's displacement extended by this many times its current speed
+// over the group's remaining steps; each later step only verifies the skin.
+constexpr double kRebuildLookahead = 2.0;
 
 struct Failure {
   int code;
@@ -352,6 +368,9 @@ struct nep_handle {
   unsigned char* pinned = nullptr;
   // timing
   bool timing = false;
+  int64_t md_group_steps = 0;  // MD steps run in captured groups (one rebuild check each)
+  int64_t md_replays = 0;      // MD chunks replayed because an atom left the skin mid-group
+  int64_t md_rebuilds = 0;     // row rebuilds of MD runs with a skin
   StageTimes times;
   std::vector<std::pair<const char*, std::pair<hipEvent_t, hipEvent_t>>> pending;
 
@@ -698,7 +717,8 @@ void ensure_atoms(nep_handle* h, int64_t N, int32_t n_cells, bool md) {
     h->rows_cap = rows_length(c, M.T);
     dev_alloc(h->rows, h->rows_cap);
     dev_alloc(h->tblk, kMaxTypes * type_row_blocks(c)); dev_alloc(h->tex, kMaxTypes * type_row_blocks(c));
-    dev_alloc(h->toff, kMaxTypes + 1); dev_alloc(h->flags, 8);
+    dev_alloc(h->toff, kMaxTypes + 1); dev_alloc(h->flags, kNumFlags);
+    HIPCHK(hipMemset(h->flags, 0, kNumFlags * sizeof(int32_t)));
     h->cap_part = num_partials(c);
     dev_alloc(h->partial, 11 * h->cap_part); dev_alloc(h->totals, 16);
     dev_alloc(h->structs, 1);
@@ -865,7 +885,7 @@ void build_rows_checked(nep_handle* h, const Prepared& pp, const BuildArgs& b, h
       launch_build_rows(b, pp.geo.st, pp.batch, h->V, h->L, s);
     }
     launch_check_rows(pp.N, h->sid, h->structs, pp.geo.st, pp.batch, h->L, h->flags + 6, s);
-    int32_t* fl = (int32_t*)(h->pinned + 384);
+    int32_t* fl = (int32_t*)(h->pinned + kPinFlags);
     HIPCHK(hipMemcpyAsync(fl, h->flags, 8 * sizeof(int32_t), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
     if (fl[3]) throw Failure{NEP_E_INVALID_ARG, "an atom type is out of range"};
@@ -2021,7 +2041,7 @@ void skin_rebuild(nep_handle* h, const Prepared& pp, double rl, const int32_t* g
   br.ext_out = h->ext_id2;
   launch_order_atoms(br, s);
   launch_commit_rebuild(N, h->pos2, h->vel2, h->types2, h->ext_id2, h->pos, h->vel, h->types,
-                        h->ext_id, h->pos_ref, gate, s, mu_cum);
+                        h->ext_id, h->pos_ref, gate, s, mu_cum, h->flags + kFlagRebuilds);
   BuildArgs bv = build_args(h, pp, nullptr, nullptr, h->pos, h->types);
   bv.rcR2 = rl * rl;
   bv.gate = gate;
@@ -2049,8 +2069,8 @@ bool grow_rows(nep_handle* h, int64_t N, const int32_t* fl) {
 }
 
 int32_t* read_flags(nep_handle* h, hipStream_t s) {
-  int32_t* fl = (int32_t*)(h->pinned + 384);
-  HIPCHK(hipMemcpyAsync(fl, h->flags, 8 * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  int32_t* fl = (int32_t*)(h->pinned + kPinFlags);
+  HIPCHK(hipMemcpyAsync(fl, h->flags, kFlagsRead * sizeof(int32_t), hipMemcpyDeviceToHost, s));
   HIPCHK(hipStreamSynchronize(s));
   return fl;
 }
@@ -2086,6 +2106,8 @@ int md_skin(nep_handle* h, const Prepared& pp, double* d_pos, double* d_vel, con
   const double thr2 = 0.25 * skin * skin;
   int32_t* gate = h->flags + 7;
   ensure_verlet(h, N, std::max(h->V.MR, estimate_capacity(rl, (double)N / pp.geo.volume)));
+  const int64_t rebuilds0 = h->md_rebuilds;  // the device counts this call's rebuilds from 0
+  launch_fill_i32(h->flags + kFlagRebuilds, 1, 0, s);
   // ensemble state on the device (thermostats and barostats)
   const bool ens = ep != nullptr;
   const bool npt = ens && ep->kind >= kEnsNptBerendsen;
@@ -2156,7 +2178,11 @@ int md_skin(nep_handle* h, const Prepared& pp, double* d_pos, double* d_vel, con
   // an ensemble run the thermostat and barostat kernels around it follow the
   // order of the ensembles' publications (see nep.h), and `row` writes the
   // step's thermo row before the barostat acts
-  auto step_body = [&](hipStream_t cs, bool virial, bool row) {
+  // chain: this step checks for a rebuild (looking `ahead` fs further ahead)
+  // and rebuilds the rows when needed; otherwise it only verifies that every
+  // atom is still within half the skin of its reference position (a sticky
+  // flag read at the end of the chunk, which is then replayed step by step)
+  auto step_body = [&](hipStream_t cs, bool virial, bool row, bool chain, double ahead) {
     if (ens) {
       Stage st(h, "ensemble", cs);
       launch_ens_step_begin(est, cs);
@@ -2173,9 +2199,15 @@ int md_skin(nep_handle* h, const Prepared& pp, double* d_pos, double* d_vel, con
     }
     {
       Stage st(h, "order_atoms", cs);
-      launch_fill_i32(gate, 1, 0, cs);
-      launch_check_displacement(h->pos, h->pos_ref, N, thr2, gate, cs, mu_cum, h->hp.rc_radial, rl);
-      skin_rebuild(h, pp, rl, gate, cs, mu_cum);
+      if (chain) {
+        launch_fill_i32(gate, 1, 0, cs);
+        launch_check_displacement(h->pos, h->pos_ref, h->vel, N, thr2, ahead, gate, cs, mu_cum,
+                                  h->hp.rc_radial, rl);
+        skin_rebuild(h, pp, rl, gate, cs, mu_cum);
+      } else {
+        launch_check_displacement(h->pos, h->pos_ref, nullptr, N, thr2, 0.0, h->flags + kFlagGuard, cs,
+                                  mu_cum, h->hp.rc_radial, rl);
+      }
     }
     {
       Stage st(h, "neighbor_rows", cs);
@@ -2208,6 +2240,10 @@ int md_skin(nep_handle* h, const Prepared& pp, double* d_pos, double* d_vel, con
   // (captured even for a call shorter than G steps, so that a warm-up call
   // leaves the graph ready for the calls after it)
   const bool use_graph = !h->timing && !(genv && genv[0] == '0') && G <= 1000;
+  // look-ahead of a group's rebuild check, in units of the group's remaining
+  // time (NEP_MD_LOOKAHEAD overrides it; 0 checks the displacement alone)
+  double lookahead = kRebuildLookahead;
+  if (const char* e = std::getenv("NEP_MD_LOOKAHEAD")) lookahead = std::max(0.0, std::atof(e));
   if (!h->row_counter) dev_alloc(h->row_counter, 1);
   hipStream_t gs = s;
   // What the captured kernels' arguments depend on besides the handle's
@@ -2227,6 +2263,7 @@ int md_skin(nep_handle* h, const Prepared& pp, double* d_pos, double* d_vel, con
     put(&dt, sizeof dt);
     put(&rl, sizeof rl);
     put(&thr2, sizeof thr2);
+    put(&lookahead, sizeof lookahead);
     put(&pp.geo.st, sizeof pp.geo.st);
     put(&pp.n_cells, sizeof pp.n_cells);
     put(&pp.batch, sizeof pp.batch);
@@ -2243,7 +2280,7 @@ int md_skin(nep_handle* h, const Prepared& pp, double* d_pos, double* d_vel, con
       HIPCHK(hipStreamBeginCapture(gs, hipStreamCaptureModeThreadLocal));
       for (int64_t k = 0; k < G; ++k) {
         const bool last_row = thermo_every > 0 && k == G - 1;
-        step_body(gs, last_row, last_row);
+        step_body(gs, last_row, last_row, k == 0, lookahead * (double)(G - 1) * dt);
       }
       if (thermo_every > 0 && !ens)
         launch_thermo_counted(h->U, h->W, h->vel, h->types, h->mass, N, h->partial, num_partials(N),
@@ -2270,7 +2307,7 @@ int md_skin(nep_handle* h, const Prepared& pp, double* d_pos, double* d_vel, con
   hipStream_t ws = use_graph ? gs : s;   // the stream every step runs on
   const int64_t chunk = use_graph ? G * std::max<int64_t>(1, 50 / G) : 50;
   int64_t row = 0;
-  bool redo = false;
+  bool redo = false, replay = false;
   for (int64_t c0 = 0; c0 < n_steps;) {
     const int64_t c1 = std::min(n_steps, c0 + chunk);
     s = ws;
@@ -2286,9 +2323,14 @@ int md_skin(nep_handle* h, const Prepared& pp, double* d_pos, double* d_vel, con
       HIPCHK(hipMemcpyAsync(ens_base + 1024, h->structs, sizeof(StructInfo), hipMemcpyDeviceToDevice, s));
     }
     const int64_t row0 = row;
-    launch_fill_i32(h->flags, 8, 0, s);
-    if (redo) {  // rows were grown: rebuild them for the restored state first
+    launch_fill_i32(h->flags, kFlagsReset, 0, s);
+    if (redo) {
+      // rows were grown or the chunk is replayed: rebuild them for the
+      // restored state, which re-sorts the atoms, so the forces the first
+      // half kick uses are evaluated again in the new order
       skin_rebuild(h, pp, rl, nullptr, s, mu_cum);
+      skin_filter(h, pp, s);
+      forces(h, pp, s);
       redo = false;
     }
     if (use_graph || ens) {
@@ -2296,15 +2338,17 @@ int md_skin(nep_handle* h, const Prepared& pp, double* d_pos, double* d_vel, con
       *rc = (int32_t)row;
       HIPCHK(hipMemcpyAsync(h->row_counter, rc, sizeof(int32_t), hipMemcpyHostToDevice, s));
     }
+    int64_t group_steps = 0;
     for (int64_t step = c0 + 1; step <= c1; ++step) {
-      if (use_graph && (step - 1) % G == 0 && step - 1 + G <= c1) {
+      if (use_graph && !replay && (step - 1) % G == 0 && step - 1 + G <= c1) {
         HIPCHK(hipGraphLaunch(h->md_exec, s));
         if (thermo_every > 0) ++row;
         step += G - 1;
+        group_steps += G;
         continue;
       }
       const bool row_due = thermo_every > 0 && step % thermo_every == 0;
-      step_body(s, row_due, row_due);
+      step_body(s, row_due, row_due, true, 0.0);
       if (ens && row_due) {
         ++row;
       } else if (row_due) {
@@ -2321,7 +2365,15 @@ int md_skin(nep_handle* h, const Prepared& pp, double* d_pos, double* d_vel, con
     const int32_t* fl = read_flags(h, s);
     if (fl[4]) throw Failure{NEP_E_NONFINITE, "positions became non-finite during the run"};
     if (npt) check_npt_cell(*(const StructInfo*)(h->pinned + 1536), pp.geo.st, rl);
-    if (grow_rows(h, N, fl)) {
+    const bool grown = grow_rows(h, N, fl);
+    if (grown || fl[kFlagGuard]) {
+      // rows overflowed, or an atom left the skin between two rebuild checks
+      // of a captured group: restore the chunk's start and run it again
+      // (with grown rows; a replay checks for a rebuild at every step)
+      if (!grown) {
+        replay = true;
+        ++h->md_replays;
+      }
       if (ens) {
         HIPCHK(hipMemcpyAsync(est, ens_base + 512, sizeof(EnsState), hipMemcpyDeviceToDevice, s));
         HIPCHK(hipMemcpyAsync(h->structs, ens_base + 1024, sizeof(StructInfo), hipMemcpyDeviceToDevice, s));
@@ -2334,11 +2386,14 @@ int md_skin(nep_handle* h, const Prepared& pp, double* d_pos, double* d_vel, con
       HIPCHK(hipMemcpyAsync(h->F, h->F_save, 3 * N * sizeof(float), hipMemcpyDeviceToDevice, s));
       row = row0;
       redo = true;
-      if (use_graph) capture();  // the grown rows live at new addresses
+      if (use_graph && grown) capture();  // the grown rows live at new addresses
       continue;
     }
     if (fl[2]) throw Failure{NEP_E_HIP, "internal error: neighbour rows are not symmetric"};
     check_row_flag(fl[6]);
+    h->md_group_steps += group_steps;
+    h->md_rebuilds = rebuilds0 + fl[kFlagRebuilds];
+    replay = false;
     c0 = c1;
   }
   launch_unpermute_md(h->ext_id, N, h->pos, h->vel, d_pos, d_vel, s);
@@ -2507,7 +2562,7 @@ static int md_impl(nep_handle* h, int64_t N, double* d_pos, double* d_vel, const
     }
     launch_check_finite(h->pos, 3 * N, h->flags + 4, s);
     launch_check_rows(N, h->sid, h->structs, pp.geo.st, pp.batch, h->L, h->flags + 6, s);
-    int32_t* fl = (int32_t*)(h->pinned + 384);
+    int32_t* fl = (int32_t*)(h->pinned + kPinFlags);
     HIPCHK(hipMemcpyAsync(fl, h->flags, 8 * sizeof(int32_t), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
     if (fl[4]) throw Failure{NEP_E_NONFINITE, "positions became non-finite during the run"};
@@ -2677,6 +2732,14 @@ int nep_get_tuning(const nep_handle* h, int32_t batch, int32_t out[7]) {
   const int32_t v[7] = {t.NG_desc, t.block_desc, t.lanes_desc, t.NG_force, t.block_force,
                         t.lanes_force, t.lanes_gather};
   for (int k = 0; k < 7; ++k) out[k] = t.done ? v[k] : 0;
+  return NEP_OK;
+}
+
+int nep_md_counters(const nep_handle* h, int64_t out[3]) {
+  if (!h || !out) return fail(nullptr, {NEP_E_INVALID_ARG, "handle and out[3] are required"});
+  out[0] = h->md_group_steps;
+  out[1] = h->md_replays;
+  out[2] = h->md_rebuilds;
   return NEP_OK;
 }
 

@@ -218,10 +218,11 @@ __global__ void k_commit_rebuild(int64_t N, const double* __restrict__ pos2,
                                  const int32_t* __restrict__ ext2, double* __restrict__ pos,
                                  double* __restrict__ vel, int32_t* __restrict__ types,
                                  int32_t* __restrict__ ext, double* __restrict__ pos_ref,
-                                 const int32_t* gate, double* mu_cum) {
+                                 const int32_t* gate, double* mu_cum, int32_t* count) {
   int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= N || gated_off(gate)) return;
   if (k == 0 && mu_cum) *mu_cum = 1.0;  // the reference positions are the current ones
+  if (k == 0 && count) atomicAdd(count, 1);  // rebuilds done
   for (int c = 0; c < 3; ++c) {
     const double x = pos2[c * N + k];
     pos[c * N + k] = x;
@@ -464,9 +465,10 @@ void launch_order_atoms(const BuildArgs& b, hipStream_t s) {
 
 void launch_commit_rebuild(int64_t N, const double* pos2, const double* vel2, const int32_t* types2,
                            const int32_t* ext2, double* pos, double* vel, int32_t* types, int32_t* ext,
-                           double* pos_ref, const int32_t* gate, hipStream_t s, double* mu_cum) {
+                           double* pos_ref, const int32_t* gate, hipStream_t s, double* mu_cum,
+                           int32_t* count) {
   hipLaunchKernelGGL(k_commit_rebuild, grid_for(N), dim3(kBlock), 0, s, N, pos2, vel2, types2, ext2,
-                     pos, vel, types, ext, pos_ref, gate, mu_cum);
+                     pos, vel, types, ext, pos_ref, gate, mu_cum, count);
 }
 
 void launch_build_rows(const BuildArgs& b, const StructInfo& st0, bool batch, const Lists& V,
@@ -785,11 +787,15 @@ void launch_filter_rows(const BuildArgs& b, const StructInfo& st0, bool batch, c
                      b.N, V, L, b.overflow + 2);
 }
 
-// gate = any |r_i - r_i(at last build)|^2 > thr2.  With a box scaled by mu
-// since the build (NPT), a pair within r_c now was within r_c + skin then as
-// long as every |r_i - mu r_i(build)| <= (mu (r_c + skin) - r_c) / 2.
+// flag = any atom whose displacement since the last build, plus horizon
+// times its speed when vel is given, exceeds half the skin: |r_i - r_i(build)|
+// + horizon |v_i| > sqrt(thr2) (the plain test |r_i - r_i(build)|^2 > thr2
+// when horizon is 0).  With a box scaled by mu since the build (NPT), a pair
+// within r_c now was within r_c + skin then as long as every
+// |r_i - mu r_i(build)| <= (mu (r_c + skin) - r_c) / 2.
 __global__ void k_check_displacement(const double* __restrict__ pos, const double* __restrict__ ref,
-                                     int64_t N, double thr2, int32_t* __restrict__ gate,
+                                     const double* __restrict__ vel, int64_t N, double thr2,
+                                     double horizon, int32_t* __restrict__ flag,
                                      const double* __restrict__ mu_cum, double rc, double rl) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= N) return;
@@ -801,13 +807,20 @@ __global__ void k_check_displacement(const double* __restrict__ pos, const doubl
   }
   const double dx = pos[i] - m * ref[i], dy = pos[N + i] - m * ref[N + i],
                dz = pos[2 * N + i] - m * ref[2 * N + i];
-  if (dx * dx + dy * dy + dz * dz > t2) atomicExch(gate, 1);
+  const double d2 = dx * dx + dy * dy + dz * dz;
+  bool out = d2 > t2;
+  if (vel && horizon > 0.0) {
+    const double vx = vel[i], vy = vel[N + i], vz = vel[2 * N + i];
+    out = sqrt(d2) + horizon * sqrt(vx * vx + vy * vy + vz * vz) > sqrt(t2);
+  }
+  if (out) atomicExch(flag, 1);
 }
 
-void launch_check_displacement(const double* pos, const double* ref, int64_t N, double thr2,
-                               int32_t* gate, hipStream_t s, const double* mu_cum, double rc, double rl) {
-  hipLaunchKernelGGL(k_check_displacement, grid_for(N), dim3(kBlock), 0, s, pos, ref, N, thr2, gate,
-                     mu_cum, rc, rl);
+void launch_check_displacement(const double* pos, const double* ref, const double* vel, int64_t N,
+                               double thr2, double horizon, int32_t* flag, hipStream_t s,
+                               const double* mu_cum, double rc, double rl) {
+  hipLaunchKernelGGL(k_check_displacement, grid_for(N), dim3(kBlock), 0, s, pos, ref, vel, N, thr2, horizon,
+                     flag, mu_cum, rc, rl);
 }
 
 template <class T>

@@ -74,19 +74,21 @@ void launch_reverse(int64_t N, const Lists& L, int32_t* err, const int32_t* gate
 void launch_check_rows(int64_t N, const int32_t* sid, const StructInfo* structs, const StructInfo& st0,
                        bool batch, const Lists& L, int32_t* bad, hipStream_t s);
 void launch_build_verlet(const BuildArgs& b, const Lists& V, hipStream_t s);
-// After a gated re-sort: pos/vel/types/ext <- their permuted copies, pos_ref <- pos.
+// After a gated re-sort: pos/vel/types/ext <- their permuted copies, pos_ref <- pos
+// (and *count += 1 when count is given).
 void launch_commit_rebuild(int64_t N, const double* pos2, const double* vel2, const int32_t* types2,
                            const int32_t* ext2, double* pos, double* vel, int32_t* types, int32_t* ext,
                            double* pos_ref, const int32_t* gate, hipStream_t s,
-                           double* mu_cum = nullptr);
+                           double* mu_cum = nullptr, int32_t* count = nullptr);
 void launch_filter_rows(const BuildArgs& b, const StructInfo& st0, bool batch, const Lists& V,
                         const Lists& L, hipStream_t s);
-// gate = 1 if an atom moved more than allowed since the last build; with
-// mu_cum (box scaling since the build, NPT) the allowance shrinks to
+// flag = 1 if an atom moved more than allowed since the last build, or will
+// have once it moves `horizon` times its current speed further (vel given);
+// with mu_cum (box scaling since the build, NPT) the allowance shrinks to
 // (mu (r_c + skin) - r_c) / 2 around the scaled reference positions.
-void launch_check_displacement(const double* pos, const double* ref, int64_t N, double thr2,
-                               int32_t* gate, hipStream_t s, const double* mu_cum = nullptr,
-                               double rc = 0.0, double rl = 0.0);
+void launch_check_displacement(const double* pos, const double* ref, const double* vel, int64_t N,
+                               double thr2, double horizon, int32_t* flag, hipStream_t s,
+                               const double* mu_cum, double rc, double rl);
 void launch_copy_gated_f64(double* dst, const double* src, int64_t n, const int32_t* gate,
                            hipStream_t s);
 void launch_copy_gated_i32(int32_t* dst, const int32_t* src, int64_t n, const int32_t* gate,

@@ -34,7 +34,7 @@ EXPORTS = ["nep_num_descriptors", "nep_num_params", "nep_create", "nep_set_param
            "nep_heat_current", "nep_heat_current_dev", "nep_neighbors", "nep_descriptors",
            "nep_latent", "nep_elastic_cubic", "nep_md_run", "nep_md_run_dev", "nep_md_run_ensemble",
            "nep_compute_batch", "nep_compute_batch_dev", "nep_batch_loss", "nep_batch_loss_noalloc", "nep_snes_step",
-           "nep_snes_sample", "nep_set_timing", "nep_get_timing", "nep_get_tuning",
+           "nep_snes_sample", "nep_set_timing", "nep_get_timing", "nep_get_tuning", "nep_md_counters",
            "nep_server_create",
            "nep_server_submit", "nep_server_poll", "nep_server_stats", "nep_server_reset_stats",
            "nep_server_destroy"]
@@ -170,6 +170,7 @@ def load():
     L.nep_set_timing.argtypes = [vp, i32]
     L.nep_get_timing.argtypes = [vp, i32, P(C.c_char_p), pd, P(i64)]
     L.nep_get_tuning.argtypes = [vp, i32, P(i32)]
+    L.nep_md_counters.argtypes = [vp, P(C.c_int64)]
     for name in EXPORTS:
         getattr(L, name).restype = getattr(L, name).restype or C.c_int
     _lib = L
@@ -533,6 +534,13 @@ class Handle:
         keys = ("ng_desc", "block_desc", "lanes_desc", "ng_force", "block_force", "lanes_force",
                 "lanes_gather")
         return dict(zip(keys, (int(x) for x in out)))
+
+    def md_counters(self):
+        """MD schedule counters (nep_md_counters): steps run in captured groups,
+        chunks replayed step by step and row rebuilds."""
+        out = np.zeros(3, np.int64)
+        self._check(load().nep_md_counters(self._h, _ptr(out, C.c_int64)))
+        return {"group_steps": int(out[0]), "replayed_chunks": int(out[1]), "rebuilds": int(out[2])}
 
 
 class Server:
