@@ -769,6 +769,9 @@ BuildArgs build_args(nep_handle* h, const Prepared& pp, const double* pos_src, c
   b.rcR2 = h->hp.rc_radial * h->hp.rc_radial;
   b.rcA2 = h->hp.rc_angular * h->hp.rc_angular;
   b.overflow = h->flags;
+  b.wide_rows = 0;
+  for (const StructInfo& st : pp.sts)
+    if (st.mode != kModeCells) b.wide_rows = 1;
   return b;
 }
 

@@ -273,9 +273,10 @@ __global__ void __launch_bounds__(kBlock) k_build_rows(
     const double* __restrict__ pos, int64_t N, const int32_t* __restrict__ sid,
     const StructInfo* __restrict__ structs, const int32_t* __restrict__ cell_start,
     const int32_t* __restrict__ cell_count, double rc2, Lists V, int32_t* __restrict__ overflow,
-    const int32_t* gate) {
+    const int32_t* gate, int32_t cells_only) {
   int64_t i = xcd_block() * blockDim.x + threadIdx.x;
   if (i >= N || gated_off(gate)) return;
+  if (cells_only && structs[sid[i]].mode != kModeCells) return;  // k_build_rows_wide's atoms
   const StructInfo st = structs[sid[i]];
   const double xi = pos[i], yi = pos[N + i], zi = pos[2 * N + i];
   RowWriter R{V.nlR, V.cdR, V.MR, 0};
@@ -325,6 +326,107 @@ __global__ void __launch_bounds__(kBlock) k_build_rows(
   }
   V.nnR[i] = R.count;
   if (R.count > V.MR) atomicMax(overflow, R.count);
+}
+
+// Candidate rows of the atoms of structures without cells (all-pairs and
+// image modes: small cells, whose rows scan every atom of the structure, or
+// every (atom, image) pair), kBuildLanes lanes per atom.  The candidates of
+// atom i form one sequence in row order -- the atoms of the structure, or
+// the (atom, image) pairs with the image offsets innermost -- and lane s takes
+// the s-th contiguous slice of it.  Pass 1 counts each slice's members, a
+// prefix sum over the atom's lanes gives every slice its place, and pass 2
+// tests the slice again and writes its members there, so the row is the one
+// the sequential scan of k_build_rows writes: sorted by (j, image).
+constexpr int kBuildLanes = 16;
+
+template <class Fn>
+__device__ __forceinline__ void visit_slice(const StructInfo& st, int64_t c0, int64_t c1, Fn&& fn) {
+  if (c0 >= c1) return;
+  if (st.mode == kModeAllPairs) {
+    for (int64_t c = c0; c < c1; ++c) fn(st.start + c, 0, 0, 0);
+    return;
+  }
+  const int R0 = st.reach[0], R1 = st.reach[1], R2 = st.reach[2];
+  const int w1 = 2 * R1 + 1, w2 = 2 * R2 + 1, nimg = (2 * R0 + 1) * w1 * w2;
+  int64_t jl = c0 / nimg;
+  int img = (int)(c0 - jl * nimg);
+  for (int64_t c = c0; c < c1; ++c) {
+    const int o0 = img / (w1 * w2) - R0, o1 = (img / w2) % w1 - R1, o2 = img % w2 - R2;
+    fn(st.start + jl, o0, o1, o2);
+    if (++img == nimg) {
+      img = 0;
+      ++jl;
+    }
+  }
+}
+
+__global__ void __launch_bounds__(kBlock) k_build_rows_wide(
+    const double* __restrict__ pos, int64_t N, const int32_t* __restrict__ sid,
+    const StructInfo* __restrict__ structs, double rc2, Lists V, int32_t* __restrict__ overflow,
+    const int32_t* gate) {
+  constexpr int G = kBuildLanes;
+  const int sub = threadIdx.x & (G - 1);
+  const int64_t i = (xcd_block() * blockDim.x + threadIdx.x) / G;
+  if (i >= N || gated_off(gate)) return;  // the lanes of an atom leave together
+  if (structs[sid[i]].mode == kModeCells) return;  // k_build_rows' atoms
+  const StructInfo st = structs[sid[i]];
+  const double xi = pos[i], yi = pos[N + i], zi = pos[2 * N + i];
+  const int64_t total = st.mode == kModeAllPairs
+                            ? st.count
+                            : st.count * (int64_t)((2 * st.reach[0] + 1) * (2 * st.reach[1] + 1) *
+                                                   (2 * st.reach[2] + 1));
+  const int64_t chunk = (total + G - 1) / G;
+  const int64_t c0 = min(total, chunk * sub), c1 = min(total, c0 + chunk);
+  // member test of candidate (j, image offset o)
+  auto member = [&](int64_t j, int o0, int o1, int o2, uint16_t& code) -> bool {
+    double Dx, Dy, Dz;
+    {
+#pragma clang fp contract(off)
+      Dx = pos[j] - xi;
+      Dy = pos[N + j] - yi;
+      Dz = pos[2 * N + j] - zi;
+    }
+    int n0, n1, n2;
+    min_image(st, Dx, Dy, Dz, n0, n1, n2);
+    n0 += o0;
+    n1 += o1;
+    n2 += o2;
+    if (j == i && n0 == 0 && n1 == 0 && n2 == 0) return false;
+    double dx, dy, dz;
+    image_disp(st, Dx, Dy, Dz, n0, n1, n2, dx, dy, dz);
+    code = make_code(o0, o1, o2);
+    return norm2_exact(dx, dy, dz) < rc2;
+  };
+  // pass 1: members of this lane's slice
+  int32_t mine = 0;
+  visit_slice(st, c0, c1, [&](int64_t j, int o0, int o1, int o2) {
+    uint16_t code;
+    if (member(j, o0, o1, o2, code)) ++mine;
+  });
+  // exclusive prefix over the atom's lanes, and the total
+  int32_t incl = mine;
+#pragma unroll
+  for (int d = 1; d < G; d <<= 1) {
+    const int32_t v = __shfl_up(incl, d, G);
+    if (sub >= d) incl += v;
+  }
+  const int32_t count = __shfl(incl, G - 1, G);
+  // pass 2: write this slice's members from its place on
+  int32_t p = incl - mine;
+  visit_slice(st, c0, c1, [&](int64_t j, int o0, int o1, int o2) {
+    uint16_t code;
+    if (member(j, o0, o1, o2, code)) {
+      if (p < V.MR) {
+        V.nlR[(int64_t)p * N + i] = (int32_t)j;
+        V.cdR[(int64_t)p * N + i] = code;
+      }
+      ++p;
+    }
+  });
+  if (sub == 0) {
+    V.nnR[i] = count;
+    if (count > V.MR) atomicMax(overflow, count);
+  }
 }
 
 // rev[m][i] = position of (i, -offset) in the row of j = nl[m][i] (rows
@@ -487,8 +589,12 @@ void launch_reverse(int64_t N, const Lists& L, int32_t* err, const int32_t* gate
 // Candidate rows at sqrt(b.rcR2) and their reverse index, rebuilt when the
 // gate is set.
 void launch_build_verlet(const BuildArgs& b, const Lists& V, hipStream_t s) {
-  hipLaunchKernelGGL(k_build_rows, grid_for(b.N), dim3(kBlock), 0, s, b.pos, b.N, b.sid,
-                     b.structs, b.cell_start, b.cell_count, b.rcR2, V, b.overflow + 5, b.gate);
+  // structures without cells take their rows from the wide kernel
+  hipLaunchKernelGGL(k_build_rows, grid_for(b.N), dim3(kBlock), 0, s, b.pos, b.N, b.sid, b.structs,
+                     b.cell_start, b.cell_count, b.rcR2, V, b.overflow + 5, b.gate, b.wide_rows);
+  if (b.wide_rows)
+    hipLaunchKernelGGL(k_build_rows_wide, grid_for(b.N * kBuildLanes), dim3(kBlock), 0, s, b.pos, b.N,
+                       b.sid, b.structs, b.rcR2, V, b.overflow + 5, b.gate);
   launch_reverse(b.N, V, b.overflow + 2, b.gate, s);
 }
 

@@ -26,6 +26,7 @@ struct BuildArgs {
   int32_t* overflow;          // flags: [0] radial row, [1] angular row, [2] rev error,
                               // [5] candidate row overflow (max counts)
   const int32_t* gate;        // rebuild kernels run only when *gate != 0 (NULL: always)
+  int32_t wide_rows = 0;      // some structure has no cells: its rows come from k_build_rows_wide
   // optional: velocities and caller indices permuted with the positions
   const double* vel_src = nullptr;
   double* vel_dst = nullptr;

@@ -397,3 +397,45 @@ def test_cell_rank_sort_emulation():
             out[rank[k]] = v
         assert (out >= 0).all()
         assert np.array_equal(out, seg[np.argsort(ext[seg])])
+
+
+def _slices(total, G):
+    chunk = -(-total // G)
+    out = []
+    for s in range(G):
+        c0 = min(total, chunk * s)
+        c1 = min(total, c0 + chunk)
+        out.append((c0, c1))
+    return out
+
+
+def test_candidate_row_slices_reproduce_the_sequential_scan():
+    """k_build_rows_wide's sixteen lanes per atom (structures without cells):
+    the slices of the candidate sequence partition it in order, and the
+    (atom, image) pairs decoded from the sequence index are those of the
+    sequential scan of k_build_rows, in its order, inside the structure's
+    atoms and image reach."""
+    G = 16
+    for total in (0, 1, 15, 16, 17, 100, 541, 8000):
+        sl = _slices(total, G)
+        flat = [c for c0, c1 in sl for c in range(c0, c1)]
+        assert flat == list(range(total))
+    # image mode: atoms x images with the offsets innermost
+    for reach in ((1, 1, 1), (2, 1, 0), (0, 0, 3), (2, 2, 2)):
+        R0, R1, R2 = reach
+        start, count = 37, 11
+        seq = [(start + j, o0, o1, o2) for j in range(count) for o0 in range(-R0, R0 + 1)
+               for o1 in range(-R1, R1 + 1) for o2 in range(-R2, R2 + 1)]
+        w1, w2 = 2 * R1 + 1, 2 * R2 + 1
+        nimg = (2 * R0 + 1) * w1 * w2
+        got = []
+        for c0, c1 in _slices(count * nimg, G):
+            if c0 >= c1:
+                continue
+            jl, img = divmod(c0, nimg)
+            for c in range(c0, c1):
+                got.append((start + jl, img // (w1 * w2) - R0, (img // w2) % w1 - R1, img % w2 - R2))
+                img += 1
+                if img == nimg:
+                    img, jl = 0, jl + 1
+        assert got == seq
