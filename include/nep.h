@@ -459,9 +459,13 @@ int nep_get_tuning(const nep_handle *h, int32_t batch, int32_t out[7]);
  * later step); out[1] = chunks run again step by step because an atom left
  * the skin between two checks (the chunk restarts from its saved state, so
  * results stay those of rows within the skin); out[2] = row rebuilds of MD
- * runs with a skin.  Not from the paper: the paper does not describe how its
- * rows are maintained. */
-int nep_md_counters(const nep_handle *h, int64_t out[3]);
+ * runs with a skin; out[3] = runs with a skin that continued from the state
+ * the previous run left (no other call on the handle in between, the same
+ * box, atom count and buffers, and positions and species equal, bit for bit,
+ * to those that run returned: the atom order, rows and forces are then kept
+ * instead of being set up again).  NPT runs always set up anew.  Not from the
+ * paper: the paper does not describe how its rows are maintained. */
+int nep_md_counters(const nep_handle *h, int64_t out[4]);
 
 #ifdef __cplusplus
 }

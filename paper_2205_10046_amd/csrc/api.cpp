@@ -371,6 +371,14 @@ struct nep_handle {
   int64_t md_group_steps = 0;  // MD steps run in captured groups (one rebuild check each)
   int64_t md_replays = 0;      // MD chunks replayed because an atom left the skin mid-group
   int64_t md_rebuilds = 0;     // row rebuilds of MD runs with a skin
+  // continuation of an MD run: after a run with a skin ends, its internal
+  // state (order, rows, forces) is reused by the next run if no other call
+  // came in between, the geometry and buffers are the same and the caller's
+  // positions and species are those the run returned
+  std::atomic<uint64_t> api_calls{0};  // also counted by a server's worker
+  uint64_t md_cont_call = 0;   // api_calls at the end of the run that left the state
+  std::vector<unsigned char> md_cont_key;
+  int64_t md_continued = 0;    // runs that reused the previous run's state
   StageTimes times;
   std::vector<std::pair<const char*, std::pair<hipEvent_t, hipEvent_t>>> pending;
 
@@ -1063,7 +1071,12 @@ int fail(nep_handle* h, const Failure& f) {
   return f.code;
 }
 
-void set_device(nep_handle* h) { HIPCHK(hipSetDevice(h->device)); }
+// Every entry point starts here; the count tells an MD run whether any other
+// call has used the handle's buffers since the previous run ended.
+void set_device(nep_handle* h) {
+  HIPCHK(hipSetDevice(h->device));
+  ++h->api_calls;
+}
 
 void check_host_types(const nep_handle* h, int64_t N, const int32_t* types) {
   for (int64_t i = 0; i < N; ++i)
@@ -1318,6 +1331,7 @@ size_t request_bytes(const nep_handle* h, int64_t n, double density) {
 void server_tick(nep_server* sv) {
   nep_handle* h = sv->h;
   hipStream_t s = sv->stream;
+  ++h->api_calls;  // the tick uses the handle's buffers
   auto& act = sv->active;
   const int32_t S = (int32_t)act.size();
   int64_t N = 0;
@@ -2141,8 +2155,41 @@ int md_skin(nep_handle* h, const Prepared& pp, double* d_pos, double* d_vel, con
     HIPCHK(hipMemcpyAsync(est, h->pinned + 1024, sizeof init, hipMemcpyHostToDevice, s));
     if (npt) mu_cum = &est->mu_cum;
   }
+  // what the internal state depends on besides the caller's arrays
+  auto state_key = [&]() {
+    std::vector<unsigned char> k;
+    auto put = [&](const void* p, size_t n) {
+      const unsigned char* c = (const unsigned char*)p;
+      k.insert(k.end(), c, c + n);
+    };
+    const uint64_t gen = g_alloc_gen.load();
+    put(&gen, sizeof gen);
+    put(&N, sizeof N);
+    put(&rl, sizeof rl);
+    put(&pp.geo.st, sizeof pp.geo.st);
+    put(&pp.n_cells, sizeof pp.n_cells);
+    put(&pp.batch, sizeof pp.batch);
+    return k;
+  };
+  // continue from the previous run's state when nothing else used the handle
+  // since, the geometry and buffers are unchanged and the caller's positions
+  // and species are the ones that run returned (checked on the device)
+  bool cont = false;
+  if (!npt && h->md_cont_call + 1 == h->api_calls && h->md_cont_key == state_key()) {
+    int32_t* differs = h->flags + kFlagGuard;  // free until the chunks start
+    launch_fill_i32(differs, 1, 0, s);
+    launch_same_state(h->ext_id, N, h->pos, h->types, d_pos, d_types, differs, s);
+    const int32_t* fl = read_flags(h, s);
+    cont = fl[kFlagGuard] == 0;
+  }
+  h->md_cont_key.clear();
+  if (cont) {
+    // velocities into the internal order; order, rows and forces are kept
+    launch_permute_md(h->ext_id, N, d_pos, d_vel, h->pos2, h->vel, s);  // pos2 is scratch here
+    ++h->md_continued;
+  }
   // initial order from the caller arrays
-  {
+  if (!cont) {
     BuildArgs b0 = build_args(h, pp, d_pos, d_types, h->pos, h->types);
     launch_order_atoms(b0, s);
     launch_permute_md(h->perm, N, d_pos, d_vel, h->pos2, h->vel, s);
@@ -2151,7 +2198,7 @@ int md_skin(nep_handle* h, const Prepared& pp, double* d_pos, double* d_vel, con
     launch_check_types(h->types, N, h->M.T, h->flags + 3, s);
     launch_check_finite(h->pos, 3 * N, h->flags + 4, s);
   }
-  for (int attempt = 0;; ++attempt) {
+  for (int attempt = 0; !cont; ++attempt) {
     launch_fill_i32(h->flags, 3, 0, s);
     launch_fill_i32(h->flags + 5, 1, 0, s);
     skin_rebuild(h, pp, rl, nullptr, s, mu_cum);
@@ -2168,7 +2215,7 @@ int md_skin(nep_handle* h, const Prepared& pp, double* d_pos, double* d_vel, con
     }
     if (attempt == 3) throw Failure{NEP_E_NEIGHBOR_OVERFLOW, "neighbour rows kept overflowing"};
   }
-  forces(h, pp, s);
+  if (!cont) forces(h, pp, s);
   MDArgs md{};
   md.N = N;
   md.F = h->F;
@@ -2418,6 +2465,10 @@ int md_skin(nep_handle* h, const Prepared& pp, double* d_pos, double* d_vel, con
     }
     if (box_out) std::memcpy(box_out, ((const StructInfo*)(h->pinned + 1536))->H, 9 * sizeof(double));
   }
+  if (!npt) {
+    h->md_cont_key = state_key();
+    h->md_cont_call = h->api_calls.load();
+  }
   return NEP_OK;
 }
 
@@ -2477,9 +2528,13 @@ static int md_impl(nep_handle* h, int64_t N, double* d_pos, double* d_vel, const
   } else {
     pp = prepare(h, N, box, pbc, h->hp.rc_radial + h->hp.skin, true, s);
   }
-  if (n_rows > h->thermo_cap) {
-    dev_alloc(h->thermo, 16 * n_rows);
-    h->thermo_cap = n_rows;
+  // rows for 4096 reports at least, allocated by the first call even when it
+  // reports none: a later call of a few more rows then keeps the buffer (and
+  // with it the captured step group and the state it may continue from)
+  if (n_rows > h->thermo_cap || !h->thermo) {
+    const int64_t cap = std::max<int64_t>(n_rows, 4096);
+    dev_alloc(h->thermo, 16 * cap);
+    h->thermo_cap = cap;
   }
   double m[kMaxTypes] = {0}, im[kMaxTypes] = {0};
   for (int t = 0; t < h->hp.n_types; ++t) {
@@ -2738,11 +2793,12 @@ int nep_get_tuning(const nep_handle* h, int32_t batch, int32_t out[7]) {
   return NEP_OK;
 }
 
-int nep_md_counters(const nep_handle* h, int64_t out[3]) {
-  if (!h || !out) return fail(nullptr, {NEP_E_INVALID_ARG, "handle and out[3] are required"});
+int nep_md_counters(const nep_handle* h, int64_t out[4]) {
+  if (!h || !out) return fail(nullptr, {NEP_E_INVALID_ARG, "handle and out[4] are required"});
   out[0] = h->md_group_steps;
   out[1] = h->md_replays;
   out[2] = h->md_rebuilds;
+  out[3] = h->md_continued;
   return NEP_OK;
 }
 

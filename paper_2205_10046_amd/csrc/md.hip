@@ -127,6 +127,25 @@ void launch_permute_md(const int32_t* src, int64_t N, const double* src_pos,
                      src_vel, dst_pos, dst_vel);
 }
 
+// *differs = 1 unless, for every internal atom k, the caller's position and
+// species of atom ext[k] are those held internally (bit for bit).
+__global__ void k_same_state(const int32_t* __restrict__ ext, int64_t N, const double* __restrict__ pos_int,
+                             const int32_t* __restrict__ types_int, const double* __restrict__ pos_caller,
+                             const int32_t* __restrict__ types_caller, int32_t* __restrict__ differs) {
+  int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= N) return;
+  const int64_t e = ext[k];
+  bool same = types_int[k] == types_caller[e];
+  for (int c = 0; c < 3; ++c) same = same && pos_int[(int64_t)c * N + k] == pos_caller[(int64_t)c * N + e];
+  if (!same) atomicExch(differs, 1);
+}
+
+void launch_same_state(const int32_t* ext, int64_t N, const double* pos_int, const int32_t* types_int,
+                       const double* pos_caller, const int32_t* types_caller, int32_t* differs, hipStream_t s) {
+  hipLaunchKernelGGL(k_same_state, dim3(div_up(N, kBlock)), dim3(kBlock), 0, s, ext, N, pos_int, types_int,
+                     pos_caller, types_caller, differs);
+}
+
 // gated gathers used by a device-decided rebuild: out[k] = in[src[k]]
 __global__ void k_gather3_gated(const int32_t* __restrict__ src, int64_t N, const double* __restrict__ in,
                                 double* __restrict__ out, const int32_t* gate) {

@@ -168,6 +168,10 @@ void launch_thermo_counted(const float* U, const float* W, const double* vel, co
                            const double* mass, int64_t N, double* partial, int64_t n_part,
                            double* rows, int32_t* counter, double every, double kin_conv, double kB,
                            hipStream_t s);
+// *differs = 1 unless the caller's positions and species (caller order) are
+// the internal ones (internal atom k is caller atom ext[k]).
+void launch_same_state(const int32_t* ext, int64_t N, const double* pos_int, const int32_t* types_int,
+                       const double* pos_caller, const int32_t* types_caller, int32_t* differs, hipStream_t s);
 void launch_permute_md(const int32_t* perm_old_to_new_src, int64_t N, const double* src_pos,
                        const double* src_vel, double* dst_pos, double* dst_vel, hipStream_t s);
 void launch_unpermute_md(const int32_t* perm, int64_t N, const double* pos_int,

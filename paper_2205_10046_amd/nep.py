@@ -537,10 +537,12 @@ class Handle:
 
     def md_counters(self):
         """MD schedule counters (nep_md_counters): steps run in captured groups,
-        chunks replayed step by step and row rebuilds."""
-        out = np.zeros(3, np.int64)
+        chunks replayed step by step, row rebuilds and runs that continued
+        from the previous run's state."""
+        out = np.zeros(4, np.int64)
         self._check(load().nep_md_counters(self._h, _ptr(out, C.c_int64)))
-        return {"group_steps": int(out[0]), "replayed_chunks": int(out[1]), "rebuilds": int(out[2])}
+        return {"group_steps": int(out[0]), "replayed_chunks": int(out[1]), "rebuilds": int(out[2]),
+                "continued_runs": int(out[3])}
 
 
 class Server:

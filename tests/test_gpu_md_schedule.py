@@ -63,3 +63,39 @@ def test_grouped_rebuild_checks_match_rows_from_scratch(hot_cell, skin, lookahea
         assert cnt["group_steps"] > 0
     assert dp < 1e-6
     np.testing.assert_allclose(tha[:, 1:3], thb[:, 1:3], atol=1e-6 * pos.shape[1])
+
+
+def test_continued_runs_reuse_the_state_and_match_one_run(hot_cell):
+    """Ten calls of 20 steps, each fed the previous call's output, keep the
+    atom order, rows and forces of the call before (no set-up in between) and
+    give the trajectory of one 200-step call bit for bit; a call whose
+    positions differ from the returned ones, or that follows another call on
+    the handle, sets up anew."""
+    h, p, pos, vel, types, m, box = hot_cell
+    one = nep.Handle(h, p, skin=0.5)
+    p1, v1, th1 = one.md_run(pos, vel, types, m, box, 1.0, 200, 10)
+    one.close()
+    split = nep.Handle(h, p, skin=0.5)
+    pc, vc, rows = pos, vel, []
+    for _ in range(10):
+        pc, vc, th = split.md_run(pc, vc, types, m, box, 1.0, 20, 10)
+        rows.append(th)
+    cnt = split.md_counters()
+    log(f"[continue] split into 10 calls: {cnt}")
+    assert cnt["continued_runs"] == 9
+    assert np.array_equal(pc, p1) and np.array_equal(vc, v1)
+    assert np.array_equal(np.concatenate(rows)[:, 1:], th1[:, 1:])
+    # a moved atom: set up again, and the result is a fresh handle's
+    moved = pc.copy()
+    moved[0, 5] += 1e-3
+    pm, vm, _ = split.md_run(moved, vc, types, m, box, 1.0, 20, 10)
+    assert split.md_counters()["continued_runs"] == 9
+    fresh = nep.Handle(h, p, skin=0.5)
+    pf, vf, _ = fresh.md_run(moved, vc, types, m, box, 1.0, 20, 10)
+    fresh.close()
+    assert np.abs(pm - pf).max() < 1e-6
+    # another call in between: set up again
+    split.compute(pm, types, box)
+    split.md_run(pm, vm, types, m, box, 1.0, 20, 10)
+    assert split.md_counters()["continued_runs"] == 9
+    split.close()
