@@ -179,13 +179,29 @@ size_t eval_lds_bytes(const DevModel& M, int block) {
 // descriptor pass
 // ---------------------------------------------------------------------------
 
-template <int NG, int L, bool BATCH, int G>
+// Basis sizes the descriptor and force kernels can take as constants: shape 1 is n_R = K_R =
+// 9 and n_A = K_A = 7 (n_max 8/6 with N_bas 8/6); with them the basis loops
+// have fixed trip counts (no per-iteration exit test) and the same arithmetic
+// in the same order, so the results are the same bits as with shape 0, which
+// reads the sizes from the model.
+template <int S> struct BasisShape {
+  static constexpr int nR = 0, KR = 0, nA = 0, KA = 0;
+};
+template <> struct BasisShape<1> {
+  static constexpr int nR = 9, KR = 9, nA = 7, KA = 7;
+};
+
+
+template <int NG, int L, bool BATCH, int G, int SH = 0>
 __global__ void __launch_bounds__(kBlock, 2) k_descriptor(EvalArgs a, StructInfo st0) {
   constexpr int NB = num_poly(L);
   extern __shared__ float4 lds_v4[];  // 16-byte aligned base
   float* lds = reinterpret_cast<float*>(lds_v4);
   const DevModel& M = a.M;
-  const int T = M.T, KR = M.KR, KA = M.KA, nR = M.nR, nA = M.nA;
+  using Sh = BasisShape<SH>;
+  const int T = M.T;
+  const int KR = SH ? Sh::KR : M.KR, KA = SH ? Sh::KA : M.KA, nR = SH ? Sh::nR : M.nR, nA = SH ? Sh::nA : M.nA;
+  const int ngroups = SH ? (Sh::nA + NG - 1) / NG : a.ngroups;
   constexpr int W = ng_pad(NG);
   float* sR = lds;
   float* sA = sR + radial_table_floats(M);
@@ -248,7 +264,7 @@ __global__ void __launch_bounds__(kBlock, 2) k_descriptor(EvalArgs a, StructInfo
   // ---- angular: S_{n,k} = sum_j g_n(r_ij) b_k(u_ij), NG radial functions at a time ----
   const float rcA = M.rcA;
   const int nnA = min(a.L.nnA[i], a.L.MR);
-  for (int g = 0; g < a.ngroups; ++g) {
+  for (int g = 0; g < ngroups; ++g) {
     float S[NG][NB];
 #pragma unroll
     for (int q = 0; q < NG; ++q)
@@ -338,18 +354,6 @@ __global__ void __launch_bounds__(kBlock, 2) k_descriptor(EvalArgs a, StructInfo
 
 // Large accumulator blocks (NG x NB > 120 floats) run at one wave per SIMD so
 // the compiler can keep the D block in registers instead of spilling.
-// Basis sizes the force kernel can take as constants: shape 1 is n_R = K_R =
-// 9 and n_A = K_A = 7 (n_max 8/6 with N_bas 8/6); with them the basis loops
-// have fixed trip counts (no per-iteration exit test) and the same arithmetic
-// in the same order, so the results are the same bits as with shape 0, which
-// reads the sizes from the model.
-template <int S> struct BasisShape {
-  static constexpr int nR = 0, KR = 0, nA = 0, KA = 0;
-};
-template <> struct BasisShape<1> {
-  static constexpr int nR = 9, KR = 9, nA = 7, KA = 7;
-};
-
 template <int NG, int L, bool BATCH, int G, int S = 0>
 __global__ void __launch_bounds__(kBlock, (NG * num_poly(L) > 120) ? 1 : 2)
     k_partial_forces(EvalArgs a, StructInfo st0) {
@@ -694,14 +698,14 @@ static bool launch_pair_g(const EvalArgs& a, const StructInfo& st0, bool force, 
   if (force)
     hipLaunchKernelGGL((k_partial_forces<NG, L, BATCH, G, S>), grid, dim3(block), lds, s, a, st0);
   else
-    hipLaunchKernelGGL((k_descriptor<NG, L, BATCH, G>), grid, dim3(block), lds, s, a, st0);
+    hipLaunchKernelGGL((k_descriptor<NG, L, BATCH, G, S>), grid, dim3(block), lds, s, a, st0);
   return true;
 }
 
 template <int NG, int L, bool BATCH>
 static bool launch_pair(const EvalArgs& a, const StructInfo& st0, bool force, hipStream_t s) {
   const DevModel& M = a.M;
-  const bool shape1 = force && M.nR == BasisShape<1>::nR && M.KR == BasisShape<1>::KR &&
+  const bool shape1 = M.nR == BasisShape<1>::nR && M.KR == BasisShape<1>::KR &&
                       M.nA == BasisShape<1>::nA && M.KA == BasisShape<1>::KA;
   if (shape1) {
     if (a.lanes == 4) return launch_pair_g<NG, L, BATCH, 4, 1>(a, st0, force, s);
