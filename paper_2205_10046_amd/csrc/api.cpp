@@ -1036,7 +1036,7 @@ void autotune(nep_handle* h, const Prepared& pp, hipStream_t s) {
 // Descriptors, network, partial forces and the force gather; the per-atom
 // virial only when `virial` (MD steps without a thermo row skip it).
 void forces(nep_handle* h, const Prepared& pp, hipStream_t s, const DevModel* model = nullptr,
-            bool virial = true) {
+            bool virial = true, const MDArgs* kick = nullptr) {
   autotune(h, pp, s);
   const Tuning& t = h->tune[pp.batch ? 1 : 0];
   EvalArgs a = eval_args(h, pp, model ? *model : h->M);
@@ -1057,6 +1057,11 @@ void forces(nep_handle* h, const Prepared& pp, hipStream_t s, const DevModel* mo
   {
     Stage st(h, "gather", s);
     a.lanes = t.lanes_gather;
+    if (kick) {  // the second half kick of a velocity-Verlet step
+      a.kick_vel = kick->vel;
+      a.kick_inv_mass = kick->inv_mass;
+      a.kick_dt = kick->dt;
+    }
     launch_gather_forces(a, virial, s);
   }
 }
@@ -2245,29 +2250,29 @@ int md_skin(nep_handle* h, const Prepared& pp, double* d_pos, double* d_vel, con
     }
     {
       Stage st(h, "integrate", cs);
-      launch_kick_drift(md, cs);
-    }
-    {
-      Stage st(h, "order_atoms", cs);
-      if (chain) {
-        launch_fill_i32(gate, 1, 0, cs);
-        launch_check_displacement(h->pos, h->pos_ref, h->vel, N, thr2, ahead, gate, cs, mu_cum,
-                                  h->hp.rc_radial, rl);
-        skin_rebuild(h, pp, rl, gate, cs, mu_cum);
-      } else {
-        launch_check_displacement(h->pos, h->pos_ref, nullptr, N, thr2, 0.0, h->flags + kFlagGuard, cs,
-                                  mu_cum, h->hp.rc_radial, rl);
+      MDArgs drift = md;
+      if (!chain) {  // the skin guard, on the new positions
+        drift.ref = h->pos_ref;
+        drift.flag = h->flags + kFlagGuard;
+        drift.thr2 = thr2;
+        drift.mu_cum = mu_cum;
+        drift.rc = h->hp.rc_radial;
+        drift.rl = rl;
       }
+      launch_kick_drift(drift, cs);
+    }
+    if (chain) {
+      Stage st(h, "order_atoms", cs);
+      launch_fill_i32(gate, 1, 0, cs);
+      launch_check_displacement(h->pos, h->pos_ref, h->vel, N, thr2, ahead, gate, cs, mu_cum,
+                                h->hp.rc_radial, rl);
+      skin_rebuild(h, pp, rl, gate, cs, mu_cum);
     }
     {
       Stage st(h, "neighbor_rows", cs);
       skin_filter(h, pp, cs);
     }
-    forces(h, pp, cs, nullptr, virial || npt);
-    {
-      Stage st(h, "integrate", cs);
-      launch_kick(md, cs);
-    }
+    forces(h, pp, cs, nullptr, virial || npt, &md);  // the gather applies the second half kick
     if (ens) {
       Stage st(h, "ensemble", cs);
       launch_ens_kinetic(h->vel, h->types, h->mass, N, kAmuA2fs2, h->ens_partial, est, cs);

@@ -641,7 +641,10 @@ __global__ void __launch_bounds__(kBlock) k_gather(EvalArgs a, StructInfo st0) {
 #pragma unroll
   for (int c = 0; c < 3; ++c) {
     const float v = group_sum<G>(F[c]);
-    if (c % G == sub) a.F[(int64_t)c * N + i] = v;
+    if (c % G == sub) {
+      a.F[(int64_t)c * N + i] = v;
+      if (a.kick_vel) a.kick_vel[(int64_t)c * N + i] += 0.5 * a.kick_dt * a.kick_inv_mass[a.types[i]] * (double)v;
+    }
   }
   if constexpr (VIRIAL) {
 #pragma unroll

@@ -10,11 +10,26 @@ __global__ void k_kick_drift(MDArgs a) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= a.N) return;
   const double s = 0.5 * a.dt * a.inv_mass[a.types[i]];
+  double r[3];
   for (int c = 0; c < 3; ++c) {
     const int64_t k = (int64_t)c * a.N + i;
     const double v = a.vel[k] + s * (double)a.F[k];
     a.vel[k] = v;
-    a.pos[k] += a.dt * v;
+    r[c] = a.pos[k] + a.dt * v;
+    a.pos[k] = r[c];
+  }
+  if (a.flag) {
+    // the skin guard on the new position (the test of k_check_displacement
+    // without look-ahead)
+    double m = 1.0, t2 = a.thr2;
+    if (a.mu_cum) {
+      m = *a.mu_cum;
+      const double h = fmax(0.0, 0.5 * (m * a.rl - a.rc));
+      t2 = h * h;
+    }
+    const int64_t N = a.N;
+    const double dx = r[0] - m * a.ref[i], dy = r[1] - m * a.ref[N + i], dz = r[2] - m * a.ref[2 * N + i];
+    if (dx * dx + dy * dy + dz * dz > t2) atomicExch(a.flag, 1);
   }
 }
 

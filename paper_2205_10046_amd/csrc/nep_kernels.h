@@ -50,6 +50,11 @@ struct EvalArgs {
   float* F;                   // [3][N] internal
   float* W;                   // [9][N] internal
   float* latent;              // [N][N_neu] w1_mu h_mu of every atom, or NULL
+  // optional second half kick fused into the force gather (kick_vel != NULL):
+  // v += dt/2 F / m with the float32 force just written, as a separate kick would
+  double* kick_vel;
+  const double* kick_inv_mass;
+  double kick_dt;
   const int32_t* rows;        // network row order, [rows_len]
   int64_t rows_len;
   int32_t ngroups;            // angular radial-function groups
@@ -158,6 +163,14 @@ struct MDArgs {
   const int32_t* types;
   const double* inv_mass;     // [T] 1 / (m * amu(A/fs)^2 in eV)
   double dt;
+  // optional skin guard fused into the drift (flag != NULL): *flag = 1 when
+  // an atom's new position is more than sqrt(thr2) from ref (with a box
+  // scaled by *mu_cum since the build: the bound of k_check_displacement)
+  const double* ref = nullptr;
+  int32_t* flag = nullptr;
+  double thr2 = 0.0;
+  const double* mu_cum = nullptr;
+  double rc = 0.0, rl = 0.0;
 };
 void launch_kick_drift(const MDArgs& a, hipStream_t s);
 void launch_kick(const MDArgs& a, hipStream_t s);
