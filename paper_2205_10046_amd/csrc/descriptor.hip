@@ -192,6 +192,9 @@ template <> struct BasisShape<1> {
 };
 
 
+// species whose radial sums the descriptor kernel can keep in registers
+constexpr int kRegTypes = 4;
+
 template <int NG, int L, bool BATCH, int G, int SH = 0>
 __global__ void __launch_bounds__(kBlock, 2) k_descriptor(EvalArgs a, StructInfo st0) {
   constexpr int NB = num_poly(L);
@@ -224,39 +227,77 @@ __global__ void __launch_bounds__(kBlock, 2) k_descriptor(EvalArgs a, StructInfo
   // ---- radial: F_{t,k} = sum_{j of species t} f_k(r_ij) ----
   const float rcR = M.rcR;
   const int nnR = min(a.L.nnR[i], a.L.MR);
-  for_entries(a, st, i, sub, nnR, G,
-              [&](int m, int64_t e, int32_t j, int32_t tj, float fx, float fy, float fz)
-                  __attribute__((always_inline)) {
-    const float r = sqrtf(fx * fx + fy * fy + fz * fz);
-    const Basis bs = make_basis(r, rcR);
-    float* slot = acc + (tj * KR) * B + tid;
-    slot[0] += bs.fc;
-    float Tm1 = 1.f, Tk = bs.x;
-#pragma unroll
-    for (int k = 1; k < kMaxBasis; ++k) {
-      if (k >= KR) break;
-      slot[k * B] += 0.5f * (Tk + 1.f) * bs.fc;
-      const float Tn = 2.f * bs.x * Tk - Tm1;
-      Tm1 = Tk;
-      Tk = Tn;
-    }
-  });
-  if constexpr (G > 1)
-    for (int k = 0; k < T * KR; ++k) acc[k * B + tid] = group_sum<G>(acc[k * B + tid]);
   // q_n = sum_t sum_k c^{t_i t}_{nk} F_{t,k}: each F read once, all n in registers
   float qr[kMaxBasis];
 #pragma unroll
   for (int n = 0; n < kMaxBasis; ++n) qr[n] = 0.f;
-  for (int t = 0; t < T; ++t)
-    for (int k = 0; k < KR; ++k) {
-      const float F = acc[(t * KR + k) * B + tid];
-      const float* c = sR + (ti * T + t) * nR * KR + k;
+  auto contract = [&](int t, int k, float F) __attribute__((always_inline)) {
+    const float* c = sR + (ti * T + t) * nR * KR + k;
 #pragma unroll
-      for (int n = 0; n < kMaxBasis; ++n) {
-        if (n >= nR) break;
-        qr[n] += c[n * KR] * F;
-      }
+    for (int n = 0; n < kMaxBasis; ++n) {
+      if (n >= nR) break;
+      qr[n] += c[n * KR] * F;
     }
+  };
+  if (SH != 0 && T <= kRegTypes) {
+    // fixed basis size and at most four species: the sums F_{t,k} in
+    // registers (an entry adds to its species' row and zero to the others,
+    // the same sums in the same order as the LDS slots)
+    constexpr int KRc = SH ? Sh::KR : 1;
+    float ar[kRegTypes][KRc];
+#pragma unroll
+    for (int t = 0; t < kRegTypes; ++t)
+#pragma unroll
+      for (int k = 0; k < KRc; ++k) ar[t][k] = 0.f;
+    for_entries(a, st, i, sub, nnR, G,
+                [&](int m, int64_t e, int32_t j, int32_t tj, float fx, float fy, float fz)
+                    __attribute__((always_inline)) {
+      const float r = sqrtf(fx * fx + fy * fy + fz * fz);
+      const Basis bs = make_basis(r, rcR);
+      float v[KRc];
+      v[0] = bs.fc;
+      float Tm1 = 1.f, Tk = bs.x;
+#pragma unroll
+      for (int k = 1; k < KRc; ++k) {
+        v[k] = 0.5f * (Tk + 1.f) * bs.fc;
+        const float Tn = 2.f * bs.x * Tk - Tm1;
+        Tm1 = Tk;
+        Tk = Tn;
+      }
+#pragma unroll
+      for (int t = 0; t < kRegTypes; ++t)
+#pragma unroll
+        for (int k = 0; k < KRc; ++k) ar[t][k] += tj == t ? v[k] : 0.f;
+    });
+#pragma unroll
+    for (int t = 0; t < kRegTypes; ++t) {
+      if (t >= T) break;
+#pragma unroll
+      for (int k = 0; k < KRc; ++k) contract(t, k, group_sum<G>(ar[t][k]));
+    }
+  } else {
+    for_entries(a, st, i, sub, nnR, G,
+                [&](int m, int64_t e, int32_t j, int32_t tj, float fx, float fy, float fz)
+                    __attribute__((always_inline)) {
+      const float r = sqrtf(fx * fx + fy * fy + fz * fz);
+      const Basis bs = make_basis(r, rcR);
+      float* slot = acc + (tj * KR) * B + tid;
+      slot[0] += bs.fc;
+      float Tm1 = 1.f, Tk = bs.x;
+#pragma unroll
+      for (int k = 1; k < kMaxBasis; ++k) {
+        if (k >= KR) break;
+        slot[k * B] += 0.5f * (Tk + 1.f) * bs.fc;
+        const float Tn = 2.f * bs.x * Tk - Tm1;
+        Tm1 = Tk;
+        Tk = Tn;
+      }
+    });
+    if constexpr (G > 1)
+      for (int k = 0; k < T * KR; ++k) acc[k * B + tid] = group_sum<G>(acc[k * B + tid]);
+    for (int t = 0; t < T; ++t)
+      for (int k = 0; k < KR; ++k) contract(t, k, acc[(t * KR + k) * B + tid]);
+  }
 #pragma unroll
   for (int n = 0; n < kMaxBasis; ++n)
     if (n < nR && n % G == sub) qrow[n] = qr[n];
