@@ -608,21 +608,11 @@ void launch_build_verlet(const BuildArgs& b, const Lists& V, hipStream_t s) {
 // then the positions (pass 1) or the row words (pass 2), so a lane has a
 // chunk's loads in flight at once instead of one dependent chain per
 // candidate.  Pass 1 classifies, counts the members and keeps the classes in
-// register bit masks; pass 2 goes through the candidates in order, and quad
-// DPP prefix sums of the class flags give each member its exact position.
+// register bit masks; pass 2 goes through the candidates in order, and
+// counts over wave ballots of the class flags give each member its exact position.
 // The rows are the same as those of a single sequential pass.
 constexpr int kFilterLanes = 4;
 constexpr int kFilterChunk = 4;
-
-// Value of v held by lane l of this lane's quad.
-__device__ __forceinline__ int32_t quad_lane(int32_t v, int l) {
-  switch (l) {
-    case 0: return __builtin_amdgcn_mov_dpp(v, 0x00, 0xF, 0xF, false);
-    case 1: return __builtin_amdgcn_mov_dpp(v, 0x55, 0xF, 0xF, false);
-    case 2: return __builtin_amdgcn_mov_dpp(v, 0xAA, 0xF, 0xF, false);
-    default: return __builtin_amdgcn_mov_dpp(v, 0xFF, 0xF, 0xF, false);
-  }
-}
 
 template <bool BATCH>
 __global__ void __launch_bounds__(kBlock) k_filter_rows(const double* __restrict__ pos, int64_t N,
@@ -711,14 +701,17 @@ __global__ void __launch_bounds__(kBlock) k_filter_rows(const double* __restrict
       }
     }
   }
-  int32_t a_all = 0, o_all = 0;
+  int32_t a_all = na, o_all = no;
 #pragma unroll
-  for (int l = 0; l < G; ++l) {
-    a_all += quad_lane(na, l);
-    o_all += quad_lane(no, l);
+  for (int off = 1; off < G; off <<= 1) {
+    a_all += __shfl_xor(a_all, off);
+    o_all += __shfl_xor(o_all, off);
   }
-  // pass 2: candidate m = 4 t + s is lane s's t-th; every lane of the quad
-  // runs every step, so the quad is whole at each prefix sum
+  // pass 2: candidate m = G t + s is lane s's t-th; every lane of the atom's
+  // group runs every step, so the group's ballot bits are whole at each step
+  const int lane = threadIdx.x & 63;
+  const uint64_t gmask = (G == 64 ? ~0ull : ((1ull << G) - 1)) << (lane & ~(G - 1));
+  const uint64_t below = (1ull << lane) - 1;
   int32_t pa = 0, po = a_all;  // next angular / outer position
   for (int t0 = 0; t0 < steps; t0 += U) {
     int32_t c[U], jn[U], rn[U];
@@ -746,17 +739,9 @@ __global__ void __launch_bounds__(kBlock) k_filter_rows(const double* __restrict
       const int m = (t0 + u) * G + sub;
       const int64_t e = (int64_t)m * N + i;
       const int32_t fa = c[u] == kAngular, fo = c[u] == kOuter;
-      int32_t ba = 0, bo = 0, ta = 0, to = 0;
-#pragma unroll
-      for (int l = 0; l < G; ++l) {
-        const int32_t al = quad_lane(fa, l), ol = quad_lane(fo, l);
-        ta += al;
-        to += ol;
-        if (l < sub) {
-          ba += al;
-          bo += ol;
-        }
-      }
+      const uint64_t ma = __ballot(fa) & gmask, mo = __ballot(fo) & gmask;
+      const int32_t ta = __popcll(ma), to = __popcll(mo);
+      const int32_t ba = __popcll(ma & below), bo = __popcll(mo & below);
       if (m < nv && !(fa | fo)) fmap[e] = -1;
       if (fa | fo) {
         const int32_t p = fa ? pa + ba : po + bo;
