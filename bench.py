@@ -46,13 +46,18 @@ def measured_traffic(kernel):
         digest = hashlib.sha256()
         for f in rec["sources"]:
             digest.update(open(os.path.join(here, f), "rb").read())
-        v = rec["variants"][kernel]
+        # the profiled name may carry one more template argument (the basis
+        # shape the library specialised the kernel for)
+        names = [k for k in rec["variants"] if k == kernel or k.startswith(kernel[:-1] + ", ")]
+        if len(names) != 1:
+            return None
+        v = rec["variants"][names[0]]
     except (OSError, KeyError, ValueError):
         return None
     if digest.hexdigest() != rec["sources_sha256"]:
         return None
     return {"bytes": v["fetch_bytes"] + v["write_bytes"], "fetch_bytes": v["fetch_bytes"],
-            "write_bytes": v["write_bytes"], "kernel": kernel, "dispatches": v["dispatches"]}
+            "write_bytes": v["write_bytes"], "kernel": names[0], "dispatches": v["dispatches"]}
 
 
 def algorithmic_flops(h, p_r, p_a):
@@ -452,7 +457,7 @@ def main():
         "roofline": {"bound": "alu", "kernel": dom, "achieved": achieved,
                      "peak": PEAK_FP32_VALU, "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_VALU,
                      "traffic": (tr or {}).get("bytes"), "traffic_unit": "bytes per launch",
-                     "traffic_detail": tr, "variant": force_kernel, "tuning": tune,
+                     "traffic_detail": tr, "variant": tr["kernel"] if tr else force_kernel, "tuning": tune,
                      "flop_per_atom": fl[dom], "avg_launch_ms": avg[dom]},
         "mlp_roofline": {"bound": "mfma", "achieved": mlp_t, "peak": PEAK_FP32_MFMA,
                          "unit": "TFLOP/s", "frac": mlp_t / PEAK_FP32_MFMA,
