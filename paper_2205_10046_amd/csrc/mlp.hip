@@ -236,12 +236,18 @@ constexpr size_t kMlpMaxLds = 160 * 1024;  // LDS a gfx950 block may hold
 
 __host__ __device__ inline int nd_pad16(int nd) { return (nd + 15) / 16 * 16; }
 
-size_t mlp_lds_bytes(const DevModel& M, bool bf16) {
+// Bytes of the staged weights w0 and w0^T (b0 and w1 follow, 2 N_neu floats).
+__host__ __device__ inline size_t mlp_weight_bytes(const DevModel& M, bool bf16) {
   if (!bf16) {
     const size_t K = (size_t)nd_pad16(M.ND);
     return ((size_t)M.NNp * (K + 4) + K * (M.NNp + 4)) * sizeof(float);
   }
-  return ((size_t)M.NNp * (M.NDp32 + 8) + (size_t)M.NDp32 * (M.NNp + 8)) * sizeof(uint16_t);
+  const size_t b = ((size_t)M.NNp * (M.NDp32 + 8) + (size_t)M.NDp32 * (M.NNp + 8)) * sizeof(uint16_t);
+  return (b + 15) / 16 * 16;
+}
+
+size_t mlp_lds_bytes(const DevModel& M, bool bf16) {
+  return mlp_weight_bytes(M, bf16) + 2 * (size_t)M.NNp * sizeof(float);
 }
 
 namespace {
@@ -282,6 +288,10 @@ __device__ __forceinline__ void load_q(const EvalArgs& a, int atom, int grp, int
 template <bool BF16>
 __device__ __forceinline__ void stage_weights(const DevModel& M, int net, int tid, float4* lds) {
   const int ND = M.ND, NNp = M.NNp, NDp32 = M.NDp32, K16 = nd_pad16(ND);
+  {  // b0 and w1 of the species after the weights
+    float* bw = reinterpret_cast<float*>(reinterpret_cast<char*>(lds) + mlp_weight_bytes(M, BF16));
+    for (int k = tid; k < 2 * NNp; k += 256) bw[k] = k < NNp ? M.b0[net * NNp + k] : M.w1[net * NNp + k - NNp];
+  }
   if constexpr (!BF16) {
     float* sw = reinterpret_cast<float*>(lds);
     const int SW = K16 + 4, ST = NNp + 4;
@@ -372,6 +382,8 @@ __global__ void __launch_bounds__(256) k_mlp_lds(EvalArgs a, int32_t groups_per_
   const int SW = K16 + 4, ST = NNp + 4;
   const int SWB = NDp32 + 8, STB = NNp + 8;
   const float* st = sw + NNp * SW;
+  const float* sbw = reinterpret_cast<const float*>(reinterpret_cast<const char*>(mlp_lds) +
+                                                    mlp_weight_bytes(M, BF16));
   const uint16_t* swb = hw;
   const uint16_t* swtb = swb + NNp * SWB;
   float qn[kMlpQ];
@@ -396,18 +408,6 @@ __global__ void __launch_bounds__(256) k_mlp_lds(EvalArgs a, int32_t groups_per_
     int out_atom[4];
 #pragma unroll
     for (int r = 0; r < 4; ++r) out_atom[r] = a.rows[base + r0 + 4 * grp + r];
-    float b0v[NNB][4], w1v[NNB][4];
-    {
-      const float* __restrict__ b0 = M.b0 + net * NNp;
-      const float* __restrict__ w1 = M.w1 + net * NNp;
-#pragma unroll
-      for (int nb = 0; nb < NNB; ++nb)
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          b0v[nb][r] = b0[16 * nb + 4 * grp + r];
-          w1v[nb][r] = w1[16 * nb + 4 * grp + r];
-        }
-    }
 
     // ---- GEMM 1: acc[nb][r] = sum_k w0[16 nb + 4 grp + r][k] q[atom col][k] ----
     v4f acc[NNB];
@@ -450,16 +450,20 @@ __global__ void __launch_bounds__(256) k_mlp_lds(EvalArgs a, int32_t groups_per_
     float g[NNB][4];
     float* __restrict__ lat = (a.latent && atom >= 0) ? a.latent + (int64_t)atom * M.NN : nullptr;
 #pragma unroll
-    for (int nb = 0; nb < NNB; ++nb)
+    for (int nb = 0; nb < NNB; ++nb) {
+      const float4 b4 = *reinterpret_cast<const float4*>(sbw + 16 * nb + 4 * grp);
+      const float4 w4 = *reinterpret_cast<const float4*>(sbw + NNp + 16 * nb + 4 * grp);
+      const float b0v[4] = {b4.x, b4.y, b4.z, b4.w}, w1v[4] = {w4.x, w4.y, w4.z, w4.w};
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int mu = 16 * nb + 4 * grp + r;
-        const float h = tanh_net(acc[nb][r] - b0v[nb][r]);
-        const float wh = w1v[nb][r] * h;
+        const float h = tanh_net(acc[nb][r] - b0v[r]);
+        const float wh = w1v[r] * h;
         u += wh;
-        g[nb][r] = w1v[nb][r] * (1.f - h * h);
+        g[nb][r] = w1v[r] * (1.f - h * h);
         if (lat && mu < M.NN) lat[mu] = wh;
       }
+    }
     u += __shfl_xor(u, 16);
     u += __shfl_xor(u, 32);
     if (grp == 0 && atom >= 0) a.U[atom] = u - *M.b1;

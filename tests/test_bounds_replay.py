@@ -263,8 +263,11 @@ def test_network_tiles_in_bounds(workload):
     SW, ST = K16 + 4, NNp + 4
     SWB, STB = NDp32 + 8, NNp + 8
     assert SW % 4 == 0 and ST % 4 == 0 and SWB % 8 == 0 and STB % 8 == 0   # 16-byte LDS words
-    use32 = 4 * (NNp * SW + K16 * ST) <= 160 * 1024 and KS <= 24      # LDS of a gfx950 block
-    use16 = 2 * (NNp * SWB + NDp32 * STB) <= 160 * 1024 and NDp32 <= 96
+    # b0 and w1 (2 N_neu floats) follow the staged weights, 16-byte aligned
+    W32 = NNp * SW + K16 * ST                                          # float index
+    W16h = (2 * (NNp * SWB + NDp32 * STB) + 15) // 16 * 16 // 2        # half index
+    use32 = 4 * (W32 + 2 * NNp) <= 160 * 1024 and KS <= 24             # LDS of a gfx950 block
+    use16 = 2 * W16h + 8 * NNp <= 160 * 1024 and NDp32 <= 96
     assert use32 and use16               # every benchmark model runs the LDS kernel
     if not (use32 or use16):
         pytest.skip("the launcher takes the global-memory kernel for this model")
@@ -281,7 +284,7 @@ def test_network_tiles_in_bounds(workload):
         nets = T
         sizes = dict(q=N * NDp, fp=N * NDp, w0=nets * NNp * nd, w0t=nets * nd * NNp,
                      w0b=nets * NNp * NDp32, w0tb=nets * NDp32 * NNp, rows=rows_len,
-                     lds32=NNp * SW + K16 * ST, lds16=NNp * SWB + NDp32 * STB)
+                     b0=nets * NNp, w1=nets * NNp, lds32=W32 + 2 * NNp, lds16=W16h + 4 * NNp)
         hi = {k: -1 for k in sizes}
 
         def touch(k, v):
@@ -310,6 +313,10 @@ def test_network_tiles_in_bounds(workload):
                 touch("lds32", (k // pad) * SW + nd + k % pad)
             for k in range(pad * NNp):
                 touch("lds32", NNp * SW + (nd + k // NNp) * ST + k % NNp)
+            for k in range(2 * NNp):
+                touch("b0" if k < NNp else "w1", net * NNp + k % NNp)
+                touch("lds32", W32 + k)
+                touch("lds16", W16h + 2 * k + 1)
             c8, t8 = NDp32 // 8, NNp // 8
             n1 = NNp * c8
             for k in range(n1 + NDp32 * t8):
@@ -338,6 +345,9 @@ def test_network_tiles_in_bounds(workload):
                         if 32 * s_ < NDp32 and atom >= 0 and d0 < NDp:
                             touch("q", atom * NDp + d0 + 7)
                     for nb in range(NNp // 16):
+                        for off in (0, NNp):             # b0 and w1 of the activation
+                            touch("lds32", W32 + off + 16 * nb + 4 * grp + 3)
+                            touch("lds16", W16h + 2 * (off + 16 * nb + 4 * grp + 3) + 1)
                         for v in range(KS // 4):
                             touch("lds32", (16 * nb + col) * SW + KS * grp + 4 * v + 3)
                         for s_ in range(NDp32 // 32):
