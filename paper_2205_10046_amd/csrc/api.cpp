@@ -366,6 +366,11 @@ struct nep_handle {
   // pinned host staging for small stream-ordered copies:
   // [0, 256) structure table, [256, 384) masses, [384, 416) flags
   unsigned char* pinned = nullptr;
+  // structure tables of batch calls: pinned staging for an asynchronous
+  // upload, rewritten only after the previous upload (tab_event) has read it
+  unsigned char* pinned_tab = nullptr;
+  size_t pinned_tab_cap = 0;
+  hipEvent_t tab_event = nullptr;
   // timing
   bool timing = false;
   int64_t md_group_steps = 0;  // MD steps run in captured groups (one rebuild check each)
@@ -409,6 +414,12 @@ struct nep_handle {
     md_stream = nullptr;
     if (pinned) (void)hipHostFree(pinned);
     pinned = nullptr;
+    if (tab_event) (void)hipEventSynchronize(tab_event);
+    if (pinned_tab) (void)hipHostFree(pinned_tab);
+    pinned_tab = nullptr;
+    pinned_tab_cap = 0;
+    if (tab_event) (void)hipEventDestroy(tab_event);
+    tab_event = nullptr;
     dev_free(loss_part); dev_free(loss_offs); dev_free(snes_util); dev_free(heat_part);
     dev_free(ens_state); dev_free(ens_partial);
     ens_partial_cap = 0;
@@ -855,10 +866,24 @@ Prepared prepare_batch(nep_handle* h, int32_t S, const int64_t* offs, const doub
     HIPCHK(hipMemcpyAsync(h->structs, h->pinned, sizeof(StructInfo), hipMemcpyHostToDevice, s));
     launch_fill_i32(h->sid_ext, N, 0, s);
   } else {
-    // larger tables go through a synchronous copy (the call synchronises later anyway)
-    HIPCHK(hipStreamSynchronize(s));
-    HIPCHK(hipMemcpy(h->structs, pp.sts.data(), S * sizeof(StructInfo), hipMemcpyHostToDevice));
-    HIPCHK(hipMemcpy(h->offs, offs, (S + 1) * sizeof(int64_t), hipMemcpyHostToDevice));
+    // the structure table and offsets go up from pinned staging in stream order
+    const size_t nb = (size_t)S * sizeof(StructInfo), need = nb + (size_t)(S + 1) * sizeof(int64_t);
+    if (h->tab_event) HIPCHK(hipEventSynchronize(h->tab_event));  // the last upload has read it
+    if (need > h->pinned_tab_cap) {
+      if (h->pinned_tab) HIPCHK(hipHostFree(h->pinned_tab));
+      h->pinned_tab = nullptr;
+      h->pinned_tab_cap = 0;
+      const size_t cap = std::max<size_t>(need + need / 2, 1 << 14);
+      HIPCHK(hipHostMalloc((void**)&h->pinned_tab, cap, hipHostMallocDefault));
+      h->pinned_tab_cap = cap;
+    }
+    std::memcpy(h->pinned_tab, pp.sts.data(), nb);
+    std::memcpy(h->pinned_tab + nb, offs, (size_t)(S + 1) * sizeof(int64_t));
+    HIPCHK(hipMemcpyAsync(h->structs, h->pinned_tab, nb, hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(h->offs, h->pinned_tab + nb, (size_t)(S + 1) * sizeof(int64_t),
+                          hipMemcpyHostToDevice, s));
+    if (!h->tab_event) HIPCHK(hipEventCreateWithFlags(&h->tab_event, hipEventDisableTiming));
+    HIPCHK(hipEventRecord(h->tab_event, s));
     launch_assign_struct(h->offs, S, N, h->sid_ext, s);
   }
   return pp;
@@ -1309,6 +1334,24 @@ struct nep_server {
   uint64_t next_ticket = 1;
   hipStream_t stream = nullptr;
   BatchState st, st2;
+  // a tick's uploads (placement table + admitted requests' data) and the
+  // finished requests' results: pinned host and device staging, one copy
+  // each way per tick
+  unsigned char* up_host = nullptr;
+  unsigned char* up_dev = nullptr;
+  size_t up_cap = 0;
+  double* out_host = nullptr;
+  double* out_dev = nullptr;
+  size_t out_cap = 0;  // doubles
+  void release_staging() {
+    if (up_host) (void)hipHostFree(up_host);
+    if (out_host) (void)hipHostFree(out_host);
+    dev_free(up_dev);
+    dev_free(out_dev);
+    up_host = nullptr;
+    out_host = nullptr;
+    up_cap = out_cap = 0;
+  }
   size_t bytes_active = 0;
   // statistics
   std::vector<double> latencies;
@@ -1356,46 +1399,68 @@ void server_tick(nep_server* sv) {
     BatchState& nx = sv->st2;
     nx.ensure(N, S);
     nx.ld = N;
-    int64_t o = 0;
+    // one upload: the placement table {dst, n, src, stg} per request, then the
+    // admitted requests' pos [3][ns], vel [3][ns], hdm [ns], dta [ns], types [ns]
+    int64_t ns = 0, max_n = 0;
+    for (auto& r : act) {
+      if (r->t_admit == 0) ns += r->n;
+      max_n = std::max(max_n, r->n);
+    }
+    const size_t tab_bytes = 4 * (size_t)S * sizeof(int64_t);
+    const size_t need = tab_bytes + (size_t)ns * (8 * sizeof(double) + sizeof(int32_t));
+    if (need > sv->up_cap) {  // the previous tick ended with a synchronisation
+      if (sv->up_host) HIPCHK(hipHostFree(sv->up_host));
+      sv->up_host = nullptr;
+      dev_free(sv->up_dev);
+      const size_t cap = std::max<size_t>(need + need / 2, 1 << 16);
+      HIPCHK(hipHostMalloc((void**)&sv->up_host, cap, hipHostMallocDefault));
+      dev_alloc(sv->up_dev, cap);
+      sv->up_cap = cap;
+    }
+    int64_t* tab = reinterpret_cast<int64_t*>(sv->up_host);
+    double* stg = reinterpret_cast<double*>(sv->up_host + tab_bytes);
+    int32_t* stg_types = reinterpret_cast<int32_t*>(stg + 8 * ns);
+    int64_t o = 0, so = 0;
     int k = 0;
     for (auto& r : act) {
-      const size_t n = r->n;
-      if (r->t_admit == 0) {  // newly admitted: upload its state
-        HIPCHK(hipMemcpyAsync(nx.types + o, r->types.data(), n * sizeof(int32_t), hipMemcpyHostToDevice, s));
+      const int64_t n = r->n;
+      tab[4 * k] = o;
+      tab[4 * k + 1] = n;
+      if (r->t_admit == 0) {  // newly admitted: its state comes from the upload
+        tab[4 * k + 2] = -1;
+        tab[4 * k + 3] = so;
+        const bool md = r->kind == NEP_REQ_MD;
         for (int c = 0; c < 3; ++c) {
-          HIPCHK(hipMemcpyAsync(nx.pos + c * N + o, r->pos.data() + c * n, n * sizeof(double),
-                                hipMemcpyHostToDevice, s));
-          if (r->kind == NEP_REQ_MD)
-            HIPCHK(hipMemcpyAsync(nx.vel + c * N + o, r->vel.data() + c * n, n * sizeof(double),
-                                  hipMemcpyHostToDevice, s));
+          std::memcpy(stg + c * ns + so, r->pos.data() + c * n, n * sizeof(double));
+          if (md) std::memcpy(stg + (3 + c) * ns + so, r->vel.data() + c * n, n * sizeof(double));
+          else std::fill(stg + (3 + c) * ns + so, stg + (3 + c) * ns + so + n, 0.0);
         }
+        // the half-step factor 0.5 dt / (m c) per atom (zero for evaluations)
         double im[kMaxTypes] = {0};
-        if (r->kind == NEP_REQ_MD)
+        if (md)
           for (int t = 0; t < h->hp.n_types; ++t) im[t] = 1.0 / (r->mass[t] * kAmuA2fs2);
-        HIPCHK(hipMemcpy(nx.inv_mass + (size_t)kMaxTypes * k, im, sizeof im, hipMemcpyHostToDevice));
-        launch_srv_factors(n, nx.types + o, nx.inv_mass + (size_t)kMaxTypes * k, 0.5 * r->dt, r->dt, nx.hdm + o,
-                           nx.dta + o, s);
-        launch_fill_u8(nx.move + o, n, 0, s);
-        r->t_admit = now_s();
-      } else {  // carried over: copy its device state to the new offset
-        const int64_t src = r->off;
-        HIPCHK(hipMemcpyAsync(nx.types + o, st.types + src, n * sizeof(int32_t), hipMemcpyDeviceToDevice, s));
-        HIPCHK(hipMemcpyAsync(nx.hdm + o, st.hdm + src, n * sizeof(double), hipMemcpyDeviceToDevice, s));
-        HIPCHK(hipMemcpyAsync(nx.dta + o, st.dta + src, n * sizeof(double), hipMemcpyDeviceToDevice, s));
-        HIPCHK(hipMemcpyAsync(nx.move + o, st.move + src, n, hipMemcpyDeviceToDevice, s));
-        for (int c = 0; c < 3; ++c) {
-          HIPCHK(hipMemcpyAsync(nx.pos + c * N + o, st.pos + c * st.ld + src, n * sizeof(double),
-                                hipMemcpyDeviceToDevice, s));
-          HIPCHK(hipMemcpyAsync(nx.vel + c * N + o, st.vel + c * st.ld + src, n * sizeof(double),
-                                hipMemcpyDeviceToDevice, s));
-          HIPCHK(hipMemcpyAsync(nx.F + c * N + o, st.F + c * st.ld + src, n * sizeof(double),
-                                hipMemcpyDeviceToDevice, s));
+        const double half_dt = 0.5 * r->dt;
+        for (int64_t e = 0; e < n; ++e) {
+          stg[6 * ns + so + e] = half_dt * im[r->types[e]];
+          stg[7 * ns + so + e] = r->dt;
         }
+        std::memcpy(stg_types + so, r->types.data(), n * sizeof(int32_t));
+        so += n;
+        r->t_admit = now_s();
+      } else {  // carried over: its device state moves to the new offset
+        tab[4 * k + 2] = r->off;
+        tab[4 * k + 3] = 0;
       }
       r->off = o;
       o += n;
       ++k;
     }
+    HIPCHK(hipMemcpyAsync(sv->up_dev, sv->up_host, need, hipMemcpyHostToDevice, s));
+    const BatchState& od = sv->st;
+    const SrvState from{od.pos, od.vel, od.F, od.hdm, od.dta, od.types, od.move, od.ld};
+    const SrvState to{nx.pos, nx.vel, nx.F, nx.hdm, nx.dta, nx.types, nx.move, nx.ld};
+    launch_srv_place(reinterpret_cast<const int64_t*>(sv->up_dev), S, max_n, from, to,
+                     reinterpret_cast<const double*>(sv->up_dev + tab_bytes), ns, s);
     std::swap(sv->st, sv->st2);
   }
   BatchState& b = sv->st;
@@ -1415,10 +1480,13 @@ void server_tick(nep_server* sv) {
   launch_scatter_outputs(a, h->perm, b.E, b.F, b.W, s);
   launch_struct_totals(h->U, h->W, N, h->structs, S, b.totals, s);
   launch_srv_kick(N, b.vel, b.F, b.hdm, b.move, s);
-  // bookkeeping: finished requests copy their results out
+  // bookkeeping: the finished requests' results go out in one packed copy
   std::vector<std::shared_ptr<ServerReq>> finished;
+  std::vector<int64_t> fin_out;  // offset of each finished request's block in the staging
   std::vector<double> tot(10 * (size_t)S);
   HIPCHK(hipMemcpyAsync(tot.data(), b.totals, tot.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+  std::vector<int64_t> ctab;
+  int64_t out_n = 0, max_fin = 0;
   for (int32_t k = 0; k < S; ++k) {
     auto& r = act[k];
     bool fin = false;
@@ -1434,31 +1502,46 @@ void server_tick(nep_server* sv) {
     }
     sv->atom_steps += r->n;
     if (fin) {
-      const size_t n = r->n;
-      r->energy.resize(n);
-      r->force.resize(3 * n);
-      r->virial.resize(9 * n);
-      HIPCHK(hipMemcpyAsync(r->energy.data(), b.E + r->off, n * sizeof(double), hipMemcpyDeviceToHost, s));
-      for (int c = 0; c < 3; ++c)
-        HIPCHK(hipMemcpyAsync(r->force.data() + c * n, b.F + c * N + r->off, n * sizeof(double),
-                              hipMemcpyDeviceToHost, s));
-      for (int v = 0; v < 9; ++v)
-        HIPCHK(hipMemcpyAsync(r->virial.data() + v * n, b.W + v * N + r->off, n * sizeof(double),
-                              hipMemcpyDeviceToHost, s));
-      if (r->kind == NEP_REQ_MD) {
-        r->out_pos.resize(3 * n);
-        r->out_vel.resize(3 * n);
-        for (int c = 0; c < 3; ++c) {
-          HIPCHK(hipMemcpyAsync(r->out_pos.data() + c * n, b.pos + c * N + r->off, n * sizeof(double),
-                                hipMemcpyDeviceToHost, s));
-          HIPCHK(hipMemcpyAsync(r->out_vel.data() + c * n, b.vel + c * N + r->off, n * sizeof(double),
-                                hipMemcpyDeviceToHost, s));
-        }
-      }
+      const int64_t md = r->kind == NEP_REQ_MD ? 1 : 0;
+      ctab.insert(ctab.end(), {r->off, r->n, out_n, md});
+      fin_out.push_back(out_n);
+      out_n += r->n * (13 + 6 * md);
+      max_fin = std::max(max_fin, r->n);
       finished.push_back(r);
     }
   }
+  if (!finished.empty()) {
+    const size_t need = (size_t)out_n + ctab.size();  // results, then the table
+    if (need > sv->out_cap) {
+      if (sv->out_host) HIPCHK(hipHostFree(sv->out_host));
+      sv->out_host = nullptr;
+      dev_free(sv->out_dev);
+      const size_t cap = std::max<size_t>(need + need / 2, 1 << 16);
+      HIPCHK(hipHostMalloc((void**)&sv->out_host, cap * sizeof(double), hipHostMallocDefault));
+      dev_alloc(sv->out_dev, cap);
+      sv->out_cap = cap;
+    }
+    // the table rides in the tail of the staging (8-byte words both ways)
+    std::memcpy(sv->out_host + out_n, ctab.data(), ctab.size() * sizeof(int64_t));
+    HIPCHK(hipMemcpyAsync(sv->out_dev + out_n, sv->out_host + out_n, ctab.size() * sizeof(int64_t),
+                          hipMemcpyHostToDevice, s));
+    launch_srv_collect(reinterpret_cast<const int64_t*>(sv->out_dev + out_n), (int32_t)finished.size(), max_fin,
+                       N, b.E, b.F, b.W, b.pos, b.vel, sv->out_dev, s);
+    HIPCHK(hipMemcpyAsync(sv->out_host, sv->out_dev, out_n * sizeof(double), hipMemcpyDeviceToHost, s));
+  }
   HIPCHK(hipStreamSynchronize(s));
+  for (size_t f = 0; f < finished.size(); ++f) {
+    auto& r = finished[f];
+    const size_t n = r->n;
+    const double* blk = sv->out_host + fin_out[f];
+    r->energy.assign(blk, blk + n);
+    r->force.assign(blk + n, blk + 4 * n);
+    r->virial.assign(blk + 4 * n, blk + 13 * n);
+    if (r->kind == NEP_REQ_MD) {
+      r->out_pos.assign(blk + 13 * n, blk + 16 * n);
+      r->out_vel.assign(blk + 16 * n, blk + 19 * n);
+    }
+  }
   const double t = now_s();
   sv->ticks += 1;
   sv->batch_atoms += N;
@@ -2960,6 +3043,7 @@ void nep_server_destroy(nep_server* sv) {
   (void)hipSetDevice(sv->h->device);
   sv->st.release();
   sv->st2.release();
+  sv->release_staging();
   if (sv->stream) (void)hipStreamDestroy(sv->stream);
   delete sv;
 }

@@ -285,21 +285,80 @@ void launch_fill_u8(uint8_t* a, int64_t n, uint8_t v, hipStream_t s) {
   if (n > 0) hipLaunchKernelGGL(k_fill_u8, dim3(div_up(n, kBlock)), dim3(kBlock), 0, s, a, n, v);
 }
 
-// Per-atom half-step factor 0.5 dt / (m c) and dt of one request segment.
-__global__ void k_srv_factors(int64_t n, const int32_t* __restrict__ types, const double* __restrict__ inv_mass,
-                              double half_dt, double dt, double* __restrict__ hdm,
-                              double* __restrict__ dta) {
-  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  hdm[i] = half_dt * inv_mass[types[i]];
-  dta[i] = dt;
+// New layout of the server's batch state, one launch for every request:
+// blockIdx.y = request k, tab[4k..4k+3] = {dst, n, src, stg}: its n atoms go
+// to dst in the new layout, from src in the old one, or (src < 0: admitted
+// this tick) from offset stg of the uploaded staging, whose parts are
+// pos [3][ns], vel [3][ns], hdm [ns], dta [ns] (doubles) then types [ns].
+__global__ void k_srv_place(const int64_t* __restrict__ tab, SrvState o, SrvState w,
+                            const double* __restrict__ stg, int64_t ns) {
+  const int k = blockIdx.y;
+  const int64_t dst = tab[4 * k], n = tab[4 * k + 1], src = tab[4 * k + 2], so = tab[4 * k + 3];
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n) return;
+  const int64_t i = dst + e;
+  if (src >= 0) {
+    const int64_t j = src + e;
+    w.types[i] = o.types[j];
+    w.hdm[i] = o.hdm[j];
+    w.dta[i] = o.dta[j];
+    w.move[i] = o.move[j];
+    for (int c = 0; c < 3; ++c) {
+      w.pos[c * w.ld + i] = o.pos[c * o.ld + j];
+      w.vel[c * w.ld + i] = o.vel[c * o.ld + j];
+      w.F[c * w.ld + i] = o.F[c * o.ld + j];
+    }
+  } else {
+    const int64_t j = so + e;
+    for (int c = 0; c < 3; ++c) {
+      w.pos[c * w.ld + i] = stg[c * ns + j];
+      w.vel[c * w.ld + i] = stg[(3 + c) * ns + j];
+    }
+    w.hdm[i] = stg[6 * ns + j];
+    w.dta[i] = stg[7 * ns + j];
+    w.types[i] = reinterpret_cast<const int32_t*>(stg + 8 * ns)[j];
+    w.move[i] = 0;  // no step before the request's first evaluation
+  }
 }
 
-void launch_srv_factors(int64_t n, const int32_t* types, const double* inv_mass, double half_dt, double dt,
-                        double* hdm, double* dta, hipStream_t s) {
-  if (n > 0)
-    hipLaunchKernelGGL(k_srv_factors, dim3(div_up(n, kBlock)), dim3(kBlock), 0, s, n, types, inv_mass,
-                       half_dt, dt, hdm, dta);
+void launch_srv_place(const int64_t* tab, int32_t n_req, int64_t max_n, const SrvState& o, const SrvState& w,
+                      const double* stg, int64_t ns, hipStream_t s) {
+  if (n_req > 0 && max_n > 0)
+    hipLaunchKernelGGL(k_srv_place, dim3(div_up(max_n, kBlock), n_req), dim3(kBlock), 0, s, tab, o, w, stg, ns);
 }
+
+// Results of the requests that finished this tick, packed for one copy to
+// the host: blockIdx.y = request k, tab[4k..4k+3] = {off, n, out, md}; its
+// block at out holds E [n], F [3][n], W [9][n] and, for MD, pos [3][n] and
+// vel [3][n].
+__global__ void k_srv_collect(const int64_t* __restrict__ tab, int64_t ld, const double* __restrict__ E,
+                              const double* __restrict__ F, const double* __restrict__ W,
+                              const double* __restrict__ pos, const double* __restrict__ vel,
+                              double* __restrict__ out) {
+  const int k = blockIdx.y;
+  const int64_t off = tab[4 * k], n = tab[4 * k + 1], o = tab[4 * k + 2], md = tab[4 * k + 3];
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n) return;
+  const int64_t i = off + e;
+  double* b = out + o;
+  b[e] = E[i];
+  for (int c = 0; c < 3; ++c) b[(1 + c) * n + e] = F[c * ld + i];
+  for (int v = 0; v < 9; ++v) b[(4 + v) * n + e] = W[v * ld + i];
+  if (md) {
+    for (int c = 0; c < 3; ++c) {
+      b[(13 + c) * n + e] = pos[c * ld + i];
+      b[(16 + c) * n + e] = vel[c * ld + i];
+    }
+  }
+}
+
+void launch_srv_collect(const int64_t* tab, int32_t n_req, int64_t max_n, int64_t ld, const double* E,
+                        const double* F, const double* W, const double* pos, const double* vel, double* out,
+                        hipStream_t s) {
+  if (n_req > 0 && max_n > 0)
+    hipLaunchKernelGGL(k_srv_collect, dim3(div_up(max_n, kBlock), n_req), dim3(kBlock), 0, s, tab, ld, E, F,
+                       W, pos, vel, out);
+}
+
 
 }  // namespace nep

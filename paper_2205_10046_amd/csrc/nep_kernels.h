@@ -197,8 +197,18 @@ void launch_srv_kick_drift(int64_t N, double* pos, double* vel, const double* F,
 void launch_srv_kick(int64_t N, double* vel, const double* F, const double* hdm, const uint8_t* move,
                      hipStream_t s);
 void launch_fill_u8(uint8_t* a, int64_t n, uint8_t v, hipStream_t s);
-void launch_srv_factors(int64_t n, const int32_t* types, const double* inv_mass, double half_dt, double dt,
-                        double* hdm, double* dta, hipStream_t s);
+// The server's per-atom batch state, [3][ld] for the vectors.
+struct SrvState {
+  double *pos, *vel, *F, *hdm, *dta;
+  int32_t* types;
+  uint8_t* move;
+  int64_t ld;
+};
+void launch_srv_place(const int64_t* tab, int32_t n_req, int64_t max_n, const SrvState& o, const SrvState& w,
+                      const double* stg, int64_t ns, hipStream_t s);
+void launch_srv_collect(const int64_t* tab, int32_t n_req, int64_t max_n, int64_t ld, const double* E,
+                        const double* F, const double* W, const double* pos, const double* vel, double* out,
+                        hipStream_t s);
 void launch_gather3_gated(const int32_t* src, int64_t N, const double* in, double* out,
                           const int32_t* gate, hipStream_t s);
 void launch_gather_i32_gated(const int32_t* src, int64_t N, const int32_t* in, int32_t* out,
