@@ -454,8 +454,8 @@ int nep_get_tuning(const nep_handle *h, int32_t batch, int32_t out[7]);
 
 /* MD schedule counters of this handle since nep_create: out[0] = steps run
  * inside captured groups (with a skin, such a group checks for a row rebuild
- * at its first step only, with each atom's displacement extended by twice
- * its speed times the group's remaining time, and verifies the skin at every
+ * at its first step only, with each atom's displacement extended by 1.5
+ * times its speed times the group's remaining time, and verifies the skin at every
  * later step); out[1] = chunks run again step by step because an atom left
  * the skin between two checks (the chunk restarts from its saved state, so
  * results stay those of rows within the skin); out[2] = row rebuilds of MD

@@ -52,7 +52,7 @@ static_assert(kFlagsRead * sizeof(int32_t) <= 64 && kPinFlags + 64 <= 4096, "sta
 // A captured MD group checks for a rebuild once, at its first step, with
 // every atom's displacement extended by this many times its current speed
 // over the group's remaining steps; each later step only verifies the skin.
-constexpr double kRebuildLookahead = 2.0;
+constexpr double kRebuildLookahead = 1.5;
 
 struct Failure {
   int code;

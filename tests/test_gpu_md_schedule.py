@@ -1,5 +1,5 @@
 """Row maintenance of MD with a skin (nep_md_run*): a captured group of steps
-checks for a rebuild at its first step only, looking ahead by twice each
+checks for a rebuild at its first step only, looking ahead by 1.5 times each
 atom's speed over the group; every later step verifies the skin, and a chunk
 in which an atom left it is replayed step by step from its saved state.
 Either way the trajectory is that of rows rebuilt from scratch every step,
