@@ -1376,6 +1376,19 @@ size_t request_bytes(const nep_handle* h, int64_t n, double density) {
 
 // One tick: every active request advances by one evaluation (and, for MD
 // requests past their initial evaluation, one velocity-Verlet step).
+}  // namespace
+
+namespace nep {
+// output.hip (declared here so that the force kernel's headers stay as profiled):
+// per-structure totals of structures of any size, in chunks of a few thousand
+// atoms (work: at least 10 doubles per structure)
+void launch_struct_totals_chunked(const float* U, const float* W, int64_t N, const StructInfo* structs,
+                                  int32_t n_struct, int64_t max_count, double* work, int64_t work_cap,
+                                  double* totals, hipStream_t s);
+}  // namespace nep
+
+namespace {
+
 void server_tick(nep_server* sv) {
   nep_handle* h = sv->h;
   hipStream_t s = sv->stream;
@@ -1478,7 +1491,11 @@ void server_tick(nep_server* sv) {
   forces(h, pp, s);
   EvalArgs a = eval_args(h, pp, h->M);
   launch_scatter_outputs(a, h->perm, b.E, b.F, b.W, s);
-  launch_struct_totals(h->U, h->W, N, h->structs, S, b.totals, s);
+  {
+    int64_t max_n = 0;
+    for (auto& r : act) max_n = std::max(max_n, r->n);
+    launch_struct_totals_chunked(h->U, h->W, N, h->structs, S, max_n, h->partial, 11 * h->cap_part, b.totals, s);
+  }
   launch_srv_kick(N, b.vel, b.F, b.hdm, b.move, s);
   // bookkeeping: the finished requests' results go out in one packed copy
   std::vector<std::shared_ptr<ServerReq>> finished;

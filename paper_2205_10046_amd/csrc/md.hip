@@ -81,19 +81,27 @@ __global__ void __launch_bounds__(kRed) k_thermo_partial(const float* __restrict
   if (t < 11) partial[blockIdx.x * 11 + t] = sh[t][0];
 }
 
+// Thread v < 11 sums column v of the partial rows in block order (the
+// fixed order of the totals); thread 0 then writes the row.
 __global__ void k_thermo_final(const double* __restrict__ partial, int64_t n_part, int64_t N,
                                double step, double kin_conv, double kB, double* __restrict__ row,
                                int32_t* __restrict__ counter, double every) {
-  if (threadIdx.x != 0) return;
+  __shared__ double s[11];
+  const int t = threadIdx.x;
+  if (t < 11) {
+    double acc = 0.0;
+#pragma unroll 8
+    for (int64_t b = 0; b < n_part; ++b) acc += partial[b * 11 + t];
+    s[t] = acc;
+  }
+  __syncthreads();
+  if (t != 0) return;
   if (counter) {  // row and step number from a device counter (graph replays)
     const int32_t r = *counter;
     *counter = r + 1;
     row += 13 * (int64_t)r;
     step = (double)(r + 1) * every;
   }
-  double s[11] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
-  for (int64_t b = 0; b < n_part; ++b)
-    for (int v = 0; v < 11; ++v) s[v] += partial[b * 11 + v];
   const double ek = 0.5 * s[1] * kin_conv;
   row[0] = step;
   row[1] = s[0];

@@ -29,6 +29,7 @@ void launch_scatter_outputs(const EvalArgs& a, const int32_t* perm, double* ener
 }
 
 constexpr int kRedBlock = 256;
+constexpr int64_t kTotalsChunk = 8192;  // atoms per block of the chunked structure totals
 
 // Block b sums items [b*chunk, (b+1)*chunk) of the 10 quantities (U, W_0..8)
 // in a fixed tree; partial[b][10].
@@ -99,6 +100,61 @@ void launch_struct_totals(const float* U, const float* W, int64_t N, const Struc
                           int32_t n_struct, double* totals, hipStream_t s) {
   hipLaunchKernelGGL(k_struct_totals, dim3((unsigned)n_struct), dim3(kRedBlock), 0, s, U, W, N,
                      structs, totals);
+}
+
+// The same totals for structures of any size, in two fixed-order levels:
+// block (c, s) reduces chunk c of structure s (C atoms from its start) with
+// the block tree into partial[s][c][10] (zeros past the structure's end),
+// then the chunk sums of a structure are added in chunk order.
+__global__ void __launch_bounds__(kRedBlock) k_struct_totals_chunks(const float* __restrict__ U,
+                                                                    const float* __restrict__ W, int64_t N,
+                                                                    const StructInfo* __restrict__ structs,
+                                                                    int64_t C, int32_t n_chunk,
+                                                                    double* __restrict__ partial) {
+  __shared__ double sh[10][kRedBlock];
+  const int t = threadIdx.x;
+  const StructInfo& st = structs[blockIdx.y];
+  const int64_t end = st.start + st.count;
+  const int64_t lo = st.start + (int64_t)blockIdx.x * C, hi = min(end, lo + C);
+  double acc[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+  for (int64_t k = lo + t; k < hi; k += kRedBlock) {
+    acc[0] += (double)U[k];
+    for (int v = 0; v < 9; ++v) acc[1 + v] += (double)W[(int64_t)v * N + k];
+  }
+  for (int v = 0; v < 10; ++v) sh[v][t] = acc[v];
+  __syncthreads();
+  for (int off = kRedBlock / 2; off > 0; off >>= 1) {
+    if (t < off)
+      for (int v = 0; v < 10; ++v) sh[v][t] += sh[v][t + off];
+    __syncthreads();
+  }
+  if (t < 10) partial[((int64_t)blockIdx.y * n_chunk + blockIdx.x) * 10 + t] = sh[t][0];
+}
+
+__global__ void k_struct_totals_final(const double* __restrict__ partial, int32_t n_struct, int32_t n_chunk,
+                                      double* __restrict__ totals) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;  // structure k / 10, column k % 10
+  if (k >= (int64_t)n_struct * 10) return;
+  const int64_t s = k / 10, v = k % 10;
+  double acc = 0.0;
+  for (int c = 0; c < n_chunk; ++c) acc += partial[(s * n_chunk + c) * 10 + v];
+  totals[k] = acc;
+}
+
+void launch_struct_totals_chunked(const float* U, const float* W, int64_t N, const StructInfo* structs,
+                                  int32_t n_struct, int64_t max_count, double* work, int64_t work_cap,
+                                  double* totals, hipStream_t s) {
+  int64_t n_chunk = std::max<int64_t>(1, (max_count + kTotalsChunk - 1) / kTotalsChunk);
+  n_chunk = std::min<int64_t>(n_chunk, work_cap / (10 * (int64_t)n_struct));
+  if (n_chunk <= 1) {
+    launch_struct_totals(U, W, N, structs, n_struct, totals, s);
+    return;
+  }
+  const int64_t C = (max_count + n_chunk - 1) / n_chunk;
+  hipLaunchKernelGGL(k_struct_totals_chunks, dim3((unsigned)n_chunk, (unsigned)n_struct), dim3(kRedBlock), 0, s,
+                     U, W, N, structs, C, (int32_t)n_chunk, work);
+  hipLaunchKernelGGL(k_struct_totals_final, dim3(div_up(10 * (int64_t)n_struct, kBlock)), dim3(kBlock), 0, s,
+                     work, n_struct, (int32_t)n_chunk, totals);
 }
 
 __global__ void k_descriptors_out(const float* __restrict__ q, int64_t N, int NDp, int ND,
