@@ -103,6 +103,11 @@ def test_error_table_served_requests(prec, table):
         res = srv.poll(t, wait_ms=-1)
         n = r.pos.shape[1]
         sizes.append(n)
+        # the request's totals (energy, then the 9 virial components) are the
+        # sums of its per-atom values, in any summation order (requests above
+        # 8,192 atoms take the chunked reduction)
+        np.testing.assert_allclose(res["totals"][0], res["U"].sum(), rtol=1e-10, atol=1e-9)
+        np.testing.assert_allclose(res["totals"][1:], res["W"].sum(axis=1), rtol=1e-10, atol=1e-9)
         if n <= 3000:
             ref = O.evaluate(h, p, r.pos, r.types, r.box)
             dU.append(res["U"] - ref["U"])
