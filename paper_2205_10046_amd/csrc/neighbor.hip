@@ -642,18 +642,30 @@ __global__ void __launch_bounds__(kBlock) k_filter_rows(const double* __restrict
   // classes of the lane's first 64 candidates (t = local index) as bit masks;
   // later ones (rows over 256 candidates) go through V.fmap
   uint64_t mask_a = 0, mask_o = 0;
+  // the index words of chunk t0 + U are loaded while chunk t0's positions
+  // are in flight
+  int32_t jn[U];
+  uint16_t cn[U];
+  auto load_words = [&](int t0) __attribute__((always_inline)) {
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int m = (t0 + u) * G + sub;
+      jn[u] = (int32_t)i;  // past the row: the atom itself, in bounds and never classified
+      cn[u] = kCodeCenter;
+      if (m < nv) {
+        jn[u] = vnl[(int64_t)m * N + i];
+        if (images) cn[u] = vcd[(int64_t)m * N + i];
+      }
+    }
+  };
+  load_words(0);
   for (int t0 = 0; t0 < steps; t0 += U) {
     int32_t j[U];
     uint16_t code[U];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-      const int m = (t0 + u) * G + sub;
-      j[u] = (int32_t)i;  // past the row: the atom itself, in bounds and never classified
-      code[u] = kCodeCenter;
-      if (m < nv) {
-        j[u] = vnl[(int64_t)m * N + i];
-        if (images) code[u] = vcd[(int64_t)m * N + i];
-      }
+      j[u] = jn[u];
+      code[u] = cn[u];
     }
     double px[U], py[U], pz[U];
 #pragma unroll
@@ -662,6 +674,7 @@ __global__ void __launch_bounds__(kBlock) k_filter_rows(const double* __restrict
       py[u] = pos[N + j[u]];
       pz[u] = pos[2 * N + j[u]];
     }
+    if (t0 + U < steps) load_words(t0 + U);
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       const int t = t0 + u, m = t * G + sub;
@@ -713,27 +726,41 @@ __global__ void __launch_bounds__(kBlock) k_filter_rows(const double* __restrict
   const uint64_t gmask = (G == 64 ? ~0ull : ((1ull << G) - 1)) << (lane & ~(G - 1));
   const uint64_t below = (1ull << lane) - 1;
   int32_t pa = 0, po = a_all;  // next angular / outer position
+  // the members' words of chunk t0 + U are loaded while chunk t0 is placed
+  int32_t cq[U], jq[U], rq[U];
+  uint16_t kq[U];
+  auto load_members = [&](int t0) __attribute__((always_inline)) {
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int t = t0 + u, m = t * G + sub;
+      const int64_t e = (int64_t)m * N + i;
+      cq[u] = -1;
+      if (m < nv) {
+        if (t < 64) cq[u] = ((mask_a >> t) & 1) ? kAngular : (((mask_o >> t) & 1) ? kOuter : -1);
+        else cq[u] = fmap[e];
+      }
+      jq[u] = 0;
+      rq[u] = 0;
+      kq[u] = kCodeCenter;
+      if (cq[u] != -1) {
+        jq[u] = vnl[e];
+        rq[u] = vrev[e];
+        if (images) kq[u] = vcd[e];
+      }
+    }
+  };
+  load_members(0);
   for (int t0 = 0; t0 < steps; t0 += U) {
     int32_t c[U], jn[U], rn[U];
     uint16_t cn[U];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-      const int t = t0 + u, m = t * G + sub;
-      const int64_t e = (int64_t)m * N + i;
-      c[u] = -1;
-      if (m < nv) {
-        if (t < 64) c[u] = ((mask_a >> t) & 1) ? kAngular : (((mask_o >> t) & 1) ? kOuter : -1);
-        else c[u] = fmap[e];
-      }
-      jn[u] = 0;
-      rn[u] = 0;
-      cn[u] = kCodeCenter;
-      if (c[u] != -1) {
-        jn[u] = vnl[e];
-        rn[u] = vrev[e];
-        if (images) cn[u] = vcd[e];
-      }
+      c[u] = cq[u];
+      jn[u] = jq[u];
+      rn[u] = rq[u];
+      cn[u] = kq[u];
     }
+    if (t0 + U < steps) load_members(t0 + U);
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       const int m = (t0 + u) * G + sub;
@@ -784,20 +811,31 @@ __global__ void __launch_bounds__(kBlock) k_reverse_from_candidates(int64_t N, L
   int32_t* __restrict__ lrev = L.revR;
   const int nn = min(L.nnR[i], L.MR);
   bool broken = false;
+  // the words of chunk p0 + U G are loaded while chunk p0's map entries are in flight
+  int32_t jq[U], rq[U];
+  auto load_words = [&](int p0) __attribute__((always_inline)) {
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int p = p0 + u * G;
+      jq[u] = 0;
+      rq[u] = 0;
+      if (p < nn) {
+        jq[u] = lnl[(int64_t)p * N + i];
+        rq[u] = lrev[(int64_t)p * N + i];
+      }
+    }
+  };
+  load_words(sub);
   for (int p0 = sub; p0 < nn; p0 += U * G) {
     int32_t j[U], r[U], g[U];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-      const int p = p0 + u * G;
-      j[u] = 0;
-      r[u] = 0;
-      if (p < nn) {
-        j[u] = lnl[(int64_t)p * N + i];
-        r[u] = lrev[(int64_t)p * N + i];
-      }
+      j[u] = jq[u];
+      r[u] = rq[u];
     }
 #pragma unroll
     for (int u = 0; u < U; ++u) g[u] = p0 + u * G < nn ? fmap[(int64_t)r[u] * N + j[u]] : 0;
+    if (p0 + U * G < nn) load_words(p0 + U * G);
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       const int p = p0 + u * G;
