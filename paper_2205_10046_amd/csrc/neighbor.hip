@@ -432,6 +432,7 @@ __global__ void __launch_bounds__(kBlock) k_build_rows_wide(
 // rev[m][i] = position of (i, -offset) in the row of j = nl[m][i] (rows
 // sorted by (j, image)).
 constexpr int kReverseLanes = 4;  // lanes per atom of k_reverse: lane s searches for entries s, s + 4, ...
+constexpr int kReverseChunk = 4;  // entries whose searches a lane of k_reverse runs together
 
 __global__ void k_reverse(int64_t N, const int32_t* __restrict__ nn, const int32_t* __restrict__ nl,
                           const uint16_t* __restrict__ cd, int32_t cap, int32_t* __restrict__ rev,
@@ -441,28 +442,67 @@ __global__ void k_reverse(int64_t N, const int32_t* __restrict__ nn, const int32
   if (i >= N || gated_off(gate)) return;
   const int cnt = min(nn[i], cap);
   bool bad = false;
-  for (int m = sub; m < cnt; m += kReverseLanes) {
-    int32_t j = nl[(int64_t)m * N + i];
-    int a, b, c;
-    split_code(cd[(int64_t)m * N + i], a, b, c);
-    uint32_t key = ((uint32_t)make_code(-a, -b, -c));
-    int lo = 0, hi = min(nn[j], cap) - 1, found = -1;
-    while (lo <= hi) {
-      int mid = (lo + hi) >> 1;
-      int32_t jj = nl[(int64_t)mid * N + j];
-      uint32_t kk = cd[(int64_t)mid * N + j];
-      if (jj == (int32_t)i && kk == key) {
-        found = mid;
-        break;
+  // kReverseChunk entries of the lane at a time: their binary searches advance
+  // together, so each step has that many independent loads in flight
+  constexpr int U = kReverseChunk;
+  for (int m0 = sub; m0 < cnt; m0 += U * kReverseLanes) {
+    int32_t j[U];
+    uint32_t key[U];
+    int lo[U], hi[U], found[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int m = m0 + u * kReverseLanes;
+      j[u] = 0;
+      key[u] = 0;
+      lo[u] = 0;
+      hi[u] = -1;  // an empty search for entries past the row
+      found[u] = -1;
+      if (m < cnt) {
+        j[u] = nl[(int64_t)m * N + i];
+        int a, b, c;
+        split_code(cd[(int64_t)m * N + i], a, b, c);
+        key[u] = (uint32_t)make_code(-a, -b, -c);
       }
-      if (jj < (int32_t)i || (jj == (int32_t)i && kk < key)) lo = mid + 1;
-      else hi = mid - 1;
     }
-    if (found < 0) {
-      bad = true;
-      found = 0;
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+      if (m0 + u * kReverseLanes < cnt) hi[u] = min(nn[j[u]], cap) - 1;
+    for (;;) {
+      bool any = false;
+      int mid[U];
+      int32_t jj[U];
+      uint32_t kk[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const bool live = found[u] < 0 && lo[u] <= hi[u];
+        any |= live;
+        mid[u] = live ? (lo[u] + hi[u]) >> 1 : -1;
+        jj[u] = 0;
+        kk[u] = 0;
+        if (live) {
+          jj[u] = nl[(int64_t)mid[u] * N + j[u]];
+          kk[u] = cd[(int64_t)mid[u] * N + j[u]];
+        }
+      }
+      if (!any) break;
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        if (mid[u] < 0) continue;
+        if (jj[u] == (int32_t)i && kk[u] == key[u]) found[u] = mid[u];
+        else if (jj[u] < (int32_t)i || (jj[u] == (int32_t)i && kk[u] < key[u])) lo[u] = mid[u] + 1;
+        else hi[u] = mid[u] - 1;
+      }
     }
-    rev[(int64_t)m * N + i] = found;
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int m = m0 + u * kReverseLanes;
+      if (m >= cnt) continue;
+      if (found[u] < 0) {
+        bad = true;
+        found[u] = 0;
+      }
+      rev[(int64_t)m * N + i] = found[u];
+    }
   }
   if (bad) atomicExch(err, 1);
 }
