@@ -898,40 +898,67 @@ __global__ void __launch_bounds__(kBlock) k_reverse_from_candidates(int64_t N, L
 // violation sets a bit of *bad (1: counts, 2: neighbour index, 4: reverse
 // position, 8: reverse entry, 16: image code); rows that overflowed their
 // capacity are reported by the overflow flags instead.
+constexpr int kCheckLanes = 4;  // lanes per atom of k_check_rows (entries s, s + 4, ...)
+constexpr int kCheckChunk = 4;  // entries a lane checks together
+
 __global__ void __launch_bounds__(kBlock) k_check_rows(int64_t N, const int32_t* __restrict__ sid,
                                                        const StructInfo* __restrict__ structs,
                                                        StructInfo st0, int32_t batch, Lists L,
                                                        int32_t* __restrict__ bad) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  constexpr int G = kCheckLanes, U = kCheckChunk;
+  const int sub = threadIdx.x & (G - 1);
+  const int64_t i = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / G;
   if (i >= N) return;
   const StructInfo& st = batch ? structs[sid[i]] : st0;
   const int nn = L.nnR[i], na = L.nnA[i];
   if (nn > L.MR) return;  // overflow: reported and handled by the caller
   int32_t b = 0;
-  if (na < 0 || nn < 0 || na > nn) b |= 1;
+  if (sub == 0 && (na < 0 || nn < 0 || na > nn)) b |= 1;
   const bool images = st.mode == kModeImages;
   const int64_t lo = st.start, hi = st.start + st.count;
-  for (int m = 0; m < max(nn, 0) && !(b & 6); ++m) {
-    const int64_t e = (int64_t)m * N + i;
-    const int32_t j = L.nlR[e];
-    if (j < lo || j >= hi) {
-      b |= 2;
-      break;
+  // a chunk's index words first, then the partners' row lengths and reverse
+  // entries (each read only when the words before it are in bounds)
+  for (int m0 = sub; m0 < max(nn, 0); m0 += U * G) {
+    int32_t j[U], r[U];
+    bool jok[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int m = m0 + u * G;
+      j[u] = 0;
+      r[u] = 0;
+      if (m < nn) {
+        j[u] = L.nlR[(int64_t)m * N + i];
+        r[u] = L.revR[(int64_t)m * N + i];
+      }
     }
-    const int32_t r = L.revR[e];
-    const int nj = L.nnR[j];
-    if (r < 0 || r >= min(nj, L.MR)) {
-      b |= 4;
-      break;
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      jok[u] = m0 + u * G < nn && j[u] >= lo && j[u] < hi;
+      if (m0 + u * G < nn && !jok[u]) b |= 2;
     }
-    const int64_t er = (int64_t)r * N + j;
-    if (L.nlR[er] != (int32_t)i) b |= 8;
-    if (images) {
-      int oa, ob, oc, ra, rb, rc;
-      split_code(L.cdR[e], oa, ob, oc);
-      split_code(L.cdR[er], ra, rb, rc);
-      if (oa != -ra || ob != -rb || oc != -rc) b |= 8;
-      if (abs(oa) > st.reach[0] || abs(ob) > st.reach[1] || abs(oc) > st.reach[2]) b |= 16;
+    int nj[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) nj[u] = jok[u] ? L.nnR[j[u]] : 0;
+    int32_t back[U];
+    bool rok[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      rok[u] = jok[u] && r[u] >= 0 && r[u] < min(nj[u], L.MR);
+      if (jok[u] && !rok[u]) b |= 4;
+      back[u] = rok[u] ? L.nlR[(int64_t)r[u] * N + j[u]] : (int32_t)i;
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      if (!rok[u]) continue;
+      if (back[u] != (int32_t)i) b |= 8;
+      if (images) {
+        const int64_t e = (int64_t)(m0 + u * G) * N + i, er = (int64_t)r[u] * N + j[u];
+        int oa, ob, oc, ra, rb, rc;
+        split_code(L.cdR[e], oa, ob, oc);
+        split_code(L.cdR[er], ra, rb, rc);
+        if (oa != -ra || ob != -rb || oc != -rc) b |= 8;
+        if (abs(oa) > st.reach[0] || abs(ob) > st.reach[1] || abs(oc) > st.reach[2]) b |= 16;
+      }
     }
   }
   if (b) atomicOr(bad, b);
@@ -939,7 +966,7 @@ __global__ void __launch_bounds__(kBlock) k_check_rows(int64_t N, const int32_t*
 
 void launch_check_rows(int64_t N, const int32_t* sid, const StructInfo* structs, const StructInfo& st0,
                        bool batch, const Lists& L, int32_t* bad, hipStream_t s) {
-  hipLaunchKernelGGL(k_check_rows, grid_for(N), dim3(kBlock), 0, s, N, sid, structs, st0,
+  hipLaunchKernelGGL(k_check_rows, grid_for(N * kCheckLanes), dim3(kBlock), 0, s, N, sid, structs, st0,
                      (int32_t)(batch ? 1 : 0), L, bad);
 }
 
