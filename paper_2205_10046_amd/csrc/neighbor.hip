@@ -255,77 +255,77 @@ __device__ inline int stencil_1d(int c, int n, int periodic, int* out) {
   return k;
 }
 
-struct RowWriter {
-  int32_t* nl;
-  uint16_t* cd;
-  int32_t cap;
-  int32_t count;
-  __device__ inline void push(int64_t N, int64_t i, int32_t j, uint16_t code) {
-    if (count < cap) {
-      nl[(int64_t)count * N + i] = j;
-      cd[(int64_t)count * N + i] = code;
-    }
-    ++count;
-  }
-};
+// Candidate rows of the atoms of cell-mode structures, kCellLanes lanes per
+// atom: the 27 stencil cells in order, each cell's atoms taken kCellLanes at
+// a time (lane s the (k0 + s)-th), each accepted one placed by a count over
+// the atom's lanes' ballot bits, so the row is the one a single lane's scan
+// writes (cells in stencil order, atoms in cell order).  Atoms of structures
+// without cells take their rows from k_build_rows_wide.
+constexpr int kCellLanes = 4;
 
 __global__ void __launch_bounds__(kBlock) k_build_rows(
     const double* __restrict__ pos, int64_t N, const int32_t* __restrict__ sid,
     const StructInfo* __restrict__ structs, const int32_t* __restrict__ cell_start,
     const int32_t* __restrict__ cell_count, double rc2, Lists V, int32_t* __restrict__ overflow,
-    const int32_t* gate, int32_t cells_only) {
-  int64_t i = xcd_block() * blockDim.x + threadIdx.x;
-  if (i >= N || gated_off(gate)) return;
-  if (cells_only && structs[sid[i]].mode != kModeCells) return;  // k_build_rows_wide's atoms
+    const int32_t* gate) {
+  constexpr int G = kCellLanes;
+  const int sub = threadIdx.x & (G - 1);
+  const int64_t i = (xcd_block() * blockDim.x + threadIdx.x) / G;
+  if (i >= N || gated_off(gate)) return;  // the lanes of an atom leave together
   const StructInfo st = structs[sid[i]];
+  if (st.mode != kModeCells) return;
   const double xi = pos[i], yi = pos[N + i], zi = pos[2 * N + i];
-  RowWriter R{V.nlR, V.cdR, V.MR, 0};
-
-  auto consider = [&](int64_t j, int o0, int o1, int o2) {
-    double Dx, Dy, Dz;
-    {
+  const int lane = threadIdx.x & 63;
+  const uint64_t gmask = ((1ull << G) - 1) << (lane & ~(G - 1));
+  const uint64_t below = (1ull << lane) - 1;
+  const uint16_t code0 = make_code(0, 0, 0);
+  int32_t count = 0;
+  int cx, cy, cz;
+  cell_coords(st, xi, yi, zi, cx, cy, cz);
+  int sx[3], sy[3], sz[3];
+  const int nx = stencil_1d(cx, st.ncell[0], st.pbc[0], sx);
+  const int ny = stencil_1d(cy, st.ncell[1], st.pbc[1], sy);
+  const int nz = stencil_1d(cz, st.ncell[2], st.pbc[2], sz);
+  for (int a = 0; a < nz; ++a)
+    for (int b = 0; b < ny; ++b)
+      for (int c = 0; c < nx; ++c) {
+        const int cell = st.cell_off + (sz[a] * st.ncell[1] + sy[b]) * st.ncell[0] + sx[c];
+        const int s0 = cell_start[cell], cnt = cell_count[cell];
+        for (int k0 = 0; k0 < cnt; k0 += G) {
+          const int k = k0 + sub;
+          const int64_t j = s0 + min(k, cnt - 1);
+          bool take = false;
+          if (k < cnt) {
+            double Dx, Dy, Dz;
+            {
 #pragma clang fp contract(off)
-      Dx = pos[j] - xi;
-      Dy = pos[N + j] - yi;
-      Dz = pos[2 * N + j] - zi;
-    }
-    int n0, n1, n2;
-    min_image(st, Dx, Dy, Dz, n0, n1, n2);
-    n0 += o0;
-    n1 += o1;
-    n2 += o2;
-    if (j == i && n0 == 0 && n1 == 0 && n2 == 0) return;
-    double dx, dy, dz;
-    image_disp(st, Dx, Dy, Dz, n0, n1, n2, dx, dy, dz);
-    double r2 = norm2_exact(dx, dy, dz);
-    if (r2 < rc2) R.push(N, i, (int32_t)j, make_code(o0, o1, o2));
-  };
-
-  if (st.mode == kModeCells) {
-    int cx, cy, cz;
-    cell_coords(st, xi, yi, zi, cx, cy, cz);
-    int sx[3], sy[3], sz[3];
-    int nx = stencil_1d(cx, st.ncell[0], st.pbc[0], sx);
-    int ny = stencil_1d(cy, st.ncell[1], st.pbc[1], sy);
-    int nz = stencil_1d(cz, st.ncell[2], st.pbc[2], sz);
-    for (int a = 0; a < nz; ++a)
-      for (int b = 0; b < ny; ++b)
-        for (int c = 0; c < nx; ++c) {
-          int cell = st.cell_off + (sz[a] * st.ncell[1] + sy[b]) * st.ncell[0] + sx[c];
-          int s0 = cell_start[cell], cnt = cell_count[cell];
-          for (int k = 0; k < cnt; ++k) consider(s0 + k, 0, 0, 0);
+              Dx = pos[j] - xi;
+              Dy = pos[N + j] - yi;
+              Dz = pos[2 * N + j] - zi;
+            }
+            int n0, n1, n2;
+            min_image(st, Dx, Dy, Dz, n0, n1, n2);
+            if (!(j == i && n0 == 0 && n1 == 0 && n2 == 0)) {
+              double dx, dy, dz;
+              image_disp(st, Dx, Dy, Dz, n0, n1, n2, dx, dy, dz);
+              take = norm2_exact(dx, dy, dz) < rc2;
+            }
+          }
+          const uint64_t mt = __ballot(take) & gmask;
+          if (take) {
+            const int32_t p = count + __popcll(mt & below);
+            if (p < V.MR) {
+              V.nlR[(int64_t)p * N + i] = (int32_t)j;
+              V.cdR[(int64_t)p * N + i] = code0;
+            }
+          }
+          count += __popcll(mt);
         }
-  } else if (st.mode == kModeAllPairs) {
-    for (int64_t j = st.start; j < st.start + st.count; ++j) consider(j, 0, 0, 0);
-  } else {
-    const int R0 = st.reach[0], R1 = st.reach[1], R2 = st.reach[2];
-    for (int64_t j = st.start; j < st.start + st.count; ++j)
-      for (int o0 = -R0; o0 <= R0; ++o0)
-        for (int o1 = -R1; o1 <= R1; ++o1)
-          for (int o2 = -R2; o2 <= R2; ++o2) consider(j, o0, o1, o2);
+      }
+  if (sub == 0) {
+    V.nnR[i] = count;
+    if (count > V.MR) atomicMax(overflow, count);
   }
-  V.nnR[i] = R.count;
-  if (R.count > V.MR) atomicMax(overflow, R.count);
 }
 
 // Candidate rows of the atoms of structures without cells (all-pairs and
@@ -630,8 +630,8 @@ void launch_reverse(int64_t N, const Lists& L, int32_t* err, const int32_t* gate
 // gate is set.
 void launch_build_verlet(const BuildArgs& b, const Lists& V, hipStream_t s) {
   // structures without cells take their rows from the wide kernel
-  hipLaunchKernelGGL(k_build_rows, grid_for(b.N), dim3(kBlock), 0, s, b.pos, b.N, b.sid, b.structs,
-                     b.cell_start, b.cell_count, b.rcR2, V, b.overflow + 5, b.gate, b.wide_rows);
+  hipLaunchKernelGGL(k_build_rows, grid_for(b.N * kCellLanes), dim3(kBlock), 0, s, b.pos, b.N, b.sid,
+                     b.structs, b.cell_start, b.cell_count, b.rcR2, V, b.overflow + 5, b.gate);
   if (b.wide_rows)
     hipLaunchKernelGGL(k_build_rows_wide, grid_for(b.N * kBuildLanes), dim3(kBlock), 0, s, b.pos, b.N,
                        b.sid, b.structs, b.rcR2, V, b.overflow + 5, b.gate);
