@@ -449,3 +449,110 @@ def test_candidate_row_slices_reproduce_the_sequential_scan():
                 if img == nimg:
                     img, jl = 0, jl + 1
         assert got == seq
+
+
+def test_cell_build_ballot_placement_emulation():
+    """k_build_rows for cell structures, four lanes per atom: a cell's atoms
+    are taken four at a time (lane s the (k0 + s)-th), and an accepted one's
+    slot is the count so far plus the accepted lanes below it in the same
+    step (ballot popcounts).  Emulated lane by lane against a one-lane scan:
+    the same row in the same order, and every slot written is below the row
+    capacity while the count keeps counting past it."""
+    rng = np.random.default_rng(12)
+    G = 4
+    for trial in range(200):
+        ncell = int(rng.integers(1, 28))
+        counts = rng.integers(0, 30, ncell)
+        starts = np.concatenate([[0], np.cumsum(counts)[:-1]])
+        accept = rng.random(int(counts.sum())) < rng.uniform(0.05, 0.9)
+        cap = int(rng.integers(1, 80))
+        seq = [int(starts[c] + k) for c in range(ncell) for k in range(counts[c])
+               if accept[starts[c] + k]]
+        row = [None] * cap
+        count = 0
+        for c in range(ncell):
+            s0, cnt = int(starts[c]), int(counts[c])
+            for k0 in range(0, cnt, G):
+                take = [k0 + s < cnt and bool(accept[s0 + k0 + s]) for s in range(G)]
+                for s in range(G):
+                    if take[s]:
+                        p = count + sum(take[:s])
+                        if p < cap:
+                            assert row[p] is None
+                            row[p] = s0 + k0 + s
+                count += sum(take)
+        assert count == len(seq)
+        assert row[:min(cap, count)] == seq[:cap]
+
+
+def test_lockstep_binary_searches_match_one_at_a_time():
+    """k_reverse's four searches per lane advance together, each stepping only
+    while it has neither found its key nor emptied its range; the positions
+    found are those of a plain binary search for the (index, code) key in a
+    row sorted by (index, code), and a missing key is reported."""
+    rng = np.random.default_rng(13)
+
+    def plain(row, key):
+        lo, hi = 0, len(row) - 1
+        while lo <= hi:
+            mid = (lo + hi) >> 1
+            if row[mid] == key:
+                return mid
+            if row[mid] < key:
+                lo = mid + 1
+            else:
+                hi = mid - 1
+        return -1
+
+    for trial in range(300):
+        rows, keys = [], []
+        for u in range(4):
+            n = int(rng.integers(0, 90))
+            row = sorted(set((int(rng.integers(0, 500)), int(rng.integers(0, 4)))
+                             for _ in range(n)))
+            rows.append(row)
+            if row and rng.random() < 0.8:
+                keys.append(row[int(rng.integers(0, len(row)))])
+            else:
+                keys.append((int(rng.integers(0, 500)), int(rng.integers(0, 4))))
+        lo = [0] * 4
+        hi = [len(r) - 1 for r in rows]
+        found = [-1] * 4
+        steps = 0
+        while True:
+            live = [found[u] < 0 and lo[u] <= hi[u] for u in range(4)]
+            if not any(live):
+                break
+            steps += 1
+            assert steps <= 64
+            for u in range(4):
+                if not live[u]:
+                    continue
+                mid = (lo[u] + hi[u]) >> 1
+                assert 0 <= mid < len(rows[u])
+                if rows[u][mid] == keys[u]:
+                    found[u] = mid
+                elif rows[u][mid] < keys[u]:
+                    lo[u] = mid + 1
+                else:
+                    hi[u] = mid - 1
+        for u in range(4):
+            assert found[u] == plain(rows[u], keys[u])
+            if keys[u] in rows[u]:
+                assert rows[u][found[u]] == keys[u]
+
+
+def test_row_check_lanes_cover_every_entry_once():
+    """k_check_rows with four lanes per atom and four entries per lane at a
+    time: lane s of an atom visits entries m0 + 4u (m0 = s, s + 16, ...), so
+    the lanes together visit every entry of the row exactly once."""
+    G, U = 4, 4
+    for nn in range(0, 130):
+        seen = []
+        for s in range(G):
+            for m0 in range(s, nn, U * G):
+                for u in range(U):
+                    m = m0 + u * G
+                    if m < nn:
+                        seen.append(m)
+        assert sorted(seen) == list(range(nn))
