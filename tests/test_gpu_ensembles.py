@@ -75,18 +75,28 @@ def test_short_run_matches_oracle(alloy, name, skin):
 
 
 def test_split_run_continues_random_streams(alloy):
-    """Two calls of 10 steps carrying the state follow one call of 20 steps
-    (to the float32 tolerance: the second call re-sorts the atoms), which
-    holds only if the second call continues the Langevin streams."""
+    """Two calls of 10 steps carrying the state follow one call of 20 steps,
+    which holds only if the second call continues the Langevin streams.  The
+    second call continues the first one's internal state (atom order, rows,
+    forces), so the split run is the single run bit for bit; a split whose
+    second call starts from a fresh handle re-sorts the atoms and agrees to
+    the float32 tolerance."""
     h, p, pos, vel, types, m, box = alloy
     ens = ENS["nvt_langevin"]
     handle = nep.Handle(h, p, skin=0.5)
     a = handle.md_run_ensemble(pos, vel, types, m, box, 1.0, 20, 0, ens)
     b = handle.md_run_ensemble(pos, vel, types, m, box, 1.0, 10, 0, ens)
+    before = handle.md_counters()["continued_runs"]
     c = handle.md_run_ensemble(b[0], b[1], types, m, b[2], 1.0, 10, 0, ens, state=b[4])
+    assert handle.md_counters()["continued_runs"] == before + 1
     assert a[4][0] == c[4][0] == 20
-    assert np.abs(a[0] - c[0]).max() < 1e-6 and np.abs(a[1] - c[1]).max() < 1e-7
+    assert np.array_equal(a[0], c[0]) and np.array_equal(a[1], c[1])
     handle.close()
+    fresh = nep.Handle(h, p, skin=0.5)
+    d = fresh.md_run_ensemble(b[0], b[1], types, m, b[2], 1.0, 10, 0, ens, state=b[4])
+    assert fresh.md_counters()["continued_runs"] == 0
+    assert np.abs(a[0] - d[0]).max() < 1e-6 and np.abs(a[1] - d[1]).max() < 1e-7
+    fresh.close()
 
 
 def test_nhc_conserves_extended_energy_gpu(alloy):
