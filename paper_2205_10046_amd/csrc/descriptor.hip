@@ -25,6 +25,7 @@
 //   W_i = sum_j r_ij (x) dU_j/dr_ji over the radial row, reading dU_j/dr_ji
 //   through the reverse index: no atomics, so results are bitwise
 //   reproducible.
+#include <type_traits>
 #include <vector>
 
 #include "angular.h"
@@ -476,11 +477,15 @@ __global__ void __launch_bounds__(kBlock, (NG * num_poly(L) > 120) ? 1 : 2)
 
   // ---- angular: sum_{n,k} D_{nk} [g'_n u b_k + g_n d b_k / d r_ij] ----
   const float rcA = M.rcA;
-  for (int g = 0; g < a.ngroups; ++g) {
+  // one pass over the angular bonds per group of radial functions; NQ of
+  // the group's NG are live (fewer in the last group when NG does not divide
+  // n_A and the basis sizes are constants)
+  auto angular_group = [&](auto nq, int g) __attribute__((always_inline)) {
+    constexpr int NQ = decltype(nq)::value;
     // D_{nk} = dU/dS_{nk} through q_{nl}, q_{n222}, q_{n1111}
-    float D[NG][NB];
+    float D[NQ][NB];
 #pragma unroll
-    for (int q = 0; q < NG; ++q) {
+    for (int q = 0; q < NQ; ++q) {
       const int n = min(g * NG + q, nA - 1);
       const bool live = g * NG + q < nA;
       const float* sums = a.sums + (int64_t)(n * NB) * N + i;
@@ -521,12 +526,12 @@ __global__ void __launch_bounds__(kBlock, (NG * num_poly(L) > 120) ? 1 : 2)
       const float ux = fx * rinv, uy = fy * rinv, uz = fz * rinv;
       const Basis bs = make_basis(r, rcA);
       const float* c = sA + (ti * T + tj) * M.cA_pair[NG] + g * KA * W;
-      float gq[NG], dgq[NG];
+      float gq[NQ], dgq[NQ];
       {
-        float cv[NG];
-        load_group<NG>(c, cv);
+        float cv[NQ];
+        load_group<NQ>(c, cv);
 #pragma unroll
-        for (int q = 0; q < NG; ++q) {
+        for (int q = 0; q < NQ; ++q) {
           gq[q] = cv[q] * bs.fc;
           dgq[q] = cv[q] * bs.dfc;
         }
@@ -535,12 +540,12 @@ __global__ void __launch_bounds__(kBlock, (NG * num_poly(L) > 120) ? 1 : 2)
 #pragma unroll
       for (int k = 1; k < kMaxBasis; ++k) {
         if (k >= KA) break;
-        float cv[NG];
-        load_group<NG>(c + k * W, cv);
+        float cv[NQ];
+        load_group<NQ>(c + k * W, cv);
         const float f = 0.5f * (Tk + 1.f) * bs.fc;
         const float df = 0.5f * dTk * bs.dxdr * bs.fc + 0.5f * (Tk + 1.f) * bs.dfc;
 #pragma unroll
-        for (int q = 0; q < NG; ++q) {
+        for (int q = 0; q < NQ; ++q) {
           gq[q] += cv[q] * f;
           dgq[q] += cv[q] * df;
         }
@@ -551,16 +556,16 @@ __global__ void __launch_bounds__(kBlock, (NG * num_poly(L) > 120) ? 1 : 2)
         dTm1 = dTk;
         dTk = dTn;
       }
-      float E[NG];
+      float E[NQ];
 #pragma unroll
-      for (int q = 0; q < NG; ++q) E[q] = 0.f;
+      for (int q = 0; q < NQ; ++q) E[q] = 0.f;
       float Vx = 0.f, Vy = 0.f, Vz = 0.f;
       angular_terms<L>(ux, uy, uz,
                        [&](int k, float b, float gx, float gy, float gz)
                            __attribute__((always_inline)) {
                              float w = 0.f;
 #pragma unroll
-                             for (int q = 0; q < NG; ++q) {
+                             for (int q = 0; q < NQ; ++q) {
                                w += gq[q] * D[q][k];
                                E[q] += D[q][k] * b;
                              }
@@ -570,7 +575,7 @@ __global__ void __launch_bounds__(kBlock, (NG * num_poly(L) > 120) ? 1 : 2)
                            });
       float s = 0.f;
 #pragma unroll
-      for (int q = 0; q < NG; ++q) s += dgq[q] * E[q];
+      for (int q = 0; q < NQ; ++q) s += dgq[q] * E[q];
       const float uV = ux * Vx + uy * Vy + uz * Vz;
       const float px = s * ux + (Vx - uV * ux) * rinv;
       const float py = s * uy + (Vy - uV * uy) * rinv;
@@ -589,6 +594,13 @@ __global__ void __launch_bounds__(kBlock, (NG * num_poly(L) > 120) ? 1 : 2)
       v.z += pz;
       a.P[e] = v;
     });
+  };
+  if constexpr (S != 0) {
+    constexpr int NGR = (Sh::nA + NG - 1) / NG, NL = Sh::nA - (NGR - 1) * NG;
+    for (int g = 0; g < NGR - 1; ++g) angular_group(std::integral_constant<int, NG>{}, g);
+    angular_group(std::integral_constant<int, NL>{}, NGR - 1);
+  } else {
+    for (int g = 0; g < a.ngroups; ++g) angular_group(std::integral_constant<int, NG>{}, g);
   }
 }
 
