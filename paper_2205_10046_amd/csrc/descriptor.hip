@@ -479,7 +479,8 @@ __global__ void __launch_bounds__(kBlock, (NG * num_poly(L) > 120) ? 1 : 2)
   const float rcA = M.rcA;
   // one pass over the angular bonds per group of radial functions; NQ of
   // the group's NG are live (fewer in the last group when NG does not divide
-  // n_A and the basis sizes are constants)
+  // n_A and the basis sizes are constants; for l_max <= 4 only: with the larger
+  // polynomial sets the second body costs more registers than it saves)
   auto angular_group = [&](auto nq, int g) __attribute__((always_inline)) {
     constexpr int NQ = decltype(nq)::value;
     // D_{nk} = dU/dS_{nk} through q_{nl}, q_{n222}, q_{n1111}
@@ -595,7 +596,7 @@ __global__ void __launch_bounds__(kBlock, (NG * num_poly(L) > 120) ? 1 : 2)
       a.P[e] = v;
     });
   };
-  if constexpr (S != 0) {
+  if constexpr (S != 0 && L <= 4) {
     constexpr int NGR = (Sh::nA + NG - 1) / NG, NL = Sh::nA - (NGR - 1) * NG;
     for (int g = 0; g < NGR - 1; ++g) angular_group(std::integral_constant<int, NG>{}, g);
     angular_group(std::integral_constant<int, NL>{}, NGR - 1);
