@@ -386,8 +386,12 @@ __global__ void __launch_bounds__(256) k_mlp_lds(EvalArgs a, int32_t groups_per_
                                                     mlp_weight_bytes(M, BF16));
   const uint16_t* swb = hw;
   const uint16_t* swtb = swb + NNp * SWB;
+  // the bf16 kernel loads the next group's q while the current group is
+  // computed; the float32 one loads each group's q when it starts (the
+  // prefetch's 24 registers cost it a wave per SIMD)
+  constexpr bool kPrefetch = BF16;
   float qn[kMlpQ];
-  if (g_begin < g_end) load_q<BF16>(a, a.rows[g_begin * kRowGroup + r0 + col], grp, KS, qn);
+  if (kPrefetch && g_begin < g_end) load_q<BF16>(a, a.rows[g_begin * kRowGroup + r0 + col], grp, KS, qn);
   int cur_net = -1;
   for (int64_t gi = g_begin; gi < g_end; ++gi) {
     const int64_t base = gi * kRowGroup;
@@ -402,9 +406,13 @@ __global__ void __launch_bounds__(256) k_mlp_lds(EvalArgs a, int32_t groups_per_
     }
     const int atom = a.rows[base + r0 + col];
     float qv[kMlpQ];
+    if constexpr (kPrefetch) {
 #pragma unroll
-    for (int k = 0; k < kMlpQ; ++k) qv[k] = qn[k];
-    if (gi + 1 < g_end) load_q<BF16>(a, a.rows[base + kRowGroup + r0 + col], grp, KS, qn);
+      for (int k = 0; k < kMlpQ; ++k) qv[k] = qn[k];
+      if (gi + 1 < g_end) load_q<BF16>(a, a.rows[base + kRowGroup + r0 + col], grp, KS, qn);
+    } else {
+      load_q<BF16>(a, atom, grp, KS, qv);
+    }
     int out_atom[4];
 #pragma unroll
     for (int r = 0; r < 4; ++r) out_atom[r] = a.rows[base + r0 + 4 * grp + r];
