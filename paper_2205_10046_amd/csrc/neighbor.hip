@@ -332,33 +332,11 @@ __global__ void __launch_bounds__(kBlock) k_build_rows(
 // image modes: small cells, whose rows scan every atom of the structure, or
 // every (atom, image) pair), kBuildLanes lanes per atom.  The candidates of
 // atom i form one sequence in row order -- the atoms of the structure, or
-// the (atom, image) pairs with the image offsets innermost -- and lane s takes
-// the s-th contiguous slice of it.  Pass 1 counts each slice's members, a
-// prefix sum over the atom's lanes gives every slice its place, and pass 2
-// tests the slice again and writes its members there, so the row is the one
-// the sequential scan of k_build_rows writes: sorted by (j, image).
+// the (atom, image) pairs with the image offsets innermost -- taken
+// kBuildLanes at a time (lane s the s-th of each step); each member is placed
+// by a count over the atom's lanes' ballot bits, so the row is the one a
+// sequential scan of the sequence writes: sorted by (j, image).
 constexpr int kBuildLanes = 16;
-
-template <class Fn>
-__device__ __forceinline__ void visit_slice(const StructInfo& st, int64_t c0, int64_t c1, Fn&& fn) {
-  if (c0 >= c1) return;
-  if (st.mode == kModeAllPairs) {
-    for (int64_t c = c0; c < c1; ++c) fn(st.start + c, 0, 0, 0);
-    return;
-  }
-  const int R0 = st.reach[0], R1 = st.reach[1], R2 = st.reach[2];
-  const int w1 = 2 * R1 + 1, w2 = 2 * R2 + 1, nimg = (2 * R0 + 1) * w1 * w2;
-  int64_t jl = c0 / nimg;
-  int img = (int)(c0 - jl * nimg);
-  for (int64_t c = c0; c < c1; ++c) {
-    const int o0 = img / (w1 * w2) - R0, o1 = (img / w2) % w1 - R1, o2 = img % w2 - R2;
-    fn(st.start + jl, o0, o1, o2);
-    if (++img == nimg) {
-      img = 0;
-      ++jl;
-    }
-  }
-}
 
 __global__ void __launch_bounds__(kBlock) k_build_rows_wide(
     const double* __restrict__ pos, int64_t N, const int32_t* __restrict__ sid,
@@ -375,8 +353,6 @@ __global__ void __launch_bounds__(kBlock) k_build_rows_wide(
                             ? st.count
                             : st.count * (int64_t)((2 * st.reach[0] + 1) * (2 * st.reach[1] + 1) *
                                                    (2 * st.reach[2] + 1));
-  const int64_t chunk = (total + G - 1) / G;
-  const int64_t c0 = min(total, chunk * sub), c1 = min(total, c0 + chunk);
   // member test of candidate (j, image offset o)
   auto member = [&](int64_t j, int o0, int o1, int o2, uint16_t& code) -> bool {
     double Dx, Dy, Dz;
@@ -397,32 +373,45 @@ __global__ void __launch_bounds__(kBlock) k_build_rows_wide(
     code = make_code(o0, o1, o2);
     return norm2_exact(dx, dy, dz) < rc2;
   };
-  // pass 1: members of this lane's slice
-  int32_t mine = 0;
-  visit_slice(st, c0, c1, [&](int64_t j, int o0, int o1, int o2) {
-    uint16_t code;
-    if (member(j, o0, o1, o2, code)) ++mine;
-  });
-  // exclusive prefix over the atom's lanes, and the total
-  int32_t incl = mine;
-#pragma unroll
-  for (int d = 1; d < G; d <<= 1) {
-    const int32_t v = __shfl_up(incl, d, G);
-    if (sub >= d) incl += v;
-  }
-  const int32_t count = __shfl(incl, G - 1, G);
-  // pass 2: write this slice's members from its place on
-  int32_t p = incl - mine;
-  visit_slice(st, c0, c1, [&](int64_t j, int o0, int o1, int o2) {
-    uint16_t code;
-    if (member(j, o0, o1, o2, code)) {
+  // candidates c = G t + s of the sequence (the atoms of the structure, or the
+  // (atom, image) pairs with the image offsets innermost), G at a time; an
+  // accepted one's slot is the count so far plus the accepted lanes below it
+  const int R0 = st.reach[0], R1 = st.reach[1], R2 = st.reach[2];
+  const int w1 = 2 * R1 + 1, w2 = 2 * R2 + 1, nimg = (2 * R0 + 1) * w1 * w2;
+  const bool all_pairs = st.mode == kModeAllPairs;
+  const int lane = threadIdx.x & 63;
+  const uint64_t gmask = ((1ull << G) - 1) << (lane & ~(G - 1));
+  const uint64_t below = (1ull << lane) - 1;
+  int32_t count = 0;
+  for (int64_t c0 = 0; c0 < total; c0 += G) {
+    const int64_t c = c0 + sub;
+    bool take = false;
+    uint16_t code = kCodeCenter;
+    int64_t j = 0;
+    if (c < total) {
+      int o0 = 0, o1 = 0, o2 = 0;
+      if (all_pairs) {
+        j = st.start + c;
+      } else {
+        const int64_t jl = c / nimg;
+        const int img = (int)(c - jl * nimg);
+        j = st.start + jl;
+        o0 = img / (w1 * w2) - R0;
+        o1 = (img / w2) % w1 - R1;
+        o2 = img % w2 - R2;
+      }
+      take = member(j, o0, o1, o2, code);
+    }
+    const uint64_t mt = __ballot(take) & gmask;
+    if (take) {
+      const int32_t p = count + __popcll(mt & below);
       if (p < V.MR) {
         V.nlR[(int64_t)p * N + i] = (int32_t)j;
         V.cdR[(int64_t)p * N + i] = code;
       }
-      ++p;
     }
-  });
+    count += __popcll(mt);
+  }
   if (sub == 0) {
     V.nnR[i] = count;
     if (count > V.MR) atomicMax(overflow, count);

@@ -409,28 +409,17 @@ def test_cell_rank_sort_emulation():
         assert np.array_equal(out, seg[np.argsort(ext[seg])])
 
 
-def _slices(total, G):
-    chunk = -(-total // G)
-    out = []
-    for s in range(G):
-        c0 = min(total, chunk * s)
-        c1 = min(total, c0 + chunk)
-        out.append((c0, c1))
-    return out
-
-
-def test_candidate_row_slices_reproduce_the_sequential_scan():
+def test_candidate_sequence_steps_reproduce_the_sequential_scan():
     """k_build_rows_wide's sixteen lanes per atom (structures without cells):
-    the slices of the candidate sequence partition it in order, and the
-    (atom, image) pairs decoded from the sequence index are those of the
-    sequential scan of k_build_rows, in its order, inside the structure's
-    atoms and image reach."""
+    the candidate sequence is taken sixteen at a time (lane s the s-th of each
+    step), and the (atom, image) pairs each lane decodes from its sequence
+    index, in step and lane order, are those of the sequential scan, inside
+    the structure's atoms and image reach (the members' slots then follow from
+    the ballot counts emulated below)."""
     G = 16
-    for total in (0, 1, 15, 16, 17, 100, 541, 8000):
-        sl = _slices(total, G)
-        flat = [c for c0, c1 in sl for c in range(c0, c1)]
-        assert flat == list(range(total))
-    # image mode: atoms x images with the offsets innermost
+    for total in (0, 1, 15, 16, 17, 100, 541):
+        got = [c0 + s for c0 in range(0, total, G) for s in range(G) if c0 + s < total]
+        assert got == list(range(total))
     for reach in ((1, 1, 1), (2, 1, 0), (0, 0, 3), (2, 2, 2)):
         R0, R1, R2 = reach
         start, count = 37, 11
@@ -438,16 +427,16 @@ def test_candidate_row_slices_reproduce_the_sequential_scan():
                for o1 in range(-R1, R1 + 1) for o2 in range(-R2, R2 + 1)]
         w1, w2 = 2 * R1 + 1, 2 * R2 + 1
         nimg = (2 * R0 + 1) * w1 * w2
+        total = count * nimg
         got = []
-        for c0, c1 in _slices(count * nimg, G):
-            if c0 >= c1:
-                continue
-            jl, img = divmod(c0, nimg)
-            for c in range(c0, c1):
+        for c0 in range(0, total, G):
+            for s_ in range(G):
+                c = c0 + s_
+                if c >= total:
+                    continue
+                jl, img = divmod(c, nimg)
+                assert 0 <= jl < count
                 got.append((start + jl, img // (w1 * w2) - R0, (img // w2) % w1 - R1, img % w2 - R2))
-                img += 1
-                if img == nimg:
-                    img, jl = 0, jl + 1
         assert got == seq
 
 
