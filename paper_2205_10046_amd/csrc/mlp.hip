@@ -367,7 +367,7 @@ __device__ __forceinline__ void stage_weights(const DevModel& M, int net, int ti
 }  // namespace
 
 template <int NNB, bool BF16>
-__global__ void __launch_bounds__(256) k_mlp_lds(EvalArgs a, int32_t groups_per_block) {
+__global__ void __launch_bounds__(256, NNB <= 4 ? 4 : 1) k_mlp_lds(EvalArgs a, int32_t groups_per_block) {
   extern __shared__ float4 mlp_lds[];
   const DevModel& M = a.M;
   const int64_t n_groups = a.rows_len / kRowGroup;
