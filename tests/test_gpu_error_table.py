@@ -27,7 +27,7 @@ from paper_2205_10046_amd import nep, synth
 
 pytestmark = pytest.mark.gpu
 
-GATES = {nep.NEP_MLP_FP32: dict(e=1e-6, f=1e-4, w=1e-4, u=1e-5),
+GATES = {nep.NEP_MLP_FP32: dict(e=1e-6, f=1e-4, w=1e-4, u=5e-6),
          nep.NEP_MLP_BF16: dict(e=1e-3, f=1e-2, w=None, u=None)}
 NAME = {nep.NEP_MLP_FP32: "fp32", nep.NEP_MLP_BF16: "bf16"}
 

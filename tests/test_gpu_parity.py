@@ -1,10 +1,12 @@
 """HIP path vs the FP64 oracle, through the C ABI.
 
-Tolerances (spec gate for the FP32 path): energy per atom
-|dE|/N <= 1e-6 eV/atom, every force component <= 1e-4 eV/A, every per-atom
-virial component <= 1e-4 eV and the total virial |dW|/N <= 1e-6 eV/atom.
-The largest single site-energy error is printed and bounded by 1e-5 eV
-(float32 pre-activation sums alone reach ~1e-6 eV per site).  BF16 network: |dE|/N <= 1 meV/atom
+Tolerances of the FP32 path: energy per atom |dE|/N <= 1e-6 eV/atom, every
+force component <= 1e-4 eV/A, every per-atom virial component <= 1e-4 eV and
+the total virial |dW|/N <= 1e-6 eV/atom.  The largest single site-energy
+error is printed and bounded by 5e-6 eV: float32 site energies carry a few
+ulps of rounding (the worst measured, 1.4e-6 eV, is a perturbed population
+set of the batch case; single structures stay below 4e-7 eV), so the bound
+leaves about 3.5 times the worst case.  BF16 network: |dE|/N <= 1 meV/atom
 and every force component <= 10 meV/A.  Neighbour rows: identical sets of (i, j, image) after sorting.
 """
 import numpy as np
@@ -16,7 +18,7 @@ from paper_2205_10046_amd import nep, synth
 pytestmark = pytest.mark.gpu
 
 TOL_E, TOL_F, TOL_W = 1e-6, 1e-4, 1e-4   # eV/atom, eV/A, eV
-TOL_SITE = 1e-5                           # eV, largest single site energy
+TOL_SITE = 5e-6                           # eV, largest single site energy
 
 
 def log(*a):
@@ -372,7 +374,7 @@ def test_batch_population_matches_oracle():
     pop = synth.population(mean, 3)
     handle = nep.Handle(h, mean)
     e, f, w, t = _run_batch(handle, pos, types, boxes, offs, pop)
-    worst = 0.0
+    worst = worst_u = 0.0
     for p in range(pop.shape[0]):
         for s, (ps, ts, bs) in enumerate(structs):
             a, b = offs[s], offs[s + 1]
@@ -382,11 +384,13 @@ def test_batch_population_matches_oracle():
             dF = np.abs(f[p, :, a:b] - ref["F"]).max()
             dW = np.abs(w[p, :, a:b] - ref["W"]).max()
             worst = max(worst, dF)
+            worst_u = max(worst_u, dU)
             assert dE <= TOL_E and dU <= TOL_SITE and dF <= TOL_F and dW <= TOL_W, \
                 (p, s, dE, dU, dF, dW)
             np.testing.assert_allclose(t[p, s, 0], ref["U"].sum(), atol=TOL_E * (b - a))
             np.testing.assert_allclose(t[p, s, 1:], w[p, :, a:b].sum(1), atol=1e-9 * (b - a))
-    log(f"[batch] {len(structs)} structures x {pop.shape[0]} sets: worst |dF| {worst:.2e}")
+    log(f"[batch] {len(structs)} structures x {pop.shape[0]} sets: worst |dF| {worst:.2e}, "
+        f"worst |dU_i| {worst_u:.2e}")
 
 
 def test_batch_invariance_bitwise():
@@ -428,7 +432,7 @@ def test_batch_full_size_sampled():
     rng = np.random.default_rng(31)
     picks = [int(np.argmin(sizes)), int(np.argmax(sizes))] + list(rng.choice(S, 4, replace=False))
     sets = [0, 17, 49]
-    worst = 0.0
+    worst = worst_u = 0.0
     for p in sets:
         for s in picks:
             a, b = int(offs[s]), int(offs[s + 1])
@@ -442,6 +446,7 @@ def test_batch_full_size_sampled():
             dF = np.abs(ff - ref["F"]).max()
             dW = np.abs(ww - ref["W"]).max()
             worst = max(worst, dF)
+            worst_u = max(worst_u, dU)
             assert dE <= TOL_E and dU <= TOL_SITE and dF <= TOL_F and dW <= TOL_W, \
                 (p, s, b - a, dE, dU, dF, dW)
     # structure totals: energy and virial sums of every structure and vector
@@ -451,7 +456,8 @@ def test_batch_full_size_sampled():
     tol = torch.tensor(sizes, dtype=torch.float64, device=dev)
     assert bool(((t[:, :, 0] - e_sum).abs() <= 1e-9 * tol).all())
     assert bool(((t[:, :, 1:] - w_sum.transpose(1, 2)).abs() <= 1e-9 * tol[None, :, None]).all())
-    log(f"[batch-full] sampled {len(sets)} x {len(picks)} pairs: worst |dF| {worst:.2e}")
+    log(f"[batch-full] sampled {len(sets)} x {len(picks)} pairs: worst |dF| {worst:.2e}, "
+        f"worst |dU_i| {worst_u:.2e}")
 
 
 def test_md_with_skin_matches_rebuild_every_step():
